@@ -1,0 +1,284 @@
+"""Python access to the CPU oracle (oracle/rlwe_oracle.c) and client-side helpers.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+CPU-baseline leg of the benchmark. The product path never imports this module.
+
+The client side of the protocol lives here too (Sec. 4.3): splitting an int8
+activation vector into L = ceil(d_in / N) zero-padded blocks, encrypting every
+block (Sec. 3.1) and decrypting returned LWE ciphertexts. Random draws (mask,
+secret, error) are inputs produced by ``paper_2505_07329_amd.synth``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Iterable, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rlwe_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i8p = ctypes.POINTER(ctypes.c_int8)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (OpenMP); returns the library path."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-Wall",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        L = _lib
+        L.orc_mulmod.restype = ctypes.c_uint64
+        L.orc_mulmod.argtypes = [ctypes.c_uint64] * 3
+        L.orc_powmod.restype = ctypes.c_uint64
+        L.orc_powmod.argtypes = [ctypes.c_uint64] * 3
+        L.orc_find_psi.restype = ctypes.c_uint64
+        L.orc_find_psi.argtypes = [ctypes.c_uint32, ctypes.c_uint64]
+        L.orc_poly_mul_schoolbook.argtypes = [_u64p, _u64p, ctypes.c_uint32, ctypes.c_uint64, _u64p]
+        L.orc_poly_mul_ntt.argtypes = [_u64p, _u64p, ctypes.c_uint32, ctypes.c_uint64,
+                                       ctypes.c_uint64, _u64p]
+        L.orc_delta.argtypes = [ctypes.c_uint32, _u64p, ctypes.c_uint32, _u64p, _u64p]
+        L.orc_encrypt.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u64p, ctypes.c_uint32, _i8p,
+                                  ctypes.c_size_t, _u64p, _i64p, _i64p, ctypes.c_int, _u64p]
+        L.orc_rlwe_phase.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u64p, _i8p,
+                                     ctypes.c_size_t, _u64p, _u64p, _u64p]
+        L.orc_sample_extract.argtypes = [_u64p, _u64p, ctypes.c_uint32, ctypes.c_uint64,
+                                         ctypes.c_uint32, _u64p, _u64p]
+        L.orc_matmul_clear.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u64p, ctypes.c_uint32,
+                                       ctypes.c_uint32, _i8p, ctypes.c_uint32, _u64p,
+                                       ctypes.c_size_t, _u32p, ctypes.c_int, _u64p]
+        L.orc_modswitch.argtypes = [ctypes.c_uint32, _u64p, ctypes.c_size_t, ctypes.c_uint32,
+                                    _u64p, _u32p]
+        L.orc_crt.argtypes = [ctypes.c_uint32, _u64p, _u64p, _u64p, _u64p]
+        L.orc_lwe_phase.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u64p, _i8p,
+                                    ctypes.c_size_t, _u64p, _u64p]
+        L.orc_lwe_phase_u32.argtypes = [ctypes.c_uint32, _i8p, ctypes.c_size_t, _u32p, _i64p]
+    return _lib
+
+
+def _p(a: np.ndarray, t):
+    return a.ctypes.data_as(t)
+
+
+def _primes(primes: Sequence[int]) -> np.ndarray:
+    return np.ascontiguousarray(np.array([int(p) for p in primes], dtype=np.uint64))
+
+
+# ------------------------------------------------------------------ scalars
+
+def modulus(primes: Sequence[int]) -> int:
+    q = 1
+    for p in primes:
+        q *= int(p)
+    return q
+
+
+def delta(primes: Sequence[int], log2_t: int) -> int:
+    """Delta = floor(q / t) (Sec. 3.1 writes q/p; q is odd so the floor is taken)."""
+    pr = _primes(primes)
+    hi = ctypes.c_uint64()
+    lo = ctypes.c_uint64()
+    lib().orc_delta(len(pr), _p(pr, _u64p), log2_t, ctypes.byref(hi), ctypes.byref(lo))
+    return (hi.value << 64) | lo.value
+
+
+def find_psi(N: int, q: int) -> int:
+    return int(lib().orc_find_psi(N, int(q)))
+
+
+def crt(primes: Sequence[int], residues: Sequence[int]) -> int:
+    pr = _primes(primes)
+    r = np.ascontiguousarray(np.array([int(x) for x in residues], dtype=np.uint64))
+    hi = ctypes.c_uint64()
+    lo = ctypes.c_uint64()
+    lib().orc_crt(len(pr), _p(pr, _u64p), _p(r, _u64p), ctypes.byref(hi), ctypes.byref(lo))
+    return (hi.value << 64) | lo.value
+
+
+def centered(c: int, q: int) -> int:
+    c %= q
+    return c - q if c > q // 2 else c
+
+
+# ------------------------------------------------------------------ ring
+
+def poly_mul_schoolbook(a: np.ndarray, b: np.ndarray, q: int) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    b = np.ascontiguousarray(b, dtype=np.uint64)
+    out = np.empty_like(a)
+    lib().orc_poly_mul_schoolbook(_p(a, _u64p), _p(b, _u64p), a.size, int(q), _p(out, _u64p))
+    return out
+
+
+def poly_mul_ntt(a: np.ndarray, b: np.ndarray, q: int, psi: int | None = None) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    b = np.ascontiguousarray(b, dtype=np.uint64)
+    if psi is None:
+        psi = find_psi(a.size, q)
+    out = np.empty_like(a)
+    lib().orc_poly_mul_ntt(_p(a, _u64p), _p(b, _u64p), a.size, int(q), int(psi), _p(out, _u64p))
+    return out
+
+
+def sample_extract(A: np.ndarray, B: np.ndarray, q: int, h: int):
+    A = np.ascontiguousarray(A, dtype=np.uint64)
+    B = np.ascontiguousarray(B, dtype=np.uint64)
+    a = np.empty_like(A)
+    b = ctypes.c_uint64()
+    lib().orc_sample_extract(_p(A, _u64p), _p(B, _u64p), A.size, int(q), h, _p(a, _u64p),
+                             ctypes.byref(b))
+    return a, b.value
+
+
+# ------------------------------------------------------------------ client side
+
+def num_blocks(d_in: int, N: int) -> int:
+    return (d_in + N - 1) // N
+
+
+def split_blocks(x: np.ndarray, N: int) -> np.ndarray:
+    """x: (T, d_in) int -> (T, L, N) int64, the last block zero-padded (Sec. 4.3)."""
+    x = np.asarray(x)
+    T, d_in = x.shape
+    L = num_blocks(d_in, N)
+    out = np.zeros((T, L * N), dtype=np.int64)
+    out[:, :d_in] = x
+    return out.reshape(T, L, N)
+
+
+def encrypt(N: int, primes, log2_t: int, S: np.ndarray, A: np.ndarray, E: np.ndarray,
+            msg: np.ndarray, use_ntt: bool = True) -> np.ndarray:
+    """B for each (A, E, msg): A (..., P, N) u64, E (..., N), msg (..., N) -> B (..., P, N)."""
+    pr = _primes(primes)
+    P = len(pr)
+    lead = A.shape[:-2]
+    count = int(np.prod(lead)) if lead else 1
+    A_ = np.ascontiguousarray(A.reshape(count, P, N), dtype=np.uint64)
+    E_ = np.ascontiguousarray(E.reshape(count, N), dtype=np.int64)
+    M_ = np.ascontiguousarray(msg.reshape(count, N), dtype=np.int64)
+    S_ = np.ascontiguousarray(S, dtype=np.int8)
+    B = np.empty_like(A_)
+    lib().orc_encrypt(N, P, _p(pr, _u64p), log2_t, _p(S_, _i8p), count, _p(A_, _u64p),
+                      _p(E_, _i64p), _p(M_, _i64p), int(use_ntt), _p(B, _u64p))
+    return B.reshape(A.shape)
+
+
+def encrypt_tokens(N: int, primes, log2_t: int, S: np.ndarray, x: np.ndarray, A: np.ndarray,
+                   E: np.ndarray, use_ntt: bool = True) -> np.ndarray:
+    """Encrypt T int8 vectors block by block.
+
+    x (T, d_in), A (T, L, P, N) uniform residues, E (T, L, N) errors
+    -> ct (T, L, 2, P, N) with ct[t, i, 0] = A, ct[t, i, 1] = B.
+    """
+    blocks = split_blocks(x, N)
+    B = encrypt(N, primes, log2_t, S, A, E, blocks, use_ntt)
+    T, L = blocks.shape[:2]
+    ct = np.empty((T, L, 2, len(primes), N), dtype=np.uint64)
+    ct[:, :, 0] = A
+    ct[:, :, 1] = B
+    return ct
+
+
+def rlwe_phase(N: int, primes, S: np.ndarray, A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    pr = _primes(primes)
+    P = len(pr)
+    count = int(np.prod(A.shape[:-2])) if A.ndim > 2 else 1
+    A_ = np.ascontiguousarray(A.reshape(count, P, N), dtype=np.uint64)
+    B_ = np.ascontiguousarray(B.reshape(count, P, N), dtype=np.uint64)
+    out = np.empty_like(A_)
+    S_ = np.ascontiguousarray(S, dtype=np.int8)
+    lib().orc_rlwe_phase(N, P, _p(pr, _u64p), _p(S_, _i8p), count, _p(A_, _u64p),
+                         _p(B_, _u64p), _p(out, _u64p))
+    return out.reshape(A.shape)
+
+
+# ------------------------------------------------------------------ server product
+
+def all_pairs(T: int, d_out: int) -> np.ndarray:
+    t, j = np.meshgrid(np.arange(T), np.arange(d_out), indexing="ij")
+    return np.stack([t.ravel(), j.ravel()], axis=1).astype(np.uint32)
+
+
+def matmul_clear(N: int, primes, W: np.ndarray, ct: np.ndarray,
+                 pairs: np.ndarray | None = None, mode: int = 1) -> np.ndarray:
+    """LWE(x . w_j) for each (t, j) pair, Eq. (LWEdot): uint64 (npairs, P, N+1).
+
+    W int8 (d_out, d_in); ct (T, L, 2, P, N); mode 0 schoolbook, 1 NTT.
+    With pairs=None every (t, j) is computed and the result is (T, d_out, P, N+1).
+    """
+    pr = _primes(primes)
+    P = len(pr)
+    W_ = np.ascontiguousarray(W, dtype=np.int8)
+    d_out, d_in = W_.shape
+    T, L = ct.shape[:2]
+    assert ct.shape == (T, L, 2, P, N) and L == num_blocks(d_in, N)
+    full = pairs is None
+    if full:
+        pairs = all_pairs(T, d_out)
+    pairs_ = np.ascontiguousarray(pairs, dtype=np.uint32)
+    ct_ = np.ascontiguousarray(ct, dtype=np.uint64)
+    out = np.empty((len(pairs_), P, N + 1), dtype=np.uint64)
+    lib().orc_matmul_clear(N, P, _p(pr, _u64p), d_out, d_in, _p(W_, _i8p), T, _p(ct_, _u64p),
+                           len(pairs_), _p(pairs_, _u32p), int(mode), _p(out, _u64p))
+    if full:
+        out = out.reshape(T, d_out, P, N + 1)
+    return out
+
+
+def modswitch(primes, raw: np.ndarray) -> np.ndarray:
+    """round(c 2^32 / q) mod 2^32 of CRT(raw[..., p, n]): (..., P, len) -> (..., len) u32."""
+    pr = _primes(primes)
+    P = len(pr)
+    ln = raw.shape[-1]
+    lead = raw.shape[:-2]
+    count = int(np.prod(lead)) if lead else 1
+    r = np.ascontiguousarray(raw.reshape(count, P, ln), dtype=np.uint64)
+    out = np.empty((count, ln), dtype=np.uint32)
+    lib().orc_modswitch(P, _p(pr, _u64p), count, ln, _p(r, _u64p), _p(out, _u32p))
+    return out.reshape(tuple(lead) + (ln,))
+
+
+def lwe_phase(N: int, primes, S: np.ndarray, lwe: np.ndarray) -> list[int]:
+    """Centred phase b - <a, S> mod q of LWE ciphertexts (..., P, N+1), as Python ints."""
+    pr = _primes(primes)
+    P = len(pr)
+    count = int(np.prod(lwe.shape[:-2])) if lwe.ndim > 2 else 1
+    c = np.ascontiguousarray(lwe.reshape(count, P, N + 1), dtype=np.uint64)
+    out = np.empty((count, P), dtype=np.uint64)
+    S_ = np.ascontiguousarray(S, dtype=np.int8)
+    lib().orc_lwe_phase(N, P, _p(pr, _u64p), _p(S_, _i8p), count, _p(c, _u64p), _p(out, _u64p))
+    q = modulus(primes)
+    return [centered(crt(primes, out[i]), q) for i in range(count)]
+
+
+def lwe_phase_u32(N: int, S: np.ndarray, lwe: np.ndarray) -> np.ndarray:
+    """Centred phase modulo 2^32 of switched LWE ciphertexts (..., N+1): int64 (...)."""
+    count = int(np.prod(lwe.shape[:-1])) if lwe.ndim > 1 else 1
+    c = np.ascontiguousarray(lwe.reshape(count, N + 1), dtype=np.uint32)
+    out = np.empty(count, dtype=np.int64)
+    S_ = np.ascontiguousarray(S, dtype=np.int8)
+    lib().orc_lwe_phase_u32(N, _p(S_, _i8p), count, _p(c, _u32p), _p(out, _i64p))
+    return out.reshape(lwe.shape[:-1])
+
+
+def decode(phase: int, delta_: int) -> int:
+    """Round a centred phase to the nearest multiple of Delta: the decrypted message."""
+    return (2 * phase + delta_) // (2 * delta_)

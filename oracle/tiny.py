@@ -1,0 +1,67 @@
+"""Pure-Python big-integer version of the scheme for tiny rings (N <= 64).
+
+TEST INFRASTRUCTURE ONLY. It works over Z_q with q the full modulus (no RNS
+split, no CRT inside the products), so agreement with the C oracle on tiny
+inputs checks the residue-wise C code against an independent route.
+
+Passages: Sec. 3.1 (RLWE encryption), Sec. 3.2 (SampleExtract, ModulusSwitch),
+Sec. 4.3 (block split, reversed weights, Eq. (LWEdot)).
+"""
+
+from __future__ import annotations
+
+
+def negacyclic_mul(a, b, q):
+    """a*b in Z_q[X]/(X^N+1), term by term."""
+    N = len(a)
+    out = [0] * N
+    for i in range(N):
+        for j in range(N):
+            if i + j < N:
+                out[i + j] += a[i] * b[j]
+            else:
+                out[i + j - N] -= a[i] * b[j]
+    return [c % q for c in out]
+
+
+def encrypt(q, t, S, A, E, msg):
+    """B = A*S + E + floor(q/t)*msg in R_q."""
+    delta = q // t
+    AS = negacyclic_mul(A, S, q)
+    return [(AS[k] + E[k] + delta * msg[k]) % q for k in range(len(A))]
+
+
+def sample_extract(A, B, q, h):
+    N = len(A)
+    a = [A[h - i] % q if i <= h else (-A[N + h - i]) % q for i in range(N)]
+    return a, B[h] % q
+
+
+def matmul_clear(q, N, W, cts):
+    """cts[i] = (A_i, B_i) for block i of one token; W rows w_j. Returns [(a, b)]."""
+    d_in = len(W[0])
+    L = len(cts)
+    res = []
+    for w in W:
+        acc_a = [0] * N
+        acc_b = 0
+        for i in range(L):
+            what = [w[i * N + N - 1 - k] if i * N + N - 1 - k < d_in else 0 for k in range(N)]
+            A, B = cts[i]
+            CA = negacyclic_mul(A, what, q)
+            CB = negacyclic_mul(B, what, q)
+            a, b = sample_extract(CA, CB, q, N - 1)
+            acc_a = [(x + y) % q for x, y in zip(acc_a, a)]
+            acc_b = (acc_b + b) % q
+        res.append((acc_a, acc_b))
+    return res
+
+
+def modswitch(c, q, bits=32):
+    """round(c 2^bits / q) mod 2^bits, half up."""
+    return ((c * (1 << (bits + 1)) + q) // (2 * q)) % (1 << bits)
+
+
+def lwe_phase(a, b, S, q):
+    ph = (b - sum(x * s for x, s in zip(a, S))) % q
+    return ph - q if ph > q // 2 else ph
