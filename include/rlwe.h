@@ -1,0 +1,151 @@
+/*
+ * rlwe.h — C ABI of the MI355X (gfx950) library for the server side of private
+ * LoRA fine-tuning under homomorphic encryption: the product of a clear int8
+ * weight matrix with RLWE-encrypted int8 vectors, W.[x]_HE (and W^T.[g]_HE for
+ * the backward pass through the frozen base), ending in a modulus switch.
+ *
+ * Paper: Frery, Bredehoft, Klemsa, Meyre, Stoian, "Private LoRA Fine-tuning of
+ * Open-Source LLMs with Homomorphic Encryption" (arXiv 2505.07329).
+ *   Sec. 3.1  RLWE ciphertext (A, B), B = A*S + E + Delta*M in Z_q[X]/(X^N+1);
+ *             LWE ciphertext (a, b), b = <a, s> + e + Delta*m.
+ *   Sec. 3.2  SampleExtract, ModulusSwitch, product with a clear polynomial.
+ *   Sec. 4.2  symmetric int8 quantization: the server computes only sum x_q w_q.
+ *   Sec. 4.3  x split into L = ceil(d_in/N) blocks, weights encoded in reverse,
+ *             Eq. (LWEdot): LWE(x.w_j) = sum_i SampleExtract(RLWE(x_i).w_ij, N-1),
+ *             then ModulusSwitch of the output.
+ *
+ * Everything here is exact integer arithmetic. Results are unique functions of
+ * the inputs: the same call gives the same bits on every run and every tiling.
+ *
+ * Conventions
+ *   - Pointers documented "device" are HIP device pointers (e.g. torch tensors
+ *     on the GPU); "host" pointers are CPU memory. The caller owns every buffer
+ *     it passes in; the library owns the context and weight handles.
+ *   - rlwe_stream_t is a hipStream_t (0 = the null stream). Compute calls only
+ *     enqueue work on it and return; errors of a kernel surface at the next
+ *     synchronisation.
+ *   - Residues crossing the ABI are canonical, in [0, q_p).
+ *   - Return value: RLWE_OK (0) or a negative RLWE_E* code; rlwe_last_error()
+ *     then describes the failure (thread-local, valid until the next call on the
+ *     same thread). No C++ exception crosses the ABI.
+ *   - A context and its workspace are not thread-safe: calls that use one
+ *     context must be issued from one thread at a time, and compute calls on a
+ *     context must be ordered on one stream (they share the workspace).
+ */
+#ifndef RLWE_H
+#define RLWE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RLWE_OK 0
+#define RLWE_EINVAL (-1)    /* null pointer, unknown flag, bad argument */
+#define RLWE_EPARAM (-2)    /* invalid cryptosystem parameters */
+#define RLWE_ESHAPE (-3)    /* shapes outside what the exact kernels support */
+#define RLWE_EOVERFLOW (-4) /* the integer product could wrap modulo t */
+#define RLWE_ENOMEM (-5)    /* device allocation failed */
+#define RLWE_EHIP (-6)      /* a HIP runtime call failed */
+
+typedef void* rlwe_stream_t; /* a hipStream_t */
+
+typedef struct rlwe_ctx rlwe_ctx;
+typedef struct rlwe_weights rlwe_weights;
+
+/* Cryptosystem parameters (Sec. 3.1, Sec. 4.4).
+ *   N           ring degree, a power of two in [64, 32768]
+ *   num_primes  P, 1 or 2: q = q_1 ... q_P in RNS form
+ *   primes      host pointer to P distinct primes, each < 2^54 and q_p = 1 mod 2N
+ *   log2_t      plaintext modulus t = 2^log2_t, 1 <= log2_t <= 32; Delta = floor(q/t)
+ *   log2_q_out  modulus of switched outputs; must be 32 */
+typedef struct rlwe_params {
+  uint32_t N;
+  uint32_t num_primes;
+  const uint64_t* primes;
+  uint32_t log2_t;
+  uint32_t log2_q_out;
+} rlwe_params;
+
+/* Validate the parameters, select device `hip_device` and build the context
+ * (CRT and switching constants). Errors: RLWE_EINVAL (null), RLWE_EPARAM, RLWE_EHIP. */
+int rlwe_params_init(const rlwe_params* params, int hip_device, rlwe_ctx** out);
+
+/* Release the context and its workspace (after all its work has completed).
+ * Weight handles created from it must be freed first. NULL is accepted. */
+int rlwe_params_destroy(rlwe_ctx* ctx);
+
+/* Flags of rlwe_weights_load */
+#define RLWE_W_FWD 1u       /* keep W for products W.[x] */
+#define RLWE_W_TRANSPOSE 2u /* keep W^T for products W^T.[g] (backward pass) */
+
+/* Make the clear weights resident on the device (Sec. 4.3, reversed block
+ * encoding is implied by the kernels; no NTT tables are needed).
+ *   W_dev   device pointer, int8 row-major [d_out][d_in], values in [-127, 127]
+ *           (symmetric quantization, Sec. 4.2); read during the call only
+ *   flags   RLWE_W_FWD and/or RLWE_W_TRANSPOSE
+ * Validation: 1 <= d_out, d_in <= 65536; the exact 128-bit accumulation needs
+ * 127 * d * q / 2 < 2^127 for the contraction length d (d_in forward, d_out
+ * transposed) -> RLWE_ESHAPE. Overflow: returns RLWE_EOVERFLOW if 127 times the
+ * largest row 1-norm (column 1-norm for W^T) reaches t/2, since W.x could then
+ * wrap modulo t (Sec. 4.4). Synchronises `stream` (set-up call). */
+int rlwe_weights_load(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32_t d_in,
+                      uint32_t flags, rlwe_stream_t stream, rlwe_weights** out);
+
+/* Release a weight handle (after all work that uses it has completed). NULL ok. */
+int rlwe_weights_free(rlwe_weights* w);
+
+/* Flags of ct_matmul_clear */
+#define RLWE_OUT_SWITCHED 0u    /* outputs switched to 2^32 (uint32) */
+#define RLWE_OUT_RAW_Q 1u       /* outputs modulo q, per prime (uint64) */
+#define RLWE_OUT_FORCE_EXACT 2u /* switched outputs through the slow exact path
+                                   for every coefficient (same bits; test hook) */
+
+/* The encrypted clear-weight product of Eq. (LWEdot) for `tokens` inputs.
+ * With transpose = 0 it computes W.[x] (d_in -> d_out); with transpose = 1,
+ * W^T.[g] (d_out -> d_in), which needs RLWE_W_TRANSPOSE at load time. Below,
+ * K is the input length (d_in, or d_out when transposed), M the output count,
+ * L = ceil(K / N).
+ *   ct_in  device, uint64 [tokens][L][2][P][N]: for token t and block i,
+ *          ct_in[t][i][0] = A and ct_in[t][i][1] = B of RLWE(x_hat_i), each
+ *          per prime p in canonical residues; x_hat_i holds inputs iN .. iN+N-1
+ *          (zero past K)
+ *   out    device; one LWE ciphertext per (token, output) under the key
+ *          (S_0 .. S_{N-1}): mask a_0 .. a_{N-1} then body b, with
+ *          a_n = sum_k w[k] * (A_i[k-n] if k >= n else -A_i[N+k-n]) summed over
+ *          blocks (SampleExtract at N-1 of the block products), b = sum_k w[k] B_i[k]
+ *            RLWE_OUT_SWITCHED: uint32 [tokens][M][N+1], each coefficient c
+ *              replaced by round(c * 2^32 / q) mod 2^32 (ModulusSwitch, Sec. 3.2)
+ *            RLWE_OUT_RAW_Q:    uint64 [tokens][M][P][N+1], residues mod q_p
+ * tokens = 0 is a no-op. Uses the context workspace (grown on demand with
+ * hipMalloc unless rlwe_workspace_reserve made it large enough). Asynchronous
+ * on `stream`. */
+int ct_matmul_clear(rlwe_ctx* ctx, const rlwe_weights* w, uint32_t transpose,
+                    const uint64_t* ct_in, uint32_t tokens, void* out, uint32_t flags,
+                    rlwe_stream_t stream);
+
+/* ModulusSwitch q -> 2^32 (Sec. 3.2) of `count` vectors of N+1 coefficients:
+ *   in   device, uint64 [count][P][N+1] canonical residues
+ *   out  device, uint32 [count][N+1], round(c * 2^32 / q) mod 2^32 with
+ *        c = CRT(residues) in [0, q) (a tie cannot occur: q is odd)
+ * count = 0 is a no-op. Asynchronous on `stream`; no workspace. */
+int ct_modswitch(rlwe_ctx* ctx, const uint64_t* in, size_t count, uint32_t* out,
+                 rlwe_stream_t stream);
+
+/* Bytes of workspace ct_matmul_clear needs for this call shape. */
+size_t rlwe_workspace_bytes(const rlwe_ctx* ctx, const rlwe_weights* w, uint32_t transpose,
+                            uint32_t tokens);
+
+/* Grow the context workspace to at least `bytes` now (hipMalloc), so that later
+ * calls within that size allocate nothing. */
+int rlwe_workspace_reserve(rlwe_ctx* ctx, size_t bytes);
+
+/* Description of the last error on this thread ("" if none). */
+const char* rlwe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

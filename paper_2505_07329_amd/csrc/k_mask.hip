@@ -1,0 +1,194 @@
+// The mask part of Eq. (LWEdot) (Sec. 4.3) on the int8 matrix cores of gfx950.
+//
+// For token t, output row j and mask index n, summed over input blocks i,
+//   a'_j[n] = sum_k w_j[iN + k] * ( A_i[k - n]        if k >= n
+//                                  -A_i[N + k - n]    if k <  n )   (mod q)
+// which is SampleExtract at N-1 of the product RLWE(x_i) . w_ij with the
+// reversed weight encoding. With A_i written in balanced base-255 digits
+// (A_i = sum_l 255^l d_l), every digit contributes an exact int32 matrix
+// product S_l[j][n] = sum_k W[j][k] T_l[k][n], T_l[k][n] = plane_l[N + k - n],
+// where the digit plane stores -d_l in front of d_l (the negacyclic wrap).
+// T_l is Toeplitz: the operand fragment of a 32-wide column block at k-step k0
+// is a 16-byte window of one plane, read from LDS at a byte offset.
+//
+// Epilogue, switched output: the integer V = sum_l 255^l S_l satisfies
+// V = a'_j[n] (mod q), and round(V 2^32 / q) mod 2^32 is the switched
+// coefficient. Digits below l0 change V 2^32/q by less than the host-computed
+// bound eps; they are skipped, the rest is folded into a 128-bit integer U and
+// multiplied by G = 255^l0 2^32 / q in fixed point. Where the result lies
+// within eps of a rounding tie, the element is recomputed exactly from all
+// digits (rare: probability about 2 eps). Raw output: all digits, V mod q_p.
+#include "rlwe_internal.hpp"
+
+namespace rlwe {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kKC = 512;                    // k-chunk staged in LDS per pass
+constexpr int kWinBytes = kKC + 64 + 16;    // per-digit window (+ over-read pad)
+constexpr int kWinWords = kWinBytes / 4;
+
+// round(U * G) mod 2^32 where U is a signed 128-bit integer (u0..u3) and
+// G = g / 2^128 (g < 2^128). Partial products of U*g below bit 96 are dropped
+// (error < 6 * 2^-32 in the result, always downwards), which the caller's
+// uncertainty band absorbs. Sets amb when the fraction is within eps of 1/2.
+__device__ inline uint32_t fixed_round(uint32_t u0, uint32_t u1, uint32_t u2, uint32_t u3,
+                                       const uint32_t* g, uint32_t eps, bool& amb) {
+  auto lo = [](uint32_t a, uint32_t b) -> uint64_t { return (uint32_t)(a * b); };
+  auto hi = [](uint32_t a, uint32_t b) -> uint64_t { return __umulhi(a, b); };
+  const uint64_t acc3 = hi(u0, g[2]) + hi(u1, g[1]) + hi(u2, g[0]) + lo(u0, g[3]) +
+                        lo(u1, g[2]) + lo(u2, g[1]) + lo(u3, g[0]);
+  const uint64_t acc4 = (acc3 >> 32) + hi(u0, g[3]) + hi(u1, g[2]) + hi(u2, g[1]) +
+                        hi(u3, g[0]) + lo(u1, g[3]) + lo(u2, g[2]) + lo(u3, g[1]);
+  uint64_t w34 = (acc4 << 32) | (uint32_t)acc3;
+  if ((int32_t)u3 < 0) w34 -= (uint64_t)g[0] << 32;  // U = U_unsigned - 2^128
+  const uint32_t w3 = (uint32_t)w34, w4 = (uint32_t)(w34 >> 32);
+  const uint32_t dist = w3 - 0x80000000u;  // fraction - 1/2, modulo 2^32
+  amb = (dist + eps) <= 2u * eps;
+  return w4 + (w3 >> 31);
+}
+
+// All digit sums of one mask element, exactly, straight from global memory.
+template <int D>
+__device__ __attribute__((noinline)) uint32_t exact_mask_element(const RingConst& rc,
+                                                                 const MatArgs& m,
+                                                                 const int8_t* emask, uint32_t t,
+                                                                 uint32_t j, uint32_t n) {
+  const uint32_t N = rc.N;
+  int32_t S[D];
+  for (int l = 0; l < D; ++l) S[l] = 0;
+  for (uint32_t i = 0; i < m.L; ++i) {
+    const uint32_t kb = min(N, m.k - i * N);
+    const int8_t* wrow = m.w + (size_t)j * m.kw + (size_t)i * N;
+    for (int l = 0; l < D; ++l) {
+      const int8_t* plane = emask + (((size_t)t * D + l) * m.L + i) * 2 * N + N - n;
+      int32_t s = 0;
+      for (uint32_t k = 0; k < kb; ++k) s += (int32_t)wrow[k] * (int32_t)plane[k];
+      S[l] += s;
+    }
+  }
+  i128 V = 0;
+  for (int l = D - 1; l >= 0; --l) V = V * 255 + S[l];
+  return switch_exact(V, rc);
+}
+
+template <int D, int DK, bool RAW>
+__global__ void __launch_bounds__(256) mask_kernel(RingConst rc, SwitchConst sc, MatArgs m,
+                                                   const int8_t* __restrict__ emask, uint32_t T,
+                                                   void* out, int force_exact) {
+  static_assert(!RAW || DK == D, "raw output keeps every digit");
+  __shared__ uint32_t win[DK][kWinWords];
+  const uint32_t N = rc.N;
+  const uint32_t t = blockIdx.z;
+  const uint32_t n0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = lane & 31, g = lane >> 5;
+  const uint32_t jb = j0 + 32 * (wave >> 1), nb = n0 + 32 * (wave & 1);
+  const uint32_t l0 = D - DK;
+
+  v16i acc[DK];
+#pragma unroll
+  for (int d = 0; d < DK; ++d) acc[d] = v16i{0};
+
+  for (uint32_t i = 0; i < m.L; ++i) {
+    const uint32_t kb = min(N, m.k - i * N);
+    const uint32_t kp = (kb + 31u) & ~31u;
+    for (uint32_t kc = 0; kc < kp; kc += kKC) {
+      const uint32_t klen = min((uint32_t)kKC, kp - kc);
+      // window = plane bytes [N + kc - n0 - 64, N + kc - n0 + klen): every Toeplitz
+      // entry of this block's columns [n0, n0+64) and rows [kc, kc+klen)
+      const uint32_t wstart = N + kc - n0 - 64;
+      const uint32_t n16 = (klen + 64) / 16;
+      __syncthreads();
+      for (uint32_t x = threadIdx.x; x < DK * n16; x += 256) {
+        const uint32_t d = x / n16, o = x % n16;
+        const int8_t* src =
+            emask + (((size_t)t * D + (l0 + d)) * m.L + i) * 2 * N + wstart + 16 * o;
+        *(uint4*)&win[d][4 * o] = *(const uint4*)src;
+      }
+      __syncthreads();
+      const int8_t* wbase = m.w + (size_t)(jb + c) * m.kw + (size_t)i * N + kc + 16 * g;
+      for (uint32_t k0 = 0; k0 < klen; k0 += 32) {
+        const v4i wf = *(const v4i*)(wbase + k0);
+        const int o = (int)k0 + 16 * g - (int)(nb - n0) - c + 64;
+        const int dw = o >> 2, sh = o & 3;
+#pragma unroll
+        for (int d = 0; d < DK; ++d) {
+          const uint32_t* p = &win[d][dw];
+          const uint32_t w0 = p[0], w1 = p[1], w2 = p[2], w3 = p[3], w4 = p[4];
+          v4i ef;
+          ef[0] = (int)__builtin_amdgcn_alignbyte(w1, w0, sh);
+          ef[1] = (int)__builtin_amdgcn_alignbyte(w2, w1, sh);
+          ef[2] = (int)__builtin_amdgcn_alignbyte(w3, w2, sh);
+          ef[3] = (int)__builtin_amdgcn_alignbyte(w4, w3, sh);
+          acc[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(wf, ef, acc[d], 0, 0, 0);
+        }
+      }
+    }
+  }
+
+  // accumulator element r of this lane: row jb + 8(r/4) + 4g + r%4, column nb + c
+  const uint32_t n = nb + c;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const uint32_t j = jb + 8 * (r >> 2) + 4 * g + (r & 3);
+    if (j >= m.rows) continue;
+    const size_t row = (size_t)t * m.rows + j;
+    if (RAW) {
+      i128 V = 0;
+#pragma unroll
+      for (int d = DK - 1; d >= 0; --d) V = V * 255 + acc[d][r];
+      uint64_t* o = (uint64_t*)out;
+      for (uint32_t p = 0; p < rc.P; ++p) o[(row * rc.P + p) * (N + 1) + n] = mod_i128(V, rc.q[p]);
+    } else {
+      i128 U = 0;
+#pragma unroll
+      for (int d = DK - 1; d >= 0; --d) U = U * 255 + acc[d][r];
+      bool amb;
+      uint32_t res = fixed_round((uint32_t)U, (uint32_t)(U >> 32), (uint32_t)(U >> 64),
+                                 (uint32_t)(U >> 96), sc.g, sc.eps, amb);
+      if (amb || force_exact) res = exact_mask_element<D>(rc, m, emask, t, j, n);
+      ((uint32_t*)out)[row * (N + 1) + n] = res;
+    }
+  }
+}
+
+template <int D, int DK, bool RAW>
+static void launch_one(const RingConst& rc, const SwitchConst& sc, const MatArgs& m,
+                       const int8_t* emask, uint32_t T, void* out, int force, hipStream_t s) {
+  const dim3 grid(rc.N / 64, m.rows_pad / 64, T);
+  hipLaunchKernelGGL((mask_kernel<D, DK, RAW>), grid, dim3(256), 0, s, rc, sc, m, emask, T, out,
+                     force);
+}
+
+hipError_t launch_mask(const RingConst& rc, const SwitchConst& sc, const MatArgs& m,
+                       const int8_t* emask, uint32_t T, void* out, bool raw, bool force_exact,
+                       hipStream_t s) {
+  if (T == 0) return hipSuccess;
+  const int f = force_exact ? 1 : 0;
+  if (rc.D == 7) {
+    if (raw || sc.dk == 7)
+      raw ? launch_one<7, 7, true>(rc, sc, m, emask, T, out, f, s)
+          : launch_one<7, 7, false>(rc, sc, m, emask, T, out, f, s);
+    else
+      return hipErrorInvalidValue;
+  } else {
+    if (raw) {
+      launch_one<14, 14, true>(rc, sc, m, emask, T, out, f, s);
+    } else {
+      switch (sc.dk) {
+        case 8: launch_one<14, 8, false>(rc, sc, m, emask, T, out, f, s); break;
+        case 9: launch_one<14, 9, false>(rc, sc, m, emask, T, out, f, s); break;
+        case 10: launch_one<14, 10, false>(rc, sc, m, emask, T, out, f, s); break;
+        case 11: launch_one<14, 11, false>(rc, sc, m, emask, T, out, f, s); break;
+        case 12: launch_one<14, 12, false>(rc, sc, m, emask, T, out, f, s); break;
+        case 14: launch_one<14, 14, false>(rc, sc, m, emask, T, out, f, s); break;
+        default: return hipErrorInvalidValue;
+      }
+    }
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rlwe

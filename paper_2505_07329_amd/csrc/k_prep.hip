@@ -1,0 +1,224 @@
+// Input preparation, the body product and the standalone modulus switch.
+//
+// prep:      residues of every ciphertext coefficient -> centred integer c in
+//            (-q/2, q/2) (CRT for two primes) -> balanced base-255 digits. Mask
+//            digits are stored twice per plane, negated in front (plane index m in
+//            [0, N) holds -d[m], m in [N, 2N) holds d[m - N]), so the Toeplitz
+//            operand of the negacyclic product (Sec. 3.2, Eq. (LWEdot)) is the
+//            plain window plane[N + k - n] for k, n in [0, N).
+// body:      b'_j = sum_k w_j[k] B[k] (coefficient N-1 of the block products,
+//            the SampleExtract body), exact per digit with packed int8 dot products.
+// modswitch: round(c 2^32 / q) mod 2^32 of raw RNS outputs (Sec. 3.2).
+#include "rlwe_internal.hpp"
+
+namespace rlwe {
+
+// Lift residues (P = 1 or 2) to the centred integer in (-q/2, q/2).
+__device__ inline i128 lift_centered(const RingConst& rc, uint64_t r0, uint64_t r1) {
+  u128 c;
+  if (rc.P == 1) {
+    c = r0;
+  } else {
+    const uint64_t y0 = mulmod_shoup(r0, rc.crt_inv[0], rc.crt_inv_shoup[0], rc.q[0]);
+    const uint64_t y1 = mulmod_shoup(r1, rc.crt_inv[1], rc.crt_inv_shoup[1], rc.q[1]);
+    c = (u128)y0 * rc.q[1] + (u128)y1 * rc.q[0];
+    const u128 Q = make_u128(rc.Q_hi, rc.Q_lo);
+    if (c >= Q) c -= Q;
+  }
+  const u128 half = make_u128(rc.half_hi, rc.half_lo);
+  const u128 Q = make_u128(rc.Q_hi, rc.Q_lo);
+  return c > half ? (i128)c - (i128)Q : (i128)c;
+}
+
+// Balanced base-255 digits of v (|v| < 2^108): v = sum_l d[l] 255^l, d in [-127, 127].
+template <int D>
+__device__ inline void digits255(i128 v, int8_t* d) {
+  const bool neg = v < 0;
+  u128 m = neg ? (u128)(-v) : (u128)v;
+  uint32_t w[4] = {(uint32_t)m, (uint32_t)(m >> 32), (uint32_t)(m >> 64), (uint32_t)(m >> 96)};
+#pragma unroll
+  for (int l = 0; l < D; ++l) {
+    uint64_t rem = 0;
+#pragma unroll
+    for (int i = 3; i >= 0; --i) {
+      const uint64_t cur = (rem << 32) | w[i];
+      w[i] = (uint32_t)(cur / 255u);
+      rem = cur % 255u;
+    }
+    int r = (int)rem;
+    if (r > 127) {  // carry into the next digit
+      r -= 255;
+      for (int i = 0; i < 4; ++i) {
+        if (++w[i] != 0) break;
+      }
+    }
+    d[l] = (int8_t)(neg ? -r : r);
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) prep_kernel(RingConst rc, PrepArgs a) {
+  const uint32_t N = rc.N, P = rc.P;
+  const size_t total = (size_t)a.T * a.L * N;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const uint32_t k = (uint32_t)(idx % N);
+  const size_t ti = idx / N;  // t * L + i
+  const uint32_t i = (uint32_t)(ti % a.L);
+  const uint32_t t = (uint32_t)(ti / a.L);
+  const uint64_t* A = a.ct + (ti * 2 + 0) * P * N;
+  const uint64_t* B = a.ct + (ti * 2 + 1) * P * N;
+  int8_t da[D], db[D];
+  digits255<D>(lift_centered(rc, A[k], P > 1 ? A[N + k] : 0), da);
+  digits255<D>(lift_centered(rc, B[k], P > 1 ? B[N + k] : 0), db);
+#pragma unroll
+  for (int l = 0; l < D; ++l) {
+    const size_t plane = ((size_t)t * D + l) * a.L + i;
+    int8_t* em = a.emask + plane * 2 * N;
+    em[N + k] = da[l];
+    em[k] = (int8_t)(-da[l]);
+    a.ebody[plane * N + k] = db[l];
+  }
+}
+
+hipError_t launch_prep(const RingConst& rc, const PrepArgs& a, hipStream_t s) {
+  const size_t total = (size_t)a.T * a.L * rc.N;
+  if (total == 0) return hipSuccess;
+  const dim3 grid((unsigned)((total + 255) / 256));
+  if (rc.D == 7)
+    hipLaunchKernelGGL(prep_kernel<7>, grid, dim3(256), 0, s, rc, a);
+  else
+    hipLaunchKernelGGL(prep_kernel<14>, grid, dim3(256), 0, s, rc, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- body
+
+template <int D, bool RAW>
+__global__ void __launch_bounds__(256) body_kernel(RingConst rc, MatArgs m, const int8_t* ebody,
+                                                   void* out) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t t = blockIdx.y;
+  if (j >= m.rows) return;
+  const uint32_t N = rc.N;
+  int32_t S[D];
+#pragma unroll
+  for (int l = 0; l < D; ++l) S[l] = 0;
+  for (uint32_t i = 0; i < m.L; ++i) {
+    const uint32_t kb = min(N, m.k - i * N);
+    const uint32_t kp = (kb + 31u) & ~31u;
+    const int8_t* wrow = m.w + (size_t)j * m.kw + (size_t)i * N;
+    for (uint32_t k = 0; k < kp; k += 4) {
+      const int w4 = *(const int*)(wrow + k);
+#pragma unroll
+      for (int l = 0; l < D; ++l) {
+        const int e4 = *(const int*)(ebody + (((size_t)t * D + l) * m.L + i) * N + k);
+        S[l] = __builtin_amdgcn_sdot4(w4, e4, S[l], false);
+      }
+    }
+  }
+  i128 V = 0;
+#pragma unroll
+  for (int l = D - 1; l >= 0; --l) V = V * 255 + S[l];
+  const size_t row = (size_t)t * m.rows + j;
+  if (RAW) {
+    uint64_t* o = (uint64_t*)out;
+    for (uint32_t p = 0; p < rc.P; ++p) o[(row * rc.P + p) * (N + 1) + N] = mod_i128(V, rc.q[p]);
+  } else {
+    ((uint32_t*)out)[row * (N + 1) + N] = switch_exact(V, rc);
+  }
+}
+
+hipError_t launch_body(const RingConst& rc, const MatArgs& m, const int8_t* ebody, uint32_t T,
+                       void* out, bool raw, hipStream_t s) {
+  if (T == 0) return hipSuccess;
+  const dim3 grid((m.rows + 255) / 256, T);
+  if (rc.D == 7) {
+    if (raw)
+      hipLaunchKernelGGL((body_kernel<7, true>), grid, dim3(256), 0, s, rc, m, ebody, out);
+    else
+      hipLaunchKernelGGL((body_kernel<7, false>), grid, dim3(256), 0, s, rc, m, ebody, out);
+  } else {
+    if (raw)
+      hipLaunchKernelGGL((body_kernel<14, true>), grid, dim3(256), 0, s, rc, m, ebody, out);
+    else
+      hipLaunchKernelGGL((body_kernel<14, false>), grid, dim3(256), 0, s, rc, m, ebody, out);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- modulus switch
+
+__global__ void __launch_bounds__(256) modswitch_kernel(RingConst rc, const uint64_t* in,
+                                                        size_t count, uint32_t* out) {
+  const uint32_t len = rc.N + 1;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= count * len) return;
+  const size_t c = idx / len;
+  const uint32_t n = (uint32_t)(idx % len);
+  const uint64_t* r = in + c * rc.P * len + n;
+  u128 v;
+  if (rc.P == 1) {
+    v = r[0];
+  } else {
+    const uint64_t y0 = mulmod_shoup(r[0], rc.crt_inv[0], rc.crt_inv_shoup[0], rc.q[0]);
+    const uint64_t y1 = mulmod_shoup(r[len], rc.crt_inv[1], rc.crt_inv_shoup[1], rc.q[1]);
+    v = (u128)y0 * rc.q[1] + (u128)y1 * rc.q[0];
+    const u128 Q = make_u128(rc.Q_hi, rc.Q_lo);
+    if (v >= Q) v -= Q;
+  }
+  out[idx] = switch_exact((i128)v, rc);
+}
+
+hipError_t launch_modswitch(const RingConst& rc, const uint64_t* in, size_t count, uint32_t* out,
+                            hipStream_t s) {
+  const size_t total = count * (rc.N + 1);
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(modswitch_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, rc,
+                     in, count, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- weight set-up
+
+__global__ void transpose_pad_kernel(const int8_t* src, uint32_t rows, uint32_t cols,
+                                     int transpose, int8_t* dst, uint32_t dst_rows_pad,
+                                     uint32_t dst_kw) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t r = blockIdx.y;
+  if (k >= dst_kw || r >= dst_rows_pad) return;
+  int8_t v = 0;
+  if (transpose) {  // dst[r][k] = src[k][r], dst has cols rows and rows columns
+    if (r < cols && k < rows) v = src[(size_t)k * cols + r];
+  } else {
+    if (r < rows && k < cols) v = src[(size_t)r * cols + k];
+  }
+  dst[(size_t)r * dst_kw + k] = v;
+}
+
+hipError_t launch_transpose_pad(const int8_t* src, uint32_t rows, uint32_t cols, bool transpose,
+                                int8_t* dst, uint32_t dst_rows_pad, uint32_t dst_kw,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(transpose_pad_kernel, dim3((dst_kw + 255) / 256, dst_rows_pad), dim3(256), 0,
+                     s, src, rows, cols, (int)transpose, dst, dst_rows_pad, dst_kw);
+  return hipGetLastError();
+}
+
+__global__ void row_l1_kernel(const int8_t* w, uint32_t rows, uint32_t kw, uint32_t* out) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  uint32_t s = 0;
+  for (uint32_t k = 0; k < kw; ++k) {
+    const int v = w[(size_t)r * kw + k];
+    s += (uint32_t)(v < 0 ? -v : v);
+  }
+  out[r] = s;
+}
+
+hipError_t launch_row_l1(const int8_t* w, uint32_t rows, uint32_t kw, uint32_t* out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(row_l1_kernel, dim3((rows + 255) / 256), dim3(256), 0, s, w, rows, kw, out);
+  return hipGetLastError();
+}
+
+}  // namespace rlwe

@@ -1,0 +1,437 @@
+// Host runtime behind include/rlwe.h: parameter validation, CRT and switching
+// constants, resident weights, workspace and kernel launches.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "rlwe.h"
+#include "rlwe_internal.hpp"
+
+using namespace rlwe;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int ok() {
+  g_err.clear();
+  return RLWE_OK;
+}
+
+uint64_t mulmod_h(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)(((u128)a * b) % m); }
+
+uint64_t powmod_h(uint64_t a, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  a %= m;
+  while (e) {
+    if (e & 1) r = mulmod_h(r, a, m);
+    a = mulmod_h(a, a, m);
+    e >>= 1;
+  }
+  return r;
+}
+
+// Deterministic Miller-Rabin for n < 2^64 (first 12 primes as bases).
+bool is_prime_h(uint64_t n) {
+  if (n < 2) return false;
+  static const uint64_t bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+  for (uint64_t p : bases)
+    if (n % p == 0) return n == p;
+  uint64_t d = n - 1;
+  int s = 0;
+  while ((d & 1) == 0) {
+    d >>= 1;
+    ++s;
+  }
+  for (uint64_t a : bases) {
+    uint64_t x = powmod_h(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int r = 1; r < s; ++r) {
+      x = mulmod_h(x, x, n);
+      if (x == n - 1) {
+        comp = false;
+        break;
+      }
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+struct rlwe_ctx {
+  int device = 0;
+  uint32_t log2_t = 0;
+  RingConst rc{};
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+};
+
+namespace {
+
+struct Mat {
+  bool present = false;
+  int8_t* w = nullptr;
+  MatArgs args{};
+  SwitchConst sc{};
+  uint32_t max_l1 = 0;
+};
+
+}  // namespace
+
+struct rlwe_weights {
+  rlwe_ctx* ctx = nullptr;
+  Mat fwd, tr;
+};
+
+namespace {
+
+// 255^e as a 128-bit integer (e <= 15).
+u128 pow255(uint32_t e) {
+  u128 r = 1;
+  for (uint32_t i = 0; i < e; ++i) r *= 255;
+  return r;
+}
+
+double u128_to_double(u128 v) { return (double)(uint64_t)(v >> 64) * 18446744073709551616.0 + (double)(uint64_t)v; }
+
+// floor(num * 2^128 / den) rounded to nearest, for num < den < 2^126.
+u128 frac_128(u128 num, u128 den) {
+  u128 r = num, quo = 0;
+  for (int b = 0; b < 128; ++b) {
+    r <<= 1;
+    quo <<= 1;
+    if (r >= den) {
+      r -= den;
+      quo |= 1;
+    }
+  }
+  if (2 * r >= den) ++quo;
+  return quo;
+}
+
+// Switched-epilogue constants for a contraction whose digit sums are bounded
+// by 127 * max_l1 (max_l1 = largest 1-norm of a weight row).
+int make_switch_const(const RingConst& rc, uint32_t max_l1, SwitchConst* sc) {
+  const u128 q = make_u128(rc.Q_hi, rc.Q_lo);
+  const double qd = u128_to_double(q);
+  const double maxS = 127.0 * (double)(max_l1 > 0 ? max_l1 : 1);
+  // Largest l0 whose skipped digits move V 2^32/q by at most 2^-18.
+  uint32_t l0 = 0;
+  for (uint32_t c = 1; c < rc.D; ++c) {
+    const double skipped = maxS * ((pow(255.0, (double)c) - 1.0) / 254.0) * 4294967296.0 / qd;
+    if (skipped <= 1.0 / 262144.0) l0 = c;
+  }
+  uint32_t dk = rc.D - l0;
+  if (rc.D == 7) {
+    dk = 7;
+  } else {
+    if (dk < 8) dk = 8;
+    if (dk == 13) dk = 14;
+  }
+  l0 = rc.D - dk;
+  // G = 255^l0 2^32 / q must be < 1 so that g = round(G 2^128) fits 128 bits.
+  const u128 num = pow255(l0) << 32;
+  if (num >= q) return fail(RLWE_ESHAPE, "internal: switching scale out of range (l0=%u)", l0);
+  const u128 g = frac_128(num, q);
+  for (int i = 0; i < 4; ++i) sc->g[i] = (uint32_t)(g >> (32 * i));
+  sc->l0 = l0;
+  sc->dk = dk;
+  // Uncertainty: skipped digits + representation error of g times |U| + dropped
+  // partial products (< 5 * 2^-32), with a factor 2 margin.
+  const double skipped = maxS * ((pow(255.0, (double)l0) - 1.0) / 254.0) * 4294967296.0 / qd;
+  const double umax = (maxS / 127.0) * (qd / (2.0 * pow(255.0, (double)l0)) + 1.0);
+  const double gerr = umax * ldexp(1.0, -129);
+  const double eps = 2.0 * (skipped + gerr) + ldexp(6.0, -32);
+  const double eps32 = ceil(eps * 4294967296.0);
+  if (eps32 > 1073741824.0) return fail(RLWE_ESHAPE, "internal: rounding band too wide");
+  sc->eps = (uint32_t)eps32 + 1;
+  return RLWE_OK;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(RLWE_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t ws_need(const RingConst& rc, const MatArgs& m, uint32_t T) {
+  const size_t em = align_up((size_t)T * rc.D * m.L * 2 * rc.N, 256);
+  const size_t eb = align_up((size_t)T * rc.D * m.L * rc.N, 256);
+  return em + eb;
+}
+
+int ensure_ws(rlwe_ctx* ctx, size_t bytes, hipStream_t s) {
+  if (bytes <= ctx->ws_bytes) return RLWE_OK;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  if (ctx->ws) {
+    e = hipFree(ctx->ws);
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    if (e != hipSuccess) return hip_fail(e, "hipFree(workspace)");
+  }
+  e = hipMalloc(&ctx->ws, bytes);
+  if (e != hipSuccess) {
+    ctx->ws = nullptr;
+    return fail(RLWE_ENOMEM, "hipMalloc(workspace, %zu bytes): %s", bytes, hipGetErrorString(e));
+  }
+  ctx->ws_bytes = bytes;
+  return RLWE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rlwe_last_error(void) { return g_err.c_str(); }
+
+int rlwe_params_init(const rlwe_params* p, int hip_device, rlwe_ctx** out) {
+  if (!p || !out) return fail(RLWE_EINVAL, "rlwe_params_init: null argument");
+  *out = nullptr;
+  const uint32_t N = p->N;
+  if (N < 64 || N > 32768 || (N & (N - 1)))
+    return fail(RLWE_EPARAM, "N = %u must be a power of two in [64, 32768]", N);
+  if (p->num_primes < 1 || p->num_primes > 2)
+    return fail(RLWE_EPARAM, "num_primes = %u must be 1 or 2", p->num_primes);
+  if (!p->primes) return fail(RLWE_EINVAL, "primes is null");
+  if (p->log2_q_out != 32) return fail(RLWE_EPARAM, "log2_q_out = %u must be 32", p->log2_q_out);
+  if (p->log2_t < 1 || p->log2_t > 32) return fail(RLWE_EPARAM, "log2_t = %u outside [1, 32]", p->log2_t);
+  RingConst rc{};
+  rc.N = N;
+  rc.logN = 0;
+  while ((1u << rc.logN) < N) ++rc.logN;
+  rc.P = p->num_primes;
+  rc.D = rc.P == 1 ? 7 : 14;
+  for (uint32_t i = 0; i < rc.P; ++i) {
+    const uint64_t q = p->primes[i];
+    if (q >= (1ull << 54) || q <= 2ull * N)
+      return fail(RLWE_EPARAM, "prime %llu must satisfy 2N < q < 2^54", (unsigned long long)q);
+    if (!is_prime_h(q)) return fail(RLWE_EPARAM, "%llu is not prime", (unsigned long long)q);
+    if (q % (2ull * N) != 1)
+      return fail(RLWE_EPARAM, "prime %llu is not 1 mod 2N", (unsigned long long)q);
+    rc.q[i] = q;
+  }
+  if (rc.P == 2 && rc.q[0] == rc.q[1]) return fail(RLWE_EPARAM, "primes must be distinct");
+  u128 Q = 1;
+  for (uint32_t i = 0; i < rc.P; ++i) Q *= rc.q[i];
+  if ((Q >> p->log2_t) == 0) return fail(RLWE_EPARAM, "t exceeds q");
+  for (uint32_t i = 0; i < rc.P; ++i) {
+    const uint64_t Mi = rc.P == 1 ? 1 : (uint64_t)((Q / rc.q[i]) % rc.q[i]);
+    rc.crt_inv[i] = rc.P == 1 ? 1 : powmod_h(Mi, rc.q[i] - 2, rc.q[i]);
+    rc.crt_inv_shoup[i] = (uint64_t)(((u128)rc.crt_inv[i] << 64) / rc.q[i]);
+  }
+  rc.Q_lo = (uint64_t)Q;
+  rc.Q_hi = (uint64_t)(Q >> 64);
+  const u128 half = (Q - 1) / 2;
+  rc.half_lo = (uint64_t)half;
+  rc.half_hi = (uint64_t)(half >> 64);
+  rc.inv_q32 = 4294967296.0 / u128_to_double(Q);
+
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (hip_device < 0 || hip_device >= ndev)
+    return fail(RLWE_EINVAL, "hip_device %d outside [0, %d)", hip_device, ndev);
+  e = hipSetDevice(hip_device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  rlwe_ctx* ctx = new (std::nothrow) rlwe_ctx;
+  if (!ctx) return fail(RLWE_ENOMEM, "out of host memory");
+  ctx->device = hip_device;
+  ctx->log2_t = p->log2_t;
+  ctx->rc = rc;
+  *out = ctx;
+  return ok();
+}
+
+int rlwe_params_destroy(rlwe_ctx* ctx) {
+  if (!ctx) return ok();
+  if (ctx->ws) {
+    hipSetDevice(ctx->device);
+    hipError_t e = hipFree(ctx->ws);
+    if (e != hipSuccess) {
+      delete ctx;
+      return hip_fail(e, "hipFree(workspace)");
+    }
+  }
+  delete ctx;
+  return ok();
+}
+
+static void free_mat(Mat& m) {
+  if (m.w) hipFree(m.w);
+  m.w = nullptr;
+  m.present = false;
+}
+
+static int load_mat(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32_t d_in,
+                    bool transpose, hipStream_t s, Mat& m) {
+  const RingConst& rc = ctx->rc;
+  MatArgs& a = m.args;
+  a.rows = transpose ? d_in : d_out;
+  a.k = transpose ? d_out : d_in;
+  a.kw = (uint32_t)align_up(a.k, 32);
+  a.rows_pad = (uint32_t)align_up(a.rows, 64);
+  a.L = (a.k + rc.N - 1) / rc.N;
+  // exact 128-bit accumulation: 127 * K * (q-1)/2 < 2^127
+  const u128 Q = make_u128(rc.Q_hi, rc.Q_lo);
+  const u128 lim = ((u128)1 << 127) / ((u128)127 * a.k);
+  if ((Q - 1) / 2 >= lim)
+    return fail(RLWE_ESHAPE, "contraction length %u too long for exact 128-bit sums at this q", a.k);
+  hipError_t e = hipMalloc(&m.w, (size_t)a.rows_pad * a.kw);
+  if (e != hipSuccess) return fail(RLWE_ENOMEM, "hipMalloc(weights): %s", hipGetErrorString(e));
+  a.w = m.w;
+  e = launch_transpose_pad(W_dev, d_out, d_in, transpose, m.w, a.rows_pad, a.kw, s);
+  if (e != hipSuccess) return hip_fail(e, "weight layout kernel");
+  uint32_t* norms = nullptr;
+  e = hipMalloc(&norms, sizeof(uint32_t) * a.rows);
+  if (e != hipSuccess) return fail(RLWE_ENOMEM, "hipMalloc(norms): %s", hipGetErrorString(e));
+  e = launch_row_l1(m.w, a.rows, a.kw, norms, s);
+  std::string hn;
+  uint32_t* host = new (std::nothrow) uint32_t[a.rows];
+  if (e == hipSuccess && host) e = hipMemcpyAsync(host, norms, sizeof(uint32_t) * a.rows, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(norms);
+  if (!host) return fail(RLWE_ENOMEM, "out of host memory");
+  if (e != hipSuccess) {
+    delete[] host;
+    return hip_fail(e, "weight norms");
+  }
+  uint32_t mx = 0;
+  for (uint32_t r = 0; r < a.rows; ++r) mx = host[r] > mx ? host[r] : mx;
+  delete[] host;
+  m.max_l1 = mx;
+  // |W x| <= 127 * max_l1 must stay below t/2 (no wrap modulo t, Sec. 4.4)
+  const uint64_t t_half = 1ull << (ctx->log2_t - 1);
+  if ((uint64_t)127 * mx >= t_half)
+    return fail(RLWE_EOVERFLOW, "127 * max row 1-norm = %llu reaches t/2 = %llu%s",
+                (unsigned long long)127 * mx, (unsigned long long)t_half,
+                transpose ? " (transposed)" : "");
+  const int rc2 = make_switch_const(rc, mx, &m.sc);
+  if (rc2 != RLWE_OK) return rc2;
+  m.present = true;
+  return RLWE_OK;
+}
+
+int rlwe_weights_load(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32_t d_in,
+                      uint32_t flags, rlwe_stream_t stream, rlwe_weights** out) {
+  if (!ctx || !W_dev || !out) return fail(RLWE_EINVAL, "rlwe_weights_load: null argument");
+  *out = nullptr;
+  if (flags == 0 || (flags & ~(RLWE_W_FWD | RLWE_W_TRANSPOSE)))
+    return fail(RLWE_EINVAL, "rlwe_weights_load: flags 0x%x invalid", flags);
+  if (d_out < 1 || d_in < 1 || d_out > 65536 || d_in > 65536)
+    return fail(RLWE_ESHAPE, "d_out = %u, d_in = %u must lie in [1, 65536]", d_out, d_in);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  rlwe_weights* w = new (std::nothrow) rlwe_weights;
+  if (!w) return fail(RLWE_ENOMEM, "out of host memory");
+  w->ctx = ctx;
+  hipStream_t s = (hipStream_t)stream;
+  int r = RLWE_OK;
+  if (flags & RLWE_W_FWD) r = load_mat(ctx, W_dev, d_out, d_in, false, s, w->fwd);
+  if (r == RLWE_OK && (flags & RLWE_W_TRANSPOSE)) r = load_mat(ctx, W_dev, d_out, d_in, true, s, w->tr);
+  if (r != RLWE_OK) {
+    std::string msg = g_err;
+    hipStreamSynchronize(s);
+    free_mat(w->fwd);
+    free_mat(w->tr);
+    delete w;
+    g_err = msg;
+    return r;
+  }
+  *out = w;
+  return ok();
+}
+
+int rlwe_weights_free(rlwe_weights* w) {
+  if (!w) return ok();
+  hipSetDevice(w->ctx->device);
+  free_mat(w->fwd);
+  free_mat(w->tr);
+  delete w;
+  return ok();
+}
+
+size_t rlwe_workspace_bytes(const rlwe_ctx* ctx, const rlwe_weights* w, uint32_t transpose,
+                            uint32_t tokens) {
+  if (!ctx || !w) return 0;
+  const Mat& m = transpose ? w->tr : w->fwd;
+  if (!m.present) return 0;
+  return ws_need(ctx->rc, m.args, tokens);
+}
+
+int rlwe_workspace_reserve(rlwe_ctx* ctx, size_t bytes) {
+  if (!ctx) return fail(RLWE_EINVAL, "rlwe_workspace_reserve: null context");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  const int r = ensure_ws(ctx, bytes, nullptr);
+  return r == RLWE_OK ? ok() : r;
+}
+
+int ct_matmul_clear(rlwe_ctx* ctx, const rlwe_weights* w, uint32_t transpose,
+                    const uint64_t* ct_in, uint32_t tokens, void* out, uint32_t flags,
+                    rlwe_stream_t stream) {
+  if (!ctx || !w) return fail(RLWE_EINVAL, "ct_matmul_clear: null context or weights");
+  if (w->ctx != ctx) return fail(RLWE_EINVAL, "ct_matmul_clear: weights belong to another context");
+  if (flags & ~(RLWE_OUT_RAW_Q | RLWE_OUT_FORCE_EXACT))
+    return fail(RLWE_EINVAL, "ct_matmul_clear: unknown flags 0x%x", flags);
+  if (transpose > 1) return fail(RLWE_EINVAL, "ct_matmul_clear: transpose must be 0 or 1");
+  const Mat& m = transpose ? w->tr : w->fwd;
+  if (!m.present)
+    return fail(RLWE_EINVAL, "ct_matmul_clear: weights were loaded without %s",
+                transpose ? "RLWE_W_TRANSPOSE" : "RLWE_W_FWD");
+  if (tokens == 0) return ok();
+  if (!ct_in || !out) return fail(RLWE_EINVAL, "ct_matmul_clear: null buffer");
+  if (tokens > 65535) return fail(RLWE_ESHAPE, "tokens = %u exceeds 65535 per call", tokens);
+  const bool raw = flags & RLWE_OUT_RAW_Q;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  const RingConst& rc = ctx->rc;
+  const size_t need = ws_need(rc, m.args, tokens);
+  int r = ensure_ws(ctx, need, s);
+  if (r != RLWE_OK) return r;
+  PrepArgs pa{};
+  pa.ct = ct_in;
+  pa.emask = (int8_t*)ctx->ws;
+  pa.ebody = (int8_t*)ctx->ws + align_up((size_t)tokens * rc.D * m.args.L * 2 * rc.N, 256);
+  pa.T = tokens;
+  pa.L = m.args.L;
+  e = launch_prep(rc, pa, s);
+  if (e != hipSuccess) return hip_fail(e, "prep kernel");
+  e = launch_mask(rc, m.sc, m.args, pa.emask, tokens, out, raw, flags & RLWE_OUT_FORCE_EXACT, s);
+  if (e != hipSuccess) return hip_fail(e, "mask kernel");
+  e = launch_body(rc, m.args, pa.ebody, tokens, out, raw, s);
+  if (e != hipSuccess) return hip_fail(e, "body kernel");
+  return ok();
+}
+
+int ct_modswitch(rlwe_ctx* ctx, const uint64_t* in, size_t count, uint32_t* out,
+                 rlwe_stream_t stream) {
+  if (!ctx) return fail(RLWE_EINVAL, "ct_modswitch: null context");
+  if (count == 0) return ok();
+  if (!in || !out) return fail(RLWE_EINVAL, "ct_modswitch: null buffer");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  e = launch_modswitch(ctx->rc, in, count, out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "modswitch kernel");
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,123 @@
+// Internal declarations of the gfx950 library: kernel argument blocks, exact
+// integer helpers shared by the kernels, launcher prototypes.
+//
+// Representation used by the kernels (free choices behind the ABI; none of them
+// changes a result bit):
+//   * A ciphertext coefficient, given by its residues mod q_p, is lifted once to
+//     its centred integer value c in (-q/2, q/2) and written in balanced base 255,
+//     c = sum_{l<D} d_l 255^l with every digit d_l in [-127, 127]. D = 7 for one
+//     54-bit prime, 14 for two.
+//   * The mask part of Eq. (LWEdot) becomes, per digit l, an exact int32 matrix
+//     product of the int8 weights with a Toeplitz matrix of int8 digits (the
+//     negacyclic sign is absorbed by storing the negated digits in front of each
+//     digit plane), executed on the int8 matrix cores; the digit sums are
+//     recombined (sum_l 255^l S_l) and the modulus switch is applied to the exact
+//     integer they represent.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rlwe {
+
+typedef unsigned __int128 u128;
+typedef __int128 i128;
+
+constexpr int kMaxDigits = 14;   // balanced base-255 digits of a value below 2^108
+constexpr int kMaxPrimes = 2;
+
+// Constants of the cryptosystem shared by every kernel (passed by value).
+struct RingConst {
+  uint32_t N, logN, P, D;          // ring degree, log2 N, #primes, #digits
+  uint64_t q[kMaxPrimes];          // RNS primes
+  uint64_t crt_inv[kMaxPrimes];    // (q / q_p)^-1 mod q_p
+  uint64_t crt_inv_shoup[kMaxPrimes];  // floor(crt_inv * 2^64 / q_p)
+  uint64_t Q_lo, Q_hi;             // q = prod q_p as 128-bit
+  uint64_t half_lo, half_hi;       // (q - 1) / 2
+  double inv_q32;                  // 2^32 / q (estimate only; results are corrected exactly)
+};
+
+// Per weight-matrix constants of the switched epilogue.
+struct SwitchConst {
+  uint32_t l0;        // digits below l0 are left out of the matrix-core sums
+  uint32_t dk;        // digits kept: D - l0
+  uint32_t g[4];      // round(255^l0 * 2^160 / q) as 4 little-endian words (< 2^128)
+  uint32_t eps;       // half-width of the uncertain band around a rounding tie, in 2^-32 units
+};
+
+// ---------------------------------------------------------------- integer helpers
+
+__host__ __device__ inline u128 make_u128(uint64_t hi, uint64_t lo) {
+  return ((u128)hi << 64) | lo;
+}
+
+// Canonical residue of a signed 128-bit value (|v| < 2^127) modulo q < 2^63.
+__device__ inline uint64_t mod_i128(i128 v, uint64_t q) {
+  const bool neg = v < 0;
+  u128 m = neg ? (u128)(-v) : (u128)v;
+  uint64_t r = (uint64_t)(m % q);
+  return (neg && r) ? q - r : r;
+}
+
+__device__ inline double i128_to_double(i128 v) {
+  const int64_t hi = (int64_t)(v >> 64);
+  const uint64_t lo = (uint64_t)v;
+  return (double)hi * 18446744073709551616.0 + (double)lo;
+}
+
+// round(V * 2^32 / q) mod 2^32 for an exact integer V with |V| < 2^127 and
+// |V 2^32 / q| < 2^53. A double estimate is corrected by exact remainder
+// arithmetic modulo 2^128: Z = V 2^32 - F q is computed with wrapping 128-bit
+// operations, which is exact because the true Z lies in [0, 2^128).
+__device__ inline uint32_t switch_exact(i128 V, const RingConst& rc) {
+  const u128 q = make_u128(rc.Q_hi, rc.Q_lo);
+  const double est = i128_to_double(V) * rc.inv_q32;
+  int64_t f = (int64_t)floor(est) - 8;  // |est - V 2^32/q| < 4 for these magnitudes
+  u128 z = ((u128)V << 32) - (u128)(i128)f * q;
+  for (int it = 0; it < 24 && z >= q; ++it) {
+    z -= q;
+    ++f;
+  }
+  return (uint32_t)(f + (2 * z > q ? 1 : 0));
+}
+
+// Shoup multiplication a * w mod q, wp = floor(w 2^64 / q), a < 2^64, q < 2^63.
+__device__ inline uint64_t mulmod_shoup(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+  const uint64_t qh = __umul64hi(a, wp);
+  uint64_t r = a * w - qh * q;
+  return r >= q ? r - q : r;
+}
+
+// ---------------------------------------------------------------- launchers
+
+struct PrepArgs {
+  const uint64_t* ct;   // [T][L][2][P][N]
+  int8_t* emask;        // [T][D][L][2N]: per digit plane, index m <-> Toeplitz offset m - N
+  int8_t* ebody;        // [T][D][L][N]
+  uint32_t T, L;
+};
+
+struct MatArgs {
+  const int8_t* w;      // resident weights [rows_pad][kw], zero padded
+  uint32_t rows;        // outputs M
+  uint32_t rows_pad;    // multiple of 64
+  uint32_t k;           // contraction length K
+  uint32_t kw;          // row pitch: K rounded up to 32
+  uint32_t L;           // input blocks
+};
+
+hipError_t launch_prep(const RingConst& rc, const PrepArgs& a, hipStream_t s);
+hipError_t launch_mask(const RingConst& rc, const SwitchConst& sc, const MatArgs& m,
+                       const int8_t* emask, uint32_t T, void* out, bool raw, bool force_exact,
+                       hipStream_t s);
+hipError_t launch_body(const RingConst& rc, const MatArgs& m, const int8_t* ebody, uint32_t T,
+                       void* out, bool raw, hipStream_t s);
+hipError_t launch_modswitch(const RingConst& rc, const uint64_t* in, size_t count, uint32_t* out,
+                            hipStream_t s);
+hipError_t launch_transpose_pad(const int8_t* src, uint32_t rows, uint32_t cols, bool transpose,
+                                int8_t* dst, uint32_t dst_rows_pad, uint32_t dst_kw,
+                                hipStream_t s);
+hipError_t launch_row_l1(const int8_t* w, uint32_t rows, uint32_t kw, uint32_t* out,
+                         hipStream_t s);
+
+}  // namespace rlwe

@@ -1,0 +1,210 @@
+"""Thin Python binding of the C ABI in include/rlwe.h (argument marshalling only).
+
+Every computation runs in the HIP library ``librlwe.so`` next to this file;
+PyTorch provides device memory and streams. If the library is missing the
+binding raises instead of computing anything on the CPU.
+
+Tensor conventions (torch has no unsigned 64/32-bit arithmetic, only storage):
+uint64 buffers are passed as torch.int64 tensors holding the same bits, uint32
+buffers as torch.int32 tensors.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librlwe.so")
+
+RLWE_OK = 0
+ERRORS = {-1: "RLWE_EINVAL", -2: "RLWE_EPARAM", -3: "RLWE_ESHAPE", -4: "RLWE_EOVERFLOW",
+          -5: "RLWE_ENOMEM", -6: "RLWE_EHIP"}
+RLWE_W_FWD = 1
+RLWE_W_TRANSPOSE = 2
+RLWE_OUT_SWITCHED = 0
+RLWE_OUT_RAW_Q = 1
+RLWE_OUT_FORCE_EXACT = 2
+
+EXPORTS = ("rlwe_params_init", "rlwe_params_destroy", "rlwe_weights_load", "rlwe_weights_free",
+           "ct_matmul_clear", "ct_modswitch", "rlwe_workspace_bytes", "rlwe_workspace_reserve",
+           "rlwe_last_error")
+
+
+class RlweError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_uint32), ("num_primes", ctypes.c_uint32),
+                ("primes", ctypes.POINTER(ctypes.c_uint64)), ("log2_t", ctypes.c_uint32),
+                ("log2_q_out", ctypes.c_uint32)]
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load librlwe.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2505_07329_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    L.rlwe_params_init.argtypes = [ctypes.POINTER(_Params), ctypes.c_int, ctypes.POINTER(vp)]
+    L.rlwe_params_destroy.argtypes = [vp]
+    L.rlwe_weights_load.argtypes = [vp, vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, vp,
+                                    ctypes.POINTER(vp)]
+    L.rlwe_weights_free.argtypes = [vp]
+    L.ct_matmul_clear.argtypes = [vp, vp, ctypes.c_uint32, vp, ctypes.c_uint32, vp,
+                                  ctypes.c_uint32, vp]
+    L.ct_modswitch.argtypes = [vp, vp, ctypes.c_size_t, vp, vp]
+    L.rlwe_workspace_bytes.argtypes = [vp, vp, ctypes.c_uint32, ctypes.c_uint32]
+    L.rlwe_workspace_bytes.restype = ctypes.c_size_t
+    L.rlwe_workspace_reserve.argtypes = [vp, ctypes.c_size_t]
+    L.rlwe_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "rlwe_last_error" and name != "rlwe_workspace_bytes":
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int) -> None:
+    if rc != RLWE_OK:
+        raise RlweError(rc, lib().rlwe_last_error().decode())
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return 0
+    assert t.is_contiguous(), "buffers must be contiguous"
+    return t.data_ptr()
+
+
+# ------------------------------------------------------------------ ABI names
+
+def rlwe_params_init(N: int, primes: Sequence[int], log2_t: int, device: int = 0,
+                     log2_q_out: int = 32) -> int:
+    arr = (ctypes.c_uint64 * len(primes))(*[int(p) for p in primes])
+    p = _Params(N, len(primes), ctypes.cast(arr, ctypes.POINTER(ctypes.c_uint64)), log2_t, log2_q_out)
+    h = ctypes.c_void_p()
+    _check(lib().rlwe_params_init(ctypes.byref(p), device, ctypes.byref(h)))
+    return h.value
+
+
+def rlwe_params_destroy(ctx: int) -> None:
+    _check(lib().rlwe_params_destroy(ctx))
+
+
+def rlwe_weights_load(ctx: int, W, flags: int = RLWE_W_FWD, stream=None) -> int:
+    """W: torch.int8 CUDA tensor (d_out, d_in)."""
+    d_out, d_in = W.shape
+    h = ctypes.c_void_p()
+    _check(lib().rlwe_weights_load(ctx, _ptr(W), d_out, d_in, flags, _stream(stream),
+                                   ctypes.byref(h)))
+    return h.value
+
+
+def rlwe_weights_free(w: int) -> None:
+    _check(lib().rlwe_weights_free(w))
+
+
+def ct_matmul_clear(ctx: int, w: int, ct, tokens: int, out, transpose: bool = False,
+                    flags: int = RLWE_OUT_SWITCHED, stream=None) -> None:
+    """ct: int64 tensor [tokens][L][2][P][N]; out: int32 [tokens][M][N+1] (switched) or
+    int64 [tokens][M][P][N+1] (RLWE_OUT_RAW_Q)."""
+    _check(lib().ct_matmul_clear(ctx, w, int(bool(transpose)), _ptr(ct), tokens, _ptr(out), flags,
+                                 _stream(stream)))
+
+
+def ct_modswitch(ctx: int, raw, count: int, out, stream=None) -> None:
+    """raw: int64 [count][P][N+1]; out: int32 [count][N+1]."""
+    _check(lib().ct_modswitch(ctx, _ptr(raw), count, _ptr(out), _stream(stream)))
+
+
+def rlwe_workspace_bytes(ctx: int, w: int, transpose: bool, tokens: int) -> int:
+    return int(lib().rlwe_workspace_bytes(ctx, w, int(bool(transpose)), tokens))
+
+
+def rlwe_workspace_reserve(ctx: int, nbytes: int) -> None:
+    _check(lib().rlwe_workspace_reserve(ctx, nbytes))
+
+
+# ------------------------------------------------------------------ conveniences
+
+class Context:
+    """Owns an rlwe_ctx handle."""
+
+    def __init__(self, N: int, primes: Sequence[int], log2_t: int, device: int = 0):
+        self.N, self.primes, self.log2_t = N, tuple(int(p) for p in primes), log2_t
+        self.P = len(self.primes)
+        self.handle = rlwe_params_init(N, self.primes, log2_t, device)
+
+    def close(self) -> None:
+        if self.handle:
+            rlwe_params_destroy(self.handle)
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Weights:
+    """Owns an rlwe_weights handle for a (d_out, d_in) int8 matrix."""
+
+    def __init__(self, ctx: Context, W, flags: int = RLWE_W_FWD, stream=None):
+        self.ctx = ctx
+        self.d_out, self.d_in = W.shape
+        self.handle = rlwe_weights_load(ctx.handle, W, flags, stream)
+
+    def close(self) -> None:
+        if self.handle:
+            rlwe_weights_free(self.handle)
+            self.handle = 0
+
+    def out_rows(self, transpose: bool) -> int:
+        return self.d_in if transpose else self.d_out
+
+    def in_len(self, transpose: bool) -> int:
+        return self.d_out if transpose else self.d_in
+
+
+def matmul(ctx: Context, w: Weights, ct, transpose: bool = False, raw: bool = False,
+           force_exact: bool = False, out=None, stream=None):
+    """Allocate the output (torch, on ct's device) and run ct_matmul_clear."""
+    import torch
+    T = ct.shape[0]
+    M = w.out_rows(transpose)
+    if out is None:
+        shape = (T, M, ctx.P, ctx.N + 1) if raw else (T, M, ctx.N + 1)
+        out = torch.empty(shape, dtype=torch.int64 if raw else torch.int32, device=ct.device)
+    flags = (RLWE_OUT_RAW_Q if raw else 0) | (RLWE_OUT_FORCE_EXACT if force_exact else 0)
+    ct_matmul_clear(ctx.handle, w.handle, ct, T, out, transpose, flags, stream)
+    return out
+
+
+def modswitch(ctx: Context, raw, out=None, stream=None):
+    import torch
+    count = raw.numel() // (ctx.P * (ctx.N + 1))
+    if out is None:
+        out = torch.empty(raw.shape[:-2] + (ctx.N + 1,), dtype=torch.int32, device=raw.device)
+    ct_modswitch(ctx.handle, raw, count, out, stream)
+    return out
