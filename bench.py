@@ -1,0 +1,159 @@
+#!/usr/bin/env python3
+"""Throughput of the encrypted clear-weight product W.[x]_HE on one MI355X.
+
+Workload (default): a Llama-3.2-1B attention projection, W 2048 x 2048 int8,
+128 encrypted int8 tokens, RLWE N = 4096, q = two 54-bit primes, t = 2^26, every
+output LWE switched to 2^32 (Sec. 4.3, Eq. (LWEdot) + ModulusSwitch). One step
+is one ct_matmul_clear call: digit preparation of the ciphertexts, the mask
+product on the int8 matrix cores, the body product, the fused modulus switch
+and the write of 128 x 2048 LWE ciphertexts of 4097 coefficients.
+
+Inputs are synthetic and seeded: int8 weights uniform in [-127, 127] and
+ciphertext residues uniform in [0, q_p) (the distribution of RLWE ciphertexts
+under a uniform mask), resident in HBM before the timed region. The kernels are
+data-oblivious apart from a rare exact-rounding fallback.
+
+Prints one JSON line: value = encrypted MACs/s (d_in * d_out * tokens / s),
+with the roofline of the dominant kernel (measured with HIP events on its
+launch stream over the timed region) and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix peak, 5.0 POP/s
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle baseline sample (0 disables it)")
+    return ap.parse_args()
+
+
+def cpu_baseline(W, ct_np, N, primes, T, d_out, d_in, target_s):
+    """The oracle (NTT mode + exact modulus switch) on sampled (token, row) outputs."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    orc.lib()
+    g = np.random.default_rng(7)
+    done = 0
+    t0 = time.perf_counter()
+    batch = 64
+    while True:
+        pairs = np.stack([g.integers(0, T, batch), g.integers(0, d_out, batch)], 1).astype(np.uint32)
+        raw = orc.matmul_clear(N, primes, W, ct_np, pairs=pairs, mode=1)
+        orc.modswitch(primes, raw)
+        done += batch
+        el = time.perf_counter() - t0
+        if el >= target_s:
+            break
+        batch = min(4096, batch * 2)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": done * d_in / el, "unit": "encrypted MAC/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} (token, row) outputs of the same workload, NTT-mode oracle plus exact "
+                      f"switch, {el:.1f} s on {cores} threads, scaled per MAC"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the encrypted product shards by tokens or output "
+              "rows with no exchange, and this build runs on a single MI355X; use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2505_07329_amd import rlwe, synth
+
+    cfg = synth.WORKLOADS[2]
+    N, primes, log2_t = cfg["N"], cfg["primes"], cfg["log2_t"]
+    d_in, d_out, T = cfg["d_in"], cfg["d_out"], cfg["tokens"]
+    L = (d_in + N - 1) // N
+    W = synth.int8_uniform(synth.rng(2, synth.P_WEIGHTS), (d_out, d_in))
+    ct_np = synth.uniform_mod_primes(synth.rng(2, synth.P_MASK), primes, (T, L, 2), N)
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = rlwe.Context(N, primes, log2_t, device=0)
+    w = rlwe.Weights(ctx, torch.from_numpy(W).to(dev))
+    ct = torch.from_numpy(ct_np.view(np.int64)).to(dev)
+    out = torch.empty((T, d_out, N + 1), dtype=torch.int32, device=dev)
+    rlwe.rlwe_workspace_reserve(ctx.handle, rlwe.rlwe_workspace_bytes(ctx.handle, w.handle, False, T))
+    kept, total = rlwe.rlwe_weights_digits(w.handle)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        rlwe.ct_matmul_clear(ctx.handle, w.handle, ct, T, out, False, rlwe.RLWE_OUT_SWITCHED, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    rlwe.rlwe_profile_begin(ctx.handle)
+    torch.cuda.synchronize()  # one GPU: the barrier is this synchronisation
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        marks[k].record(stream)
+        step()
+    marks[-1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = rlwe.rlwe_profile_end(ctx.handle)
+
+    macs = d_in * d_out * T
+    value = macs * args.steps / wall
+    lat = np.array([marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps)])
+    mask_ms = kt["mask_ms"] / max(1, kt["mask_n"])
+    # algorithmic int8 matrix-core work of one mask launch: every (token, row,
+    # mask index) contracts d_in products per kept digit
+    ops = 2.0 * T * d_out * N * d_in * kept
+    achieved = ops / (mask_ms * 1e-3) / 1e12
+    result = {
+        "metric": "encrypted MACs/s (d_in*d_out*tokens/s), W.[x]_HE with outputs switched to 2^32",
+        "value": value,
+        "unit": "MAC/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic (seeded uniform int8 weights, uniform ciphertext residues)",
+        "config": {"workload": cfg["name"], "d_in": d_in, "d_out": d_out, "tokens": T, "N": N,
+                   "primes": len(primes), "log2_t": log2_t, "q_out": "2^32",
+                   "digits_on_matrix_cores": f"{kept}/{total}"},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "kernels_ms": {"prep": kt["prep_ms"] / max(1, kt["prep_n"]), "mask": mask_ms,
+                       "body": kt["body_ms"] / max(1, kt["body_n"])},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
+                     "unit": "TOP/s (int8)", "frac": achieved / INT8_PEAK_TOPS, "traffic": None},
+        "cpu_baseline": None,
+    }
+    w.close()
+    ctx.close()
+    if args.cpu_seconds > 0:
+        result["cpu_baseline"] = cpu_baseline(W, ct_np, N, primes, T, d_out, d_in, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -142,6 +142,27 @@ size_t rlwe_workspace_bytes(const rlwe_ctx* ctx, const rlwe_weights* w, uint32_t
  * calls within that size allocate nothing. */
 int rlwe_workspace_reserve(rlwe_ctx* ctx, size_t bytes);
 
+/* Per-kernel device timing (HIP events recorded on the launch stream around
+ * every kernel the library enqueues while profiling is on), for roofline
+ * accounting. rlwe_profile_begin starts a recording window (at most 4096
+ * launches are recorded, later ones are counted in `dropped`);
+ * rlwe_profile_end waits for the recorded events, fills `out` (host pointer)
+ * and closes the window. Not for use inside hipGraph capture. */
+typedef struct rlwe_kernel_times {
+  double prep_ms, mask_ms, body_ms, modswitch_ms; /* summed durations */
+  uint32_t prep_n, mask_n, body_n, modswitch_n;   /* launches recorded */
+  uint32_t dropped;
+} rlwe_kernel_times;
+
+int rlwe_profile_begin(rlwe_ctx* ctx);
+int rlwe_profile_end(rlwe_ctx* ctx, rlwe_kernel_times* out);
+
+/* Digits of the balanced base-255 expansion of ciphertext coefficients that
+ * the switched product feeds to the int8 matrix cores (`kept`) out of `total`
+ * (7 for one prime, 14 for two). Host pointers; for work accounting. */
+int rlwe_weights_digits(const rlwe_weights* w, uint32_t transpose, uint32_t* kept,
+                        uint32_t* total);
+
 /* Description of the last error on this thread ("" if none). */
 const char* rlwe_last_error(void);
 

@@ -77,13 +77,56 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 }  // namespace
 
+namespace {
+enum KernelKind { K_PREP = 0, K_MASK = 1, K_BODY = 2, K_MODSWITCH = 3 };
+constexpr int kMaxProfiled = 4096;
+struct Profiler {
+  bool on = false;
+  int used = 0;
+  uint32_t dropped = 0;
+  hipEvent_t ev[kMaxProfiled][2] = {};
+  int kind[kMaxProfiled] = {};
+  int created = 0;
+};
+}  // namespace
+
 struct rlwe_ctx {
   int device = 0;
   uint32_t log2_t = 0;
   RingConst rc{};
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  Profiler* prof = nullptr;
 };
+
+namespace {
+// Runs `launch` on stream s; while profiling, brackets it with two events.
+template <class F>
+hipError_t timed(rlwe_ctx* ctx, int kind, hipStream_t s, F launch) {
+  Profiler* p = ctx->prof;
+  if (!p || !p->on) return launch();
+  if (p->used >= kMaxProfiled) {
+    ++p->dropped;
+    return launch();
+  }
+  const int i = p->used;
+  if (i >= p->created) {
+    hipError_t e = hipEventCreate(&p->ev[i][0]);
+    if (e == hipSuccess) e = hipEventCreate(&p->ev[i][1]);
+    if (e != hipSuccess) return e;
+    p->created = i + 1;
+  }
+  hipError_t e = hipEventRecord(p->ev[i][0], s);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(p->ev[i][1], s);
+  if (e != hipSuccess) return e;
+  p->kind[i] = kind;
+  p->used = i + 1;
+  return hipSuccess;
+}
+}  // namespace
 
 namespace {
 
@@ -260,8 +303,52 @@ int rlwe_params_init(const rlwe_params* p, int hip_device, rlwe_ctx** out) {
   return ok();
 }
 
+int rlwe_profile_begin(rlwe_ctx* ctx) {
+  if (!ctx) return fail(RLWE_EINVAL, "rlwe_profile_begin: null context");
+  if (!ctx->prof) {
+    ctx->prof = new (std::nothrow) Profiler;
+    if (!ctx->prof) return fail(RLWE_ENOMEM, "out of host memory");
+  }
+  ctx->prof->on = true;
+  ctx->prof->used = 0;
+  ctx->prof->dropped = 0;
+  return ok();
+}
+
+int rlwe_profile_end(rlwe_ctx* ctx, rlwe_kernel_times* out) {
+  if (!ctx || !out) return fail(RLWE_EINVAL, "rlwe_profile_end: null argument");
+  memset(out, 0, sizeof *out);
+  Profiler* p = ctx->prof;
+  if (!p || !p->on) return fail(RLWE_EINVAL, "rlwe_profile_end: no profiling window open");
+  p->on = false;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  double* ms[4] = {&out->prep_ms, &out->mask_ms, &out->body_ms, &out->modswitch_ms};
+  uint32_t* n[4] = {&out->prep_n, &out->mask_n, &out->body_n, &out->modswitch_n};
+  for (int i = 0; i < p->used; ++i) {
+    e = hipEventSynchronize(p->ev[i][1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float t = 0.f;
+    e = hipEventElapsedTime(&t, p->ev[i][0], p->ev[i][1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    *ms[p->kind[i]] += t;
+    ++*n[p->kind[i]];
+  }
+  out->dropped = p->dropped;
+  p->used = 0;
+  return ok();
+}
+
 int rlwe_params_destroy(rlwe_ctx* ctx) {
   if (!ctx) return ok();
+  if (ctx->prof) {
+    hipSetDevice(ctx->device);
+    for (int i = 0; i < ctx->prof->created; ++i) {
+      hipEventDestroy(ctx->prof->ev[i][0]);
+      hipEventDestroy(ctx->prof->ev[i][1]);
+    }
+    delete ctx->prof;
+  }
   if (ctx->ws) {
     hipSetDevice(ctx->device);
     hipError_t e = hipFree(ctx->ws);
@@ -376,6 +463,16 @@ size_t rlwe_workspace_bytes(const rlwe_ctx* ctx, const rlwe_weights* w, uint32_t
   return ws_need(ctx->rc, m.args, tokens);
 }
 
+int rlwe_weights_digits(const rlwe_weights* w, uint32_t transpose, uint32_t* kept,
+                        uint32_t* total) {
+  if (!w || !kept || !total) return fail(RLWE_EINVAL, "rlwe_weights_digits: null argument");
+  const Mat& m = transpose ? w->tr : w->fwd;
+  if (!m.present) return fail(RLWE_EINVAL, "rlwe_weights_digits: orientation not loaded");
+  *kept = m.sc.dk;
+  *total = w->ctx->rc.D;
+  return ok();
+}
+
 int rlwe_workspace_reserve(rlwe_ctx* ctx, size_t bytes) {
   if (!ctx) return fail(RLWE_EINVAL, "rlwe_workspace_reserve: null context");
   hipError_t e = hipSetDevice(ctx->device);
@@ -413,11 +510,14 @@ int ct_matmul_clear(rlwe_ctx* ctx, const rlwe_weights* w, uint32_t transpose,
   pa.ebody = (int8_t*)ctx->ws + align_up((size_t)tokens * rc.D * m.args.L * 2 * rc.N, 256);
   pa.T = tokens;
   pa.L = m.args.L;
-  e = launch_prep(rc, pa, s);
+  e = timed(ctx, K_PREP, s, [&] { return launch_prep(rc, pa, s); });
   if (e != hipSuccess) return hip_fail(e, "prep kernel");
-  e = launch_mask(rc, m.sc, m.args, pa.emask, tokens, out, raw, flags & RLWE_OUT_FORCE_EXACT, s);
+  const bool force = flags & RLWE_OUT_FORCE_EXACT;
+  e = timed(ctx, K_MASK, s, [&] {
+    return launch_mask(rc, m.sc, m.args, pa.emask, tokens, out, raw, force, s);
+  });
   if (e != hipSuccess) return hip_fail(e, "mask kernel");
-  e = launch_body(rc, m.args, pa.ebody, tokens, out, raw, s);
+  e = timed(ctx, K_BODY, s, [&] { return launch_body(rc, m.args, pa.ebody, tokens, out, raw, s); });
   if (e != hipSuccess) return hip_fail(e, "body kernel");
   return ok();
 }
@@ -429,7 +529,8 @@ int ct_modswitch(rlwe_ctx* ctx, const uint64_t* in, size_t count, uint32_t* out,
   if (!in || !out) return fail(RLWE_EINVAL, "ct_modswitch: null buffer");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  e = launch_modswitch(ctx->rc, in, count, out, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  e = timed(ctx, K_MODSWITCH, s, [&] { return launch_modswitch(ctx->rc, in, count, out, s); });
   if (e != hipSuccess) return hip_fail(e, "modswitch kernel");
   return ok();
 }

@@ -29,13 +29,24 @@ RLWE_OUT_FORCE_EXACT = 2
 
 EXPORTS = ("rlwe_params_init", "rlwe_params_destroy", "rlwe_weights_load", "rlwe_weights_free",
            "ct_matmul_clear", "ct_modswitch", "rlwe_workspace_bytes", "rlwe_workspace_reserve",
-           "rlwe_last_error")
+           "rlwe_profile_begin", "rlwe_profile_end", "rlwe_weights_digits", "rlwe_last_error")
 
 
 class RlweError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{ERRORS.get(code, code)}: {msg}")
         self.code = code
+
+
+class KernelTimes(ctypes.Structure):
+    _fields_ = [("prep_ms", ctypes.c_double), ("mask_ms", ctypes.c_double),
+                ("body_ms", ctypes.c_double), ("modswitch_ms", ctypes.c_double),
+                ("prep_n", ctypes.c_uint32), ("mask_n", ctypes.c_uint32),
+                ("body_n", ctypes.c_uint32), ("modswitch_n", ctypes.c_uint32),
+                ("dropped", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class _Params(ctypes.Structure):
@@ -67,6 +78,10 @@ def lib() -> ctypes.CDLL:
     L.rlwe_workspace_bytes.argtypes = [vp, vp, ctypes.c_uint32, ctypes.c_uint32]
     L.rlwe_workspace_bytes.restype = ctypes.c_size_t
     L.rlwe_workspace_reserve.argtypes = [vp, ctypes.c_size_t]
+    L.rlwe_profile_begin.argtypes = [vp]
+    L.rlwe_profile_end.argtypes = [vp, ctypes.POINTER(KernelTimes)]
+    L.rlwe_weights_digits.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
+                                      ctypes.POINTER(ctypes.c_uint32)]
     L.rlwe_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "rlwe_last_error" and name != "rlwe_workspace_bytes":
@@ -143,6 +158,22 @@ def rlwe_workspace_bytes(ctx: int, w: int, transpose: bool, tokens: int) -> int:
 
 def rlwe_workspace_reserve(ctx: int, nbytes: int) -> None:
     _check(lib().rlwe_workspace_reserve(ctx, nbytes))
+
+
+def rlwe_weights_digits(w: int, transpose: bool = False) -> tuple[int, int]:
+    kept, total = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib().rlwe_weights_digits(w, int(bool(transpose)), ctypes.byref(kept), ctypes.byref(total)))
+    return kept.value, total.value
+
+
+def rlwe_profile_begin(ctx: int) -> None:
+    _check(lib().rlwe_profile_begin(ctx))
+
+
+def rlwe_profile_end(ctx: int) -> dict:
+    kt = KernelTimes()
+    _check(lib().rlwe_profile_end(ctx, ctypes.byref(kt)))
+    return kt.as_dict()
 
 
 # ------------------------------------------------------------------ conveniences
