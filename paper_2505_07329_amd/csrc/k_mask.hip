@@ -49,107 +49,182 @@ __device__ inline uint32_t fixed_round(uint32_t u0, uint32_t u1, uint32_t u2, ui
   return w4 + (w3 >> 31);
 }
 
-// All digit sums of one mask element, exactly, straight from global memory.
+// Exact switched value of element (t, jj, nn), computed by the whole wave: every
+// lane accumulates a strided share of the contraction for all D digits, the
+// shares are summed across the wave, and the exact rounding is taken from the
+// integer V = sum_l 255^l S_l. Used where the fast path lies near a tie.
 template <int D>
-__device__ __attribute__((noinline)) uint32_t exact_mask_element(const RingConst& rc,
+__device__ __attribute__((noinline)) uint32_t exact_element_wave(const RingConst& rc,
                                                                  const MatArgs& m,
                                                                  const int8_t* emask, uint32_t t,
-                                                                 uint32_t j, uint32_t n) {
+                                                                 uint32_t jj, uint32_t nn,
+                                                                 int lane) {
   const uint32_t N = rc.N;
   int32_t S[D];
+#pragma unroll
   for (int l = 0; l < D; ++l) S[l] = 0;
   for (uint32_t i = 0; i < m.L; ++i) {
     const uint32_t kb = min(N, m.k - i * N);
-    const int8_t* wrow = m.w + (size_t)j * m.kw + (size_t)i * N;
-    for (int l = 0; l < D; ++l) {
-      const int8_t* plane = emask + (((size_t)t * D + l) * m.L + i) * 2 * N + N - n;
-      int32_t s = 0;
-      for (uint32_t k = 0; k < kb; ++k) s += (int32_t)wrow[k] * (int32_t)plane[k];
-      S[l] += s;
+    const int8_t* wrow = m.w + (size_t)jj * m.kw + (size_t)i * N;
+    for (uint32_t k = lane; k < kb; k += 64) {
+      const int32_t wv = wrow[k];
+#pragma unroll
+      for (int l = 0; l < D; ++l)
+        S[l] += wv * (int32_t)emask[(((size_t)t * D + l) * m.L + i) * 2 * N + N + k - nn];
     }
   }
+#pragma unroll
+  for (int l = 0; l < D; ++l) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) S[l] += __shfl_xor(S[l], off);
+  }
   i128 V = 0;
+#pragma unroll
   for (int l = D - 1; l >= 0; --l) V = V * 255 + S[l];
   return switch_exact(V, rc);
 }
 
+// 16-byte Toeplitz fragment at byte offset o of a digit window in LDS.
+__device__ inline v4i toeplitz_frag(const uint32_t* w, int o) {
+  const uint32_t* p = w + (o >> 2);
+  const int sh = o & 3;
+  const uint32_t w0 = p[0], w1 = p[1], w2 = p[2], w3 = p[3], w4 = p[4];
+  v4i f;
+  f[0] = (int)__builtin_amdgcn_alignbyte(w1, w0, sh);
+  f[1] = (int)__builtin_amdgcn_alignbyte(w2, w1, sh);
+  f[2] = (int)__builtin_amdgcn_alignbyte(w3, w2, sh);
+  f[3] = (int)__builtin_amdgcn_alignbyte(w4, w3, sh);
+  return f;
+}
+
+// Work split: a workgroup owns a 32-row x 64-column output tile of one token
+// and all DK kept digits; its NW = ceil(DK/3) waves each take at most 3 digits
+// (the role of a wave rotates with the tile so that heavier roles spread over
+// the SIMDs). Each wave covers both 32-column blocks: along a diagonal the
+// Toeplitz fragment of block 1 at k-step k0 equals that of block 0 at k0 - 32,
+// so every k-step reads one new fragment per digit and feeds two MFMAs.
+// Epilogue: per-wave partial sums over its digits (int64) meet in LDS; each
+// wave finishes a share of the elements.
 template <int D, int DK, bool RAW>
-__global__ void __launch_bounds__(256) mask_kernel(RingConst rc, SwitchConst sc, MatArgs m,
-                                                   const int8_t* __restrict__ emask, uint32_t T,
-                                                   void* out, int force_exact) {
+__global__ void __launch_bounds__(64 * ((DK + 2) / 3)) mask_kernel(RingConst rc, SwitchConst sc,
+                                                                   MatArgs m,
+                                                                   const int8_t* __restrict__ emask,
+                                                                   void* out, int force_exact) {
   static_assert(!RAW || DK == D, "raw output keeps every digit");
-  __shared__ uint32_t win[DK][kWinWords];
+  constexpr int NW = (DK + 2) / 3;
+  constexpr int DPW = 3;
+  constexpr int kWinLds = DK * kWinWords * 4;
+  constexpr int kPartLds = NW * 32 * 64 * 8;
+  constexpr int kLds = kWinLds > kPartLds ? kWinLds : kPartLds;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kLds];
+  uint32_t(*win)[kWinWords] = reinterpret_cast<uint32_t(*)[kWinWords]>(smem);
+  int64_t* part = reinterpret_cast<int64_t*>(smem);
+
   const uint32_t N = rc.N;
   const uint32_t t = blockIdx.z;
-  const uint32_t n0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  const uint32_t n0 = blockIdx.x * 64, jb = blockIdx.y * 32;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c = lane & 31, g = lane >> 5;
-  const uint32_t jb = j0 + 32 * (wave >> 1), nb = n0 + 32 * (wave & 1);
+  const int role = (wave + blockIdx.x + blockIdx.y) % NW;
+  const int cnt = DK / NW + (role < DK % NW ? 1 : 0);
+  const int dlo = role * (DK / NW) + min(role, DK % NW);
   const uint32_t l0 = D - DK;
 
-  v16i acc[DK];
+  v16i acc0[DPW], acc1[DPW];
 #pragma unroll
-  for (int d = 0; d < DK; ++d) acc[d] = v16i{0};
+  for (int d = 0; d < DPW; ++d) acc0[d] = acc1[d] = v16i{0};
 
   for (uint32_t i = 0; i < m.L; ++i) {
     const uint32_t kb = min(N, m.k - i * N);
     const uint32_t kp = (kb + 31u) & ~31u;
     for (uint32_t kc = 0; kc < kp; kc += kKC) {
       const uint32_t klen = min((uint32_t)kKC, kp - kc);
-      // window = plane bytes [N + kc - n0 - 64, N + kc - n0 + klen): every Toeplitz
-      // entry of this block's columns [n0, n0+64) and rows [kc, kc+klen)
+      // plane bytes [N + kc - n0 - 64, N + kc - n0 + klen) hold every Toeplitz
+      // entry of rows [kc, kc + klen) and columns [n0, n0 + 64)
       const uint32_t wstart = N + kc - n0 - 64;
       const uint32_t n16 = (klen + 64) / 16;
       __syncthreads();
-      for (uint32_t x = threadIdx.x; x < DK * n16; x += 256) {
+      for (uint32_t x = threadIdx.x; x < DK * n16; x += 64 * NW) {
         const uint32_t d = x / n16, o = x % n16;
         const int8_t* src =
             emask + (((size_t)t * D + (l0 + d)) * m.L + i) * 2 * N + wstart + 16 * o;
         *(uint4*)&win[d][4 * o] = *(const uint4*)src;
       }
       __syncthreads();
-      const int8_t* wbase = m.w + (size_t)(jb + c) * m.kw + (size_t)i * N + kc + 16 * g;
-      for (uint32_t k0 = 0; k0 < klen; k0 += 32) {
-        const v4i wf = *(const v4i*)(wbase + k0);
-        const int o = (int)k0 + 16 * g - (int)(nb - n0) - c + 64;
-        const int dw = o >> 2, sh = o & 3;
+      const int8_t* wrow = m.w + (size_t)(jb + c) * m.kw + (size_t)i * N + kc + 16 * g;
+      // block 1 at the first k-step reads offset o_0 - 32
+      v4i fprev[DPW];
 #pragma unroll
-        for (int d = 0; d < DK; ++d) {
-          const uint32_t* p = &win[d][dw];
-          const uint32_t w0 = p[0], w1 = p[1], w2 = p[2], w3 = p[3], w4 = p[4];
-          v4i ef;
-          ef[0] = (int)__builtin_amdgcn_alignbyte(w1, w0, sh);
-          ef[1] = (int)__builtin_amdgcn_alignbyte(w2, w1, sh);
-          ef[2] = (int)__builtin_amdgcn_alignbyte(w3, w2, sh);
-          ef[3] = (int)__builtin_amdgcn_alignbyte(w4, w3, sh);
-          acc[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(wf, ef, acc[d], 0, 0, 0);
+      for (int d = 0; d < DPW; ++d)
+        if (d < cnt) fprev[d] = toeplitz_frag(win[dlo + d], 16 * g - c + 32);
+      v4i wf = *(const v4i*)wrow;
+      for (uint32_t k0 = 0; k0 < klen; k0 += 32) {
+        const v4i wcur = wf;
+        if (k0 + 32 < klen) wf = *(const v4i*)(wrow + k0 + 32);
+        const int o = (int)k0 + 16 * g - c + 64;
+#pragma unroll
+        for (int d = 0; d < DPW; ++d) {
+          if (d < cnt) {
+            const v4i fnew = toeplitz_frag(win[dlo + d], o);
+            acc0[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(wcur, fnew, acc0[d], 0, 0, 0);
+            acc1[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(wcur, fprev[d], acc1[d], 0, 0, 0);
+            fprev[d] = fnew;
+          }
         }
       }
     }
   }
 
-  // accumulator element r of this lane: row jb + 8(r/4) + 4g + r%4, column nb + c
-  const uint32_t n = nb + c;
+  // accumulator element e of this lane: row jb + 8(e/4) + 4g + e%4, column n0 + 32b + c.
+  // All partials go to LDS first so that no accumulator is live in the final loop.
+  __syncthreads();  // the digit windows are no longer read
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const uint32_t j = jb + 8 * (r >> 2) + 4 * g + (r & 3);
-    if (j >= m.rows) continue;
+  for (int e = 0; e < 16; ++e) {
+    int64_t P0 = 0, P1 = 0;
+#pragma unroll
+    for (int d = DPW - 1; d >= 0; --d) {
+      if (d < cnt) {
+        P0 = P0 * 255 + acc0[d][e];
+        P1 = P1 * 255 + acc1[d][e];
+      }
+    }
+    part[(role * 32 + e) * 64 + lane] = P0;
+    part[(role * 32 + 16 + e) * 64 + lane] = P1;
+  }
+  __syncthreads();
+  for (int eb = wave; eb < 32; eb += NW) {
+    const int b = eb >> 4, e = eb & 15;
+    const uint32_t n = n0 + 32 * b + c;
+    const uint32_t j = jb + 8 * (e >> 2) + 4 * g + (e & 3);
+    // U = sum over roles of 255^dlo_r P_r, Horner from the highest role
+    i128 U = 0;
+#pragma unroll
+    for (int r = NW - 1; r >= 0; --r) {
+      const int cr = DK / NW + (r < DK % NW ? 1 : 0);
+      i128 scale = 1;
+      for (int x = 0; x < cr; ++x) scale *= 255;
+      U = U * scale + part[(r * 32 + eb) * 64 + lane];
+    }
+    const bool live = j < m.rows;
     const size_t row = (size_t)t * m.rows + j;
     if (RAW) {
-      i128 V = 0;
-#pragma unroll
-      for (int d = DK - 1; d >= 0; --d) V = V * 255 + acc[d][r];
-      uint64_t* o = (uint64_t*)out;
-      for (uint32_t p = 0; p < rc.P; ++p) o[(row * rc.P + p) * (N + 1) + n] = mod_i128(V, rc.q[p]);
+      if (live) {
+        uint64_t* o = (uint64_t*)out;
+        for (uint32_t p = 0; p < rc.P; ++p) o[(row * rc.P + p) * (N + 1) + n] = mod_i128(U, rc.q[p]);
+      }
     } else {
-      i128 U = 0;
-#pragma unroll
-      for (int d = DK - 1; d >= 0; --d) U = U * 255 + acc[d][r];
       bool amb;
       uint32_t res = fixed_round((uint32_t)U, (uint32_t)(U >> 32), (uint32_t)(U >> 64),
                                  (uint32_t)(U >> 96), sc.g, sc.eps, amb);
-      if (amb || force_exact) res = exact_mask_element<D>(rc, m, emask, t, j, n);
-      ((uint32_t*)out)[row * (N + 1) + n] = res;
+      uint64_t pending = __ballot(live && (amb || force_exact));
+      while (pending) {
+        const int src = __ffsll((unsigned long long)pending) - 1;
+        pending &= pending - 1;
+        const uint32_t jj = __shfl(j, src), nn = __shfl(n, src);
+        const uint32_t r = exact_element_wave<D>(rc, m, emask, t, jj, nn, lane);
+        if (lane == src) res = r;
+      }
+      if (live) ((uint32_t*)out)[row * (N + 1) + n] = res;
     }
   }
 }
@@ -157,9 +232,9 @@ __global__ void __launch_bounds__(256) mask_kernel(RingConst rc, SwitchConst sc,
 template <int D, int DK, bool RAW>
 static void launch_one(const RingConst& rc, const SwitchConst& sc, const MatArgs& m,
                        const int8_t* emask, uint32_t T, void* out, int force, hipStream_t s) {
-  const dim3 grid(rc.N / 64, m.rows_pad / 64, T);
-  hipLaunchKernelGGL((mask_kernel<D, DK, RAW>), grid, dim3(256), 0, s, rc, sc, m, emask, T, out,
-                     force);
+  const dim3 grid(rc.N / 64, m.rows_pad / 32, T);
+  hipLaunchKernelGGL((mask_kernel<D, DK, RAW>), grid, dim3(64 * ((DK + 2) / 3)), 0, s, rc, sc, m,
+                     emask, out, force);
 }
 
 hipError_t launch_mask(const RingConst& rc, const SwitchConst& sc, const MatArgs& m,
@@ -168,9 +243,10 @@ hipError_t launch_mask(const RingConst& rc, const SwitchConst& sc, const MatArgs
   if (T == 0) return hipSuccess;
   const int f = force_exact ? 1 : 0;
   if (rc.D == 7) {
-    if (raw || sc.dk == 7)
-      raw ? launch_one<7, 7, true>(rc, sc, m, emask, T, out, f, s)
-          : launch_one<7, 7, false>(rc, sc, m, emask, T, out, f, s);
+    if (raw)
+      launch_one<7, 7, true>(rc, sc, m, emask, T, out, f, s);
+    else if (sc.dk == 7)
+      launch_one<7, 7, false>(rc, sc, m, emask, T, out, f, s);
     else
       return hipErrorInvalidValue;
   } else {

@@ -177,11 +177,11 @@ int make_switch_const(const RingConst& rc, uint32_t max_l1, SwitchConst* sc) {
   const u128 q = make_u128(rc.Q_hi, rc.Q_lo);
   const double qd = u128_to_double(q);
   const double maxS = 127.0 * (double)(max_l1 > 0 ? max_l1 : 1);
-  // Largest l0 whose skipped digits move V 2^32/q by at most 2^-18.
+  // Largest l0 whose skipped digits move V 2^32/q by at most 2^-16.
   uint32_t l0 = 0;
   for (uint32_t c = 1; c < rc.D; ++c) {
     const double skipped = maxS * ((pow(255.0, (double)c) - 1.0) / 254.0) * 4294967296.0 / qd;
-    if (skipped <= 1.0 / 262144.0) l0 = c;
+    if (skipped <= 1.0 / 65536.0) l0 = c;
   }
   uint32_t dk = rc.D - l0;
   if (rc.D == 7) {
