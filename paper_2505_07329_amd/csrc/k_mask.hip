@@ -25,9 +25,17 @@ namespace rlwe {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kKC = 512;                    // k-chunk staged in LDS per pass
-constexpr int kWinBytes = kKC + 64 + 16;    // per-digit window (+ over-read pad)
-constexpr int kWinWords = kWinBytes / 4;
+constexpr int kKC = 256;                 // k-chunk staged in LDS per pass (8 k-steps)
+// LDS layout of one digit window: four copies, copy s shifted by s bytes, each
+// kCopyWords long; copy s starts at s * kCopyPitch + skew(s) dwords with
+// skew = 0, 9, 17, 25 so that the 32 lanes of a half-wave, which read 8
+// consecutive dwords from each of the four copies in one fragment load, hit 32
+// distinct banks.
+constexpr int kCopyWords = (kKC + 96) / 4;
+constexpr int kCopyPitch = (kCopyWords + 31) / 32 * 32;
+constexpr int kDigitWords = 3 * kCopyPitch + 25 + kCopyWords + 31 - (3 * kCopyPitch + 25 + kCopyWords + 31) % 32;
+__host__ __device__ constexpr int copy_base(int s) { return s * kCopyPitch + (s ? 8 * s + 1 : 0); }
+constexpr int kWRowWords = kKC / 4 + 4;    // LDS row pitch of the weight tile (dwords)
 
 // round(U * G) mod 2^32 where U is a signed 128-bit integer (u0..u3) and
 // G = g / 2^128 (g < 2^128). Partial products of U*g below bit 96 are dropped
@@ -84,16 +92,10 @@ __device__ __attribute__((noinline)) uint32_t exact_element_wave(const RingConst
   return switch_exact(V, rc);
 }
 
-// 16-byte Toeplitz fragment at byte offset o of a digit window in LDS.
-__device__ inline v4i toeplitz_frag(const uint32_t* w, int o) {
-  const uint32_t* p = w + (o >> 2);
-  const int sh = o & 3;
-  const uint32_t w0 = p[0], w1 = p[1], w2 = p[2], w3 = p[3], w4 = p[4];
+// 16-byte Toeplitz fragment: four consecutive dwords of a byte-shifted window copy.
+__device__ inline v4i toeplitz_frag(const uint32_t* p) {
   v4i f;
-  f[0] = (int)__builtin_amdgcn_alignbyte(w1, w0, sh);
-  f[1] = (int)__builtin_amdgcn_alignbyte(w2, w1, sh);
-  f[2] = (int)__builtin_amdgcn_alignbyte(w3, w2, sh);
-  f[3] = (int)__builtin_amdgcn_alignbyte(w4, w3, sh);
+  __builtin_memcpy(&f, p, 16);
   return f;
 }
 
@@ -106,18 +108,24 @@ __device__ inline v4i toeplitz_frag(const uint32_t* w, int o) {
 // Epilogue: per-wave partial sums over its digits (int64) meet in LDS; each
 // wave finishes a share of the elements.
 template <int D, int DK, bool RAW>
-__global__ void __launch_bounds__(64 * ((DK + 2) / 3)) mask_kernel(RingConst rc, SwitchConst sc,
+__global__ void __launch_bounds__(64 * ((DK + 2) / 3)) __attribute__((amdgpu_waves_per_eu(3)))
+mask_kernel(RingConst rc, SwitchConst sc,
                                                                    MatArgs m,
                                                                    const int8_t* __restrict__ emask,
                                                                    void* out, int force_exact) {
   static_assert(!RAW || DK == D, "raw output keeps every digit");
   constexpr int NW = (DK + 2) / 3;
   constexpr int DPW = 3;
-  constexpr int kWinLds = DK * kWinWords * 4;
-  constexpr int kPartLds = NW * 32 * 64 * 8;
-  constexpr int kLds = kWinLds > kPartLds ? kWinLds : kPartLds;
+  // LDS: per kept digit four copies of the chunk's window, copy s shifted by s bytes
+  // (every fragment becomes an aligned-dword read), plus the 32-row weight tile;
+  // after the k-loop the same memory holds the per-wave partial sums.
+  constexpr int kWinLds = DK * kDigitWords * 4;
+  constexpr int kWLds = 32 * kWRowWords * 4;
+  constexpr int kPartLds = NW * 16 * 64 * 8;
+  constexpr int kLds = kWinLds + kWLds > kPartLds ? kWinLds + kWLds : kPartLds;
   __shared__ __attribute__((aligned(16))) unsigned char smem[kLds];
-  uint32_t(*win)[kWinWords] = reinterpret_cast<uint32_t(*)[kWinWords]>(smem);
+  uint32_t* win = reinterpret_cast<uint32_t*>(smem);
+  uint32_t(*wt)[kWRowWords] = reinterpret_cast<uint32_t(*)[kWRowWords]>(smem + kWinLds);
   int64_t* part = reinterpret_cast<int64_t*>(smem);
 
   const uint32_t N = rc.N;
@@ -126,49 +134,74 @@ __global__ void __launch_bounds__(64 * ((DK + 2) / 3)) mask_kernel(RingConst rc,
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c = lane & 31, g = lane >> 5;
   const int role = (wave + blockIdx.x + blockIdx.y) % NW;
-  const int cnt = DK / NW + (role < DK % NW ? 1 : 0);
+  const int cnt = (DK % NW == 0) ? DK / NW : DK / NW + (role < DK % NW ? 1 : 0);
   const int dlo = role * (DK / NW) + min(role, DK % NW);
   const uint32_t l0 = D - DK;
+  // lane byte offset of block 0 at k-step 0 inside a window; block 1 sits 32 bytes
+  // (8 dwords) lower and each k-step moves 32 bytes up, so the shift is fixed
+  const int lb = 16 * g - c + 64;
+  const int sh = lb & 3;
 
   v16i acc0[DPW], acc1[DPW];
 #pragma unroll
   for (int d = 0; d < DPW; ++d) acc0[d] = acc1[d] = v16i{0};
 
-  for (uint32_t i = 0; i < m.L; ++i) {
-    const uint32_t kb = min(N, m.k - i * N);
+  const uint32_t L = __builtin_amdgcn_readfirstlane(m.L);
+  for (uint32_t i = 0; i < L; ++i) {
+    const uint32_t kb = __builtin_amdgcn_readfirstlane(min(N, m.k - i * N));
     const uint32_t kp = (kb + 31u) & ~31u;
     for (uint32_t kc = 0; kc < kp; kc += kKC) {
-      const uint32_t klen = min((uint32_t)kKC, kp - kc);
+      const uint32_t klen = __builtin_amdgcn_readfirstlane(min((uint32_t)kKC, kp - kc));
       // plane bytes [N + kc - n0 - 64, N + kc - n0 + klen) hold every Toeplitz
       // entry of rows [kc, kc + klen) and columns [n0, n0 + 64)
       const uint32_t wstart = N + kc - n0 - 64;
-      const uint32_t n16 = (klen + 64) / 16;
       __syncthreads();
-      for (uint32_t x = threadIdx.x; x < DK * n16; x += 64 * NW) {
-        const uint32_t d = x / n16, o = x % n16;
-        const int8_t* src =
-            emask + (((size_t)t * D + (l0 + d)) * m.L + i) * 2 * N + wstart + 16 * o;
-        *(uint4*)&win[d][4 * o] = *(const uint4*)src;
+      {
+        // Stage the windows (four byte-shifted copies per digit) and the weight tile.
+        // Shapes are compile-time so the index arithmetic is shifts and multiplies;
+        // bytes past the plane or the padded weight row read as zero (never used).
+        constexpr int kNT = 64 * NW;
+        constexpr int kW16 = kKC / 16;
+        const int8_t* wsrc = m.w + (size_t)jb * m.kw + (size_t)i * N + kc;
+        const uint32_t wlim = m.kw - i * N - kc;
+        for (uint32_t x = threadIdx.x; x < (uint32_t)(DK * kCopyWords); x += kNT) {
+          const uint32_t d = x / kCopyWords, u = x % kCopyWords;
+          const uint32_t at = wstart + 4 * u;
+          const int8_t* plane = emask + (((size_t)t * D + (l0 + d)) * L + i) * 2 * N;
+          const uint32_t g0 = at < 2 * N ? *(const uint32_t*)(plane + at) : 0u;
+          const uint32_t g1 = at + 4 < 2 * N ? *(const uint32_t*)(plane + at + 4) : 0u;
+          uint32_t* wd = win + d * kDigitWords + u;
+          wd[copy_base(0)] = g0;
+          wd[copy_base(1)] = __builtin_amdgcn_alignbyte(g1, g0, 1);
+          wd[copy_base(2)] = __builtin_amdgcn_alignbyte(g1, g0, 2);
+          wd[copy_base(3)] = __builtin_amdgcn_alignbyte(g1, g0, 3);
+        }
+        for (uint32_t x = threadIdx.x; x < 32u * kW16; x += kNT) {
+          const uint32_t r = x / kW16, o = x % kW16;
+          *(uint4*)&wt[r][4 * o] = 16 * o < wlim
+                                       ? *(const uint4*)(wsrc + (size_t)r * m.kw + 16 * o)
+                                       : make_uint4(0, 0, 0, 0);
+        }
       }
       __syncthreads();
-      const int8_t* wrow = m.w + (size_t)(jb + c) * m.kw + (size_t)i * N + kc + 16 * g;
-      // block 1 at the first k-step reads offset o_0 - 32
+      const uint32_t* ep[DPW];
       v4i fprev[DPW];
 #pragma unroll
-      for (int d = 0; d < DPW; ++d)
-        if (d < cnt) fprev[d] = toeplitz_frag(win[dlo + d], 16 * g - c + 32);
-      v4i wf = *(const v4i*)wrow;
-      for (uint32_t k0 = 0; k0 < klen; k0 += 32) {
-        const v4i wcur = wf;
-        if (k0 + 32 < klen) wf = *(const v4i*)(wrow + k0 + 32);
-        const int o = (int)k0 + 16 * g - c + 64;
+      for (int d = 0; d < DPW; ++d) {
+        ep[d] = win + (dlo + d) * kDigitWords + copy_base(sh) + (lb >> 2);
+        if (d < cnt) fprev[d] = toeplitz_frag(ep[d] - 8);
+      }
+      const uint32_t* wl = &wt[c][4 * g];
+      const uint32_t nstep = klen / 32;
+      for (uint32_t st = 0; st < nstep; ++st) {
+        const v4i wf = toeplitz_frag(wl + 8 * st);
 #pragma unroll
         for (int d = 0; d < DPW; ++d) {
           if (d < cnt) {
-            const v4i fnew = toeplitz_frag(win[dlo + d], o);
-            acc0[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(wcur, fnew, acc0[d], 0, 0, 0);
-            acc1[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(wcur, fprev[d], acc1[d], 0, 0, 0);
-            fprev[d] = fnew;
+            const v4i fa = toeplitz_frag(ep[d] + 8 * st);
+            acc0[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(wf, fa, acc0[d], 0, 0, 0);
+            acc1[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(wf, fprev[d], acc1[d], 0, 0, 0);
+            fprev[d] = fa;
           }
         }
       }
@@ -176,55 +209,60 @@ __global__ void __launch_bounds__(64 * ((DK + 2) / 3)) mask_kernel(RingConst rc,
   }
 
   // accumulator element e of this lane: row jb + 8(e/4) + 4g + e%4, column n0 + 32b + c.
-  // All partials go to LDS first so that no accumulator is live in the final loop.
-  __syncthreads();  // the digit windows are no longer read
+  // Each wave folds its digits into int64 partials; the partials of the two column
+  // blocks meet in LDS in two rounds, and every wave finishes a share of the elements.
+  int64_t P0[16], P1[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
-    int64_t P0 = 0, P1 = 0;
+    P0[e] = 0;
+    P1[e] = 0;
 #pragma unroll
     for (int d = DPW - 1; d >= 0; --d) {
       if (d < cnt) {
-        P0 = P0 * 255 + acc0[d][e];
-        P1 = P1 * 255 + acc1[d][e];
+        P0[e] = P0[e] * 255 + acc0[d][e];
+        P1[e] = P1[e] * 255 + acc1[d][e];
       }
     }
-    part[(role * 32 + e) * 64 + lane] = P0;
-    part[(role * 32 + 16 + e) * 64 + lane] = P1;
   }
-  __syncthreads();
-  for (int eb = wave; eb < 32; eb += NW) {
-    const int b = eb >> 4, e = eb & 15;
-    const uint32_t n = n0 + 32 * b + c;
-    const uint32_t j = jb + 8 * (e >> 2) + 4 * g + (e & 3);
-    // U = sum over roles of 255^dlo_r P_r, Horner from the highest role
-    i128 U = 0;
 #pragma unroll
-    for (int r = NW - 1; r >= 0; --r) {
-      const int cr = DK / NW + (r < DK % NW ? 1 : 0);
-      i128 scale = 1;
-      for (int x = 0; x < cr; ++x) scale *= 255;
-      U = U * scale + part[(r * 32 + eb) * 64 + lane];
-    }
-    const bool live = j < m.rows;
-    const size_t row = (size_t)t * m.rows + j;
-    if (RAW) {
-      if (live) {
-        uint64_t* o = (uint64_t*)out;
-        for (uint32_t p = 0; p < rc.P; ++p) o[(row * rc.P + p) * (N + 1) + n] = mod_i128(U, rc.q[p]);
+  for (int b = 0; b < 2; ++b) {
+    __syncthreads();  // LDS windows (or the previous round's partials) are no longer read
+#pragma unroll
+    for (int e = 0; e < 16; ++e) part[(role * 16 + e) * 64 + lane] = b == 0 ? P0[e] : P1[e];
+    __syncthreads();
+    const uint32_t n = n0 + 32 * b + c;
+    for (int e = wave; e < 16; e += NW) {
+      const uint32_t j = jb + 8 * (e >> 2) + 4 * g + (e & 3);
+      // U = sum over roles of 255^dlo_r P_r, Horner from the highest role
+      i128 U = 0;
+#pragma unroll
+      for (int r = NW - 1; r >= 0; --r) {
+        const int cr = DK / NW + (r < DK % NW ? 1 : 0);
+        i128 scale = 1;
+        for (int x = 0; x < cr; ++x) scale *= 255;
+        U = U * scale + part[(r * 16 + e) * 64 + lane];
       }
-    } else {
-      bool amb;
-      uint32_t res = fixed_round((uint32_t)U, (uint32_t)(U >> 32), (uint32_t)(U >> 64),
-                                 (uint32_t)(U >> 96), sc.g, sc.eps, amb);
-      uint64_t pending = __ballot(live && (amb || force_exact));
-      while (pending) {
-        const int src = __ffsll((unsigned long long)pending) - 1;
-        pending &= pending - 1;
-        const uint32_t jj = __shfl(j, src), nn = __shfl(n, src);
-        const uint32_t r = exact_element_wave<D>(rc, m, emask, t, jj, nn, lane);
-        if (lane == src) res = r;
+      const bool live = j < m.rows;
+      const size_t row = (size_t)t * m.rows + j;
+      if (RAW) {
+        if (live) {
+          uint64_t* o = (uint64_t*)out;
+          for (uint32_t p = 0; p < rc.P; ++p) o[(row * rc.P + p) * (N + 1) + n] = mod_i128(U, rc.q[p]);
+        }
+      } else {
+        bool amb;
+        uint32_t res = fixed_round((uint32_t)U, (uint32_t)(U >> 32), (uint32_t)(U >> 64),
+                                   (uint32_t)(U >> 96), sc.g, sc.eps, amb);
+        uint64_t pending = __ballot(live && (amb || force_exact));
+        while (pending) {
+          const int src = __ffsll((unsigned long long)pending) - 1;
+          pending &= pending - 1;
+          const uint32_t jj = __shfl(j, src), nn = __shfl(n, src);
+          const uint32_t r = exact_element_wave<D>(rc, m, emask, t, jj, nn, lane);
+          if (lane == src) res = r;
+        }
+        if (live) ((uint32_t*)out)[row * (N + 1) + n] = res;
       }
-      if (live) ((uint32_t*)out)[row * (N + 1) + n] = res;
     }
   }
 }
