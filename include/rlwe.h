@@ -126,6 +126,42 @@ int ct_matmul_clear(rlwe_ctx* ctx, const rlwe_weights* w, uint32_t transpose,
                     const uint64_t* ct_in, uint32_t tokens, void* out, uint32_t flags,
                     rlwe_stream_t stream);
 
+/* One product of a batch: W.[x] (transpose = 0) or W^T.[g] (transpose = 1) for
+ * `tokens` inputs; ct_in and out are device buffers laid out as for
+ * ct_matmul_clear. */
+typedef struct ct_matmul_desc {
+  const rlwe_weights* w;
+  uint32_t transpose;
+  const uint64_t* ct_in;
+  uint32_t tokens;
+  void* out;
+} ct_matmul_desc;
+
+/* Several products of Eq. (LWEdot) with different weights and token counts
+ * (e.g. all projections of a transformer layer, forward and transposed) in
+ * grouped launches: one preparation launch, one matrix-core launch per number of
+ * kept digits, one body launch, for every 16 descriptors. `descs` is a host
+ * array of n descriptors; flags as for ct_matmul_clear and applied to all. The
+ * products with the longest contraction are scheduled first. Results are the
+ * same bits as n separate ct_matmul_clear calls. Asynchronous; allocates only if
+ * the context workspace is smaller than rlwe_batch_workspace_bytes (refused with
+ * RLWE_EINVAL while the stream is being captured). */
+int ct_matmul_batch(rlwe_ctx* ctx, const ct_matmul_desc* descs, uint32_t n, uint32_t flags,
+                    rlwe_stream_t stream);
+
+/* Workspace bytes ct_matmul_batch needs for these descriptors (0 on bad input). */
+size_t rlwe_batch_workspace_bytes(const rlwe_ctx* ctx, const ct_matmul_desc* descs, uint32_t n);
+
+/* A batch captured once into a HIP graph with its own workspace, for replay:
+ * rlwe_graph_capture_batch records ct_matmul_batch(descs) (the descriptors'
+ * buffers are baked into the graph and must stay valid); rlwe_graph_launch
+ * replays it on `stream`; rlwe_graph_destroy frees it (after its work is done). */
+typedef struct rlwe_graph rlwe_graph;
+int rlwe_graph_capture_batch(rlwe_ctx* ctx, const ct_matmul_desc* descs, uint32_t n,
+                             uint32_t flags, rlwe_graph** out);
+int rlwe_graph_launch(rlwe_graph* g, rlwe_stream_t stream);
+int rlwe_graph_destroy(rlwe_graph* g);
+
 /* ModulusSwitch q -> 2^32 (Sec. 3.2) of `count` vectors of N+1 coefficients:
  *   in   device, uint64 [count][P][N+1] canonical residues
  *   out  device, uint32 [count][N+1], round(c * 2^32 / q) mod 2^32 with

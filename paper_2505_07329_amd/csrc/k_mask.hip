@@ -109,10 +109,7 @@ __device__ inline v4i toeplitz_frag(const uint32_t* p) {
 // wave finishes a share of the elements.
 template <int D, int DK, bool RAW>
 __global__ void __launch_bounds__(64 * ((DK + 2) / 3)) __attribute__((amdgpu_waves_per_eu(3)))
-mask_kernel(RingConst rc, SwitchConst sc,
-                                                                   MatArgs m,
-                                                                   const int8_t* __restrict__ emask,
-                                                                   void* out, int force_exact) {
+mask_kernel(RingConst rc, Batch bt) {
   static_assert(!RAW || DK == D, "raw output keeps every digit");
   constexpr int NW = (DK + 2) / 3;
   constexpr int DPW = 3;
@@ -128,12 +125,24 @@ mask_kernel(RingConst rc, SwitchConst sc,
   uint32_t(*wt)[kWRowWords] = reinterpret_cast<uint32_t(*)[kWRowWords]>(smem + kWinLds);
   int64_t* part = reinterpret_cast<int64_t*>(smem);
 
+  const uint32_t blk = linear_block();
+  if (blk >= bt.mask_start[bt.n]) return;
+  const uint32_t ii = find_item(bt.mask_start, bt.n, blk);
+  const MatArgs& m = bt.it[ii].m;
+  const SwitchConst& sc = bt.it[ii].sc;
+  const int8_t* __restrict__ emask = bt.it[ii].emask;
+  void* out = bt.it[ii].out;
+  const int force_exact = bt.force_exact;
   const uint32_t N = rc.N;
-  const uint32_t t = blockIdx.z;
-  const uint32_t n0 = blockIdx.x * 64, jb = blockIdx.y * 32;
+  // tile order: column tiles fastest, then row tiles, then tokens
+  const uint32_t ntn = N / 64, ntj = m.rows_pad / 32;
+  const uint32_t loc = blk - bt.mask_start[ii];
+  const uint32_t tn = loc % ntn, tj = (loc / ntn) % ntj;
+  const uint32_t t = loc / (ntn * ntj);
+  const uint32_t n0 = tn * 64, jb = tj * 32;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int c = lane & 31, g = lane >> 5;
-  const int role = (wave + blockIdx.x + blockIdx.y) % NW;
+  const int role = (wave + tn + tj) % NW;
   const int cnt = (DK % NW == 0) ? DK / NW : DK / NW + (role < DK % NW ? 1 : 0);
   const int dlo = role * (DK / NW) + min(role, DK % NW);
   const uint32_t l0 = D - DK;
@@ -268,36 +277,31 @@ mask_kernel(RingConst rc, SwitchConst sc,
 }
 
 template <int D, int DK, bool RAW>
-static void launch_one(const RingConst& rc, const SwitchConst& sc, const MatArgs& m,
-                       const int8_t* emask, uint32_t T, void* out, int force, hipStream_t s) {
-  const dim3 grid(rc.N / 64, m.rows_pad / 32, T);
-  hipLaunchKernelGGL((mask_kernel<D, DK, RAW>), grid, dim3(64 * ((DK + 2) / 3)), 0, s, rc, sc, m,
-                     emask, out, force);
+static void launch_one(const RingConst& rc, const Batch& b, hipStream_t s) {
+  hipLaunchKernelGGL((mask_kernel<D, DK, RAW>), grid_for(b.mask_start[b.n]),
+                     dim3(64 * ((DK + 2) / 3)), 0, s, rc, b);
 }
 
-hipError_t launch_mask(const RingConst& rc, const SwitchConst& sc, const MatArgs& m,
-                       const int8_t* emask, uint32_t T, void* out, bool raw, bool force_exact,
-                       hipStream_t s) {
-  if (T == 0) return hipSuccess;
-  const int f = force_exact ? 1 : 0;
+hipError_t launch_mask(const RingConst& rc, const Batch& b, uint32_t dk, hipStream_t s) {
+  if (b.n == 0 || b.mask_start[b.n] == 0) return hipSuccess;
   if (rc.D == 7) {
-    if (raw)
-      launch_one<7, 7, true>(rc, sc, m, emask, T, out, f, s);
-    else if (sc.dk == 7)
-      launch_one<7, 7, false>(rc, sc, m, emask, T, out, f, s);
+    if (b.raw)
+      launch_one<7, 7, true>(rc, b, s);
+    else if (dk == 7)
+      launch_one<7, 7, false>(rc, b, s);
     else
       return hipErrorInvalidValue;
   } else {
-    if (raw) {
-      launch_one<14, 14, true>(rc, sc, m, emask, T, out, f, s);
+    if (b.raw) {
+      launch_one<14, 14, true>(rc, b, s);
     } else {
-      switch (sc.dk) {
-        case 8: launch_one<14, 8, false>(rc, sc, m, emask, T, out, f, s); break;
-        case 9: launch_one<14, 9, false>(rc, sc, m, emask, T, out, f, s); break;
-        case 10: launch_one<14, 10, false>(rc, sc, m, emask, T, out, f, s); break;
-        case 11: launch_one<14, 11, false>(rc, sc, m, emask, T, out, f, s); break;
-        case 12: launch_one<14, 12, false>(rc, sc, m, emask, T, out, f, s); break;
-        case 14: launch_one<14, 14, false>(rc, sc, m, emask, T, out, f, s); break;
+      switch (dk) {
+        case 8: launch_one<14, 8, false>(rc, b, s); break;
+        case 9: launch_one<14, 9, false>(rc, b, s); break;
+        case 10: launch_one<14, 10, false>(rc, b, s); break;
+        case 11: launch_one<14, 11, false>(rc, b, s); break;
+        case 12: launch_one<14, 12, false>(rc, b, s); break;
+        case 14: launch_one<14, 14, false>(rc, b, s); break;
         default: return hipErrorInvalidValue;
       }
     }

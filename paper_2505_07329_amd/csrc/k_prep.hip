@@ -57,15 +57,18 @@ __device__ inline void digits255(i128 v, int8_t* d) {
 }
 
 template <int D>
-__global__ void __launch_bounds__(256) prep_kernel(RingConst rc, PrepArgs a) {
-  const uint32_t N = rc.N, P = rc.P;
-  const size_t total = (size_t)a.T * a.L * N;
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
+__global__ void __launch_bounds__(256) prep_kernel(RingConst rc, Batch bt) {
+  const uint32_t blk = linear_block();
+  if (blk >= bt.prep_start[bt.n]) return;
+  const uint32_t ii = find_item(bt.prep_start, bt.n, blk);
+  const Item& a = bt.it[ii];
+  const uint32_t N = rc.N, P = rc.P, L = a.m.L;
+  const size_t idx = (size_t)(blk - bt.prep_start[ii]) * 256 + threadIdx.x;
+  if (idx >= (size_t)a.T * L * N) return;
   const uint32_t k = (uint32_t)(idx % N);
   const size_t ti = idx / N;  // t * L + i
-  const uint32_t i = (uint32_t)(ti % a.L);
-  const uint32_t t = (uint32_t)(ti / a.L);
+  const uint32_t i = (uint32_t)(ti % L);
+  const uint32_t t = (uint32_t)(ti / L);
   const uint64_t* A = a.ct + (ti * 2 + 0) * P * N;
   const uint64_t* B = a.ct + (ti * 2 + 1) * P * N;
   int8_t da[D], db[D];
@@ -73,7 +76,7 @@ __global__ void __launch_bounds__(256) prep_kernel(RingConst rc, PrepArgs a) {
   digits255<D>(lift_centered(rc, B[k], P > 1 ? B[N + k] : 0), db);
 #pragma unroll
   for (int l = 0; l < D; ++l) {
-    const size_t plane = ((size_t)t * D + l) * a.L + i;
+    const size_t plane = ((size_t)t * D + l) * L + i;
     int8_t* em = a.emask + plane * 2 * N;
     em[N + k] = da[l];
     em[k] = (int8_t)(-da[l]);
@@ -81,25 +84,29 @@ __global__ void __launch_bounds__(256) prep_kernel(RingConst rc, PrepArgs a) {
   }
 }
 
-hipError_t launch_prep(const RingConst& rc, const PrepArgs& a, hipStream_t s) {
-  const size_t total = (size_t)a.T * a.L * rc.N;
-  if (total == 0) return hipSuccess;
-  const dim3 grid((unsigned)((total + 255) / 256));
+hipError_t launch_prep(const RingConst& rc, const Batch& b, hipStream_t s) {
+  const uint32_t blocks = b.prep_start[b.n];
+  if (blocks == 0) return hipSuccess;
   if (rc.D == 7)
-    hipLaunchKernelGGL(prep_kernel<7>, grid, dim3(256), 0, s, rc, a);
+    hipLaunchKernelGGL(prep_kernel<7>, grid_for(blocks), dim3(256), 0, s, rc, b);
   else
-    hipLaunchKernelGGL(prep_kernel<14>, grid, dim3(256), 0, s, rc, a);
+    hipLaunchKernelGGL(prep_kernel<14>, grid_for(blocks), dim3(256), 0, s, rc, b);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- body
 
 template <int D, bool RAW>
-__global__ void __launch_bounds__(256) body_kernel(RingConst rc, MatArgs m, const int8_t* ebody,
-                                                   void* out) {
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t t = blockIdx.y;
-  if (j >= m.rows) return;
+__global__ void __launch_bounds__(256) body_kernel(RingConst rc, Batch bt) {
+  const uint32_t blk = linear_block();
+  if (blk >= bt.body_start[bt.n]) return;
+  const uint32_t ii = find_item(bt.body_start, bt.n, blk);
+  const Item& a = bt.it[ii];
+  const MatArgs& m = a.m;
+  const size_t idx = (size_t)(blk - bt.body_start[ii]) * 256 + threadIdx.x;
+  if (idx >= (size_t)a.T * m.rows) return;
+  const uint32_t j = (uint32_t)(idx % m.rows);
+  const uint32_t t = (uint32_t)(idx / m.rows);
   const uint32_t N = rc.N;
   int32_t S[D];
 #pragma unroll
@@ -112,7 +119,7 @@ __global__ void __launch_bounds__(256) body_kernel(RingConst rc, MatArgs m, cons
       const int w4 = *(const int*)(wrow + k);
 #pragma unroll
       for (int l = 0; l < D; ++l) {
-        const int e4 = *(const int*)(ebody + (((size_t)t * D + l) * m.L + i) * N + k);
+        const int e4 = *(const int*)(a.ebody + (((size_t)t * D + l) * m.L + i) * N + k);
         S[l] = __builtin_amdgcn_sdot4(w4, e4, S[l], false);
       }
     }
@@ -122,27 +129,27 @@ __global__ void __launch_bounds__(256) body_kernel(RingConst rc, MatArgs m, cons
   for (int l = D - 1; l >= 0; --l) V = V * 255 + S[l];
   const size_t row = (size_t)t * m.rows + j;
   if (RAW) {
-    uint64_t* o = (uint64_t*)out;
+    uint64_t* o = (uint64_t*)a.out;
     for (uint32_t p = 0; p < rc.P; ++p) o[(row * rc.P + p) * (N + 1) + N] = mod_i128(V, rc.q[p]);
   } else {
-    ((uint32_t*)out)[row * (N + 1) + N] = switch_exact(V, rc);
+    ((uint32_t*)a.out)[row * (N + 1) + N] = switch_exact(V, rc);
   }
 }
 
-hipError_t launch_body(const RingConst& rc, const MatArgs& m, const int8_t* ebody, uint32_t T,
-                       void* out, bool raw, hipStream_t s) {
-  if (T == 0) return hipSuccess;
-  const dim3 grid((m.rows + 255) / 256, T);
+hipError_t launch_body(const RingConst& rc, const Batch& b, hipStream_t s) {
+  const uint32_t blocks = b.body_start[b.n];
+  if (blocks == 0) return hipSuccess;
+  const dim3 grid = grid_for(blocks);
   if (rc.D == 7) {
-    if (raw)
-      hipLaunchKernelGGL((body_kernel<7, true>), grid, dim3(256), 0, s, rc, m, ebody, out);
+    if (b.raw)
+      hipLaunchKernelGGL((body_kernel<7, true>), grid, dim3(256), 0, s, rc, b);
     else
-      hipLaunchKernelGGL((body_kernel<7, false>), grid, dim3(256), 0, s, rc, m, ebody, out);
+      hipLaunchKernelGGL((body_kernel<7, false>), grid, dim3(256), 0, s, rc, b);
   } else {
-    if (raw)
-      hipLaunchKernelGGL((body_kernel<14, true>), grid, dim3(256), 0, s, rc, m, ebody, out);
+    if (b.raw)
+      hipLaunchKernelGGL((body_kernel<14, true>), grid, dim3(256), 0, s, rc, b);
     else
-      hipLaunchKernelGGL((body_kernel<14, false>), grid, dim3(256), 0, s, rc, m, ebody, out);
+      hipLaunchKernelGGL((body_kernel<14, false>), grid, dim3(256), 0, s, rc, b);
   }
   return hipGetLastError();
 }
@@ -152,7 +159,7 @@ hipError_t launch_body(const RingConst& rc, const MatArgs& m, const int8_t* ebod
 __global__ void __launch_bounds__(256) modswitch_kernel(RingConst rc, const uint64_t* in,
                                                         size_t count, uint32_t* out) {
   const uint32_t len = rc.N + 1;
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t idx = (size_t)linear_block() * blockDim.x + threadIdx.x;
   if (idx >= count * len) return;
   const size_t c = idx / len;
   const uint32_t n = (uint32_t)(idx % len);
@@ -174,8 +181,9 @@ hipError_t launch_modswitch(const RingConst& rc, const uint64_t* in, size_t coun
                             hipStream_t s) {
   const size_t total = count * (rc.N + 1);
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(modswitch_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, rc,
-                     in, count, out);
+  if ((total + 255) / 256 >= (1ull << 31)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(modswitch_kernel, grid_for((uint32_t)((total + 255) / 256)), dim3(256), 0, s,
+                     rc, in, count, out);
   return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 
@@ -105,6 +106,9 @@ template <class F>
 hipError_t timed(rlwe_ctx* ctx, int kind, hipStream_t s, F launch) {
   Profiler* p = ctx->prof;
   if (!p || !p->on) return launch();
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    return launch();  // no events inside a captured graph
   if (p->used >= kMaxProfiled) {
     ++p->dropped;
     return launch();
@@ -214,7 +218,8 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(RLWE_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-size_t ws_need(const RingConst& rc, const MatArgs& m, uint32_t T) {
+// Workspace of one product: mask digit planes then body digit planes.
+size_t ws_item(const RingConst& rc, const MatArgs& m, uint32_t T) {
   const size_t em = align_up((size_t)T * rc.D * m.L * 2 * rc.N, 256);
   const size_t eb = align_up((size_t)T * rc.D * m.L * rc.N, 256);
   return em + eb;
@@ -460,7 +465,7 @@ size_t rlwe_workspace_bytes(const rlwe_ctx* ctx, const rlwe_weights* w, uint32_t
   if (!ctx || !w) return 0;
   const Mat& m = transpose ? w->tr : w->fwd;
   if (!m.present) return 0;
-  return ws_need(ctx->rc, m.args, tokens);
+  return ws_item(ctx->rc, m.args, tokens);
 }
 
 int rlwe_weights_digits(const rlwe_weights* w, uint32_t transpose, uint32_t* kept,
@@ -481,44 +486,235 @@ int rlwe_workspace_reserve(rlwe_ctx* ctx, size_t bytes) {
   return r == RLWE_OK ? ok() : r;
 }
 
+static int validate_desc(const rlwe_ctx* ctx, const ct_matmul_desc& d, const Mat** out) {
+  if (!d.w) return fail(RLWE_EINVAL, "ct_matmul: null weights");
+  if (d.w->ctx != ctx) return fail(RLWE_EINVAL, "ct_matmul: weights belong to another context");
+  if (d.transpose > 1) return fail(RLWE_EINVAL, "ct_matmul: transpose must be 0 or 1");
+  const Mat& m = d.transpose ? d.w->tr : d.w->fwd;
+  if (!m.present)
+    return fail(RLWE_EINVAL, "ct_matmul: weights were loaded without %s",
+                d.transpose ? "RLWE_W_TRANSPOSE" : "RLWE_W_FWD");
+  if (d.tokens > 65535) return fail(RLWE_ESHAPE, "tokens = %u exceeds 65535 per product", d.tokens);
+  if (d.tokens && (!d.ct_in || !d.out)) return fail(RLWE_EINVAL, "ct_matmul: null buffer");
+  const RingConst& rc = ctx->rc;
+  if ((uint64_t)d.tokens * (m.args.rows_pad / 32) * (rc.N / 64) >= (1ull << 31) ||
+      (uint64_t)d.tokens * m.args.L * rc.N / 256 >= (1ull << 31))
+    return fail(RLWE_ESHAPE, "ct_matmul: product too large for one launch; split the tokens");
+  *out = &m;
+  return RLWE_OK;
+}
+
+static size_t batch_ws(const rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n) {
+  size_t total = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    const Mat& m = d[i].transpose ? d[i].w->tr : d[i].w->fwd;
+    total += ws_item(ctx->rc, m.args, d[i].tokens);
+  }
+  return total;
+}
+
+// Enqueue a validated batch using workspace `ws` (at least batch_ws bytes).
+static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_t flags,
+                     hipStream_t s, unsigned char* ws) {
+  const RingConst& rc = ctx->rc;
+  const bool raw = flags & RLWE_OUT_RAW_Q;
+  // longest contraction first: its tiles are the most expensive (tail balance)
+  uint32_t order[kMaxBatch];
+  uint32_t cnt = 0;
+  for (uint32_t i = 0; i < n; ++i)
+    if (d[i].tokens) order[cnt++] = i;
+  const Mat* mats[kMaxBatch];
+  for (uint32_t i = 0; i < n; ++i) mats[i] = d[i].transpose ? &d[i].w->tr : &d[i].w->fwd;
+  for (uint32_t a = 1; a < cnt; ++a)
+    for (uint32_t b = a; b > 0 && mats[order[b]]->args.k > mats[order[b - 1]]->args.k; --b) {
+      const uint32_t tmp = order[b];
+      order[b] = order[b - 1];
+      order[b - 1] = tmp;
+    }
+  if (cnt == 0) return RLWE_OK;
+  Batch all{};
+  all.raw = raw;
+  all.force_exact = (flags & RLWE_OUT_FORCE_EXACT) ? 1 : 0;
+  size_t off = 0;
+  for (uint32_t x = 0; x < cnt; ++x) {
+    const ct_matmul_desc& dd = d[order[x]];
+    const Mat& m = *mats[order[x]];
+    Item& it = all.it[x];
+    it.m = m.args;
+    it.sc = m.sc;
+    if (raw) {
+      it.sc.l0 = 0;
+      it.sc.dk = rc.D;
+    }
+    it.ct = dd.ct_in;
+    it.emask = (int8_t*)(ws + off);
+    it.ebody = (int8_t*)(ws + off + align_up((size_t)dd.tokens * rc.D * m.args.L * 2 * rc.N, 256));
+    off += ws_item(rc, m.args, dd.tokens);
+    it.out = dd.out;
+    it.T = dd.tokens;
+    all.prep_start[x + 1] = all.prep_start[x] + (uint32_t)(((size_t)dd.tokens * m.args.L * rc.N + 255) / 256);
+    all.body_start[x + 1] = all.body_start[x] + (uint32_t)(((size_t)dd.tokens * m.args.rows + 255) / 256);
+  }
+  all.n = cnt;
+  hipError_t e = timed(ctx, K_PREP, s, [&] { return launch_prep(rc, all, s); });
+  if (e != hipSuccess) return hip_fail(e, "prep kernel");
+  // one mask launch per distinct number of kept digits
+  bool done[kMaxBatch] = {};
+  for (uint32_t x = 0; x < cnt; ++x) {
+    if (done[x]) continue;
+    const uint32_t dk = all.it[x].sc.dk;
+    Batch mb{};
+    mb.raw = all.raw;
+    mb.force_exact = all.force_exact;
+    for (uint32_t y = x; y < cnt; ++y) {
+      if (done[y] || all.it[y].sc.dk != dk) continue;
+      done[y] = true;
+      const Item& it = all.it[y];
+      mb.it[mb.n] = it;
+      mb.mask_start[mb.n + 1] = mb.mask_start[mb.n] + it.T * (it.m.rows_pad / 32) * (rc.N / 64);
+      ++mb.n;
+    }
+    e = timed(ctx, K_MASK, s, [&] { return launch_mask(rc, mb, dk, s); });
+    if (e != hipSuccess) return hip_fail(e, "mask kernel");
+  }
+  e = timed(ctx, K_BODY, s, [&] { return launch_body(rc, all, s); });
+  if (e != hipSuccess) return hip_fail(e, "body kernel");
+  return RLWE_OK;
+}
+
+int ct_matmul_batch(rlwe_ctx* ctx, const ct_matmul_desc* descs, uint32_t n, uint32_t flags,
+                    rlwe_stream_t stream) {
+  if (!ctx) return fail(RLWE_EINVAL, "ct_matmul_batch: null context");
+  if (n == 0) return ok();
+  if (!descs) return fail(RLWE_EINVAL, "ct_matmul_batch: null descriptors");
+  if (flags & ~(RLWE_OUT_RAW_Q | RLWE_OUT_FORCE_EXACT))
+    return fail(RLWE_EINVAL, "ct_matmul_batch: unknown flags 0x%x", flags);
+  for (uint32_t i = 0; i < n; ++i) {
+    const Mat* m;
+    const int r = validate_desc(ctx, descs[i], &m);
+    if (r != RLWE_OK) return r;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  // workspace for the largest group of kMaxBatch products
+  size_t need = 0;
+  for (uint32_t i = 0; i < n; i += kMaxBatch)
+    need = std::max(need, batch_ws(ctx, descs + i, std::min<uint32_t>(kMaxBatch, n - i)));
+  if (need > ctx->ws_bytes) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+      return fail(RLWE_EINVAL, "workspace must be reserved (rlwe_workspace_reserve) before capture");
+    const int r = ensure_ws(ctx, need, s);
+    if (r != RLWE_OK) return r;
+  }
+  for (uint32_t i = 0; i < n; i += kMaxBatch) {
+    const int r = run_batch(ctx, descs + i, std::min<uint32_t>(kMaxBatch, n - i), flags, s,
+                            (unsigned char*)ctx->ws);
+    if (r != RLWE_OK) return r;
+  }
+  return ok();
+}
+
 int ct_matmul_clear(rlwe_ctx* ctx, const rlwe_weights* w, uint32_t transpose,
                     const uint64_t* ct_in, uint32_t tokens, void* out, uint32_t flags,
                     rlwe_stream_t stream) {
   if (!ctx || !w) return fail(RLWE_EINVAL, "ct_matmul_clear: null context or weights");
-  if (w->ctx != ctx) return fail(RLWE_EINVAL, "ct_matmul_clear: weights belong to another context");
+  ct_matmul_desc d{};
+  d.w = w;
+  d.transpose = transpose;
+  d.ct_in = ct_in;
+  d.tokens = tokens;
+  d.out = out;
+  return ct_matmul_batch(ctx, &d, 1, flags, stream);
+}
+
+size_t rlwe_batch_workspace_bytes(const rlwe_ctx* ctx, const ct_matmul_desc* descs, uint32_t n) {
+  if (!ctx || !descs) return 0;
+  size_t need = 0;
+  for (uint32_t i = 0; i < n; ++i)
+    if (!descs[i].w || (descs[i].transpose ? !descs[i].w->tr.present : !descs[i].w->fwd.present))
+      return 0;
+  for (uint32_t i = 0; i < n; i += kMaxBatch)
+    need = std::max(need, batch_ws(ctx, descs + i, std::min<uint32_t>(kMaxBatch, n - i)));
+  return need;
+}
+
+struct rlwe_graph {
+  rlwe_ctx* ctx = nullptr;
+  void* ws = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+int rlwe_graph_capture_batch(rlwe_ctx* ctx, const ct_matmul_desc* descs, uint32_t n,
+                             uint32_t flags, rlwe_graph** out) {
+  if (!ctx || !descs || !out || n == 0) return fail(RLWE_EINVAL, "rlwe_graph_capture_batch: bad argument");
+  *out = nullptr;
   if (flags & ~(RLWE_OUT_RAW_Q | RLWE_OUT_FORCE_EXACT))
-    return fail(RLWE_EINVAL, "ct_matmul_clear: unknown flags 0x%x", flags);
-  if (transpose > 1) return fail(RLWE_EINVAL, "ct_matmul_clear: transpose must be 0 or 1");
-  const Mat& m = transpose ? w->tr : w->fwd;
-  if (!m.present)
-    return fail(RLWE_EINVAL, "ct_matmul_clear: weights were loaded without %s",
-                transpose ? "RLWE_W_TRANSPOSE" : "RLWE_W_FWD");
-  if (tokens == 0) return ok();
-  if (!ct_in || !out) return fail(RLWE_EINVAL, "ct_matmul_clear: null buffer");
-  if (tokens > 65535) return fail(RLWE_ESHAPE, "tokens = %u exceeds 65535 per call", tokens);
-  const bool raw = flags & RLWE_OUT_RAW_Q;
-  hipStream_t s = (hipStream_t)stream;
+    return fail(RLWE_EINVAL, "rlwe_graph_capture_batch: unknown flags 0x%x", flags);
+  for (uint32_t i = 0; i < n; ++i) {
+    const Mat* m;
+    const int r = validate_desc(ctx, descs[i], &m);
+    if (r != RLWE_OK) return r;
+  }
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  const RingConst& rc = ctx->rc;
-  const size_t need = ws_need(rc, m.args, tokens);
-  int r = ensure_ws(ctx, need, s);
-  if (r != RLWE_OK) return r;
-  PrepArgs pa{};
-  pa.ct = ct_in;
-  pa.emask = (int8_t*)ctx->ws;
-  pa.ebody = (int8_t*)ctx->ws + align_up((size_t)tokens * rc.D * m.args.L * 2 * rc.N, 256);
-  pa.T = tokens;
-  pa.L = m.args.L;
-  e = timed(ctx, K_PREP, s, [&] { return launch_prep(rc, pa, s); });
-  if (e != hipSuccess) return hip_fail(e, "prep kernel");
-  const bool force = flags & RLWE_OUT_FORCE_EXACT;
-  e = timed(ctx, K_MASK, s, [&] {
-    return launch_mask(rc, m.sc, m.args, pa.emask, tokens, out, raw, force, s);
-  });
-  if (e != hipSuccess) return hip_fail(e, "mask kernel");
-  e = timed(ctx, K_BODY, s, [&] { return launch_body(rc, m.args, pa.ebody, tokens, out, raw, s); });
-  if (e != hipSuccess) return hip_fail(e, "body kernel");
+  rlwe_graph* g = new (std::nothrow) rlwe_graph;
+  if (!g) return fail(RLWE_ENOMEM, "out of host memory");
+  g->ctx = ctx;
+  size_t need = 0;
+  for (uint32_t i = 0; i < n; i += kMaxBatch)
+    need = std::max(need, batch_ws(ctx, descs + i, std::min<uint32_t>(kMaxBatch, n - i)));
+  if (need && hipMalloc(&g->ws, need) != hipSuccess) {
+    delete g;
+    return fail(RLWE_ENOMEM, "hipMalloc(graph workspace, %zu bytes)", need);
+  }
+  hipStream_t cs = nullptr;
+  e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  int r = RLWE_OK;
+  Profiler* prof = ctx->prof;
+  const bool was_on = prof && prof->on;
+  if (prof) prof->on = false;  // no events inside a captured graph
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (uint32_t i = 0; i < n && r == RLWE_OK; i += kMaxBatch)
+      r = run_batch(ctx, descs + i, std::min<uint32_t>(kMaxBatch, n - i), flags, cs,
+                    (unsigned char*)g->ws);
+    const hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
+    if (r == RLWE_OK && e2 != hipSuccess) e = e2;
+  }
+  if (prof) prof->on = was_on;
+  if (r == RLWE_OK && e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (cs) hipStreamDestroy(cs);
+  if (r != RLWE_OK || e != hipSuccess) {
+    const std::string msg = r != RLWE_OK ? g_err : std::string("graph capture: ") + hipGetErrorString(e);
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    if (g->ws) hipFree(g->ws);
+    delete g;
+    g_err = msg;
+    return r != RLWE_OK ? r : RLWE_EHIP;
+  }
+  *out = g;
+  return ok();
+}
+
+int rlwe_graph_launch(rlwe_graph* g, rlwe_stream_t stream) {
+  if (!g) return fail(RLWE_EINVAL, "rlwe_graph_launch: null graph");
+  hipError_t e = hipSetDevice(g->ctx->device);
+  if (e == hipSuccess) e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return ok();
+}
+
+int rlwe_graph_destroy(rlwe_graph* g) {
+  if (!g) return ok();
+  hipSetDevice(g->ctx->device);
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  if (g->ws) hipFree(g->ws);
+  delete g;
   return ok();
 }
 

@@ -90,13 +90,6 @@ __device__ inline uint64_t mulmod_shoup(uint64_t a, uint64_t w, uint64_t wp, uin
 
 // ---------------------------------------------------------------- launchers
 
-struct PrepArgs {
-  const uint64_t* ct;   // [T][L][2][P][N]
-  int8_t* emask;        // [T][D][L][2N]: per digit plane, index m <-> Toeplitz offset m - N
-  int8_t* ebody;        // [T][D][L][N]
-  uint32_t T, L;
-};
-
 struct MatArgs {
   const int8_t* w;      // resident weights [rows_pad][kw], zero padded
   uint32_t rows;        // outputs M
@@ -106,12 +99,50 @@ struct MatArgs {
   uint32_t L;           // input blocks
 };
 
-hipError_t launch_prep(const RingConst& rc, const PrepArgs& a, hipStream_t s);
-hipError_t launch_mask(const RingConst& rc, const SwitchConst& sc, const MatArgs& m,
-                       const int8_t* emask, uint32_t T, void* out, bool raw, bool force_exact,
-                       hipStream_t s);
-hipError_t launch_body(const RingConst& rc, const MatArgs& m, const int8_t* ebody, uint32_t T,
-                       void* out, bool raw, hipStream_t s);
+// One product of a batch: weights, input ciphertexts, workspace planes, output.
+struct Item {
+  MatArgs m;
+  SwitchConst sc;
+  const uint64_t* ct;  // [T][L][2][P][N]
+  int8_t* emask;       // [T][D][L][2N]: per digit plane, index m <-> Toeplitz offset m - N
+  int8_t* ebody;       // [T][D][L][N]
+  void* out;           // switched u32 [T][M][N+1] or raw u64 [T][M][P][N+1]
+  uint32_t T;
+};
+
+constexpr int kMaxBatch = 16;
+
+// A batch of products launched together; every kernel maps its linear block index
+// onto (item, local block) through the prefix sums below. Passed by value.
+struct Batch {
+  uint32_t n;
+  uint32_t raw;
+  uint32_t force_exact;
+  uint32_t prep_start[kMaxBatch + 1];  // blocks of 256 threads over T*L*N coefficients
+  uint32_t mask_start[kMaxBatch + 1];  // workgroups over T * rows_pad/32 * N/64 tiles
+  uint32_t body_start[kMaxBatch + 1];  // blocks of 256 threads over T * rows
+  Item it[kMaxBatch];
+};
+
+// Linear block index of a 2D grid (grids are split over y to keep x * block < 2^32).
+__device__ inline uint32_t linear_block() { return blockIdx.y * gridDim.x + blockIdx.x; }
+
+// Item owning linear block b (uniform per workgroup).
+__device__ inline uint32_t find_item(const uint32_t* start, uint32_t n, uint32_t b) {
+  uint32_t i = 0;
+  while (i + 1 < n && b >= start[i + 1]) ++i;
+  return i;
+}
+
+// 2D grid covering `blocks` blocks of `threads` threads.
+inline dim3 grid_for(uint32_t blocks) {
+  const uint32_t x = blocks < 32768u ? blocks : 32768u;
+  return dim3(x, (blocks + x - 1) / x);
+}
+
+hipError_t launch_prep(const RingConst& rc, const Batch& b, hipStream_t s);
+hipError_t launch_mask(const RingConst& rc, const Batch& b, uint32_t dk, hipStream_t s);
+hipError_t launch_body(const RingConst& rc, const Batch& b, hipStream_t s);
 hipError_t launch_modswitch(const RingConst& rc, const uint64_t* in, size_t count, uint32_t* out,
                             hipStream_t s);
 hipError_t launch_transpose_pad(const int8_t* src, uint32_t rows, uint32_t cols, bool transpose,

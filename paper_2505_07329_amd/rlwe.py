@@ -29,7 +29,9 @@ RLWE_OUT_FORCE_EXACT = 2
 
 EXPORTS = ("rlwe_params_init", "rlwe_params_destroy", "rlwe_weights_load", "rlwe_weights_free",
            "ct_matmul_clear", "ct_modswitch", "rlwe_workspace_bytes", "rlwe_workspace_reserve",
-           "rlwe_profile_begin", "rlwe_profile_end", "rlwe_weights_digits", "rlwe_last_error")
+           "rlwe_profile_begin", "rlwe_profile_end", "rlwe_weights_digits", "ct_matmul_batch",
+           "rlwe_batch_workspace_bytes", "rlwe_graph_capture_batch", "rlwe_graph_launch",
+           "rlwe_graph_destroy", "rlwe_last_error")
 
 
 class RlweError(RuntimeError):
@@ -47,6 +49,11 @@ class KernelTimes(ctypes.Structure):
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class CtMatmulDesc(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p), ("transpose", ctypes.c_uint32),
+                ("ct_in", ctypes.c_void_p), ("tokens", ctypes.c_uint32), ("out", ctypes.c_void_p)]
 
 
 class _Params(ctypes.Structure):
@@ -82,9 +89,17 @@ def lib() -> ctypes.CDLL:
     L.rlwe_profile_end.argtypes = [vp, ctypes.POINTER(KernelTimes)]
     L.rlwe_weights_digits.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
                                       ctypes.POINTER(ctypes.c_uint32)]
+    L.ct_matmul_batch.argtypes = [vp, ctypes.POINTER(CtMatmulDesc), ctypes.c_uint32,
+                                  ctypes.c_uint32, vp]
+    L.rlwe_batch_workspace_bytes.argtypes = [vp, ctypes.POINTER(CtMatmulDesc), ctypes.c_uint32]
+    L.rlwe_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.rlwe_graph_capture_batch.argtypes = [vp, ctypes.POINTER(CtMatmulDesc), ctypes.c_uint32,
+                                           ctypes.c_uint32, ctypes.POINTER(vp)]
+    L.rlwe_graph_launch.argtypes = [vp, vp]
+    L.rlwe_graph_destroy.argtypes = [vp]
     L.rlwe_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name != "rlwe_last_error" and name != "rlwe_workspace_bytes":
+        if name not in ("rlwe_last_error", "rlwe_workspace_bytes", "rlwe_batch_workspace_bytes"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -164,6 +179,39 @@ def rlwe_weights_digits(w: int, transpose: bool = False) -> tuple[int, int]:
     kept, total = ctypes.c_uint32(), ctypes.c_uint32()
     _check(lib().rlwe_weights_digits(w, int(bool(transpose)), ctypes.byref(kept), ctypes.byref(total)))
     return kept.value, total.value
+
+
+def _descs(items):
+    """items: sequence of (weights_handle, transpose, ct_tensor, tokens, out_tensor)."""
+    arr = (CtMatmulDesc * len(items))()
+    for i, (w, tr, ct, tokens, out) in enumerate(items):
+        arr[i] = CtMatmulDesc(w, int(bool(tr)), _ptr(ct), tokens, _ptr(out))
+    return arr
+
+
+def ct_matmul_batch(ctx: int, items, flags: int = RLWE_OUT_SWITCHED, stream=None) -> None:
+    arr = _descs(items)
+    _check(lib().ct_matmul_batch(ctx, arr, len(items), flags, _stream(stream)))
+
+
+def rlwe_batch_workspace_bytes(ctx: int, items) -> int:
+    arr = _descs(items)
+    return int(lib().rlwe_batch_workspace_bytes(ctx, arr, len(items)))
+
+
+def rlwe_graph_capture_batch(ctx: int, items, flags: int = RLWE_OUT_SWITCHED) -> int:
+    arr = _descs(items)
+    h = ctypes.c_void_p()
+    _check(lib().rlwe_graph_capture_batch(ctx, arr, len(items), flags, ctypes.byref(h)))
+    return h.value
+
+
+def rlwe_graph_launch(graph: int, stream=None) -> None:
+    _check(lib().rlwe_graph_launch(graph, _stream(stream)))
+
+
+def rlwe_graph_destroy(graph: int) -> None:
+    _check(lib().rlwe_graph_destroy(graph))
 
 
 def rlwe_profile_begin(ctx: int) -> None:
