@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample (0 disables it)")
+    ap.add_argument("--workload", choices=["attn", "layer"], default="attn",
+                    help="attn: one 2048x2048 projection, 128 tokens (default); layer: the 14 "
+                         "products of a Llama-3.2-1B layer, forward and transposed, with uneven "
+                         "token counts, captured once as a graph and replayed")
     return ap.parse_args()
 
 
@@ -69,6 +73,116 @@ def cpu_baseline(W, ct_np, N, primes, T, d_out, d_in, target_s):
                       f"switch, {el:.1f} s on {cores} threads, scaled per MAC"}
 
 
+LAYER_BUDGET = 250e9  # output bytes per captured graph
+
+
+def layer_workload(args):
+    """All 7 projections of one Llama-3.2-1B layer, forward and transposed (14 products),
+    token counts drawn uniformly in 1..512, one captured graph replayed per step, against
+    the same 14 products issued as plain ct_matmul_clear calls."""
+    import numpy as np
+    import torch
+
+    from paper_2505_07329_amd import rlwe, synth
+
+    cfg = synth.WORKLOADS[4]
+    N, primes, log2_t = cfg["N"], cfg["primes"], cfg["log2_t"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = rlwe.Context(N, primes, log2_t, device=0)
+    g = synth.rng(4, synth.P_MISC)
+    products, weights = [], []
+    for pi, (name, (d_in, d_out)) in enumerate(synth.LLAMA_1B_PROJ.items()):
+        W = synth.int8_uniform(synth.rng(4, synth.P_WEIGHTS, pi), (d_out, d_in))
+        w = rlwe.Weights(ctx, torch.from_numpy(W).to(dev), rlwe.RLWE_W_FWD | rlwe.RLWE_W_TRANSPOSE)
+        weights.append(w)
+        for tr in (False, True):
+            K, M = (d_out, d_in) if tr else (d_in, d_out)
+            T = int(g.integers(1, 513))
+            products.append(dict(name=name + ("^T" if tr else ""), w=w, tr=tr, K=K, M=M, T=T))
+    macs = sum(p["T"] * p["K"] * p["M"] for p in products)
+    groups, cur, cur_bytes = [], [], 0
+    for p in products:
+        ob = p["T"] * p["M"] * (N + 1) * 4
+        if cur and cur_bytes + ob > LAYER_BUDGET:
+            groups.append(cur)
+            cur, cur_bytes = [], 0
+        cur.append(p)
+        cur_bytes += ob
+    groups.append(cur)
+    items_per_group = []
+    for grp in groups:
+        items = []
+        for p in grp:
+            L = (p["K"] + N - 1) // N
+            ct = synth.uniform_mod_primes(synth.rng(4, synth.P_MASK, len(items)), primes, (p["T"], L, 2), N)
+            p["ct"] = torch.from_numpy(ct.view(np.int64)).to(dev)
+            p["out"] = torch.empty((p["T"], p["M"], N + 1), dtype=torch.int32, device=dev)
+            items.append((p["w"].handle, p["tr"], p["ct"], p["T"], p["out"]))
+        items_per_group.append(items)
+    stream = torch.cuda.current_stream()
+    graphs = [rlwe.rlwe_graph_capture_batch(ctx.handle, items) for items in items_per_group]
+
+    def step_graph():
+        for gr in graphs:
+            rlwe.rlwe_graph_launch(gr, stream)
+
+    def step_plain():
+        for p in products:
+            rlwe.ct_matmul_clear(ctx.handle, p["w"].handle, p["ct"], p["T"], p["out"], p["tr"],
+                                 rlwe.RLWE_OUT_SWITCHED, stream)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    plain_steps = max(1, args.steps // 4)
+    rlwe.rlwe_workspace_reserve(ctx.handle, max(
+        rlwe.rlwe_workspace_bytes(ctx.handle, p["w"].handle, p["tr"], p["T"]) for p in products))
+    t_plain = timed(step_plain, plain_steps, 1)
+    t_graph = timed(step_graph, args.steps, args.warmup)
+    rlwe.rlwe_profile_begin(ctx.handle)
+    step_plain()
+    torch.cuda.synchronize()
+    kt = rlwe.rlwe_profile_end(ctx.handle)
+    ops = 0.0
+    for p in products:
+        kept, _ = rlwe.rlwe_weights_digits(p["w"].handle, p["tr"])
+        ops += 2.0 * p["T"] * p["M"] * N * p["K"] * kept
+    achieved = ops / (kt["mask_ms"] * 1e-3) / 1e12
+    value = macs / t_graph
+    result = {
+        "metric": "encrypted MACs/s (sum d_in*d_out*tokens / s), one Llama-3.2-1B layer, 7 projections "
+                  "forward and transposed in one captured graph",
+        "value": value, "unit": "MAC/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_graph * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int8",
+        "data": "synthetic (seeded uniform int8 weights, uniform ciphertext residues)",
+        "config": {"workload": cfg["name"], "N": N, "primes": len(primes), "log2_t": log2_t,
+                   "products": [f'{p["name"]}:{p["K"]}->{p["M"]}x{p["T"]}' for p in products],
+                   "graphs": len(graphs),
+                   "output_GB": sum(p["T"] * p["M"] * (N + 1) * 4 for p in products) / 1e9},
+        "plain_per_call": {"value": macs / t_plain, "ms_per_step": t_plain * 1e3,
+                           "speedup_graph": t_plain / t_graph},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
+                     "unit": "TOP/s (int8), matrix-core launches of the plain per-call sequence",
+                     "frac": achieved / INT8_PEAK_TOPS, "traffic": None},
+        "cpu_baseline": None,
+    }
+    for gr in graphs:
+        rlwe.rlwe_graph_destroy(gr)
+    for w in weights:
+        w.close()
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -76,6 +190,9 @@ def main():
               "rows with no exchange, and this build runs on a single MI355X; use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "layer":
+        layer_workload(args)
+        return
     import numpy as np
     import torch
 

@@ -109,7 +109,7 @@ __device__ inline v4i toeplitz_frag(const uint32_t* p) {
 // wave finishes a share of the elements.
 template <int D, int DK, bool RAW>
 __global__ void __launch_bounds__(64 * ((DK + 2) / 3)) __attribute__((amdgpu_waves_per_eu(3)))
-mask_kernel(RingConst rc, Batch bt) {
+mask_kernel(Batch) {
   static_assert(!RAW || DK == D, "raw output keeps every digit");
   constexpr int NW = (DK + 2) / 3;
   constexpr int DPW = 3;
@@ -125,18 +125,21 @@ mask_kernel(RingConst rc, Batch bt) {
   uint32_t(*wt)[kWRowWords] = reinterpret_cast<uint32_t(*)[kWRowWords]>(smem + kWinLds);
   int64_t* part = reinterpret_cast<int64_t*>(smem);
 
+  const BatchPtr bt = kernarg_batch();
   const uint32_t blk = linear_block();
-  if (blk >= bt.mask_start[bt.n]) return;
-  const uint32_t ii = find_item(bt.mask_start, bt.n, blk);
-  const MatArgs& m = bt.it[ii].m;
-  const SwitchConst& sc = bt.it[ii].sc;
-  const int8_t* __restrict__ emask = bt.it[ii].emask;
-  void* out = bt.it[ii].out;
-  const int force_exact = bt.force_exact;
+  const uint32_t nb = bt->n;
+  if (blk >= bt->mask_start[nb]) return;
+  const uint32_t ii = find_item(bt->mask_start, nb, blk);
+  const RingConst rc = kernarg_load(&bt->rc);
+  const MatArgs m = kernarg_load(&bt->it[ii].m);
+  const SwitchConst sc = kernarg_load(&bt->it[ii].sc);
+  const int8_t* __restrict__ emask = bt->it[ii].emask;
+  void* out = bt->it[ii].out;
+  const int force_exact = bt->force_exact;
   const uint32_t N = rc.N;
   // tile order: column tiles fastest, then row tiles, then tokens
   const uint32_t ntn = N / 64, ntj = m.rows_pad / 32;
-  const uint32_t loc = blk - bt.mask_start[ii];
+  const uint32_t loc = blk - bt->mask_start[ii];
   const uint32_t tn = loc % ntn, tj = (loc / ntn) % ntj;
   const uint32_t t = loc / (ntn * ntj);
   const uint32_t n0 = tn * 64, jb = tj * 32;
@@ -277,31 +280,31 @@ mask_kernel(RingConst rc, Batch bt) {
 }
 
 template <int D, int DK, bool RAW>
-static void launch_one(const RingConst& rc, const Batch& b, hipStream_t s) {
+static void launch_one(const Batch& b, hipStream_t s) {
   hipLaunchKernelGGL((mask_kernel<D, DK, RAW>), grid_for(b.mask_start[b.n]),
-                     dim3(64 * ((DK + 2) / 3)), 0, s, rc, b);
+                     dim3(64 * ((DK + 2) / 3)), 0, s, b);
 }
 
-hipError_t launch_mask(const RingConst& rc, const Batch& b, uint32_t dk, hipStream_t s) {
+hipError_t launch_mask(const Batch& b, uint32_t dk, hipStream_t s) {
   if (b.n == 0 || b.mask_start[b.n] == 0) return hipSuccess;
-  if (rc.D == 7) {
+  if (b.rc.D == 7) {
     if (b.raw)
-      launch_one<7, 7, true>(rc, b, s);
+      launch_one<7, 7, true>(b, s);
     else if (dk == 7)
-      launch_one<7, 7, false>(rc, b, s);
+      launch_one<7, 7, false>(b, s);
     else
       return hipErrorInvalidValue;
   } else {
     if (b.raw) {
-      launch_one<14, 14, true>(rc, b, s);
+      launch_one<14, 14, true>(b, s);
     } else {
       switch (dk) {
-        case 8: launch_one<14, 8, false>(rc, b, s); break;
-        case 9: launch_one<14, 9, false>(rc, b, s); break;
-        case 10: launch_one<14, 10, false>(rc, b, s); break;
-        case 11: launch_one<14, 11, false>(rc, b, s); break;
-        case 12: launch_one<14, 12, false>(rc, b, s); break;
-        case 14: launch_one<14, 14, false>(rc, b, s); break;
+        case 8: launch_one<14, 8, false>(b, s); break;
+        case 9: launch_one<14, 9, false>(b, s); break;
+        case 10: launch_one<14, 10, false>(b, s); break;
+        case 11: launch_one<14, 11, false>(b, s); break;
+        case 12: launch_one<14, 12, false>(b, s); break;
+        case 14: launch_one<14, 14, false>(b, s); break;
         default: return hipErrorInvalidValue;
       }
     }

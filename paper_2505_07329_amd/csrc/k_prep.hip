@@ -57,18 +57,23 @@ __device__ inline void digits255(i128 v, int8_t* d) {
 }
 
 template <int D>
-__global__ void __launch_bounds__(256) prep_kernel(RingConst rc, Batch bt) {
+__global__ void __launch_bounds__(256) prep_kernel(Batch) {
+  const BatchPtr bt = kernarg_batch();
   const uint32_t blk = linear_block();
-  if (blk >= bt.prep_start[bt.n]) return;
-  const uint32_t ii = find_item(bt.prep_start, bt.n, blk);
-  const Item& a = bt.it[ii];
+  const uint32_t nb = bt->n;
+  if (blk >= bt->prep_start[nb]) return;
+  const uint32_t ii = find_item(bt->prep_start, nb, blk);
+  const RingConst rc = kernarg_load(&bt->rc);
+  const Item a = kernarg_load(&bt->it[ii]);
   const uint32_t N = rc.N, P = rc.P, L = a.m.L;
-  const size_t idx = (size_t)(blk - bt.prep_start[ii]) * 256 + threadIdx.x;
-  if (idx >= (size_t)a.T * L * N) return;
-  const uint32_t k = (uint32_t)(idx % N);
-  const size_t ti = idx / N;  // t * L + i
-  const uint32_t i = (uint32_t)(ti % L);
-  const uint32_t t = (uint32_t)(ti / L);
+  // blocks of one (token, input block) pair: N / 256 when N >= 256, else 1
+  const uint32_t per = N >= 256 ? N >> 8 : 1;
+  const uint32_t loc = blk - bt->prep_start[ii];
+  const uint32_t ti = loc / per;  // t * L + i
+  const uint32_t k = (loc - ti * per) * 256 + threadIdx.x;
+  if (ti >= a.T * L || k >= N) return;
+  const uint32_t i = ti % L;
+  const uint32_t t = ti / L;
   const uint64_t* A = a.ct + (ti * 2 + 0) * P * N;
   const uint64_t* B = a.ct + (ti * 2 + 1) * P * N;
   int8_t da[D], db[D];
@@ -84,29 +89,34 @@ __global__ void __launch_bounds__(256) prep_kernel(RingConst rc, Batch bt) {
   }
 }
 
-hipError_t launch_prep(const RingConst& rc, const Batch& b, hipStream_t s) {
+hipError_t launch_prep(const Batch& b, hipStream_t s) {
   const uint32_t blocks = b.prep_start[b.n];
   if (blocks == 0) return hipSuccess;
-  if (rc.D == 7)
-    hipLaunchKernelGGL(prep_kernel<7>, grid_for(blocks), dim3(256), 0, s, rc, b);
+  if (b.rc.D == 7)
+    hipLaunchKernelGGL(prep_kernel<7>, grid_for(blocks), dim3(256), 0, s, b);
   else
-    hipLaunchKernelGGL(prep_kernel<14>, grid_for(blocks), dim3(256), 0, s, rc, b);
+    hipLaunchKernelGGL(prep_kernel<14>, grid_for(blocks), dim3(256), 0, s, b);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- body
 
 template <int D, bool RAW>
-__global__ void __launch_bounds__(256) body_kernel(RingConst rc, Batch bt) {
+__global__ void __launch_bounds__(256) body_kernel(Batch) {
+  const BatchPtr bt = kernarg_batch();
   const uint32_t blk = linear_block();
-  if (blk >= bt.body_start[bt.n]) return;
-  const uint32_t ii = find_item(bt.body_start, bt.n, blk);
-  const Item& a = bt.it[ii];
+  const uint32_t nb = bt->n;
+  if (blk >= bt->body_start[nb]) return;
+  const uint32_t ii = find_item(bt->body_start, nb, blk);
+  const RingConst rc = kernarg_load(&bt->rc);
+  const Item a = kernarg_load(&bt->it[ii]);
   const MatArgs& m = a.m;
-  const size_t idx = (size_t)(blk - bt.body_start[ii]) * 256 + threadIdx.x;
-  if (idx >= (size_t)a.T * m.rows) return;
-  const uint32_t j = (uint32_t)(idx % m.rows);
-  const uint32_t t = (uint32_t)(idx / m.rows);
+  // blocks of one token: ceil(rows / 256)
+  const uint32_t per = (m.rows + 255) / 256;
+  const uint32_t loc = blk - bt->body_start[ii];
+  const uint32_t t = loc / per;
+  const uint32_t j = (loc - t * per) * 256 + threadIdx.x;
+  if (t >= a.T || j >= m.rows) return;
   const uint32_t N = rc.N;
   int32_t S[D];
 #pragma unroll
@@ -136,20 +146,20 @@ __global__ void __launch_bounds__(256) body_kernel(RingConst rc, Batch bt) {
   }
 }
 
-hipError_t launch_body(const RingConst& rc, const Batch& b, hipStream_t s) {
+hipError_t launch_body(const Batch& b, hipStream_t s) {
   const uint32_t blocks = b.body_start[b.n];
   if (blocks == 0) return hipSuccess;
   const dim3 grid = grid_for(blocks);
-  if (rc.D == 7) {
+  if (b.rc.D == 7) {
     if (b.raw)
-      hipLaunchKernelGGL((body_kernel<7, true>), grid, dim3(256), 0, s, rc, b);
+      hipLaunchKernelGGL((body_kernel<7, true>), grid, dim3(256), 0, s, b);
     else
-      hipLaunchKernelGGL((body_kernel<7, false>), grid, dim3(256), 0, s, rc, b);
+      hipLaunchKernelGGL((body_kernel<7, false>), grid, dim3(256), 0, s, b);
   } else {
     if (b.raw)
-      hipLaunchKernelGGL((body_kernel<14, true>), grid, dim3(256), 0, s, rc, b);
+      hipLaunchKernelGGL((body_kernel<14, true>), grid, dim3(256), 0, s, b);
     else
-      hipLaunchKernelGGL((body_kernel<14, false>), grid, dim3(256), 0, s, rc, b);
+      hipLaunchKernelGGL((body_kernel<14, false>), grid, dim3(256), 0, s, b);
   }
   return hipGetLastError();
 }

@@ -533,6 +533,7 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
     }
   if (cnt == 0) return RLWE_OK;
   Batch all{};
+  all.rc = rc;
   all.raw = raw;
   all.force_exact = (flags & RLWE_OUT_FORCE_EXACT) ? 1 : 0;
   size_t off = 0;
@@ -552,11 +553,12 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
     off += ws_item(rc, m.args, dd.tokens);
     it.out = dd.out;
     it.T = dd.tokens;
-    all.prep_start[x + 1] = all.prep_start[x] + (uint32_t)(((size_t)dd.tokens * m.args.L * rc.N + 255) / 256);
-    all.body_start[x + 1] = all.body_start[x] + (uint32_t)(((size_t)dd.tokens * m.args.rows + 255) / 256);
+    const uint32_t prep_per = rc.N >= 256 ? rc.N / 256 : 1;
+    all.prep_start[x + 1] = all.prep_start[x] + dd.tokens * m.args.L * prep_per;
+    all.body_start[x + 1] = all.body_start[x] + dd.tokens * ((m.args.rows + 255) / 256);
   }
   all.n = cnt;
-  hipError_t e = timed(ctx, K_PREP, s, [&] { return launch_prep(rc, all, s); });
+  hipError_t e = timed(ctx, K_PREP, s, [&] { return launch_prep(all, s); });
   if (e != hipSuccess) return hip_fail(e, "prep kernel");
   // one mask launch per distinct number of kept digits
   bool done[kMaxBatch] = {};
@@ -564,6 +566,7 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
     if (done[x]) continue;
     const uint32_t dk = all.it[x].sc.dk;
     Batch mb{};
+    mb.rc = rc;
     mb.raw = all.raw;
     mb.force_exact = all.force_exact;
     for (uint32_t y = x; y < cnt; ++y) {
@@ -574,10 +577,10 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
       mb.mask_start[mb.n + 1] = mb.mask_start[mb.n] + it.T * (it.m.rows_pad / 32) * (rc.N / 64);
       ++mb.n;
     }
-    e = timed(ctx, K_MASK, s, [&] { return launch_mask(rc, mb, dk, s); });
+    e = timed(ctx, K_MASK, s, [&] { return launch_mask(mb, dk, s); });
     if (e != hipSuccess) return hip_fail(e, "mask kernel");
   }
-  e = timed(ctx, K_BODY, s, [&] { return launch_body(rc, all, s); });
+  e = timed(ctx, K_BODY, s, [&] { return launch_body(all, s); });
   if (e != hipSuccess) return hip_fail(e, "body kernel");
   return RLWE_OK;
 }

@@ -115,6 +115,7 @@ constexpr int kMaxBatch = 16;
 // A batch of products launched together; every kernel maps its linear block index
 // onto (item, local block) through the prefix sums below. Passed by value.
 struct Batch {
+  RingConst rc;
   uint32_t n;
   uint32_t raw;
   uint32_t force_exact;
@@ -124,15 +125,33 @@ struct Batch {
   Item it[kMaxBatch];
 };
 
-// Linear block index of a 2D grid (grids are split over y to keep x * block < 2^32).
-__device__ inline uint32_t linear_block() { return blockIdx.y * gridDim.x + blockIdx.x; }
+// Kernels take the Batch as their only argument and read it in place through the
+// kernarg segment pointer (constant address space, uniform scalar loads); indexing
+// the by-value parameter directly would make every thread copy it to scratch.
+typedef const __attribute__((address_space(4))) Batch* BatchPtr;
+__device__ inline BatchPtr kernarg_batch() {
+  return (BatchPtr)__builtin_amdgcn_kernarg_segment_ptr();
+}
 
-// Item owning linear block b (uniform per workgroup).
-__device__ inline uint32_t find_item(const uint32_t* start, uint32_t n, uint32_t b) {
+// Copy of a kernarg-resident object into private storage (registers).
+template <class T>
+__device__ inline T kernarg_load(const __attribute__((address_space(4))) T* p) {
+  T r;
+  __builtin_memcpy(&r, (const void*)p, sizeof(T));
+  return r;
+}
+
+// Item owning linear block b (uniform per workgroup); start is a prefix-sum table.
+__device__ inline uint32_t find_item(const __attribute__((address_space(4))) uint32_t* start,
+                                     uint32_t n, uint32_t b) {
   uint32_t i = 0;
   while (i + 1 < n && b >= start[i + 1]) ++i;
   return i;
 }
+
+// Linear block index of a 2D grid (grids are split over y to keep x * block < 2^32).
+__device__ inline uint32_t linear_block() { return blockIdx.y * gridDim.x + blockIdx.x; }
+
 
 // 2D grid covering `blocks` blocks of `threads` threads.
 inline dim3 grid_for(uint32_t blocks) {
@@ -140,9 +159,9 @@ inline dim3 grid_for(uint32_t blocks) {
   return dim3(x, (blocks + x - 1) / x);
 }
 
-hipError_t launch_prep(const RingConst& rc, const Batch& b, hipStream_t s);
-hipError_t launch_mask(const RingConst& rc, const Batch& b, uint32_t dk, hipStream_t s);
-hipError_t launch_body(const RingConst& rc, const Batch& b, hipStream_t s);
+hipError_t launch_prep(const Batch& b, hipStream_t s);
+hipError_t launch_mask(const Batch& b, uint32_t dk, hipStream_t s);
+hipError_t launch_body(const Batch& b, hipStream_t s);
 hipError_t launch_modswitch(const RingConst& rc, const uint64_t* in, size_t count, uint32_t* out,
                             hipStream_t s);
 hipError_t launch_transpose_pad(const int8_t* src, uint32_t rows, uint32_t cols, bool transpose,
