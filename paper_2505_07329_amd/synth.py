@@ -46,6 +46,14 @@ def int8_uniform(g: np.random.Generator, shape, lo: int = -127, hi: int = 127) -
     return g.integers(lo, hi + 1, size=shape, dtype=np.int64).astype(np.int8)
 
 
+def int8_uniform_device(config: int, purpose: int, salt: int, shape, device):
+    """int8 uniform in [-127, 127] drawn on a torch device (large resident weight sets)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(SEED_BASE + 1000 * config + purpose + 100000 * salt)
+    return torch.randint(-127, 128, tuple(shape), generator=gen, device=device, dtype=torch.int8)
+
+
 def uniform_mod_primes(g: np.random.Generator, primes, lead_shape, N: int) -> np.ndarray:
     """Uniform residues, shape ``lead_shape + (P, N)``, entry [..., p, k] in [0, primes[p])."""
     P = len(primes)
