@@ -37,14 +37,17 @@ INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix peak, 5.0 POP/s
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 20; mlp: 1 pass over all 2048 tokens of 6 products)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 3; mlp: 1)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample (0 disables it)")
-    ap.add_argument("--workload", choices=["attn", "layer", "serve"], default="attn",
+    ap.add_argument("--chunk", type=int, default=256, help="mlp: tokens per call")
+    ap.add_argument("--workload", choices=["attn", "layer", "mlp", "serve"], default="attn",
                     help="attn: one 2048x2048 projection, 128 tokens (default); layer: the 14 "
                          "products of a Llama-3.2-1B layer, forward and transposed, with uneven "
-                         "token counts, captured once as a graph and replayed; serve: Poisson "
+                         "token counts, captured once as a graph and replayed; mlp: gate/up/down "
+                         "forward and transposed over 2048 tokens in chunks; serve: Poisson "
                          "requests from 16 clients over a resident 16-layer model")
     ap.add_argument("--requests", type=int, default=96,
                     help="serve: requests per run (saturated run and each load point)")
@@ -54,7 +57,12 @@ def parse():
                     help="serve: MACs after which a scheduling round stops adding requests")
     ap.add_argument("--loads", default="0.5,0.8,0.95",
                     help="serve: arrival rates as fractions of the saturated request rate")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 1 if args.workload == "mlp" else 20
+    if args.warmup is None:
+        args.warmup = 1 if args.workload == "mlp" else 3
+    return args
 
 
 def cpu_baseline(W, ct_np, N, primes, T, d_out, d_in, target_s):
@@ -190,6 +198,137 @@ def layer_workload(args):
         w.close()
     ctx.close()
     print(json.dumps(result), flush=True)
+
+MLP_TOKENS = 2048
+
+
+def mlp_workload(args):
+    """Llama-3.2-1B MLP over 2048 encrypted tokens (batch 4 x context 512): gate and up
+    (2048 -> 8192) and down (8192 -> 2048) forward, and the backward products with their
+    transposes (gate^T, up^T: 8192 -> 2048; down^T: 2048 -> 8192). One step is one pass
+    over all six products and all tokens, issued as plain ct_matmul_clear calls of
+    `chunk` tokens that alternate between two output slots (one full product's switched
+    output is 275 GB; the slots stand in for the transfer buffers of a server)."""
+    import numpy as np
+    import torch
+
+    from paper_2505_07329_amd import rlwe, synth
+
+    cfg = synth.WORKLOADS[3]
+    N, primes, log2_t = cfg["N"], cfg["primes"], cfg["log2_t"]
+    T, C = MLP_TOKENS, args.chunk
+    if T % C:
+        raise SystemExit("--chunk must divide 2048")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = rlwe.Context(N, primes, log2_t, device=0)
+    mats = {}
+    for pi, name in enumerate(("gate", "up", "down")):
+        d_in, d_out = synth.LLAMA_1B_PROJ[name]
+        W = synth.int8_uniform_device(3, synth.P_WEIGHTS, pi, (d_out, d_in), dev)
+        mats[name] = rlwe.Weights(ctx, W, rlwe.RLWE_W_FWD | rlwe.RLWE_W_TRANSPOSE)
+        del W
+    cts = {}
+    for L in (1, 2):
+        ct = synth.uniform_mod_primes(synth.rng(3, synth.P_MASK, L), primes, (T, L, 2), N)
+        cts[L] = torch.from_numpy(ct.view(np.int64)).to(dev)
+        del ct
+    products = []
+    for name in ("gate", "up", "down"):
+        w = mats[name]
+        for tr in (False, True):
+            K, M = (w.d_out, w.d_in) if tr else (w.d_in, w.d_out)
+            products.append(dict(name=name + ("^T" if tr else ""), w=w, tr=tr, K=K, M=M,
+                                 L=(K + N - 1) // N))
+    Mmax = max(p["M"] for p in products)
+    slots = [torch.empty((C, Mmax, N + 1), dtype=torch.int32, device=dev) for _ in range(2)]
+    rlwe.rlwe_workspace_reserve(ctx.handle, max(
+        rlwe.rlwe_workspace_bytes(ctx.handle, p["w"].handle, p["tr"], C) for p in products))
+    stream = torch.cuda.current_stream()
+
+    def one_pass(chunks):
+        k = 0
+        for p in products:
+            for c in range(chunks):
+                out = slots[k % 2][:, : p["M"]] if p["M"] == Mmax else \
+                    slots[k % 2].view(-1)[: C * p["M"] * (N + 1)].view(C, p["M"], N + 1)
+                rlwe.ct_matmul_clear(ctx.handle, p["w"].handle, cts[p["L"]][c * C:(c + 1) * C], C,
+                                     out, p["tr"], rlwe.RLWE_OUT_SWITCHED, stream)
+                k += 1
+
+    for _ in range(args.warmup):
+        one_pass(1)
+    torch.cuda.synchronize()
+    rlwe.rlwe_profile_begin(ctx.handle)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_pass(T // C)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = rlwe.rlwe_profile_end(ctx.handle)
+    macs = args.steps * T * sum(p["K"] * p["M"] for p in products)
+    ops = 0.0
+    for p in products:
+        kept, _ = rlwe.rlwe_weights_digits(p["w"].handle, p["tr"])
+        ops += 2.0 * args.steps * T * p["M"] * N * p["K"] * kept
+    achieved = ops / (kt["mask_ms"] * 1e-3) / 1e12
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = mlp_cpu_baseline(products, N, primes, args.cpu_seconds)
+    result = {
+        "metric": "encrypted MACs/s (sum d_in*d_out*tokens / s), Llama-3.2-1B MLP forward and backward "
+                  "through the frozen weights, outputs switched to 2^32",
+        "value": macs / wall, "unit": "MAC/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int8",
+        "data": "synthetic (seeded uniform int8 weights, uniform ciphertext residues)",
+        "config": {"workload": cfg["name"], "N": N, "primes": len(primes), "log2_t": log2_t,
+                   "tokens": T, "chunk": C,
+                   "products": [f'{p["name"]}:{p["K"]}->{p["M"]}' for p in products],
+                   "digits_on_matrix_cores": {p["name"]: rlwe.rlwe_weights_digits(p["w"].handle, p["tr"])[0]
+                                              for p in products}},
+        "kernels_ms": {"prep": kt["prep_ms"], "mask": kt["mask_ms"], "body": kt["body_ms"]},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
+                     "unit": "TOP/s (int8), matrix-core launches of the timed pass",
+                     "frac": achieved / INT8_PEAK_TOPS, "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    for w in mats.values():
+        w.close()
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+def mlp_cpu_baseline(products, N, primes, target_s):
+    """The oracle on 32 sampled output LWEs of each of the six products in turn, credited
+    d_in MACs per output LWE (its cost is linear in the token count)."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    orc.lib()
+    g = np.random.default_rng(9)
+    data = []
+    for p in products:
+        W = g.integers(-127, 128, size=(p["M"], p["K"]), dtype=np.int64).astype(np.int8)
+        ct = np.stack([g.integers(0, q, size=(8, p["L"], 2, N), dtype=np.uint64) for q in primes], -2)
+        data.append((p, W, ct))
+    done = macs = 0
+    el = 0.0
+    i = 0
+    while el < target_s:
+        p, W, ct = data[i % len(data)]
+        i += 1
+        pairs = np.stack([g.integers(0, 8, 32), g.integers(0, p["M"], 32)], 1).astype(np.uint32)
+        t0 = time.perf_counter()
+        orc.modswitch(primes, orc.matmul_clear(N, primes, W, ct, pairs=pairs, mode=1))
+        el += time.perf_counter() - t0
+        done += len(pairs)
+        macs += len(pairs) * p["K"]
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": macs / el, "unit": "encrypted MAC/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} output LWEs, 32 from each of the six products in turn, NTT-mode oracle "
+                      f"plus exact switch, {el:.1f} s on {cores} threads, scaled per MAC"}
+
 
 SERVE_LAYERS = 16
 SERVE_CLIENTS = 16
@@ -351,6 +490,9 @@ def main():
         return
     if args.workload == "serve":
         serve_workload(args)
+        return
+    if args.workload == "mlp":
+        mlp_workload(args)
         return
     import numpy as np
     import torch

@@ -207,6 +207,61 @@ def test_two_blocks_and_transpose():
     ctx.close()
 
 
+def _switched_bound_holds(case, W, out, g, n=512):
+    """Deterministic modulus-switch noise bound (Sec. 3.2) on n random outputs."""
+    T, M = out.shape[0], out.shape[1]
+    ts = g.integers(0, T, n)
+    js = g.integers(0, M, n)
+    rows = host_u32(out[torch.from_numpy(ts).cuda(), torch.from_numpy(js).cuda()])
+    ph = orc.lwe_phase_u32(case.N, case.S, rows)
+    q, t = case.q, 1 << case.log2_t
+    dprime = (1 << 32) // t
+    Wr = W.astype(np.int64)[js]
+    v = np.einsum("nk,nk->n", case.x.astype(np.int64)[ts], Wr)
+    e = np.einsum("nk,nk->n", case.errors_flat().astype(np.int64)[ts], Wr)
+    s1 = int(np.abs(case.S.astype(np.int64)).sum())
+    bound = dprime * np.abs(v) * (q % t) / q + (2 ** 32) * np.abs(e) / q + (1 + s1) / 2 + 1e-6
+    return bool(np.all(np.abs(ph - dprime * v) <= bound))
+
+
+def test_config3_mlp_chunk_launch_config():
+    """Down projection of the MLP workload (W 2048 x 8192, t = 2^28) in the launch
+    configuration the benchmark times: 256-token chunks, forward (L = 2, 2048 outputs)
+    and transposed (L = 1, 8192 outputs). Sampled outputs against the oracle, and the
+    switched-noise bound on random outputs."""
+    print("case: mlp down 2048x8192 fwd+transposed, chunk 256", flush=True)
+    N, primes, log2_t, C = 4096, P4096, 28, 256
+    fwd = make_case(N, primes, log2_t, 2048, 8192, C, config=3, salt=11)
+    r = rl()
+    ctx = r.Context(N, primes, log2_t)
+    w = r.Weights(ctx, dev(fwd.W), r.RLWE_W_FWD | r.RLWE_W_TRANSPOSE)
+    g = np.random.default_rng(3)
+    out = r.matmul(ctx, w, dev(fwd.ct))
+    torch.cuda.synchronize()
+    pf = np.stack([g.integers(0, C, 8), g.integers(0, 2048, 8)], 1).astype(np.uint32)
+    pf = np.concatenate([pf, np.array([[0, 0], [C - 1, 2047]], dtype=np.uint32)])
+    ref = orc.modswitch(primes, orc.matmul_clear(N, primes, fwd.W, fwd.ct, pairs=pf))
+    got = host_u32(out[torch.from_numpy(pf[:, 0].astype(np.int64)).cuda(),
+                       torch.from_numpy(pf[:, 1].astype(np.int64)).cuda()])
+    assert np.array_equal(got, ref)
+    assert _switched_bound_holds(fwd, fwd.W, out, g)
+    del out
+    WT = np.ascontiguousarray(fwd.W.T)
+    bwd = make_case(N, primes, log2_t, 8192, 2048, C, config=3, salt=12, W=WT)
+    out = r.matmul(ctx, w, dev(bwd.ct), transpose=True)
+    torch.cuda.synchronize()
+    pb = np.stack([g.integers(0, C, 8), g.integers(0, 8192, 8)], 1).astype(np.uint32)
+    pb = np.concatenate([pb, np.array([[0, 0], [C - 1, 8191]], dtype=np.uint32)])
+    ref = orc.modswitch(primes, orc.matmul_clear(N, primes, WT, bwd.ct, pairs=pb))
+    got = host_u32(out[torch.from_numpy(pb[:, 0].astype(np.int64)).cuda(),
+                       torch.from_numpy(pb[:, 1].astype(np.int64)).cuda()])
+    assert np.array_equal(got, ref)
+    assert _switched_bound_holds(bwd, WT, out, g)
+    del out
+    w.close()
+    ctx.close()
+
+
 @pytest.mark.parametrize("primes,N", [(P2048, 2048), (P4096, 4096)])
 def test_modswitch_standalone(primes, N):
     print(f"case: modswitch P{len(primes)}", flush=True)
