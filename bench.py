@@ -33,6 +33,25 @@ if ROOT not in sys.path:
 
 INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix peak, 5.0 POP/s
 
+# HBM bytes moved by one mask-kernel launch of the default workload: two rocprofv3
+# --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by the
+# ratio of known to counted bytes of a plain copy kernel in the same run
+# (--copy-calibration). Valid for the kernel source it was taken on (sha256 of
+# csrc/k_mask.hip); for any other source the roofline reports traffic as null.
+MASK_TRAFFIC = {"fetch_bytes": 4378030701, "write_bytes": 4767445499,
+                "k_mask_sha256": "8be813ebf550814d15155e3952764602aa2022b8fc9a9ce14a39ad401a5cf23e"}
+
+
+def mask_traffic():
+    import hashlib
+    if not MASK_TRAFFIC:
+        return None
+    src = os.path.join(ROOT, "paper_2505_07329_amd", "csrc", "k_mask.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != MASK_TRAFFIC["k_mask_sha256"]:
+            return None
+    return MASK_TRAFFIC["fetch_bytes"] + MASK_TRAFFIC["write_bytes"]
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -43,6 +62,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample (0 disables it)")
     ap.add_argument("--chunk", type=int, default=256, help="mlp: tokens per call")
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                    help="attn: before the timed region, run one plain elementwise copy kernel "
+                         "(int32 bitwise not) reading and writing GIB GiB each, as the known-size "
+                         "reference for the FETCH_SIZE / WRITE_SIZE counters")
     ap.add_argument("--workload", choices=["attn", "layer", "mlp", "serve"], default="attn",
                     help="attn: one 2048x2048 projection, 128 tokens (default); layer: the 14 "
                          "products of a Llama-3.2-1B layer, forward and transposed, with uneven "
@@ -522,6 +545,14 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    if args.copy_calibration > 0:
+        n = int(args.copy_calibration * (1 << 30)) // 4
+        src = torch.zeros(n, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.bitwise_not(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     rlwe.rlwe_profile_begin(ctx.handle)
@@ -563,7 +594,8 @@ def main():
         "kernels_ms": {"prep": kt["prep_ms"] / max(1, kt["prep_n"]), "mask": mask_ms,
                        "body": kt["body_ms"] / max(1, kt["body_n"])},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
-                     "unit": "TOP/s (int8)", "frac": achieved / INT8_PEAK_TOPS, "traffic": None},
+                     "unit": "TOP/s (int8)", "frac": achieved / INT8_PEAK_TOPS,
+                     "traffic": mask_traffic()},
         "cpu_baseline": None,
     }
     w.close()

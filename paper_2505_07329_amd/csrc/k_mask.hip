@@ -61,12 +61,15 @@ __device__ inline uint32_t fixed_round(uint32_t u0, uint32_t u1, uint32_t u2, ui
 // lane accumulates a strided share of the contraction for all D digits, the
 // shares are summed across the wave, and the exact rounding is taken from the
 // integer V = sum_l 255^l S_l. Used where the fast path lies near a tie.
+// The constants are read from the kernarg segment here: handing the caller's
+// copies over by reference would force every thread to keep them in scratch.
 template <int D>
-__device__ __attribute__((noinline)) uint32_t exact_element_wave(const RingConst& rc,
-                                                                 const MatArgs& m,
-                                                                 const int8_t* emask, uint32_t t,
-                                                                 uint32_t jj, uint32_t nn,
-                                                                 int lane) {
+__device__ inline uint32_t exact_element_wave(BatchPtr bt, uint32_t ii,
+                                                                 uint32_t t, uint32_t jj,
+                                                                 uint32_t nn, int lane) {
+  const RingConst rc = kernarg_load(&bt->rc);
+  const MatArgs m = kernarg_load(&bt->it[ii].m);
+  const int8_t* emask = bt->it[ii].emask;
   const uint32_t N = rc.N;
   int32_t S[D];
 #pragma unroll
@@ -270,7 +273,7 @@ mask_kernel(Batch) {
           const int src = __ffsll((unsigned long long)pending) - 1;
           pending &= pending - 1;
           const uint32_t jj = __shfl(j, src), nn = __shfl(n, src);
-          const uint32_t r = exact_element_wave<D>(rc, m, emask, t, jj, nn, lane);
+          const uint32_t r = exact_element_wave<D>(bt, ii, t, jj, nn, lane);
           if (lane == src) res = r;
         }
         if (live) ((uint32_t*)out)[row * (N + 1) + n] = res;
