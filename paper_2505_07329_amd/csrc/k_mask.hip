@@ -101,6 +101,9 @@ __device__ inline v4i toeplitz_frag(const uint32_t* p) {
   __builtin_memcpy(&f, p, 16);
   return f;
 }
+__device__ inline v4i toeplitz_frag(const __attribute__((address_space(3))) uint32_t* p) {
+  return v4i{(int)p[0], (int)p[1], (int)p[2], (int)p[3]};
+}
 
 // Work split: a workgroup owns a 32-row x 64-column output tile of one token
 // and all DK kept digits; its NW = ceil(DK/3) waves each take at most 3 digits
@@ -110,7 +113,9 @@ __device__ inline v4i toeplitz_frag(const uint32_t* p) {
 // so every k-step reads one new fragment per digit and feeds two MFMAs.
 // Epilogue: per-wave partial sums over its digits (int64) meet in LDS; each
 // wave finishes a share of the elements.
-template <int D, int DK, bool RAW>
+// FULL: every chunk of every item spans kKC contraction bytes (K a multiple of kKC,
+// N >= kKC), so the k-loop is straight-line code with immediate LDS offsets.
+template <int D, int DK, bool RAW, bool FULL>
 __global__ void __launch_bounds__(64 * ((DK + 2) / 3)) __attribute__((amdgpu_waves_per_eu(3)))
 mask_kernel(Batch) {
   static_assert(!RAW || DK == D, "raw output keeps every digit");
@@ -161,10 +166,49 @@ mask_kernel(Batch) {
 #pragma unroll
   for (int d = 0; d < DPW; ++d) acc0[d] = acc1[d] = v16i{0};
 
+  // Fragment addresses of this lane are the same for every chunk: block 0's
+  // Toeplitz fragment of digit d at k-step st is 16 bytes at ep[d] + 8 st
+  // (dwords), the weight fragment at wl + 8 st.
+  // Each base is made opaque to the compiler: derived from one another they would be
+  // folded into one register plus offsets beyond the 8-bit range of ds_read2_b32,
+  // costing an address addition per fragment.
+  typedef const __attribute__((address_space(3))) uint32_t* lds_u32;
+  lds_u32 ep[DPW];
+#pragma unroll
+  for (int d = 0; d < DPW; ++d) {
+    ep[d] = (lds_u32)(win + (dlo + d) * kDigitWords + copy_base(sh) + (lb >> 2));
+    asm volatile("" : "+v"(ep[d]));
+  }
+  const uint32_t* wl = &wt[c][4 * g];
+  v4i fprev[DPW];
+  // Operands of one k-step: the weight fragment and a new Toeplitz fragment per digit.
+  struct Frags {
+    v4i w, a[DPW];
+  };
+  auto load = [&](uint32_t st) __attribute__((always_inline)) {
+    Frags f;
+    f.w = toeplitz_frag(wl + 8 * st);
+#pragma unroll
+    for (int d = 0; d < DPW; ++d)
+      if (d < cnt) f.a[d] = toeplitz_frag(ep[d] + 8 * st);
+    return f;
+  };
+  // One k-step: each new fragment feeds block 0 and, one step late, block 1.
+  auto mma = [&](const Frags& f) __attribute__((always_inline)) {
+#pragma unroll
+    for (int d = 0; d < DPW; ++d) {
+      if (d < cnt) {
+        acc0[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.w, f.a[d], acc0[d], 0, 0, 0);
+        acc1[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.w, fprev[d], acc1[d], 0, 0, 0);
+        fprev[d] = f.a[d];
+      }
+    }
+  };
+
   const uint32_t L = __builtin_amdgcn_readfirstlane(m.L);
   for (uint32_t i = 0; i < L; ++i) {
     const uint32_t kb = __builtin_amdgcn_readfirstlane(min(N, m.k - i * N));
-    const uint32_t kp = (kb + 31u) & ~31u;
+    const uint32_t kp = (kb + 63u) & ~63u;  // the weight rows are zero up to a multiple of 64
     for (uint32_t kc = 0; kc < kp; kc += kKC) {
       const uint32_t klen = __builtin_amdgcn_readfirstlane(min((uint32_t)kKC, kp - kc));
       // plane bytes [N + kc - n0 - 64, N + kc - n0 + klen) hold every Toeplitz
@@ -172,24 +216,31 @@ mask_kernel(Batch) {
       const uint32_t wstart = N + kc - n0 - 64;
       __syncthreads();
       {
-        // Stage the windows (four byte-shifted copies per digit) and the weight tile.
-        // Shapes are compile-time so the index arithmetic is shifts and multiplies;
-        // bytes past the plane or the padded weight row read as zero (never used).
+        // Stage the windows (four byte-shifted copies per digit, 16 plane bytes per
+        // thread and pass) and the weight tile. Window bytes past the plane are
+        // read from the workspace that follows it and never used: the Toeplitz
+        // entries of the chunk end at plane byte N + kp - n0 - 1 < 2N.
         constexpr int kNT = 64 * NW;
+        constexpr int kQuads = kCopyWords / 4;
         constexpr int kW16 = kKC / 16;
         const int8_t* wsrc = m.w + (size_t)jb * m.kw + (size_t)i * N + kc;
         const uint32_t wlim = m.kw - i * N - kc;
-        for (uint32_t x = threadIdx.x; x < (uint32_t)(DK * kCopyWords); x += kNT) {
-          const uint32_t d = x / kCopyWords, u = x % kCopyWords;
-          const uint32_t at = wstart + 4 * u;
-          const int8_t* plane = emask + (((size_t)t * D + (l0 + d)) * L + i) * 2 * N;
-          const uint32_t g0 = at < 2 * N ? *(const uint32_t*)(plane + at) : 0u;
-          const uint32_t g1 = at + 4 < 2 * N ? *(const uint32_t*)(plane + at + 4) : 0u;
-          uint32_t* wd = win + d * kDigitWords + u;
-          wd[copy_base(0)] = g0;
-          wd[copy_base(1)] = __builtin_amdgcn_alignbyte(g1, g0, 1);
-          wd[copy_base(2)] = __builtin_amdgcn_alignbyte(g1, g0, 2);
-          wd[copy_base(3)] = __builtin_amdgcn_alignbyte(g1, g0, 3);
+        const int8_t* planes = emask + (((size_t)t * D + l0) * L + i) * 2 * N + wstart;
+        for (uint32_t x = threadIdx.x; x < (uint32_t)(DK * kQuads); x += kNT) {
+          const uint32_t d = x / kQuads, v = x % kQuads;
+          const int8_t* src = planes + (size_t)d * L * 2 * N + 16 * v;
+          const uint4 q = *(const uint4*)src;
+          const uint32_t q4 = *(const uint32_t*)(src + 16);
+          uint32_t* wd = win + d * kDigitWords + 4 * v;
+          *(uint4*)(wd + copy_base(0)) = q;
+#pragma unroll
+          for (int sft = 1; sft < 4; ++sft) {
+            uint32_t* o = wd + copy_base(sft);
+            o[0] = __builtin_amdgcn_alignbyte(q.y, q.x, sft);
+            o[1] = __builtin_amdgcn_alignbyte(q.z, q.y, sft);
+            o[2] = __builtin_amdgcn_alignbyte(q.w, q.z, sft);
+            o[3] = __builtin_amdgcn_alignbyte(q4, q.w, sft);
+          }
         }
         for (uint32_t x = threadIdx.x; x < 32u * kW16; x += kNT) {
           const uint32_t r = x / kW16, o = x % kW16;
@@ -199,25 +250,26 @@ mask_kernel(Batch) {
         }
       }
       __syncthreads();
-      const uint32_t* ep[DPW];
-      v4i fprev[DPW];
 #pragma unroll
-      for (int d = 0; d < DPW; ++d) {
-        ep[d] = win + (dlo + d) * kDigitWords + copy_base(sh) + (lb >> 2);
+      for (int d = 0; d < DPW; ++d)
         if (d < cnt) fprev[d] = toeplitz_frag(ep[d] - 8);
-      }
-      const uint32_t* wl = &wt[c][4 * g];
-      const uint32_t nstep = klen / 32;
-      for (uint32_t st = 0; st < nstep; ++st) {
-        const v4i wf = toeplitz_frag(wl + 8 * st);
+      if constexpr (FULL) {
+        // full chunk: straight-line code with immediate LDS offsets; the operands of
+        // step st + 1 are requested before the matrix instructions of step st
+        Frags cur = load(0);
 #pragma unroll
-        for (int d = 0; d < DPW; ++d) {
-          if (d < cnt) {
-            const v4i fa = toeplitz_frag(ep[d] + 8 * st);
-            acc0[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(wf, fa, acc0[d], 0, 0, 0);
-            acc1[d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(wf, fprev[d], acc1[d], 0, 0, 0);
-            fprev[d] = fa;
-          }
+        for (int st = 0; st < kKC / 32; ++st) {
+          Frags nxt;
+          if (st + 1 < kKC / 32) nxt = load(st + 1);
+          mma(cur);
+          cur = nxt;
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      } else {
+        for (uint32_t st = 0; st < klen / 32; st += 2) {  // klen is a multiple of 64
+          const Frags f0 = load(st), f1 = load(st + 1);
+          mma(f0);
+          mma(f1);
         }
       }
     }
@@ -284,8 +336,14 @@ mask_kernel(Batch) {
 
 template <int D, int DK, bool RAW>
 static void launch_one(const Batch& b, hipStream_t s) {
-  hipLaunchKernelGGL((mask_kernel<D, DK, RAW>), grid_for(b.mask_start[b.n]),
-                     dim3(64 * ((DK + 2) / 3)), 0, s, b);
+  bool full = b.rc.N >= (uint32_t)kKC;
+  for (uint32_t x = 0; x < b.n; ++x) full = full && b.it[x].m.k % kKC == 0;
+  if (full)
+    hipLaunchKernelGGL((mask_kernel<D, DK, RAW, true>), grid_for(b.mask_start[b.n]),
+                       dim3(64 * ((DK + 2) / 3)), 0, s, b);
+  else
+    hipLaunchKernelGGL((mask_kernel<D, DK, RAW, false>), grid_for(b.mask_start[b.n]),
+                       dim3(64 * ((DK + 2) / 3)), 0, s, b);
 }
 
 hipError_t launch_mask(const Batch& b, uint32_t dk, hipStream_t s) {

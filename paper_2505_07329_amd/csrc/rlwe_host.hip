@@ -378,7 +378,7 @@ static int load_mat(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32_t
   MatArgs& a = m.args;
   a.rows = transpose ? d_in : d_out;
   a.k = transpose ? d_out : d_in;
-  a.kw = (uint32_t)align_up(a.k, 32);
+  a.kw = (uint32_t)align_up(a.k, 64);
   a.rows_pad = (uint32_t)align_up(a.rows, 64);
   a.L = (a.k + rc.N - 1) / rc.N;
   // exact 128-bit accumulation: 127 * K * (q-1)/2 < 2^127

@@ -95,7 +95,7 @@ struct MatArgs {
   uint32_t rows;        // outputs M
   uint32_t rows_pad;    // multiple of 64
   uint32_t k;           // contraction length K
-  uint32_t kw;          // row pitch: K rounded up to 32
+  uint32_t kw;          // row pitch: K rounded up to 64
   uint32_t L;           // input blocks
 };
 
