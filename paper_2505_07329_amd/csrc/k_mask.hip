@@ -27,14 +27,14 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kKC = 256;                 // k-chunk staged in LDS per pass (8 k-steps)
 // LDS layout of one digit window: four copies, copy s shifted by s bytes, each
-// kCopyWords long; copy s starts at s * kCopyPitch + skew(s) dwords with
-// skew = 0, 9, 17, 25 so that the 32 lanes of a half-wave, which read 8
-// consecutive dwords from each of the four copies in one fragment load, hit 32
-// distinct banks.
+// kCopyWords long, at dword offsets 0, 88, 176, 268. The offsets are multiples of
+// four (the staging writes are aligned 16-byte stores) and place the dwords that
+// the 32 lanes of a half-wave read from the four copies in one fragment load
+// (nine consecutive dwords per copy) on distinct banks for 32- and 64-bank LDS.
 constexpr int kCopyWords = (kKC + 96) / 4;
-constexpr int kCopyPitch = (kCopyWords + 31) / 32 * 32;
-constexpr int kDigitWords = 3 * kCopyPitch + 25 + kCopyWords + 31 - (3 * kCopyPitch + 25 + kCopyWords + 31) % 32;
-__host__ __device__ constexpr int copy_base(int s) { return s * kCopyPitch + (s ? 8 * s + 1 : 0); }
+static_assert(kCopyWords == 88, "copy offsets are laid out for 256-byte chunks");
+__host__ __device__ constexpr int copy_base(int s) { return s == 3 ? 268 : 88 * s; }
+constexpr int kDigitWords = 268 + kCopyWords;  // 356: one digit's four copies
 constexpr int kWRowWords = kKC / 4 + 4;    // LDS row pitch of the weight tile (dwords)
 
 // round(U * G) mod 2^32 where U is a signed 128-bit integer (u0..u3) and
@@ -234,13 +234,11 @@ mask_kernel(Batch) {
           uint32_t* wd = win + d * kDigitWords + 4 * v;
           *(uint4*)(wd + copy_base(0)) = q;
 #pragma unroll
-          for (int sft = 1; sft < 4; ++sft) {
-            uint32_t* o = wd + copy_base(sft);
-            o[0] = __builtin_amdgcn_alignbyte(q.y, q.x, sft);
-            o[1] = __builtin_amdgcn_alignbyte(q.z, q.y, sft);
-            o[2] = __builtin_amdgcn_alignbyte(q.w, q.z, sft);
-            o[3] = __builtin_amdgcn_alignbyte(q4, q.w, sft);
-          }
+          for (int sft = 1; sft < 4; ++sft)
+            *(uint4*)(wd + copy_base(sft)) = make_uint4(__builtin_amdgcn_alignbyte(q.y, q.x, sft),
+                                                        __builtin_amdgcn_alignbyte(q.z, q.y, sft),
+                                                        __builtin_amdgcn_alignbyte(q.w, q.z, sft),
+                                                        __builtin_amdgcn_alignbyte(q4, q.w, sft));
         }
         for (uint32_t x = threadIdx.x; x < 32u * kW16; x += kNT) {
           const uint32_t r = x / kW16, o = x % kW16;
