@@ -27,14 +27,16 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kKC = 256;                 // k-chunk staged in LDS per pass (8 k-steps)
 // LDS layout of one digit window: four copies, copy s shifted by s bytes, each
-// kCopyWords long, at dword offsets 0, 88, 176, 268. The offsets are multiples of
-// four (the staging writes are aligned 16-byte stores) and place the dwords that
-// the 32 lanes of a half-wave read from the four copies in one fragment load
-// (nine consecutive dwords per copy) on distinct banks for 32- and 64-bank LDS.
-constexpr int kCopyWords = (kKC + 96) / 4;
-static_assert(kCopyWords == 88, "copy offsets are laid out for 256-byte chunks");
-__host__ __device__ constexpr int copy_base(int s) { return s == 3 ? 268 : 88 * s; }
-constexpr int kDigitWords = 268 + kCopyWords;  // 356: one digit's four copies
+// kCopyWords long, back to back. A lane's block-0 fragment at k-step st starts at
+// copy word (lb >> 2) + 8 st with lb = 16 g - c + 64 in [33, 80], so the words read
+// span [0, 80) (the one-step-late block-1 fragment included). Offsets that are
+// multiples of 80 dwords keep the staging stores 16-byte aligned and place the
+// nine consecutive dwords that a half-wave reads from each copy in one fragment
+// load on distinct banks, for 32- and 64-bank LDS.
+constexpr int kCopyWords = 80;
+static_assert(80 / 4 + 8 * (kKC / 32 - 1) + 3 < kCopyWords, "window covers every fragment");
+__host__ __device__ constexpr int copy_base(int s) { return kCopyWords * s; }
+constexpr int kDigitWords = 4 * kCopyWords;
 constexpr int kWRowWords = kKC / 4 + 4;    // LDS row pitch of the weight tile (dwords)
 
 // round(U * G) mod 2^32 where U is a signed 128-bit integer (u0..u3) and
@@ -105,6 +107,25 @@ __device__ inline v4i toeplitz_frag(const __attribute__((address_space(3))) uint
   return v4i{(int)p[0], (int)p[1], (int)p[2], (int)p[3]};
 }
 
+// Asynchronous 16-byte copy global -> LDS (LDS DMA): lane x of the wave writes its
+// 16 bytes at LDS byte address lds_wave + 16 x (lds_wave uniform across the wave).
+// Issued as assembly so that the compiler does not make every later LDS read wait
+// for it; callers wait for completion themselves (wait_vmem) before the barrier
+// that publishes the data.
+__device__ inline void lds_dma16(const void* src, uint32_t lds_wave) {
+  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off"
+               :
+               : "v"(src), "s"(lds_wave)
+               : "memory", "m0");
+}
+
+__device__ inline uint32_t lds_addr(const void* p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) unsigned char*)p;
+}
+
+// s_waitcnt vmcnt(0): every vector memory load of this thread (LDS DMA included) landed.
+__device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0f70); }
+
 // Work split: a workgroup owns a 32-row x 64-column output tile of one token
 // and all DK kept digits; its NW = ceil(DK/3) waves each take at most 3 digits
 // (the role of a wave rotates with the tile so that heavier roles spread over
@@ -121,16 +142,20 @@ mask_kernel(Batch) {
   static_assert(!RAW || DK == D, "raw output keeps every digit");
   constexpr int NW = (DK + 2) / 3;
   constexpr int DPW = 3;
+  constexpr int NT = 64 * NW;
   // LDS: per kept digit four copies of the chunk's window, copy s shifted by s bytes
-  // (every fragment becomes an aligned-dword read), plus the 32-row weight tile;
+  // (every fragment becomes an aligned-dword read), then two weight-tile buffers
+  // (rows of 17 16-byte slots, the last one padding) filled by LDS DMA;
   // after the k-loop the same memory holds the per-wave partial sums.
   constexpr int kWinLds = DK * kDigitWords * 4;
-  constexpr int kWLds = 32 * kWRowWords * 4;
+  constexpr int kWSlots = 32 * (kWRowWords / 4);           // 544 16-byte slots per tile
+  constexpr int kWIters = (kWSlots + NT - 1) / NT;         // DMA passes per thread
+  constexpr int kWBuf = kWIters * NT * 16;                 // bytes per weight buffer
   constexpr int kPartLds = NW * 16 * 64 * 8;
-  constexpr int kLds = kWinLds + kWLds > kPartLds ? kWinLds + kWLds : kPartLds;
+  constexpr int kLds = kWinLds + 2 * kWBuf > kPartLds ? kWinLds + 2 * kWBuf : kPartLds;
+  static_assert(kWRowWords == 68, "weight rows of 16 data slots and one pad slot");
   __shared__ __attribute__((aligned(16))) unsigned char smem[kLds];
   uint32_t* win = reinterpret_cast<uint32_t*>(smem);
-  uint32_t(*wt)[kWRowWords] = reinterpret_cast<uint32_t(*)[kWRowWords]>(smem + kWinLds);
   int64_t* part = reinterpret_cast<int64_t*>(smem);
 
   const BatchPtr bt = kernarg_batch();
@@ -179,7 +204,9 @@ mask_kernel(Batch) {
     ep[d] = (lds_u32)(win + (dlo + d) * kDigitWords + copy_base(sh) + (lb >> 2));
     asm volatile("" : "+v"(ep[d]));
   }
-  const uint32_t* wl = &wt[c][4 * g];
+  // weight fragment of this lane in buffer b: row c, bytes 16 g + 32 st
+  const uint32_t* wl0 = reinterpret_cast<const uint32_t*>(smem + kWinLds) + c * kWRowWords + 4 * g;
+  const uint32_t* wl = wl0;
   v4i fprev[DPW];
   // Operands of one k-step: the weight fragment and a new Toeplitz fragment per digit.
   struct Frags {
@@ -206,71 +233,126 @@ mask_kernel(Batch) {
   };
 
   const uint32_t L = __builtin_amdgcn_readfirstlane(m.L);
-  for (uint32_t i = 0; i < L; ++i) {
-    const uint32_t kb = __builtin_amdgcn_readfirstlane(min(N, m.k - i * N));
-    const uint32_t kp = (kb + 63u) & ~63u;  // the weight rows are zero up to a multiple of 64
-    for (uint32_t kc = 0; kc < kp; kc += kKC) {
-      const uint32_t klen = __builtin_amdgcn_readfirstlane(min((uint32_t)kKC, kp - kc));
-      // plane bytes [N + kc - n0 - 64, N + kc - n0 + klen) hold every Toeplitz
-      // entry of rows [kc, kc + klen) and columns [n0, n0 + 64)
-      const uint32_t wstart = N + kc - n0 - 64;
-      __syncthreads();
-      {
-        // Stage the windows (four byte-shifted copies per digit, 16 plane bytes per
-        // thread and pass) and the weight tile. Window bytes past the plane are
-        // read from the workspace that follows it and never used: the Toeplitz
-        // entries of the chunk end at plane byte N + kp - n0 - 1 < 2N.
-        constexpr int kNT = 64 * NW;
-        constexpr int kQuads = kCopyWords / 4;
-        constexpr int kW16 = kKC / 16;
-        const int8_t* wsrc = m.w + (size_t)jb * m.kw + (size_t)i * N + kc;
-        const uint32_t wlim = m.kw - i * N - kc;
-        const int8_t* planes = emask + (((size_t)t * D + l0) * L + i) * 2 * N + wstart;
-        for (uint32_t x = threadIdx.x; x < (uint32_t)(DK * kQuads); x += kNT) {
-          const uint32_t d = x / kQuads, v = x % kQuads;
-          const int8_t* src = planes + (size_t)d * L * 2 * N + 16 * v;
-          const uint4 q = *(const uint4*)src;
-          const uint32_t q4 = *(const uint32_t*)(src + 16);
-          uint32_t* wd = win + d * kDigitWords + 4 * v;
-          *(uint4*)(wd + copy_base(0)) = q;
+  // Staging of chunk (i, kc): plane bytes [N + kc - n0 - 64, N + kc - n0 + kKC) hold
+  // every Toeplitz entry of rows [kc, kc + kKC) and columns [n0, n0 + 64). Window
+  // bytes past the plane are read from the workspace that follows it and never
+  // used (the chunk's Toeplitz entries end at plane byte N + kp - n0 - 1 < 2N).
+  // Windows: loaded 16 plane bytes (+ the next dword) per item into registers,
+  // written as four shifted copies. Weights: LDS DMA into one of two buffers.
+  constexpr int kQuads = kCopyWords / 4;
+  constexpr int kItems = DK * kQuads;
+  constexpr int kWinRegs = (kItems + NT - 1) / NT;
+  static_assert(kWinRegs == 1, "one window item per thread");
+  struct WinRegs {
+    uint4 q[kWinRegs];
+    uint32_t q4[kWinRegs];
+  };
+  auto win_load = [&](uint32_t i, uint32_t kc, WinRegs& r) __attribute__((always_inline)) {
+    const int8_t* planes = emask + (((size_t)t * D + l0) * L + i) * 2 * N + (N + kc - n0 - 64);
 #pragma unroll
-          for (int sft = 1; sft < 4; ++sft)
-            *(uint4*)(wd + copy_base(sft)) = make_uint4(__builtin_amdgcn_alignbyte(q.y, q.x, sft),
-                                                        __builtin_amdgcn_alignbyte(q.z, q.y, sft),
-                                                        __builtin_amdgcn_alignbyte(q.w, q.z, sft),
-                                                        __builtin_amdgcn_alignbyte(q4, q.w, sft));
-        }
-        for (uint32_t x = threadIdx.x; x < 32u * kW16; x += kNT) {
-          const uint32_t r = x / kW16, o = x % kW16;
-          *(uint4*)&wt[r][4 * o] = 16 * o < wlim
-                                       ? *(const uint4*)(wsrc + (size_t)r * m.kw + 16 * o)
-                                       : make_uint4(0, 0, 0, 0);
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int d = 0; d < DPW; ++d)
-        if (d < cnt) fprev[d] = toeplitz_frag(ep[d] - 8);
-      if constexpr (FULL) {
-        // full chunk: straight-line code with immediate LDS offsets; the operands of
-        // step st + 1 are requested before the matrix instructions of step st
-        Frags cur = load(0);
-#pragma unroll
-        for (int st = 0; st < kKC / 32; ++st) {
-          Frags nxt;
-          if (st + 1 < kKC / 32) nxt = load(st + 1);
-          mma(cur);
-          cur = nxt;
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      } else {
-        for (uint32_t st = 0; st < klen / 32; st += 2) {  // klen is a multiple of 64
-          const Frags f0 = load(st), f1 = load(st + 1);
-          mma(f0);
-          mma(f1);
-        }
+    for (int it = 0; it < kWinRegs; ++it) {
+      const uint32_t x = it * NT + threadIdx.x;
+      if (it == 0 || x < (uint32_t)kItems) {
+        const uint32_t d = x / kQuads, v = x % kQuads;
+        const int8_t* src = planes + (size_t)d * L * 2 * N + 16 * v;
+        r.q[it] = *(const uint4*)src;
+        r.q4[it] = *(const uint32_t*)(src + 16);
       }
     }
+  };
+  auto win_store = [&](const WinRegs& r) __attribute__((always_inline)) {
+#pragma unroll
+    for (int it = 0; it < kWinRegs; ++it) {
+      const uint32_t x = it * NT + threadIdx.x;
+      if (x < (uint32_t)kItems) {
+        const uint32_t d = x / kQuads, v = x % kQuads;
+        const uint4 q = r.q[it];
+        const uint32_t q4 = r.q4[it];
+        uint32_t* wd = win + d * kDigitWords + 4 * v;
+        *(uint4*)(wd + copy_base(0)) = q;
+#pragma unroll
+        for (int sft = 1; sft < 4; ++sft)
+          *(uint4*)(wd + copy_base(sft)) = make_uint4(__builtin_amdgcn_alignbyte(q.y, q.x, sft),
+                                                      __builtin_amdgcn_alignbyte(q.z, q.y, sft),
+                                                      __builtin_amdgcn_alignbyte(q.w, q.z, sft),
+                                                      __builtin_amdgcn_alignbyte(q4, q.w, sft));
+      }
+    }
+  };
+  const uint32_t wave_lds = __builtin_amdgcn_readfirstlane(wave * 64 * 16);
+  auto w_dma = [&](int b, uint32_t i, uint32_t kc) __attribute__((always_inline)) {
+    const int8_t* wsrc = m.w + (size_t)jb * m.kw + (size_t)i * N + kc;
+    const uint32_t wlim = m.kw - i * N - kc;  // row bytes left from kc
+    const uint32_t base = lds_addr(smem + kWinLds + b * kWBuf);
+#pragma unroll
+    for (int it = 0; it < kWIters; ++it) {
+      const uint32_t x = it * NT + threadIdx.x;   // slot: row x / 17, position x % 17
+      const uint32_t r = x / 17, pos = x % 17;
+      const bool data = r < 32 && pos < 16 && 16 * pos < wlim;
+      const int8_t* src = wsrc + (r < 32 ? r * m.kw : 0) + (data ? 16 * pos : 0);
+      lds_dma16(src, __builtin_amdgcn_readfirstlane(base + it * NT * 16) + wave_lds);
+    }
+  };
+  auto compute = [&](int b, uint32_t klen) __attribute__((always_inline)) {
+    wl = wl0 + b * (kWBuf / 4);
+#pragma unroll
+    for (int d = 0; d < DPW; ++d)
+      if (d < cnt) fprev[d] = toeplitz_frag(ep[d] - 8);
+    if constexpr (FULL) {
+      // full chunk: straight-line code with immediate LDS offsets; the operands of
+      // step st + 1 are requested before the matrix instructions of step st
+      Frags cur = load(0);
+#pragma unroll
+      for (int st = 0; st < kKC / 32; ++st) {
+        Frags nxt;
+        if (st + 1 < kKC / 32) nxt = load(st + 1);
+        mma(cur);
+        cur = nxt;
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+      for (uint32_t st = 0; st < klen / 32; st += 2) {  // klen is a multiple of 64
+        const Frags f0 = load(st), f1 = load(st + 1);
+        mma(f0);
+        mma(f1);
+      }
+    }
+  };
+
+  // Chunks in order (block i, offset kc). The next chunk's window loads and weight
+  // DMA are issued before the matrix-core work on the current one.
+  WinRegs wr;
+  win_load(0, 0, wr);
+  w_dma(0, 0, 0);
+  win_store(wr);
+  wait_vmem();
+  __syncthreads();
+  uint32_t ci = 0, ckc = 0;
+  int buf = 0;
+  for (;;) {
+    const uint32_t kb = __builtin_amdgcn_readfirstlane(min(N, m.k - ci * N));
+    const uint32_t kp = (kb + 63u) & ~63u;  // the weight rows are zero up to a multiple of 64
+    const uint32_t klen = min((uint32_t)kKC, kp - ckc);
+    uint32_t ni = ci, nkc = ckc + kKC;
+    if (nkc >= kp) {
+      ++ni;
+      nkc = 0;
+    }
+    const bool more = ni < L;
+    if (more) {
+      win_load(ni, nkc, wr);
+      w_dma(buf ^ 1, ni, nkc);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    compute(buf, klen);
+    if (!more) break;
+    __syncthreads();  // the windows of this chunk are no longer read
+    win_store(wr);
+    wait_vmem();      // the weight DMA of the next chunk landed
+    __syncthreads();
+    ci = ni;
+    ckc = nkc;
+    buf ^= 1;
   }
 
   // accumulator element e of this lane: row jb + 8(e/4) + 4g + e%4, column n0 + 32b + c.
