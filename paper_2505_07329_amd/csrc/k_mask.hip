@@ -27,16 +27,18 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kKC = 256;                 // k-chunk staged in LDS per pass (8 k-steps)
 // LDS layout of one digit window: four copies, copy s shifted by s bytes, each
-// kCopyWords long, back to back. A lane's block-0 fragment at k-step st starts at
-// copy word (lb >> 2) + 8 st with lb = 16 g - c + 64 in [33, 80], so the words read
-// span [0, 80) (the one-step-late block-1 fragment included). Offsets that are
-// multiples of 80 dwords keep the staging stores 16-byte aligned and place the
-// nine consecutive dwords that a half-wave reads from each copy in one fragment
-// load on distinct banks, for 32- and 64-bank LDS.
+// kCopyWords long, at dword offsets 0, 80, 168, 248. A lane's block-0 fragment at
+// k-step st starts at copy word (lb >> 2) + 8 st with lb = 16 g - c + 64 in
+// [33, 80], so the words read span [0, 80) (the one-step-late block-1 fragment
+// included). A fragment is read as two 8-byte halves, which LDS serves 16 lanes
+// at a time over 32 banks; in each 16-lane group four lanes read five consecutive
+// dwords from each copy, and the offsets put the four groups of five on distinct
+// banks (any multiple of 80 would put two copies on the same banks). The offsets
+// are multiples of four dwords, so the staging stores are aligned 16-byte stores.
 constexpr int kCopyWords = 80;
 static_assert(80 / 4 + 8 * (kKC / 32 - 1) + 3 < kCopyWords, "window covers every fragment");
-__host__ __device__ constexpr int copy_base(int s) { return kCopyWords * s; }
-constexpr int kDigitWords = 4 * kCopyWords;
+__host__ __device__ constexpr int copy_base(int s) { return s == 0 ? 0 : s == 1 ? 80 : s == 2 ? 168 : 248; }
+constexpr int kDigitWords = 248 + kCopyWords;  // 328
 constexpr int kWRowWords = kKC / 4 + 4;    // LDS row pitch of the weight tile (dwords)
 
 // round(U * G) mod 2^32 where U is a signed 128-bit integer (u0..u3) and
