@@ -26,17 +26,18 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kKC = 256;                 // k-chunk staged in LDS per pass (8 k-steps)
-// LDS layout of one digit window: four copies, copy s shifted by s bytes, each
-// kCopyWords long, at dword offsets 0, 80, 168, 248. A lane's block-0 fragment at
-// k-step st starts at copy word (lb >> 2) + 8 st with lb = 16 g - c + 64 in
-// [33, 80], so the words read span [0, 80) (the one-step-late block-1 fragment
-// included). A fragment is read as two 8-byte halves, which LDS serves 16 lanes
-// at a time over 32 banks; in each 16-lane group four lanes read five consecutive
-// dwords from each copy, and the offsets put the four groups of five on distinct
-// banks (any multiple of 80 would put two copies on the same banks). The offsets
-// are multiples of four dwords, so the staging stores are aligned 16-byte stores.
+// LDS layout of one digit window: four copies of kCopyWords dwords at dword offsets
+// 0, 80, 168, 248. Copy 0 holds the window as is; copy s = 1..3 holds it shifted
+// by s - 4 bytes (word u = window bytes [4u + s - 4, 4u + s)). A lane's 16-byte
+// fragment starts at window byte lb + 32 st (lb = 16 g - c + 64 in [33, 80]); it
+// is the aligned quad at word ceil(lb / 4) + 8 st of copy lb & 3, so the words
+// read span [1, 80) for every copy. A fragment is read as dword pairs, which LDS
+// serves as dword accesses of 32 lanes over 32 banks: per half-wave each copy is
+// read at eight consecutive words starting at the same index, and offsets in four
+// distinct residue classes mod 32 in steps of 8 put the four copies on disjoint
+// banks. The offsets are multiples of four dwords (aligned 16-byte staging stores).
 constexpr int kCopyWords = 80;
-static_assert(80 / 4 + 8 * (kKC / 32 - 1) + 3 < kCopyWords, "window covers every fragment");
+static_assert((80 + 3) / 4 + 8 * (kKC / 32 - 1) + 3 < kCopyWords, "window covers every fragment");
 __host__ __device__ constexpr int copy_base(int s) { return s == 0 ? 0 : s == 1 ? 80 : s == 2 ? 168 : 248; }
 constexpr int kDigitWords = 248 + kCopyWords;  // 328
 constexpr int kWRowWords = kKC / 4 + 4;    // LDS row pitch of the weight tile (dwords)
@@ -203,7 +204,7 @@ mask_kernel(Batch) {
   lds_u32 ep[DPW];
 #pragma unroll
   for (int d = 0; d < DPW; ++d) {
-    ep[d] = (lds_u32)(win + (dlo + d) * kDigitWords + copy_base(sh) + (lb >> 2));
+    ep[d] = (lds_u32)(win + (dlo + d) * kDigitWords + copy_base(sh) + ((lb + 3) >> 2));
     asm volatile("" : "+v"(ep[d]));
   }
   // weight fragment of this lane in buffer b: row c, bytes 16 g + 32 st
@@ -236,49 +237,44 @@ mask_kernel(Batch) {
 
   const uint32_t L = __builtin_amdgcn_readfirstlane(m.L);
   // Staging of chunk (i, kc): plane bytes [N + kc - n0 - 64, N + kc - n0 + kKC) hold
-  // every Toeplitz entry of rows [kc, kc + kKC) and columns [n0, n0 + 64). Window
-  // bytes past the plane are read from the workspace that follows it and never
-  // used (the chunk's Toeplitz entries end at plane byte N + kp - n0 - 1 < 2N).
-  // Windows: loaded 16 plane bytes (+ the next dword) per item into registers,
-  // written as four shifted copies. Weights: LDS DMA into one of two buffers.
+  // every Toeplitz entry of rows [kc, kc + kKC) and columns [n0, n0 + 64). A chunk
+  // shorter than kKC reads window bytes past the plane from the workspace that
+  // follows it; they are never used (its Toeplitz entries end at plane byte
+  // N + kp - n0 - 1 < 2N).
+  // Windows: loaded 16 plane bytes (+ the dword before them) per item into
+  // registers, written as four copies. Weights: LDS DMA into one of two buffers.
   constexpr int kQuads = kCopyWords / 4;
   constexpr int kItems = DK * kQuads;
   constexpr int kWinRegs = (kItems + NT - 1) / NT;
   static_assert(kWinRegs == 1, "one window item per thread");
   struct WinRegs {
-    uint4 q[kWinRegs];
-    uint32_t q4[kWinRegs];
+    uint4 q;
+    uint32_t qp;
   };
   auto win_load = [&](uint32_t i, uint32_t kc, WinRegs& r) __attribute__((always_inline)) {
     const int8_t* planes = emask + (((size_t)t * D + l0) * L + i) * 2 * N + (N + kc - n0 - 64);
-#pragma unroll
-    for (int it = 0; it < kWinRegs; ++it) {
-      const uint32_t x = it * NT + threadIdx.x;
-      if (it == 0 || x < (uint32_t)kItems) {
-        const uint32_t d = x / kQuads, v = x % kQuads;
-        const int8_t* src = planes + (size_t)d * L * 2 * N + 16 * v;
-        r.q[it] = *(const uint4*)src;
-        r.q4[it] = *(const uint32_t*)(src + 16);
-      }
+    const uint32_t x = threadIdx.x;
+    if (x < (uint32_t)kItems) {
+      const uint32_t d = x / kQuads, v = x % kQuads;
+      const int8_t* src = planes + (size_t)d * L * 2 * N + 16 * v;
+      r.q = *(const uint4*)src;
+      // word -1 of the window only feeds word 0 of copies 1..3, which no fragment reads
+      r.qp = *(const uint32_t*)(v ? src - 4 : src);
     }
   };
   auto win_store = [&](const WinRegs& r) __attribute__((always_inline)) {
+    const uint32_t x = threadIdx.x;
+    if (x < (uint32_t)kItems) {
+      const uint32_t d = x / kQuads, v = x % kQuads;
+      const uint4 q = r.q;
+      uint32_t* wd = win + d * kDigitWords + 4 * v;
+      *(uint4*)(wd + copy_base(0)) = q;
 #pragma unroll
-    for (int it = 0; it < kWinRegs; ++it) {
-      const uint32_t x = it * NT + threadIdx.x;
-      if (x < (uint32_t)kItems) {
-        const uint32_t d = x / kQuads, v = x % kQuads;
-        const uint4 q = r.q[it];
-        const uint32_t q4 = r.q4[it];
-        uint32_t* wd = win + d * kDigitWords + 4 * v;
-        *(uint4*)(wd + copy_base(0)) = q;
-#pragma unroll
-        for (int sft = 1; sft < 4; ++sft)
-          *(uint4*)(wd + copy_base(sft)) = make_uint4(__builtin_amdgcn_alignbyte(q.y, q.x, sft),
-                                                      __builtin_amdgcn_alignbyte(q.z, q.y, sft),
-                                                      __builtin_amdgcn_alignbyte(q.w, q.z, sft),
-                                                      __builtin_amdgcn_alignbyte(q4, q.w, sft));
-      }
+      for (int sft = 1; sft < 4; ++sft)
+        *(uint4*)(wd + copy_base(sft)) = make_uint4(__builtin_amdgcn_alignbyte(q.x, r.qp, sft),
+                                                    __builtin_amdgcn_alignbyte(q.y, q.x, sft),
+                                                    __builtin_amdgcn_alignbyte(q.z, q.y, sft),
+                                                    __builtin_amdgcn_alignbyte(q.w, q.z, sft));
     }
   };
   const uint32_t wave_lds = __builtin_amdgcn_readfirstlane(wave * 64 * 16);
