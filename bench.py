@@ -38,8 +38,8 @@ INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix peak, 5.0 POP/s
 # ratio of known to counted bytes of a plain copy kernel in the same run
 # (--copy-calibration). Valid for the kernel source it was taken on (sha256 of
 # csrc/k_mask.hip); for any other source the roofline reports traffic as null.
-MASK_TRAFFIC = {"fetch_bytes": 4378030701, "write_bytes": 4767445499,
-                "k_mask_sha256": "8be813ebf550814d15155e3952764602aa2022b8fc9a9ce14a39ad401a5cf23e"}
+MASK_TRAFFIC = {"fetch_bytes": 4382392135, "write_bytes": 4766662645,
+                "k_mask_sha256": "b71d09264e517098c1179f16657d1e4fa62f1eaae851294a6d0fdb5115986154"}
 
 
 def mask_traffic():
