@@ -80,12 +80,23 @@ int rlwe_params_destroy(rlwe_ctx* ctx);
 /* Flags of rlwe_weights_load */
 #define RLWE_W_FWD 1u       /* keep W for products W.[x] */
 #define RLWE_W_TRANSPOSE 2u /* keep W^T for products W^T.[g] (backward pass) */
+#define RLWE_W_NTT 4u       /* mask product by number-theoretic transforms (N = 4096 only) */
+#define RLWE_W_TOEPLITZ 8u  /* mask product on the int8 matrix cores (digit planes) */
 
-/* Make the clear weights resident on the device (Sec. 4.3, reversed block
- * encoding is implied by the kernels; no NTT tables are needed).
+/* Mask-product methods (rlwe_weights_method). Both give the same bits. */
+#define RLWE_METHOD_TOEPLITZ 0u
+#define RLWE_METHOD_NTT 1u
+
+/* Make the clear weights resident on the device (Sec. 4.3: block i of row j is
+ * used in the reversed encoding w_hat_ij[k] = w_j[iN + N - 1 - k]).
  *   W_dev   device pointer, int8 row-major [d_out][d_in], values in [-127, 127]
  *           (symmetric quantization, Sec. 4.2); read during the call only
- *   flags   RLWE_W_FWD and/or RLWE_W_TRANSPOSE
+ *   flags   RLWE_W_FWD and/or RLWE_W_TRANSPOSE, plus at most one method flag:
+ *           RLWE_W_NTT keeps the reversed blocks in the NTT domain per prime
+ *           (rows * L * P * N * 16 bytes; RLWE_EPARAM unless N = 4096),
+ *           RLWE_W_TOEPLITZ keeps int8 only; without one, each orientation uses
+ *           the NTT method when N = 4096 and its contraction spans two or more
+ *           blocks of N, the matrix-core method otherwise
  * Validation: 1 <= d_out, d_in <= 65536; the exact 128-bit accumulation needs
  * 127 * d * q / 2 < 2^127 for the contraction length d (d_in forward, d_out
  * transposed) -> RLWE_ESHAPE. Overflow: returns RLWE_EOVERFLOW if 127 times the
@@ -198,6 +209,11 @@ int rlwe_profile_end(rlwe_ctx* ctx, rlwe_kernel_times* out);
  * (7 for one prime, 14 for two). Host pointers; for work accounting. */
 int rlwe_weights_digits(const rlwe_weights* w, uint32_t transpose, uint32_t* kept,
                         uint32_t* total);
+
+/* Mask-product method of one loaded orientation: *method = RLWE_METHOD_TOEPLITZ
+ * or RLWE_METHOD_NTT (host pointer). RLWE_EINVAL for null arguments or an
+ * orientation that was not loaded. */
+int rlwe_weights_method(const rlwe_weights* w, uint32_t transpose, uint32_t* method);
 
 /* Description of the last error on this thread ("" if none). */
 const char* rlwe_last_error(void);

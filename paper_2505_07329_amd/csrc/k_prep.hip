@@ -82,9 +82,11 @@ __global__ void __launch_bounds__(256) prep_kernel(Batch) {
 #pragma unroll
   for (int l = 0; l < D; ++l) {
     const size_t plane = ((size_t)t * D + l) * L + i;
-    int8_t* em = a.emask + plane * 2 * N;
-    em[N + k] = da[l];
-    em[k] = (int8_t)(-da[l]);
+    if (a.method == 0) {  // the NTT method needs the body digits only
+      int8_t* em = a.emask + plane * 2 * N;
+      em[N + k] = da[l];
+      em[k] = (int8_t)(-da[l]);
+    }
     a.ebody[plane * N + k] = db[l];
   }
 }

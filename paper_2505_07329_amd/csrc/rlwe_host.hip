@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "rlwe.h"
 #include "rlwe_internal.hpp"
@@ -98,6 +99,9 @@ struct rlwe_ctx {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   Profiler* prof = nullptr;
+  bool ntt_ok = false;      // the NTT method is available (N = kNttN)
+  NttConst ntt{};
+  uint64_t* ntt_tables = nullptr;
 };
 
 namespace {
@@ -140,6 +144,8 @@ struct Mat {
   MatArgs args{};
   SwitchConst sc{};
   uint32_t max_l1 = 0;
+  bool ntt = false;         // mask product by NTT (otherwise digit planes on the matrix cores)
+  uint64_t* what = nullptr; // NTT method: [rows][L][P][N] (value, Shoup companion)
 };
 
 }  // namespace
@@ -218,11 +224,64 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(RLWE_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Workspace of one product: mask digit planes then body digit planes.
-size_t ws_item(const RingConst& rc, const MatArgs& m, uint32_t T) {
-  const size_t em = align_up((size_t)T * rc.D * m.L * 2 * rc.N, 256);
-  const size_t eb = align_up((size_t)T * rc.D * m.L * rc.N, 256);
-  return em + eb;
+// Workspace of one product: mask digit planes (matrix-core method) or transformed
+// masks (NTT method), then body digit planes.
+size_t ws_mask_bytes(const RingConst& rc, const MatArgs& m, uint32_t T, bool ntt) {
+  return ntt ? align_up((size_t)T * m.L * rc.P * rc.N * 8, 256)
+             : align_up((size_t)T * rc.D * m.L * 2 * rc.N, 256);
+}
+size_t ws_item(const RingConst& rc, const MatArgs& m, uint32_t T, bool ntt) {
+  return ws_mask_bytes(rc, m, T, ntt) + align_up((size_t)T * rc.D * m.L * rc.N, 256);
+}
+
+uint32_t bitrev_h(uint32_t x, uint32_t bits) {
+  uint32_t r = 0;
+  for (uint32_t i = 0; i < bits; ++i) r |= ((x >> i) & 1u) << (bits - 1 - i);
+  return r;
+}
+
+// Twiddle tables of the NTT method: per prime psi^bitrev(k) and psi^-bitrev(k) with
+// Shoup companions, psi a primitive 2N-th root of unity (psi^N = -1 mod q_p).
+int build_ntt(rlwe_ctx* ctx) {
+  const RingConst& rc = ctx->rc;
+  const uint32_t N = rc.N;
+  const size_t per = (size_t)2 * N;  // (value, companion) pairs
+  std::vector<uint64_t> host(per * 2 * rc.P);
+  for (uint32_t pi = 0; pi < rc.P; ++pi) {
+    const uint64_t q = rc.q[pi];
+    uint64_t psi = 0;
+    for (uint64_t g = 2; g < 100000 && !psi; ++g) {
+      const uint64_t c = powmod_h(g, (q - 1) / (2 * N), q);
+      if (powmod_h(c, N, q) == q - 1) psi = c;
+    }
+    if (!psi) return fail(RLWE_EPARAM, "no primitive 2N-th root of unity found mod %llu", (unsigned long long)q);
+    const uint64_t psi_inv = powmod_h(psi, q - 2, q);
+    uint64_t* f = host.data() + (2 * pi) * per;
+    uint64_t* v = host.data() + (2 * pi + 1) * per;
+    for (uint32_t k = 0; k < N; ++k) {
+      const uint32_t e = bitrev_h(k, rc.logN);
+      f[2 * k] = powmod_h(psi, e, q);
+      f[2 * k + 1] = (uint64_t)(((u128)f[2 * k] << 64) / q);
+      v[2 * k] = powmod_h(psi_inv, e, q);
+      v[2 * k + 1] = (uint64_t)(((u128)v[2 * k] << 64) / q);
+    }
+    const uint64_t ninv = powmod_h(N % q, q - 2, q);
+    ctx->ntt.ninv[pi] = ninv;
+    ctx->ntt.ninv_shoup[pi] = (uint64_t)(((u128)ninv << 64) / q);
+    const uint64_t c = mulmod_h(ninv, rc.crt_inv[pi], q);
+    ctx->ntt.crt[pi] = c;
+    ctx->ntt.crt_shoup[pi] = (uint64_t)(((u128)c << 64) / q);
+  }
+  hipError_t e = hipMalloc(&ctx->ntt_tables, host.size() * 8);
+  if (e != hipSuccess) return fail(RLWE_ENOMEM, "hipMalloc(NTT tables): %s", hipGetErrorString(e));
+  e = hipMemcpy(ctx->ntt_tables, host.data(), host.size() * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "NTT tables upload");
+  for (uint32_t pi = 0; pi < rc.P; ++pi) {
+    ctx->ntt.fwd[pi] = ctx->ntt_tables + (2 * pi) * per;
+    ctx->ntt.inv[pi] = ctx->ntt_tables + (2 * pi + 1) * per;
+  }
+  ctx->ntt_ok = true;
+  return RLWE_OK;
 }
 
 int ensure_ws(rlwe_ctx* ctx, size_t bytes, hipStream_t s) {
@@ -304,6 +363,14 @@ int rlwe_params_init(const rlwe_params* p, int hip_device, rlwe_ctx** out) {
   ctx->device = hip_device;
   ctx->log2_t = p->log2_t;
   ctx->rc = rc;
+  if (N == kNttN) {
+    const int r = build_ntt(ctx);
+    if (r != RLWE_OK) {
+      if (ctx->ntt_tables) hipFree(ctx->ntt_tables);
+      delete ctx;
+      return r;
+    }
+  }
   *out = ctx;
   return ok();
 }
@@ -354,6 +421,10 @@ int rlwe_params_destroy(rlwe_ctx* ctx) {
     }
     delete ctx->prof;
   }
+  if (ctx->ntt_tables) {
+    hipSetDevice(ctx->device);
+    hipFree(ctx->ntt_tables);
+  }
   if (ctx->ws) {
     hipSetDevice(ctx->device);
     hipError_t e = hipFree(ctx->ws);
@@ -368,12 +439,14 @@ int rlwe_params_destroy(rlwe_ctx* ctx) {
 
 static void free_mat(Mat& m) {
   if (m.w) hipFree(m.w);
+  if (m.what) hipFree(m.what);
   m.w = nullptr;
+  m.what = nullptr;
   m.present = false;
 }
 
 static int load_mat(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32_t d_in,
-                    bool transpose, hipStream_t s, Mat& m) {
+                    bool transpose, int method, hipStream_t s, Mat& m) {
   const RingConst& rc = ctx->rc;
   MatArgs& a = m.args;
   a.rows = transpose ? d_in : d_out;
@@ -417,6 +490,19 @@ static int load_mat(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32_t
                 transpose ? " (transposed)" : "");
   const int rc2 = make_switch_const(rc, mx, &m.sc);
   if (rc2 != RLWE_OK) return rc2;
+  // method: NTT when asked for, or by default when available and K spans several
+  // blocks (the transform cost per output does not grow with K, the matrix-core
+  // cost does)
+  m.ntt = method == 1 || (method == 0 && ctx->ntt_ok && a.L >= 2);
+  if (m.ntt) {
+    if (!ctx->ntt_ok) return fail(RLWE_EPARAM, "the NTT method needs N = %u", kNttN);
+    const size_t bytes = (size_t)a.rows * a.L * rc.P * rc.N * 16;
+    e = hipMalloc(&m.what, bytes);
+    if (e != hipSuccess) return fail(RLWE_ENOMEM, "hipMalloc(NTT weights, %zu bytes): %s", bytes, hipGetErrorString(e));
+    e = launch_ntt_weights(a, ctx->ntt, rc, m.what, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "NTT weights kernel");
+  }
   m.present = true;
   return RLWE_OK;
 }
@@ -425,8 +511,13 @@ int rlwe_weights_load(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32
                       uint32_t flags, rlwe_stream_t stream, rlwe_weights** out) {
   if (!ctx || !W_dev || !out) return fail(RLWE_EINVAL, "rlwe_weights_load: null argument");
   *out = nullptr;
-  if (flags == 0 || (flags & ~(RLWE_W_FWD | RLWE_W_TRANSPOSE)))
+  if ((flags & (RLWE_W_FWD | RLWE_W_TRANSPOSE)) == 0 ||
+      (flags & ~(RLWE_W_FWD | RLWE_W_TRANSPOSE | RLWE_W_NTT | RLWE_W_TOEPLITZ)) ||
+      ((flags & RLWE_W_NTT) && (flags & RLWE_W_TOEPLITZ)))
     return fail(RLWE_EINVAL, "rlwe_weights_load: flags 0x%x invalid", flags);
+  if ((flags & RLWE_W_NTT) && !ctx->ntt_ok)
+    return fail(RLWE_EPARAM, "RLWE_W_NTT needs N = %u (N = %u)", kNttN, ctx->rc.N);
+  const int method = (flags & RLWE_W_NTT) ? 1 : (flags & RLWE_W_TOEPLITZ) ? 2 : 0;
   if (d_out < 1 || d_in < 1 || d_out > 65536 || d_in > 65536)
     return fail(RLWE_ESHAPE, "d_out = %u, d_in = %u must lie in [1, 65536]", d_out, d_in);
   hipError_t e = hipSetDevice(ctx->device);
@@ -436,8 +527,9 @@ int rlwe_weights_load(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32
   w->ctx = ctx;
   hipStream_t s = (hipStream_t)stream;
   int r = RLWE_OK;
-  if (flags & RLWE_W_FWD) r = load_mat(ctx, W_dev, d_out, d_in, false, s, w->fwd);
-  if (r == RLWE_OK && (flags & RLWE_W_TRANSPOSE)) r = load_mat(ctx, W_dev, d_out, d_in, true, s, w->tr);
+  if (flags & RLWE_W_FWD) r = load_mat(ctx, W_dev, d_out, d_in, false, method, s, w->fwd);
+  if (r == RLWE_OK && (flags & RLWE_W_TRANSPOSE))
+    r = load_mat(ctx, W_dev, d_out, d_in, true, method, s, w->tr);
   if (r != RLWE_OK) {
     std::string msg = g_err;
     hipStreamSynchronize(s);
@@ -465,7 +557,7 @@ size_t rlwe_workspace_bytes(const rlwe_ctx* ctx, const rlwe_weights* w, uint32_t
   if (!ctx || !w) return 0;
   const Mat& m = transpose ? w->tr : w->fwd;
   if (!m.present) return 0;
-  return ws_item(ctx->rc, m.args, tokens);
+  return ws_item(ctx->rc, m.args, tokens, m.ntt);
 }
 
 int rlwe_weights_digits(const rlwe_weights* w, uint32_t transpose, uint32_t* kept,
@@ -475,6 +567,14 @@ int rlwe_weights_digits(const rlwe_weights* w, uint32_t transpose, uint32_t* kep
   if (!m.present) return fail(RLWE_EINVAL, "rlwe_weights_digits: orientation not loaded");
   *kept = m.sc.dk;
   *total = w->ctx->rc.D;
+  return ok();
+}
+
+int rlwe_weights_method(const rlwe_weights* w, uint32_t transpose, uint32_t* method) {
+  if (!w || !method) return fail(RLWE_EINVAL, "rlwe_weights_method: null argument");
+  const Mat& m = transpose ? w->tr : w->fwd;
+  if (!m.present) return fail(RLWE_EINVAL, "rlwe_weights_method: orientation not loaded");
+  *method = m.ntt ? RLWE_METHOD_NTT : RLWE_METHOD_TOEPLITZ;
   return ok();
 }
 
@@ -508,7 +608,7 @@ static size_t batch_ws(const rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n)
   size_t total = 0;
   for (uint32_t i = 0; i < n; ++i) {
     const Mat& m = d[i].transpose ? d[i].w->tr : d[i].w->fwd;
-    total += ws_item(ctx->rc, m.args, d[i].tokens);
+    total += ws_item(ctx->rc, m.args, d[i].tokens, m.ntt);
   }
   return total;
 }
@@ -534,6 +634,7 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
   if (cnt == 0) return RLWE_OK;
   Batch all{};
   all.rc = rc;
+  all.ntt = ctx->ntt;
   all.raw = raw;
   all.force_exact = (flags & RLWE_OUT_FORCE_EXACT) ? 1 : 0;
   size_t off = 0;
@@ -547,37 +648,51 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
       it.sc.l0 = 0;
       it.sc.dk = rc.D;
     }
+    it.method = m.ntt ? 1 : 0;
+    it.what = m.what;
     it.ct = dd.ct_in;
-    it.emask = (int8_t*)(ws + off);
-    it.ebody = (int8_t*)(ws + off + align_up((size_t)dd.tokens * rc.D * m.args.L * 2 * rc.N, 256));
-    off += ws_item(rc, m.args, dd.tokens);
+    const size_t mask_bytes = ws_mask_bytes(rc, m.args, dd.tokens, m.ntt);
+    it.emask = m.ntt ? nullptr : (int8_t*)(ws + off);
+    it.ahat = m.ntt ? (uint64_t*)(ws + off) : nullptr;
+    it.ebody = (int8_t*)(ws + off + mask_bytes);
+    off += ws_item(rc, m.args, dd.tokens, m.ntt);
     it.out = dd.out;
     it.T = dd.tokens;
     const uint32_t prep_per = rc.N >= 256 ? rc.N / 256 : 1;
     all.prep_start[x + 1] = all.prep_start[x] + dd.tokens * m.args.L * prep_per;
+    all.fwd_start[x + 1] = all.fwd_start[x] + (m.ntt ? dd.tokens * m.args.L * rc.P : 0);
     all.body_start[x + 1] = all.body_start[x] + dd.tokens * ((m.args.rows + 255) / 256);
   }
   all.n = cnt;
   hipError_t e = timed(ctx, K_PREP, s, [&] { return launch_prep(all, s); });
   if (e != hipSuccess) return hip_fail(e, "prep kernel");
-  // one mask launch per distinct number of kept digits
+  if (all.fwd_start[cnt]) {
+    e = timed(ctx, K_PREP, s, [&] { return launch_ntt_mask_fwd(all, s); });
+    if (e != hipSuccess) return hip_fail(e, "mask NTT kernel");
+  }
+  // matrix-core method: one mask launch per distinct number of kept digits;
+  // NTT method: one launch for all its products
   bool done[kMaxBatch] = {};
   for (uint32_t x = 0; x < cnt; ++x) {
     if (done[x]) continue;
+    const bool ntt = all.it[x].method == 1;
     const uint32_t dk = all.it[x].sc.dk;
     Batch mb{};
     mb.rc = rc;
+    mb.ntt = all.ntt;
     mb.raw = all.raw;
     mb.force_exact = all.force_exact;
     for (uint32_t y = x; y < cnt; ++y) {
-      if (done[y] || all.it[y].sc.dk != dk) continue;
+      if (done[y] || (all.it[y].method == 1) != ntt || (!ntt && all.it[y].sc.dk != dk)) continue;
       done[y] = true;
       const Item& it = all.it[y];
       mb.it[mb.n] = it;
-      mb.mask_start[mb.n + 1] = mb.mask_start[mb.n] + it.T * (it.m.rows_pad / 32) * (rc.N / 64);
+      const uint32_t blocks = ntt ? it.m.rows * ((it.T + kTokTile - 1) / kTokTile)
+                                  : it.T * (it.m.rows_pad / 32) * (rc.N / 64);
+      mb.mask_start[mb.n + 1] = mb.mask_start[mb.n] + blocks;
       ++mb.n;
     }
-    e = timed(ctx, K_MASK, s, [&] { return launch_mask(mb, dk, s); });
+    e = timed(ctx, K_MASK, s, [&] { return ntt ? launch_ntt_mask(mb, s) : launch_mask(mb, dk, s); });
     if (e != hipSuccess) return hip_fail(e, "mask kernel");
   }
   e = timed(ctx, K_BODY, s, [&] { return launch_body(all, s); });

@@ -37,6 +37,18 @@ struct RingConst {
   double inv_q32;                  // 2^32 / q (estimate only; results are corrected exactly)
 };
 
+// Constants of the number-theoretic-transform method (N = kNttN only).
+constexpr uint32_t kNttN = 4096;
+constexpr uint32_t kTokTile = 8;  // tokens per workgroup of the NTT product kernel
+struct NttConst {
+  const uint64_t* fwd[kMaxPrimes];  // [N] (psi^bitrev(k), Shoup companion), device
+  const uint64_t* inv[kMaxPrimes];  // [N] (psi^-bitrev(k), Shoup companion), device
+  uint64_t crt[kMaxPrimes];         // N^-1 (q / q_p)^-1 mod q_p (N^-1 mod q_0 for one prime)
+  uint64_t crt_shoup[kMaxPrimes];
+  uint64_t ninv[kMaxPrimes];        // N^-1 mod q_p
+  uint64_t ninv_shoup[kMaxPrimes];
+};
+
 // Per weight-matrix constants of the switched epilogue.
 struct SwitchConst {
   uint32_t l0;        // digits below l0 are left out of the matrix-core sums
@@ -103,6 +115,9 @@ struct MatArgs {
 struct Item {
   MatArgs m;
   SwitchConst sc;
+  uint32_t method;     // 0: digit planes on the matrix cores, 1: NTT
+  const uint64_t* what;  // NTT method: [rows][L][P][N] (value, Shoup companion) pairs
+  uint64_t* ahat;        // NTT method: [T][L][P][N] transformed masks (workspace)
   const uint64_t* ct;  // [T][L][2][P][N]
   int8_t* emask;       // [T][D][L][2N]: per digit plane, index m <-> Toeplitz offset m - N
   int8_t* ebody;       // [T][D][L][N]
@@ -119,8 +134,10 @@ struct Batch {
   uint32_t n;
   uint32_t raw;
   uint32_t force_exact;
+  NttConst ntt;
   uint32_t prep_start[kMaxBatch + 1];  // blocks of 256 threads over T*L*N coefficients
-  uint32_t mask_start[kMaxBatch + 1];  // workgroups over T * rows_pad/32 * N/64 tiles
+  uint32_t fwd_start[kMaxBatch + 1];   // NTT method: one transform per (token, block, prime)
+  uint32_t mask_start[kMaxBatch + 1];  // workgroups over T * rows_pad/32 * N/64 tiles (NTT: rows * token tiles)
   uint32_t body_start[kMaxBatch + 1];  // blocks of 256 threads over T * rows
   Item it[kMaxBatch];
 };
@@ -162,6 +179,10 @@ inline dim3 grid_for(uint32_t blocks) {
 hipError_t launch_prep(const Batch& b, hipStream_t s);
 hipError_t launch_mask(const Batch& b, uint32_t dk, hipStream_t s);
 hipError_t launch_body(const Batch& b, hipStream_t s);
+hipError_t launch_ntt_mask_fwd(const Batch& b, hipStream_t s);
+hipError_t launch_ntt_mask(const Batch& b, hipStream_t s);
+hipError_t launch_ntt_weights(const MatArgs& m, const NttConst& ntt, const RingConst& rc,
+                              uint64_t* what, hipStream_t s);
 hipError_t launch_modswitch(const RingConst& rc, const uint64_t* in, size_t count, uint32_t* out,
                             hipStream_t s);
 hipError_t launch_transpose_pad(const int8_t* src, uint32_t rows, uint32_t cols, bool transpose,

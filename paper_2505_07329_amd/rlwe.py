@@ -19,10 +19,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librlwe.so")
 
 RLWE_OK = 0
+RLWE_EINVAL, RLWE_EPARAM, RLWE_ESHAPE, RLWE_EOVERFLOW, RLWE_ENOMEM, RLWE_EHIP = -1, -2, -3, -4, -5, -6
 ERRORS = {-1: "RLWE_EINVAL", -2: "RLWE_EPARAM", -3: "RLWE_ESHAPE", -4: "RLWE_EOVERFLOW",
           -5: "RLWE_ENOMEM", -6: "RLWE_EHIP"}
 RLWE_W_FWD = 1
 RLWE_W_TRANSPOSE = 2
+RLWE_W_NTT = 4
+RLWE_W_TOEPLITZ = 8
+RLWE_METHOD_TOEPLITZ = 0
+RLWE_METHOD_NTT = 1
 RLWE_OUT_SWITCHED = 0
 RLWE_OUT_RAW_Q = 1
 RLWE_OUT_FORCE_EXACT = 2
@@ -31,7 +36,7 @@ EXPORTS = ("rlwe_params_init", "rlwe_params_destroy", "rlwe_weights_load", "rlwe
            "ct_matmul_clear", "ct_modswitch", "rlwe_workspace_bytes", "rlwe_workspace_reserve",
            "rlwe_profile_begin", "rlwe_profile_end", "rlwe_weights_digits", "ct_matmul_batch",
            "rlwe_batch_workspace_bytes", "rlwe_graph_capture_batch", "rlwe_graph_launch",
-           "rlwe_graph_destroy", "rlwe_last_error")
+           "rlwe_graph_destroy", "rlwe_weights_method", "rlwe_last_error")
 
 
 class RlweError(RuntimeError):
@@ -89,6 +94,7 @@ def lib() -> ctypes.CDLL:
     L.rlwe_profile_end.argtypes = [vp, ctypes.POINTER(KernelTimes)]
     L.rlwe_weights_digits.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
                                       ctypes.POINTER(ctypes.c_uint32)]
+    L.rlwe_weights_method.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
     L.ct_matmul_batch.argtypes = [vp, ctypes.POINTER(CtMatmulDesc), ctypes.c_uint32,
                                   ctypes.c_uint32, vp]
     L.rlwe_batch_workspace_bytes.argtypes = [vp, ctypes.POINTER(CtMatmulDesc), ctypes.c_uint32]
@@ -97,6 +103,7 @@ def lib() -> ctypes.CDLL:
                                            ctypes.c_uint32, ctypes.POINTER(vp)]
     L.rlwe_graph_launch.argtypes = [vp, vp]
     L.rlwe_graph_destroy.argtypes = [vp]
+    L.rlwe_last_error.argtypes = []
     L.rlwe_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name not in ("rlwe_last_error", "rlwe_workspace_bytes", "rlwe_batch_workspace_bytes"):
@@ -179,6 +186,12 @@ def rlwe_weights_digits(w: int, transpose: bool = False) -> tuple[int, int]:
     kept, total = ctypes.c_uint32(), ctypes.c_uint32()
     _check(lib().rlwe_weights_digits(w, int(bool(transpose)), ctypes.byref(kept), ctypes.byref(total)))
     return kept.value, total.value
+
+
+def rlwe_weights_method(w: int, transpose: bool = False) -> int:
+    m = ctypes.c_uint32()
+    _check(lib().rlwe_weights_method(w, int(bool(transpose)), ctypes.byref(m)))
+    return m.value
 
 
 def _descs(items):

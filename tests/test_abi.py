@@ -34,6 +34,14 @@ def test_library_exports_every_declared_symbol():
         assert ctypes.cast(getattr(L, name), ctypes.c_void_p).value
 
 
+def test_binding_declares_every_signature():
+    """Every exported function has its argument types declared in the binding (an
+    undeclared pointer argument would be passed as a 32-bit int)."""
+    L = rlwe.lib()
+    for name in rlwe.EXPORTS:
+        assert getattr(L, name).argtypes is not None, name
+
+
 P4096 = (18014398509309953, 18014398509293569)
 
 
