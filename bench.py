@@ -32,6 +32,49 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix peak, 5.0 POP/s
+# NTT method: VALU-bound. 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 7.86e13 32-bit lane
+# operations/s (the issue rate behind the 157.3 TFLOP/s fp32 vector peak), and one lazy
+# 54-bit Shoup butterfly compiles to 28 VALU instructions.
+NTT_PEAK_GBFLY = 256 * 4 * 32 * 2.4e9 / 28 / 1e9
+
+
+def method_flag(args):
+    from paper_2505_07329_amd import rlwe
+    return {"auto": 0, "ntt": rlwe.RLWE_W_NTT, "toeplitz": rlwe.RLWE_W_TOEPLITZ}[args.method]
+
+
+def product_info(rlwe, w, tr, T, M, K):
+    kept, _ = rlwe.rlwe_weights_digits(w.handle, tr)
+    ntt = rlwe.rlwe_weights_method(w.handle, tr) == rlwe.RLWE_METHOD_NTT
+    return dict(T=T, M=M, K=K, kept=kept, ntt=ntt)
+
+
+def roofline(products, kt, N, P, traffic=None):
+    """Roofline of the dominant mask kernel of a set of products, each a dict with
+    T, M (outputs per token), K, kept (digits on the matrix cores), ntt (method).
+    Matrix cores: 2 T M N K kept int8 ops; NTT: per output and prime one inverse
+    transform ((N/2) log2 N butterflies) and L N pointwise products."""
+    import math
+    mf_ops = sum(2.0 * p["T"] * p["M"] * N * p["K"] * p["kept"] for p in products if not p["ntt"])
+    nt_ops = sum(p["T"] * p["M"] * P * ((N // 2) * math.log2(N) + ((p["K"] + N - 1) // N) * N)
+                 for p in products if p["ntt"])
+    parts = {}
+    if mf_ops and kt["mask_ms"] > 0:
+        a = mf_ops / (kt["mask_ms"] * 1e-3) / 1e12
+        parts["mfma"] = {"bound": "mfma", "achieved": a, "peak": INT8_PEAK_TOPS,
+                         "unit": "TOP/s (int8)", "frac": a / INT8_PEAK_TOPS,
+                         "traffic": traffic, "ms": kt["mask_ms"]}
+    if nt_ops and kt.get("ntt_ms", 0) > 0:
+        a = nt_ops / (kt["ntt_ms"] * 1e-3) / 1e9
+        parts["alu"] = {"bound": "alu", "achieved": a, "peak": NTT_PEAK_GBFLY,
+                        "unit": "G butterfly/s (54-bit lazy Shoup, NTT method)",
+                        "frac": a / NTT_PEAK_GBFLY, "traffic": None, "ms": kt["ntt_ms"]}
+    if not parts:
+        return None, None
+    dom = max(parts.values(), key=lambda x: x["ms"])
+    other = [v for v in parts.values() if v is not dom]
+    return ({k: v for k, v in dom.items() if k != "ms"},
+            {k: v for k, v in other[0].items() if k != "ms"} if other else None)
 
 # HBM bytes moved by one mask-kernel launch of the default workload: two rocprofv3
 # --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by the
@@ -62,6 +105,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample (0 disables it)")
     ap.add_argument("--chunk", type=int, default=256, help="mlp: tokens per call")
+    ap.add_argument("--method", choices=["auto", "ntt", "toeplitz"], default="auto",
+                    help="mask-product method of every weight matrix (auto: NTT where the "
+                         "contraction spans two or more blocks of N, matrix cores otherwise)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="attn: before the timed region, run one plain elementwise copy kernel "
                          "(int32 bitwise not) reading and writing GIB GiB each, as the known-size "
@@ -134,7 +180,8 @@ def layer_workload(args):
     products, weights = [], []
     for pi, (name, (d_in, d_out)) in enumerate(synth.LLAMA_1B_PROJ.items()):
         W = synth.int8_uniform(synth.rng(4, synth.P_WEIGHTS, pi), (d_out, d_in))
-        w = rlwe.Weights(ctx, torch.from_numpy(W).to(dev), rlwe.RLWE_W_FWD | rlwe.RLWE_W_TRANSPOSE)
+        w = rlwe.Weights(ctx, torch.from_numpy(W).to(dev),
+                         rlwe.RLWE_W_FWD | rlwe.RLWE_W_TRANSPOSE | method_flag(args))
         weights.append(w)
         for tr in (False, True):
             K, M = (d_out, d_in) if tr else (d_in, d_out)
@@ -191,11 +238,8 @@ def layer_workload(args):
     step_plain()
     torch.cuda.synchronize()
     kt = rlwe.rlwe_profile_end(ctx.handle)
-    ops = 0.0
-    for p in products:
-        kept, _ = rlwe.rlwe_weights_digits(p["w"].handle, p["tr"])
-        ops += 2.0 * p["T"] * p["M"] * N * p["K"] * kept
-    achieved = ops / (kt["mask_ms"] * 1e-3) / 1e12
+    roof, roof_other = roofline([product_info(rlwe, p["w"], p["tr"], p["T"], p["M"], p["K"])
+                                 for p in products], kt, N, len(primes))
     value = macs / t_graph
     result = {
         "metric": "encrypted MACs/s (sum d_in*d_out*tokens / s), one Llama-3.2-1B layer, 7 projections "
@@ -210,9 +254,9 @@ def layer_workload(args):
                    "output_GB": sum(p["T"] * p["M"] * (N + 1) * 4 for p in products) / 1e9},
         "plain_per_call": {"value": macs / t_plain, "ms_per_step": t_plain * 1e3,
                            "speedup_graph": t_plain / t_graph},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
-                     "unit": "TOP/s (int8), matrix-core launches of the plain per-call sequence",
-                     "frac": achieved / INT8_PEAK_TOPS, "traffic": None},
+        "methods": {p["name"]: ("ntt" if rlwe.rlwe_weights_method(p["w"].handle, p["tr"]) else "toeplitz")
+                    for p in products},
+        "roofline": roof, "roofline_other_method": roof_other,
         "cpu_baseline": None,
     }
     for gr in graphs:
@@ -249,7 +293,7 @@ def mlp_workload(args):
     for pi, name in enumerate(("gate", "up", "down")):
         d_in, d_out = synth.LLAMA_1B_PROJ[name]
         W = synth.int8_uniform_device(3, synth.P_WEIGHTS, pi, (d_out, d_in), dev)
-        mats[name] = rlwe.Weights(ctx, W, rlwe.RLWE_W_FWD | rlwe.RLWE_W_TRANSPOSE)
+        mats[name] = rlwe.Weights(ctx, W, rlwe.RLWE_W_FWD | rlwe.RLWE_W_TRANSPOSE | method_flag(args))
         del W
     cts = {}
     for L in (1, 2):
@@ -290,11 +334,8 @@ def mlp_workload(args):
     wall = time.perf_counter() - t0
     kt = rlwe.rlwe_profile_end(ctx.handle)
     macs = args.steps * T * sum(p["K"] * p["M"] for p in products)
-    ops = 0.0
-    for p in products:
-        kept, _ = rlwe.rlwe_weights_digits(p["w"].handle, p["tr"])
-        ops += 2.0 * args.steps * T * p["M"] * N * p["K"] * kept
-    achieved = ops / (kt["mask_ms"] * 1e-3) / 1e12
+    roof, roof_other = roofline([product_info(rlwe, p["w"], p["tr"], args.steps * T, p["M"], p["K"])
+                                 for p in products], kt, N, len(primes))
     cpu = None
     if args.cpu_seconds > 0:
         cpu = mlp_cpu_baseline(products, N, primes, args.cpu_seconds)
@@ -310,10 +351,11 @@ def mlp_workload(args):
                    "products": [f'{p["name"]}:{p["K"]}->{p["M"]}' for p in products],
                    "digits_on_matrix_cores": {p["name"]: rlwe.rlwe_weights_digits(p["w"].handle, p["tr"])[0]
                                               for p in products}},
-        "kernels_ms": {"prep": kt["prep_ms"], "mask": kt["mask_ms"], "body": kt["body_ms"]},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
-                     "unit": "TOP/s (int8), matrix-core launches of the timed pass",
-                     "frac": achieved / INT8_PEAK_TOPS, "traffic": None},
+        "kernels_ms": {"prep": kt["prep_ms"], "mask": kt["mask_ms"], "ntt": kt["ntt_ms"],
+                       "body": kt["body_ms"]},
+        "methods": {p["name"]: ("ntt" if rlwe.rlwe_weights_method(p["w"].handle, p["tr"]) else "toeplitz")
+                    for p in products},
+        "roofline": roof, "roofline_other_method": roof_other,
         "cpu_baseline": cpu,
     }
     for w in mats.values():
@@ -381,7 +423,8 @@ def serve_workload(args):
     for layer in range(SERVE_LAYERS):
         for pi, (name, (d_in, d_out)) in enumerate(synth.LLAMA_1B_PROJ.items()):
             W = synth.int8_uniform_device(5, synth.P_WEIGHTS, layer * 16 + pi, (d_out, d_in), dev)
-            weights[(layer, name)] = rlwe.Weights(ctx, W, rlwe.RLWE_W_FWD | rlwe.RLWE_W_TRANSPOSE)
+            weights[(layer, name)] = rlwe.Weights(ctx, W, rlwe.RLWE_W_FWD | rlwe.RLWE_W_TRANSPOSE
+                                                  | method_flag(args))
             del W
     pools = {}
     for L in (1, 2):
@@ -419,11 +462,8 @@ def serve_workload(args):
     rlwe.rlwe_profile_begin(ctx.handle)
     sat = run(sat_reqs, 16)
     kt = rlwe.rlwe_profile_end(ctx.handle)
-    ops = 0.0
-    for r in sat_reqs:
-        kept, _ = rlwe.rlwe_weights_digits(weights[(r.layer, r.proj)].handle, r.transpose)
-        ops += 2.0 * r.tokens * r.d_out * N * r.d_in * kept
-    achieved = ops / (kt["mask_ms"] * 1e-3) / 1e12
+    roof, roof_other = roofline([product_info(rlwe, weights[(r.layer, r.proj)], r.transpose, r.tokens,
+                                              r.d_out, r.d_in) for r in sat_reqs], kt, N, len(primes))
     plain = run(requests(math.inf, 0), 1)
     sat_rate = sat["requests"] / sat["span_s"]
     sweep = []
@@ -455,9 +495,7 @@ def serve_workload(args):
                       "rate_req_s": sat_rate, "span_s": sat["span_s"]},
         "plain_per_call": {"value": plain["macs_per_s"], "speedup_grouped": sat["macs_per_s"] / plain["macs_per_s"]},
         "sweep": sweep,
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
-                     "unit": "TOP/s (int8), matrix-core launches of the saturated run",
-                     "frac": achieved / INT8_PEAK_TOPS, "traffic": None},
+        "roofline": roof, "roofline_other_method": roof_other,
         "cpu_baseline": cpu,
     }
     for w in weights.values():
@@ -532,7 +570,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     ctx = rlwe.Context(N, primes, log2_t, device=0)
-    w = rlwe.Weights(ctx, torch.from_numpy(W).to(dev))
+    w = rlwe.Weights(ctx, torch.from_numpy(W).to(dev), rlwe.RLWE_W_FWD | method_flag(args))
     ct = torch.from_numpy(ct_np.view(np.int64)).to(dev)
     out = torch.empty((T, d_out, N + 1), dtype=torch.int32, device=dev)
     rlwe.rlwe_workspace_reserve(ctx.handle, rlwe.rlwe_workspace_bytes(ctx.handle, w.handle, False, T))
@@ -569,11 +607,11 @@ def main():
     macs = d_in * d_out * T
     value = macs * args.steps / wall
     lat = np.array([marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps)])
-    mask_ms = kt["mask_ms"] / max(1, kt["mask_n"])
-    # algorithmic int8 matrix-core work of one mask launch: every (token, row,
-    # mask index) contracts d_in products per kept digit
-    ops = 2.0 * T * d_out * N * d_in * kept
-    achieved = ops / (mask_ms * 1e-3) / 1e12
+    per_launch = {k: kt[k] / max(1, kt[k.replace("_ms", "_n")]) for k in ("prep_ms", "mask_ms", "ntt_ms", "body_ms")}
+    one = dict(kt, mask_ms=per_launch["mask_ms"], ntt_ms=per_launch["ntt_ms"])
+    is_ntt = rlwe.rlwe_weights_method(w.handle) == rlwe.RLWE_METHOD_NTT
+    roof, _ = roofline([dict(T=T, M=d_out, K=d_in, kept=kept, ntt=is_ntt)], one, N, len(primes),
+                       traffic=None if is_ntt else mask_traffic())
     result = {
         "metric": "encrypted MACs/s (d_in*d_out*tokens/s), W.[x]_HE with outputs switched to 2^32",
         "value": value,
@@ -589,13 +627,12 @@ def main():
         "data": "synthetic (seeded uniform int8 weights, uniform ciphertext residues)",
         "config": {"workload": cfg["name"], "d_in": d_in, "d_out": d_out, "tokens": T, "N": N,
                    "primes": len(primes), "log2_t": log2_t, "q_out": "2^32",
-                   "digits_on_matrix_cores": f"{kept}/{total}"},
+                   "method": "ntt" if is_ntt else "toeplitz",
+                   "digits_on_matrix_cores": None if is_ntt else f"{kept}/{total}"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "kernels_ms": {"prep": kt["prep_ms"] / max(1, kt["prep_n"]), "mask": mask_ms,
-                       "body": kt["body_ms"] / max(1, kt["body_n"])},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
-                     "unit": "TOP/s (int8)", "frac": achieved / INT8_PEAK_TOPS,
-                     "traffic": mask_traffic()},
+        "kernels_ms": {"prep": per_launch["prep_ms"], "mask": per_launch["mask_ms"],
+                       "ntt": per_launch["ntt_ms"], "body": per_launch["body_ms"]},
+        "roofline": roof,
         "cpu_baseline": None,
     }
     w.close()

@@ -196,8 +196,10 @@ int rlwe_workspace_reserve(rlwe_ctx* ctx, size_t bytes);
  * rlwe_profile_end waits for the recorded events, fills `out` (host pointer)
  * and closes the window. Not for use inside hipGraph capture. */
 typedef struct rlwe_kernel_times {
-  double prep_ms, mask_ms, body_ms, modswitch_ms; /* summed durations */
-  uint32_t prep_n, mask_n, body_n, modswitch_n;   /* launches recorded */
+  /* summed durations: digit preparation and mask transforms (prep), matrix-core
+   * mask products (mask), NTT mask products (ntt), body, standalone switch */
+  double prep_ms, mask_ms, body_ms, modswitch_ms, ntt_ms;
+  uint32_t prep_n, mask_n, body_n, modswitch_n, ntt_n; /* launches recorded */
   uint32_t dropped;
 } rlwe_kernel_times;
 

@@ -80,7 +80,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 }  // namespace
 
 namespace {
-enum KernelKind { K_PREP = 0, K_MASK = 1, K_BODY = 2, K_MODSWITCH = 3 };
+enum KernelKind { K_PREP = 0, K_MASK = 1, K_BODY = 2, K_MODSWITCH = 3, K_NTT = 4 };
 constexpr int kMaxProfiled = 4096;
 struct Profiler {
   bool on = false;
@@ -395,8 +395,8 @@ int rlwe_profile_end(rlwe_ctx* ctx, rlwe_kernel_times* out) {
   p->on = false;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  double* ms[4] = {&out->prep_ms, &out->mask_ms, &out->body_ms, &out->modswitch_ms};
-  uint32_t* n[4] = {&out->prep_n, &out->mask_n, &out->body_n, &out->modswitch_n};
+  double* ms[5] = {&out->prep_ms, &out->mask_ms, &out->body_ms, &out->modswitch_ms, &out->ntt_ms};
+  uint32_t* n[5] = {&out->prep_n, &out->mask_n, &out->body_n, &out->modswitch_n, &out->ntt_n};
   for (int i = 0; i < p->used; ++i) {
     e = hipEventSynchronize(p->ev[i][1]);
     if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
@@ -692,7 +692,7 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
       mb.mask_start[mb.n + 1] = mb.mask_start[mb.n] + blocks;
       ++mb.n;
     }
-    e = timed(ctx, K_MASK, s, [&] { return ntt ? launch_ntt_mask(mb, s) : launch_mask(mb, dk, s); });
+    e = timed(ctx, ntt ? K_NTT : K_MASK, s, [&] { return ntt ? launch_ntt_mask(mb, s) : launch_mask(mb, dk, s); });
     if (e != hipSuccess) return hip_fail(e, "mask kernel");
   }
   e = timed(ctx, K_BODY, s, [&] { return launch_body(all, s); });

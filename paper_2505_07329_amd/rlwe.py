@@ -48,9 +48,10 @@ class RlweError(RuntimeError):
 class KernelTimes(ctypes.Structure):
     _fields_ = [("prep_ms", ctypes.c_double), ("mask_ms", ctypes.c_double),
                 ("body_ms", ctypes.c_double), ("modswitch_ms", ctypes.c_double),
+                ("ntt_ms", ctypes.c_double),
                 ("prep_n", ctypes.c_uint32), ("mask_n", ctypes.c_uint32),
                 ("body_n", ctypes.c_uint32), ("modswitch_n", ctypes.c_uint32),
-                ("dropped", ctypes.c_uint32)]
+                ("ntt_n", ctypes.c_uint32), ("dropped", ctypes.c_uint32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
