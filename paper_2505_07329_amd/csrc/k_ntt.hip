@@ -11,13 +11,29 @@
 // (Sec. 3.2), so a'[n] is the inverse transform's coefficient N - 1 - n. The two
 // residues are combined by CRT and switched to 2^32 exactly in the epilogue.
 //
-// A transform runs on 256 threads holding 16 residues each, in three passes of
-// four radix-2 stages in registers with two exchanges through LDS. Residue
-// positions per thread in the three layouts:
+// The forward transforms (masks once per token, weights once per load) run on
+// 256 threads holding 16 residues each, in three passes of four radix-2 stages
+// in registers with two exchanges through LDS. Residue positions per thread:
 //   L1: 16 tid + k          (spans 1..8)
 //   L2: 256 b + r + 16 k    (spans 16..128, b = tid / 16, r = tid % 16)
 //   L3: tid + 256 k         (spans 256..2048)
-// Arithmetic is lazy (Harvey): values stay below 4p, Shoup products below 2p.
+// The inverse transforms, one per output and prime, run on 512 threads holding
+// 8 residues of each prime, in four passes of three stages:
+//   Q1: 8 tid + k                      (spans 1..4)
+//   Q2: 64 (tid / 8) + tid % 8 + 8 k    (spans 8..32)
+//   Q3: 512 (tid / 64) + tid % 64 + 64 k (spans 64..256)
+//   Q4: tid + 512 k                    (spans 512..2048)
+// Q1 -> Q2 and Q2 -> Q3 move residues only among the 64 threads of one wave
+// (positions 512 w .. 512 w + 511), so those exchanges need no workgroup
+// barrier; Q3 -> Q4 crosses waves. The primes of a token are transformed
+// together: two independent chains per butterfly position.
+// Arithmetic is lazy (Harvey). The forward transforms keep values below 4p with
+// exact Shoup products below 2p. The inverse trades exactness for instructions:
+// its Shoup products take the quotient without the partial products that end
+// below bit 64 (results below 4p for any 64-bit input), its sums are left
+// unreduced inside a pass (each difference is biased by the stage's bound) and a
+// Barrett step at the end of a pass brings back the two elements that can exceed
+// 8p. With q_p < 2^54 every intermediate stays below 64 q_p < 2^60.
 #include "rlwe_internal.hpp"
 
 namespace rlwe {
@@ -26,6 +42,8 @@ namespace {
 constexpr int kN = kNttN;
 constexpr int kThreads = 256;
 constexpr int kLdsWords = kN + kN / 16;  // padded exchange buffer: position + position / 16
+constexpr int kInvThreads = 512;
+constexpr int kInvLdsWords = kN + kN / 8;  // inverse exchange buffer per prime: position + position / 8
 
 struct Tw {
   uint64_t w, wp;
@@ -42,6 +60,49 @@ __device__ __forceinline__ uint64_t reduce4(uint64_t x, uint64_t p) {  // [0, 4p
   x = x >= 2 * p ? x - 2 * p : x;
   return x >= p ? x - p : x;
 }
+// Bits 64..127 of c * h (mod 2^128) for any 64-bit c and 128-bit h, dropping the
+// partial products that end below bit 64 (the result is at most 3 units low);
+// carries past bit 127 fall off, as the sum is wanted mod 2^128.
+template <class HP>  // h: a pointer to the four words, in any address space
+__device__ __forceinline__ uint64_t fixed_part(uint64_t c, HP h) {
+  const uint32_t c0 = (uint32_t)c, c1 = (uint32_t)(c >> 32);
+  uint64_t a = (uint64_t)__umulhi(c0, h[1]) + __umulhi(c1, h[0]);
+  a += (uint64_t)c0 * h[2] + (uint64_t)c1 * h[1];
+  a += (uint64_t)(c0 * h[3] + c1 * h[2]) << 32;
+  return a;
+}
+
+// a * w mod p in [0, 4p) for any a < 2^64, pn = 2^64 - p: Shoup's quotient
+// floor(a wp / 2^64) less the partial products below bit 64 (at most 2 low), and
+// the remainder a w + q pn taken mod 2^64.
+__device__ __forceinline__ uint64_t mul_shoup4(uint64_t a, uint64_t w, uint64_t wp, uint64_t pn) {
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t wp0 = (uint32_t)wp, wp1 = (uint32_t)(wp >> 32);
+  uint64_t q = (uint64_t)a1 * wp1 + __umulhi(a0, wp1);
+  q += __umulhi(a1, wp0);
+  const uint32_t q0 = (uint32_t)q, q1 = (uint32_t)(q >> 32);
+  const uint32_t w0 = (uint32_t)w, w1 = (uint32_t)(w >> 32);
+  const uint32_t n0 = (uint32_t)pn, n1 = (uint32_t)(pn >> 32);
+  uint64_t r = (uint64_t)a0 * w0;
+  r = (uint64_t)q0 * n0 + r;
+  const uint32_t h = (uint32_t)(r >> 32) + a0 * w1 + a1 * w0 + q0 * n1 + q1 * n0;
+  return ((uint64_t)h << 32) | (uint32_t)r;
+}
+
+// Constants of the inverse transform for one prime.
+struct InvMod {
+  uint64_t pn;  // 2^64 - p
+  uint64_t p8;  // 8p, the bound of a pass's inputs
+  uint32_t bm;  // floor(2^64 / p)
+};
+// v mod p in [0, 3p) for any v < 2^64: the quotient estimate from the high word
+// is at most 2 low.
+__device__ __forceinline__ uint64_t reduce_barrett(uint64_t v, const InvMod& md) {
+  const uint32_t q = __umulhi((uint32_t)(v >> 32), md.bm);
+  const uint64_t r = (uint64_t)q * (uint32_t)md.pn + v;
+  return r + ((uint64_t)(q * (uint32_t)(md.pn >> 32)) << 32);
+}
+
 // forward butterfly: X, Y < 4p -> X + wY, X - wY (both < 4p)
 __device__ __forceinline__ void ct_bfly(uint64_t& X, uint64_t& Y, const Tw& t, uint64_t p) {
   const uint64_t twop = 2 * p;
@@ -50,40 +111,33 @@ __device__ __forceinline__ void ct_bfly(uint64_t& X, uint64_t& Y, const Tw& t, u
   X = x + v;
   Y = x + twop - v;
 }
-// inverse butterfly: X, Y < 2p -> X + Y, (X - Y) w (both < 2p)
-__device__ __forceinline__ void gs_bfly(uint64_t& X, uint64_t& Y, const Tw& t, uint64_t p) {
-  const uint64_t twop = 2 * p;
-  uint64_t s = X + Y;
-  s = s >= twop ? s - twop : s;
-  Y = mul_shoup(X + twop - Y, t.w, t.wp, p);
-  X = s;
+// inverse butterfly: X, Y < B -> X + Y (< 2B), (X - Y) w (< 4p)
+__device__ __forceinline__ void gs_bfly(uint64_t& X, uint64_t& Y, const Tw& t, uint64_t B,
+                                        uint64_t pn) {
+  const uint64_t d = X + B - Y;
+  X += Y;
+  Y = mul_shoup4(d, t.w, t.wp, pn);
 }
 
 __device__ __forceinline__ uint32_t pad(uint32_t pos) { return pos + pos / 16; }
 
-// Four stages of one pass on x[16] at positions base + STRIDE * k. FWD: spans
-// STRIDE * 8, * 4, * 2, * 1 (Cooley-Tukey); otherwise spans STRIDE * 1 .. * 8
-// (Gentleman-Sande). The twiddle of the pair at position pos, span t, is entry
-// N / (2t) + pos / (2t) of the table.
-template <bool FWD, int STRIDE>
-__device__ __forceinline__ void pass4(uint64_t* x, uint32_t base, const uint64_t* tw, uint64_t p) {
+// Four stages of one pass on x[16] at positions base + STRIDE * k. The twiddle
+// of the pair at position pos, span t, is entry N / (2t) + pos / (2t) of the table.
+// Forward: spans STRIDE * 8, * 4, * 2, * 1 (Cooley-Tukey).
+template <int STRIDE>
+__device__ __forceinline__ void fwd_pass(uint64_t* x, uint32_t base, const uint64_t* tw, uint64_t p) {
 #pragma unroll
   for (int st = 0; st < 4; ++st) {
-    const int sp = FWD ? (8 >> st) : (1 << st);  // distance in k
-    const uint32_t t = STRIDE * sp;               // span in positions
+    const int sp = 8 >> st;        // distance in k
+    const uint32_t t = STRIDE * sp;  // span in positions
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       if (k & sp) continue;
       const uint32_t pos = base + STRIDE * k;
-      const Tw w = ld_tw(tw, kN / (2 * t) + pos / (2 * t));
-      if (FWD)
-        ct_bfly(x[k], x[k + sp], w, p);
-      else
-        gs_bfly(x[k], x[k + sp], w, p);
+      ct_bfly(x[k], x[k + sp], ld_tw(tw, kN / (2 * t) + pos / (2 * t)), p);
     }
   }
 }
-
 __device__ __forceinline__ void store_l1(uint64_t* lds, const uint64_t* x, int tid) {
 #pragma unroll
   for (int k = 0; k < 16; ++k) lds[pad(16 * tid + k)] = x[k];
@@ -114,34 +168,109 @@ __device__ __forceinline__ void load_l3(const uint64_t* lds, uint64_t* x, int ti
 // Forward transform: x in layout L3, natural order -> x in layout L1, bit-reversed order.
 __device__ __forceinline__ void ntt_forward(uint64_t* x, uint64_t* lds, const uint64_t* tw,
                                             uint64_t p, int tid) {
-  pass4<true, 256>(x, 0, tw, p);  // spans 2048..256: twiddles do not depend on tid
+  fwd_pass<256>(x, 0, tw, p);  // spans 2048..256: twiddles do not depend on tid
   store_l3(lds, x, tid);
   __syncthreads();
   load_l2(lds, x, tid);
-  pass4<true, 16>(x, 256 * (tid >> 4), tw, p);  // spans 128..16: r never reaches a block edge
+  fwd_pass<16>(x, 256 * (tid >> 4), tw, p);  // spans 128..16: r never reaches a block edge
   __syncthreads();
   store_l2(lds, x, tid);
   __syncthreads();
   load_l1(lds, x, tid);
-  pass4<true, 1>(x, 16 * tid, tw, p);
+  fwd_pass<1>(x, 16 * tid, tw, p);
   __syncthreads();
 }
 
-// Inverse transform without the 1/N factor: x in layout L1, bit-reversed order ->
-// x in layout L3, natural order.
-__device__ __forceinline__ void ntt_inverse(uint64_t* x, uint64_t* lds, const uint64_t* tw,
-                                            uint64_t p, int tid) {
-  pass4<false, 1>(x, 16 * tid, tw, p);
-  store_l1(lds, x, tid);
+// Inverse pass PASS (layout Q1..Q4) on NP transforms at once: three
+// Gentleman-Sande stages, spans S, 2S, 4S, on inputs below 8p. Stage s sees
+// inputs below 8p 2^s; element k keeps its sum through the stages after the last
+// one in which it took a product (k's highest set bit), so at the end elements
+// 0, 1 are below 64p, 16p and the rest below 8p. END brings elements 0, 1 below
+// 3p, so the next pass again starts below 8p.
+template <int PASS>
+struct InvLayout {
+  static constexpr int S = PASS == 0 ? 1 : PASS == 1 ? 8 : PASS == 2 ? 64 : 512;  // stride in k
+  __device__ static uint32_t base(int tid) {
+    return PASS == 0   ? 8 * tid
+           : PASS == 1 ? 64 * (tid >> 3) + (tid & 7)
+           : PASS == 2 ? 512 * (tid >> 6) + (tid & 63)
+                       : tid;
+  }
+};
+__device__ __forceinline__ uint32_t pad8(uint32_t pos) { return pos + pos / 8; }
+
+template <int NP, int PASS, bool END>
+__device__ __forceinline__ void inv_pass(uint64_t (&x)[NP][8], int tid,
+                                         const uint64_t* const (&tw)[NP], const InvMod (&md)[NP]) {
+  constexpr int S = InvLayout<PASS>::S;
+  const uint32_t base = InvLayout<PASS>::base(tid);
+#pragma unroll
+  for (int st = 0; st < 3; ++st) {
+    const int sp = 1 << st;
+    const uint32_t t = S * sp;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (k & sp) continue;
+      const uint32_t idx = kN / (2 * t) + (base + S * k) / (2 * t);
+#pragma unroll
+      for (int r = 0; r < NP; ++r)
+        gs_bfly(x[r][k], x[r][k + sp], ld_tw(tw[r], idx), md[r].p8 << st, md[r].pn);
+    }
+  }
+  if (END) {
+#pragma unroll
+    for (int r = 0; r < NP; ++r)
+#pragma unroll
+      for (int k = 0; k < 2; ++k) x[r][k] = reduce_barrett(x[r][k], md[r]);
+  }
+}
+template <int NP, int PASS>
+__device__ __forceinline__ void inv_store(uint64_t* lds, const uint64_t (&x)[NP][8], int tid) {
+  const uint32_t base = InvLayout<PASS>::base(tid);
+#pragma unroll
+  for (int r = 0; r < NP; ++r)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) lds[r * kInvLdsWords + pad8(base + InvLayout<PASS>::S * k)] = x[r][k];
+}
+template <int NP, int PASS>
+__device__ __forceinline__ void inv_load(const uint64_t* lds, uint64_t (&x)[NP][8], int tid) {
+  const uint32_t base = InvLayout<PASS>::base(tid);
+#pragma unroll
+  for (int r = 0; r < NP; ++r)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[r][k] = lds[r * kInvLdsWords + pad8(base + InvLayout<PASS>::S * k)];
+}
+// Orders a wave's LDS stores before its following loads (the exchange partners
+// are lanes of the same wave; the LDS serves one wave's operations in order).
+__device__ __forceinline__ void wave_exchange_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Inverse transforms of NP primes without the 1/N factor: x[r] in layout Q1,
+// bit-reversed order, below 8p_r -> layout Q4, natural order, congruent to the
+// result mod p_r (below 64p_r, not reduced). lds holds NP exchange buffers.
+template <int NP>
+__device__ __forceinline__ void ntt_inverse(uint64_t (&x)[NP][8], uint64_t* lds,
+                                            const uint64_t* const (&tw)[NP],
+                                            const InvMod (&md)[NP], int tid) {
+  inv_pass<NP, 0, true>(x, tid, tw, md);
+  __syncthreads();  // no wave still reads the previous transform's Q4 positions
+  inv_store<NP, 0>(lds, x, tid);
+  wave_exchange_fence();
+  inv_load<NP, 1>(lds, x, tid);
+  inv_pass<NP, 1, true>(x, tid, tw, md);
+  wave_exchange_fence();  // every lane of the wave has read its Q2 positions
+  inv_store<NP, 1>(lds, x, tid);
+  wave_exchange_fence();
+  inv_load<NP, 2>(lds, x, tid);
+  inv_pass<NP, 2, true>(x, tid, tw, md);
+  __syncthreads();  // every wave is done with its own region
+  inv_store<NP, 2>(lds, x, tid);
   __syncthreads();
-  load_l2(lds, x, tid);
-  pass4<false, 16>(x, 256 * (tid >> 4), tw, p);
-  __syncthreads();
-  store_l2(lds, x, tid);
-  __syncthreads();
-  load_l3(lds, x, tid);
-  pass4<false, 256>(x, 0, tw, p);
-  __syncthreads();
+  inv_load<NP, 3>(lds, x, tid);
+  inv_pass<NP, 3, false>(x, tid, tw, md);
 }
 
 }  // namespace
@@ -171,74 +300,111 @@ __global__ void __launch_bounds__(kThreads) ntt_mask_fwd_kernel(Batch) {
   for (int k = 0; k < 16; ++k) dst[k] = reduce4(x[k], p);
 }
 
-// Product kernel: one workgroup per (row j, tile of kTokTile tokens) of each item.
-template <bool RAW>
-__global__ void __launch_bounds__(kThreads) ntt_mask_kernel(Batch) {
-  __shared__ uint64_t lds[kLdsWords];
-  __shared__ uint64_t stash[kN];  // first prime's coefficients while the second is computed
+// Product kernel: one workgroup per (row j, tile of kTokTile tokens) of each item;
+// the NP = P primes of a token are transformed together.
+template <bool RAW, int NP>
+__global__ void __launch_bounds__(kInvThreads) ntt_mask_kernel(Batch) {
+  __shared__ uint64_t lds[NP * kInvLdsWords];
   const BatchPtr bt = kernarg_batch();
   const uint32_t blk = linear_block();
   const uint32_t nb = bt->n;
   if (blk >= bt->mask_start[nb]) return;
   const uint32_t ii = find_item(bt->mask_start, nb, blk);
-  const RingConst rc = kernarg_load(&bt->rc);
-  const uint32_t P = rc.P, L = bt->it[ii].m.L, rows = bt->it[ii].m.rows, T = bt->it[ii].T;
+  const uint32_t L = bt->it[ii].m.L, rows = bt->it[ii].m.rows, T = bt->it[ii].T;
   const uint32_t loc = blk - bt->mask_start[ii];
   const uint32_t j = loc % rows, t0 = (loc / rows) * kTokTile;
   const uint64_t* ahat = bt->it[ii].ahat;
   const uint64_t* what = bt->it[ii].what;  // [rows][L][P][N] (w, w') pairs
   void* out = bt->it[ii].out;
-  const int tid = threadIdx.x;
+  // per-prime constants, indexed by compile-time prime numbers only (ring
+  // constants are read in place: a local copy indexed at run time would live in
+  // scratch)
+  uint64_t p[NP];
+  InvMod md[NP];
+  const uint64_t* tw[NP];
+#pragma unroll
+  for (int r = 0; r < NP; ++r) {
+    p[r] = bt->rc.q[r];
+    md[r] = InvMod{0 - p[r], 8 * p[r], bt->ntt.bm[r]};
+    tw[r] = bt->ntt.inv[r];
+  }
   const uint32_t t_end = min(T, t0 + kTokTile);
   for (uint32_t t = t0; t < t_end; ++t) {
-    for (uint32_t pi = 0; pi < P; ++pi) {
-      const uint64_t p = rc.q[pi];
-      uint64_t x[16];
+    // the thread index is opaque per token, so the many thread-dependent twiddle
+    // and exchange addresses are formed where they are used instead of being
+    // hoisted out of the token loop (and spilled)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    uint64_t x[NP][8];
+    // pointwise products below 4p each: two blocks stay below 8p, more are reduced
 #pragma unroll
-      for (int k = 0; k < 16; ++k) x[k] = 0;
-      for (uint32_t i = 0; i < L; ++i) {
-        const uint64_t* a = ahat + (((size_t)t * L + i) * P + pi) * kN + 16 * tid;
-        const uint64_t* w = what + 2 * ((((size_t)j * L + i) * P + pi) * kN + 16 * tid);
+    for (int r = 0; r < NP; ++r) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const uint64_t v = x[k] + mul_shoup(a[k], w[2 * k], w[2 * k + 1], p);
-          x[k] = v >= 2 * p ? v - 2 * p : v;
+      for (int k = 0; k < 8; ++k) x[r][k] = 0;
+      for (uint32_t i = 0; i < L; ++i) {  // positions 8 tid + k (layout Q1)
+        const uint64_t* a = ahat + (((size_t)t * L + i) * NP + r) * kN + 8 * tid;
+        const uint64_t* w = what + 2 * ((((size_t)j * L + i) * NP + r) * kN + 8 * tid);
+        if (L <= 2) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) x[r][k] += mul_shoup4(a[k], w[2 * k], w[2 * k + 1], md[r].pn);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            x[r][k] = reduce_barrett(x[r][k] + mul_shoup4(a[k], w[2 * k], w[2 * k + 1], md[r].pn),
+                                     md[r]);
         }
       }
-      ntt_inverse(x, lds, bt->ntt.inv[pi], p, tid);
-      // coefficient m = tid + 256 k of C; a'[N - 1 - m]
-      if (RAW) {
-        uint64_t* o = (uint64_t*)out + ((size_t)t * rows + j) * P * (kN + 1) + pi * (kN + 1);
+    }
+    ntt_inverse<NP>(x, lds, tw, md, tid);
+    // coefficient m = tid + 512 k of C (layout Q4); a'[N - 1 - m]
+    if (RAW) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const uint32_t m = tid + 256 * k;
-          const uint64_t c = mul_shoup(x[k], bt->ntt.ninv[pi], bt->ntt.ninv_shoup[pi], p);
-          o[kN - 1 - m] = c >= p ? c - p : c;
+      for (int r = 0; r < NP; ++r) {
+        uint64_t* o = (uint64_t*)out + ((size_t)t * rows + j) * NP * (kN + 1) + r * (kN + 1);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t m = tid + 512 * k;
+          const uint64_t c = mul_shoup(x[r][k], bt->ntt.ninv[r], bt->ntt.ninv_shoup[r], p[r]);
+          o[kN - 1 - m] = c >= p[r] ? c - p[r] : c;
         }
-      } else if (P == 2 && pi == 0) {
+      }
+    } else {
+      uint32_t* o = (uint32_t*)out + ((size_t)t * rows + j) * (kN + 1);
+      uint32_t tie = 0;  // coefficients within 8 units below a rounding tie
 #pragma unroll
-        for (int k = 0; k < 16; ++k) stash[tid + 256 * k] = x[k];
-      } else {
-        uint32_t* o = (uint32_t*)out + ((size_t)t * rows + j) * (kN + 1);
-        const u128 Q = make_u128(rc.Q_hi, rc.Q_lo);
+      for (int k = 0; k < 8; ++k) {
+        uint64_t A = fixed_part(x[0][k], bt->ntt.h[0]);
+        if (NP == 2) A += fixed_part(x[NP - 1][k], bt->ntt.h[NP - 1]);
+        // A = bits 64..127 of sum_p c_p H_p 2^96 (mod 2^128), at most 7 units low:
+        // integer part A >> 32, fraction A mod 2^32
+        const uint32_t f = (uint32_t)A;
+        if (0x80000000u - f - 1u < 8u) tie |= 1u << k;
+        o[kN - 1 - (tid + 512 * k)] = (uint32_t)(A >> 32) + (f >> 31);
+      }
+      while (tie) {  // rare: exact CRT and switch, rewriting the coefficient
+        const int k = __builtin_ctz(tie);
+        tie &= tie - 1;
+        uint64_t c[NP];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const uint32_t m = tid + 256 * k;
-          u128 v;
-          if (P == 1) {
-            const uint64_t c = mul_shoup(x[k], bt->ntt.crt[0], bt->ntt.crt_shoup[0], p);
-            v = c >= p ? c - p : c;
-          } else {
-            // y_p = c_p N^-1 (q / q_p)^-1 mod q_p; c = y_0 q_1 + y_1 q_0 mod q
-            uint64_t y0 = mul_shoup(stash[m], bt->ntt.crt[0], bt->ntt.crt_shoup[0], rc.q[0]);
-            y0 = y0 >= rc.q[0] ? y0 - rc.q[0] : y0;
-            uint64_t y1 = mul_shoup(x[k], bt->ntt.crt[1], bt->ntt.crt_shoup[1], rc.q[1]);
-            y1 = y1 >= rc.q[1] ? y1 - rc.q[1] : y1;
-            v = (u128)y0 * rc.q[1] + (u128)y1 * rc.q[0];
-            v = v >= Q ? v - Q : v;
-          }
-          o[kN - 1 - m] = switch_exact((i128)v, rc);
+        for (int r = 0; r < NP; ++r) {
+          c[r] = x[r][0];
+#pragma unroll
+          for (int kk = 1; kk < 8; ++kk) c[r] = k == kk ? x[r][kk] : c[r];
         }
+        const RingConst rc = kernarg_load(&bt->rc);
+        uint64_t y[NP];
+#pragma unroll
+        for (int r = 0; r < NP; ++r) {
+          y[r] = mul_shoup(c[r], bt->ntt.crt[r], bt->ntt.crt_shoup[r], p[r]);
+          y[r] = y[r] >= p[r] ? y[r] - p[r] : y[r];
+        }
+        u128 v = y[0];
+        if (NP == 2) {
+          const u128 Q = make_u128(rc.Q_hi, rc.Q_lo);
+          v = (u128)y[0] * p[NP - 1] + (u128)y[NP - 1] * p[0];
+          v = v >= Q ? v - Q : v;
+        }
+        o[kN - 1 - (tid + 512 * k)] = switch_exact((i128)v, rc);
       }
     }
   }
@@ -283,10 +449,18 @@ hipError_t launch_ntt_mask_fwd(const Batch& b, hipStream_t s) {
 hipError_t launch_ntt_mask(const Batch& b, hipStream_t s) {
   const uint32_t blocks = b.mask_start[b.n];
   if (blocks == 0) return hipSuccess;
-  if (b.raw)
-    hipLaunchKernelGGL(ntt_mask_kernel<true>, grid_for(blocks), dim3(kThreads), 0, s, b);
-  else
-    hipLaunchKernelGGL(ntt_mask_kernel<false>, grid_for(blocks), dim3(kThreads), 0, s, b);
+  const dim3 g = grid_for(blocks);
+  if (b.rc.P == 2) {
+    if (b.raw)
+      hipLaunchKernelGGL((ntt_mask_kernel<true, 2>), g, dim3(kInvThreads), 0, s, b);
+    else
+      hipLaunchKernelGGL((ntt_mask_kernel<false, 2>), g, dim3(kInvThreads), 0, s, b);
+  } else {
+    if (b.raw)
+      hipLaunchKernelGGL((ntt_mask_kernel<true, 1>), g, dim3(kInvThreads), 0, s, b);
+    else
+      hipLaunchKernelGGL((ntt_mask_kernel<false, 1>), g, dim3(kInvThreads), 0, s, b);
+  }
   return hipGetLastError();
 }
 

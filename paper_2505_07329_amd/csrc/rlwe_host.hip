@@ -267,10 +267,20 @@ int build_ntt(rlwe_ctx* ctx) {
     }
     const uint64_t ninv = powmod_h(N % q, q - 2, q);
     ctx->ntt.ninv[pi] = ninv;
+    ctx->ntt.bm[pi] = (uint32_t)(~0ull / q);
     ctx->ntt.ninv_shoup[pi] = (uint64_t)(((u128)ninv << 64) / q);
     const uint64_t c = mulmod_h(ninv, rc.crt_inv[pi], q);
     ctx->ntt.crt[pi] = c;
     ctx->ntt.crt_shoup[pi] = (uint64_t)(((u128)c << 64) / q);
+    // h = floor(c 2^128 / q) mod 2^128 = c floor(2^128 / q) + floor(c (2^128 mod q) / q)
+    const u128 all = ~(u128)0;                      // 2^128 - 1
+    u128 qd = all / q, rm = all % q + 1;            // 2^128 = qd q + rm
+    if (rm == q) {
+      ++qd;
+      rm = 0;
+    }
+    const u128 h = (u128)c * qd + ((u128)c * rm) / q;  // first product wraps mod 2^128
+    for (int w = 0; w < 4; ++w) ctx->ntt.h[pi][w] = (uint32_t)(h >> (32 * w));
   }
   hipError_t e = hipMalloc(&ctx->ntt_tables, host.size() * 8);
   if (e != hipSuccess) return fail(RLWE_ENOMEM, "hipMalloc(NTT tables): %s", hipGetErrorString(e));

@@ -47,6 +47,11 @@ struct NttConst {
   uint64_t crt_shoup[kMaxPrimes];
   uint64_t ninv[kMaxPrimes];        // N^-1 mod q_p
   uint64_t ninv_shoup[kMaxPrimes];
+  uint32_t bm[kMaxPrimes];          // floor(2^64 / q_p), the Barrett factor of the inverse
+  // H_p = crt_p 2^32 / q_p mod 2^32 in 32.96 fixed point (little-endian words):
+  // the switched coefficient is round(sum_p c_p H_p) mod 2^32 for any integers
+  // c_p = C mod q_p (multiples of q_p change the sum by multiples of 2^32)
+  uint32_t h[kMaxPrimes][4];
 };
 
 // Per weight-matrix constants of the switched epilogue.

@@ -41,16 +41,19 @@ def both_methods(ctx, W, flags_orient):
     return wn, wt
 
 
-@pytest.mark.parametrize("primes,d_out,d_in,T", [
-    (P4096, 64, 300, 3),       # one block, ragged
-    (P4096, 40, 5000, 2),      # two blocks, ragged second block
-    (P4096, 33, 8192, 2),      # two full blocks
-    (P4096[:1], 48, 4500, 2),  # one prime
+@pytest.mark.parametrize("primes,d_out,d_in,T,log_t", [
+    (P4096, 64, 300, 3, 28),       # one block, ragged
+    (P4096, 40, 5000, 2, 28),      # two blocks, ragged second block
+    (P4096, 33, 8192, 2, 28),      # two full blocks
+    (P4096[:1], 48, 4500, 2, 28),  # one prime
+    (P4096[:1], 20, 12300, 2, 30),  # four blocks (one prime: two cap K near 8256 for exact
+                                    # 128-bit sums): the pointwise sums are reduced per block
 ])
-def test_ntt_equals_matrix_cores(primes, d_out, d_in, T):
+def test_ntt_equals_matrix_cores(primes, d_out, d_in, T, log_t):
     print(f"case: ntt vs toeplitz {len(primes)} primes {d_out}x{d_in} T={T}", flush=True)
     r = rl()
-    ctx = r.Context(N, primes, 28)  # t = 2^28 keeps 127 * (row 1-norm) < t/2 up to K = 8192
+    # t = 2^28 keeps 127 * (row 1-norm) < t/2 up to K = 8192, 2^30 up to K = 33000
+    ctx = r.Context(N, primes, log_t)
     g = np.random.default_rng(d_out * 7 + d_in)
     W = synth.int8_uniform(g, (d_out, d_in))
     wn, wt = both_methods(ctx, W, r.RLWE_W_FWD | r.RLWE_W_TRANSPOSE)
