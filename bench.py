@@ -32,10 +32,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix peak, 5.0 POP/s
-# NTT method: VALU-bound. 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 7.86e13 32-bit lane
-# operations/s (the issue rate behind the 157.3 TFLOP/s fp32 vector peak), and one lazy
-# 54-bit Shoup butterfly compiles to 28 VALU instructions.
-NTT_PEAK_GBFLY = 256 * 4 * 32 * 2.4e9 / 28 / 1e9
+# NTT method: VALU-bound. A wave64 VALU instruction occupies a 16-lane SIMD for four
+# clocks (measured on MI355X for the 32-bit multiplies, 64-bit mads and adds, carry
+# chains and selects the transforms use; only plain 32-bit add/sub/move issue faster), so
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 lane operations/s, the rate behind the
+# 78.6 TFLOP/s fp64 and unpacked fp32 vector peaks. One lazy Gentleman-Sande butterfly
+# on 54-bit residues is 17 of them: 4 for the sum and the biased difference, 13 for the
+# Shoup product with a truncated quotient. A pointwise product counts as one butterfly.
+NTT_PEAK_GBFLY = 256 * 4 * 16 * 2.4e9 / 17 / 1e9
 
 
 def method_flag(args):
@@ -53,7 +57,9 @@ def roofline(products, kt, N, P, traffic=None):
     """Roofline of the dominant mask kernel of a set of products, each a dict with
     T, M (outputs per token), K, kept (digits on the matrix cores), ntt (method).
     Matrix cores: 2 T M N K kept int8 ops; NTT: per output and prime one inverse
-    transform ((N/2) log2 N butterflies) and L N pointwise products."""
+    transform ((N/2) log2 N butterflies) and L N pointwise products. traffic: measured
+    HBM bytes per launch by kernel kind ("mfma", "alu"), where known."""
+    traffic = traffic or {}
     import math
     mf_ops = sum(2.0 * p["T"] * p["M"] * N * p["K"] * p["kept"] for p in products if not p["ntt"])
     nt_ops = sum(p["T"] * p["M"] * P * ((N // 2) * math.log2(N) + ((p["K"] + N - 1) // N) * N)
@@ -63,12 +69,12 @@ def roofline(products, kt, N, P, traffic=None):
         a = mf_ops / (kt["mask_ms"] * 1e-3) / 1e12
         parts["mfma"] = {"bound": "mfma", "achieved": a, "peak": INT8_PEAK_TOPS,
                          "unit": "TOP/s (int8)", "frac": a / INT8_PEAK_TOPS,
-                         "traffic": traffic, "ms": kt["mask_ms"]}
+                         "traffic": traffic.get("mfma"), "ms": kt["mask_ms"]}
     if nt_ops and kt.get("ntt_ms", 0) > 0:
         a = nt_ops / (kt["ntt_ms"] * 1e-3) / 1e9
         parts["alu"] = {"bound": "alu", "achieved": a, "peak": NTT_PEAK_GBFLY,
                         "unit": "G butterfly/s (54-bit lazy Shoup, NTT method)",
-                        "frac": a / NTT_PEAK_GBFLY, "traffic": None, "ms": kt["ntt_ms"]}
+                        "frac": a / NTT_PEAK_GBFLY, "traffic": traffic.get("alu"), "ms": kt["ntt_ms"]}
     if not parts:
         return None, None
     dom = max(parts.values(), key=lambda x: x["ms"])
@@ -76,24 +82,29 @@ def roofline(products, kt, N, P, traffic=None):
     return ({k: v for k, v in dom.items() if k != "ms"},
             {k: v for k, v in other[0].items() if k != "ms"} if other else None)
 
-# HBM bytes moved by one mask-kernel launch of the default workload: two rocprofv3
-# --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by the
-# ratio of known to counted bytes of a plain copy kernel in the same run
-# (--copy-calibration). Valid for the kernel source it was taken on (sha256 of
-# csrc/k_mask.hip); for any other source the roofline reports traffic as null.
-MASK_TRAFFIC = {"fetch_bytes": 4382392135, "write_bytes": 4766662645,
-                "k_mask_sha256": "b71d09264e517098c1179f16657d1e4fa62f1eaae851294a6d0fdb5115986154"}
+# HBM bytes moved by one launch of each mask kernel on the default workload: two
+# rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by
+# the ratio of known to counted bytes of a plain copy kernel in the same run
+# (--copy-calibration). Valid for the kernel source it was taken on (sha256); for any
+# other source the roofline reports traffic as null.
+KERNEL_TRAFFIC = {
+    "mask": {"source": "k_mask.hip", "fetch_bytes": 4382392135, "write_bytes": 4766662645,
+             "sha256": "b71d09264e517098c1179f16657d1e4fa62f1eaae851294a6d0fdb5115986154"},
+    "ntt": {"source": "k_ntt.hip", "fetch_bytes": 17669736752, "write_bytes": 4365840928,
+            "sha256": "b369e138154be78737f47ae8525f6042a7770b75bc5a4a1c12d9f0186a915694"},
+}
 
 
-def mask_traffic():
+def kernel_traffic(kind):
     import hashlib
-    if not MASK_TRAFFIC:
+    rec = KERNEL_TRAFFIC.get(kind)
+    if not rec:
         return None
-    src = os.path.join(ROOT, "paper_2505_07329_amd", "csrc", "k_mask.hip")
+    src = os.path.join(ROOT, "paper_2505_07329_amd", "csrc", rec["source"])
     with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != MASK_TRAFFIC["k_mask_sha256"]:
+        if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
             return None
-    return MASK_TRAFFIC["fetch_bytes"] + MASK_TRAFFIC["write_bytes"]
+    return rec["fetch_bytes"] + rec["write_bytes"]
 
 
 def parse():
@@ -611,7 +622,7 @@ def main():
     one = dict(kt, mask_ms=per_launch["mask_ms"], ntt_ms=per_launch["ntt_ms"])
     is_ntt = rlwe.rlwe_weights_method(w.handle) == rlwe.RLWE_METHOD_NTT
     roof, _ = roofline([dict(T=T, M=d_out, K=d_in, kept=kept, ntt=is_ntt)], one, N, len(primes),
-                       traffic=None if is_ntt else mask_traffic())
+                       traffic={"mfma": kernel_traffic("mask"), "alu": kernel_traffic("ntt")})
     result = {
         "metric": "encrypted MACs/s (d_in*d_out*tokens/s), W.[x]_HE with outputs switched to 2^32",
         "value": value,

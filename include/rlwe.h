@@ -93,10 +93,13 @@ int rlwe_params_destroy(rlwe_ctx* ctx);
  *           (symmetric quantization, Sec. 4.2); read during the call only
  *   flags   RLWE_W_FWD and/or RLWE_W_TRANSPOSE, plus at most one method flag:
  *           RLWE_W_NTT keeps the reversed blocks in the NTT domain per prime
- *           (rows * L * P * N * 16 bytes; RLWE_EPARAM unless N = 4096),
- *           RLWE_W_TOEPLITZ keeps int8 only; without one, each orientation uses
- *           the NTT method when N = 4096 and its contraction spans two or more
- *           blocks of N, the matrix-core method otherwise
+ *           (rows * L * P * N * 8 bytes; RLWE_EPARAM unless N = 4096),
+ *           RLWE_W_TOEPLITZ keeps int8 only; without one, each orientation
+ *           (N = 4096) takes the method with the smaller estimated time per
+ *           output: matrix cores 8 + 0.0033 K dk ns (K the contraction length,
+ *           dk the digit planes kept, rlwe_weights_digits), transforms
+ *           (12.75 + 11.25 L) P ns (L = ceil(K / N) blocks, P primes), fitted to
+ *           MI355X timings; at other N the matrix-core method
  * Validation: 1 <= d_out, d_in <= 65536; the exact 128-bit accumulation needs
  * 127 * d * q / 2 < 2^127 for the contraction length d (d_in forward, d_out
  * transposed) -> RLWE_ESHAPE. Overflow: returns RLWE_EOVERFLOW if 127 times the

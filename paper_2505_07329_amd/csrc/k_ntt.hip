@@ -276,7 +276,9 @@ __device__ __forceinline__ void ntt_inverse(uint64_t (&x)[NP][8], uint64_t* lds,
 }  // namespace
 
 // NTT of the masks of every NTT-method product: one workgroup per (token, block,
-// prime). ahat[((t L + i) P + p) N + pos], bit-reversed order, residues in [0, p).
+// prime). ahat[(((t L + i) P + p) N + pos) * 2 + {0, 1}], bit-reversed order:
+// residue in [0, p) and its Shoup companion (the mask side carries the companions,
+// computed once per token, so the resident weights need only their residues).
 __global__ void __launch_bounds__(kThreads) ntt_mask_fwd_kernel(Batch) {
   __shared__ uint64_t lds[kLdsWords];
   const BatchPtr bt = kernarg_batch();
@@ -295,9 +297,17 @@ __global__ void __launch_bounds__(kThreads) ntt_mask_fwd_kernel(Batch) {
 #pragma unroll
   for (int k = 0; k < 16; ++k) x[k] = A[tid + 256 * k];
   ntt_forward(x, lds, tw, p, tid);
-  uint64_t* dst = bt->it[ii].ahat + (size_t)loc * kN + 16 * tid;
+  uint64_t* dst = bt->it[ii].ahat + 2 * ((size_t)loc * kN + 16 * tid);
+  const uint64_t r1 = bt->ntt.rq[p_idx][0], r0 = bt->ntt.rq[p_idx][1];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) dst[k] = reduce4(x[k], p);
+  for (int k = 0; k < 16; ++k) {
+    const uint64_t v = reduce4(x[k], p);
+    // Shoup companion floor(v 2^64 / p): v floor(2^128 / p) / 2^64 is at most 1 low
+    uint64_t c = v * r1 + __umul64hi(v, r0);
+    c += (0 - c * p) >= p ? 1 : 0;
+    dst[2 * k] = v;
+    dst[2 * k + 1] = c;
+  }
 }
 
 // Product kernel: one workgroup per (row j, tile of kTokTile tokens) of each item;
@@ -314,7 +324,7 @@ __global__ void __launch_bounds__(kInvThreads) ntt_mask_kernel(Batch) {
   const uint32_t loc = blk - bt->mask_start[ii];
   const uint32_t j = loc % rows, t0 = (loc / rows) * kTokTile;
   const uint64_t* ahat = bt->it[ii].ahat;
-  const uint64_t* what = bt->it[ii].what;  // [rows][L][P][N] (w, w') pairs
+  const uint64_t* what = bt->it[ii].what;  // [rows][L][P][N] residues
   void* out = bt->it[ii].out;
   // per-prime constants, indexed by compile-time prime numbers only (ring
   // constants are read in place: a local copy indexed at run time would live in
@@ -342,15 +352,15 @@ __global__ void __launch_bounds__(kInvThreads) ntt_mask_kernel(Batch) {
 #pragma unroll
       for (int k = 0; k < 8; ++k) x[r][k] = 0;
       for (uint32_t i = 0; i < L; ++i) {  // positions 8 tid + k (layout Q1)
-        const uint64_t* a = ahat + (((size_t)t * L + i) * NP + r) * kN + 8 * tid;
-        const uint64_t* w = what + 2 * ((((size_t)j * L + i) * NP + r) * kN + 8 * tid);
+        const uint64_t* a = ahat + 2 * ((((size_t)t * L + i) * NP + r) * kN + 8 * tid);
+        const uint64_t* w = what + (((size_t)j * L + i) * NP + r) * kN + 8 * tid;
         if (L <= 2) {
 #pragma unroll
-          for (int k = 0; k < 8; ++k) x[r][k] += mul_shoup4(a[k], w[2 * k], w[2 * k + 1], md[r].pn);
+          for (int k = 0; k < 8; ++k) x[r][k] += mul_shoup4(w[k], a[2 * k], a[2 * k + 1], md[r].pn);
         } else {
 #pragma unroll
           for (int k = 0; k < 8; ++k)
-            x[r][k] = reduce_barrett(x[r][k] + mul_shoup4(a[k], w[2 * k], w[2 * k + 1], md[r].pn),
+            x[r][k] = reduce_barrett(x[r][k] + mul_shoup4(w[k], a[2 * k], a[2 * k + 1], md[r].pn),
                                      md[r]);
         }
       }
@@ -412,7 +422,7 @@ __global__ void __launch_bounds__(kInvThreads) ntt_mask_kernel(Batch) {
 
 // NTT-domain weights: one workgroup per (row j, block i, prime p). Block i of row
 // j is encoded reversed, w_hat[k] = w_j[iN + N - 1 - k] (zero past K), Sec. 4.3.
-// what[(((j L + i) P + p) N + pos) * 2 + {0, 1}] = (value, Shoup companion).
+// what[((j L + i) P + p) N + pos], bit-reversed order, residues in [0, p).
 __global__ void __launch_bounds__(kThreads) ntt_weights_kernel(MatArgs m, NttConst ntt,
                                                                RingConst rc, uint64_t* what) {
   __shared__ uint64_t lds[kLdsWords];
@@ -430,13 +440,9 @@ __global__ void __launch_bounds__(kThreads) ntt_weights_kernel(MatArgs m, NttCon
     x[k] = v < 0 ? p - (uint64_t)(-v) : (uint64_t)v;
   }
   ntt_forward(x, lds, ntt.fwd[p_idx], p, tid);
-  uint64_t* dst = what + 2 * ((size_t)loc * kN + 16 * tid);
+  uint64_t* dst = what + (size_t)loc * kN + 16 * tid;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const uint64_t v = reduce4(x[k], p);
-    dst[2 * k] = v;
-    dst[2 * k + 1] = (uint64_t)(((u128)v << 64) / p);
-  }
+  for (int k = 0; k < 16; ++k) dst[k] = reduce4(x[k], p);
 }
 
 hipError_t launch_ntt_mask_fwd(const Batch& b, hipStream_t s) {

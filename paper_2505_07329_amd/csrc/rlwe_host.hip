@@ -225,9 +225,9 @@ int hip_fail(hipError_t e, const char* what) {
 }
 
 // Workspace of one product: mask digit planes (matrix-core method) or transformed
-// masks (NTT method), then body digit planes.
+// masks with their Shoup companions (NTT method), then body digit planes.
 size_t ws_mask_bytes(const RingConst& rc, const MatArgs& m, uint32_t T, bool ntt) {
-  return ntt ? align_up((size_t)T * m.L * rc.P * rc.N * 8, 256)
+  return ntt ? align_up((size_t)T * m.L * rc.P * rc.N * 16, 256)
              : align_up((size_t)T * rc.D * m.L * 2 * rc.N, 256);
 }
 size_t ws_item(const RingConst& rc, const MatArgs& m, uint32_t T, bool ntt) {
@@ -268,6 +268,9 @@ int build_ntt(rlwe_ctx* ctx) {
     const uint64_t ninv = powmod_h(N % q, q - 2, q);
     ctx->ntt.ninv[pi] = ninv;
     ctx->ntt.bm[pi] = (uint32_t)(~0ull / q);
+    const u128 rq = ~(u128)0 / q;  // floor((2^128 - 1) / q) = floor(2^128 / q) for odd q
+    ctx->ntt.rq[pi][0] = (uint64_t)(rq >> 64);
+    ctx->ntt.rq[pi][1] = (uint64_t)rq;
     ctx->ntt.ninv_shoup[pi] = (uint64_t)(((u128)ninv << 64) / q);
     const uint64_t c = mulmod_h(ninv, rc.crt_inv[pi], q);
     ctx->ntt.crt[pi] = c;
@@ -500,13 +503,20 @@ static int load_mat(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32_t
                 transpose ? " (transposed)" : "");
   const int rc2 = make_switch_const(rc, mx, &m.sc);
   if (rc2 != RLWE_OK) return rc2;
-  // method: NTT when asked for, or by default when available and K spans several
-  // blocks (the transform cost per output does not grow with K, the matrix-core
-  // cost does)
-  m.ntt = method == 1 || (method == 0 && ctx->ntt_ok && a.L >= 2);
+  // method: as asked for, else the one with the smaller estimated time per output
+  // (token x output row). The matrix-core cost grows with K times the digit planes
+  // kept, the transform cost with the blocks L only; the constants are fitted to
+  // MI355X timings of both kernels at N = 4096 with two primes (K = 512 .. 8192),
+  // the transform cost taken per prime.
+  m.ntt = method == 1;
+  if (method == 0 && ctx->ntt_ok) {
+    const double mfma_ns = 8.0 + 0.0033 * (double)a.k * m.sc.dk;
+    const double ntt_ns = (12.75 + 11.25 * a.L) * rc.P;
+    m.ntt = ntt_ns < mfma_ns;
+  }
   if (m.ntt) {
     if (!ctx->ntt_ok) return fail(RLWE_EPARAM, "the NTT method needs N = %u", kNttN);
-    const size_t bytes = (size_t)a.rows * a.L * rc.P * rc.N * 16;
+    const size_t bytes = (size_t)a.rows * a.L * rc.P * rc.N * 8;
     e = hipMalloc(&m.what, bytes);
     if (e != hipSuccess) return fail(RLWE_ENOMEM, "hipMalloc(NTT weights, %zu bytes): %s", bytes, hipGetErrorString(e));
     e = launch_ntt_weights(a, ctx->ntt, rc, m.what, s);

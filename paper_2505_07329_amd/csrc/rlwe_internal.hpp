@@ -48,6 +48,7 @@ struct NttConst {
   uint64_t ninv[kMaxPrimes];        // N^-1 mod q_p
   uint64_t ninv_shoup[kMaxPrimes];
   uint32_t bm[kMaxPrimes];          // floor(2^64 / q_p), the Barrett factor of the inverse
+  uint64_t rq[kMaxPrimes][2];       // floor(2^128 / q_p): high word, low word
   // H_p = crt_p 2^32 / q_p mod 2^32 in 32.96 fixed point (little-endian words):
   // the switched coefficient is round(sum_p c_p H_p) mod 2^32 for any integers
   // c_p = C mod q_p (multiples of q_p change the sum by multiples of 2^32)
@@ -121,8 +122,8 @@ struct Item {
   MatArgs m;
   SwitchConst sc;
   uint32_t method;     // 0: digit planes on the matrix cores, 1: NTT
-  const uint64_t* what;  // NTT method: [rows][L][P][N] (value, Shoup companion) pairs
-  uint64_t* ahat;        // NTT method: [T][L][P][N] transformed masks (workspace)
+  const uint64_t* what;  // NTT method: [rows][L][P][N] transformed weight blocks
+  uint64_t* ahat;        // NTT method: [T][L][P][N] (mask, Shoup companion) pairs (workspace)
   const uint64_t* ct;  // [T][L][2][P][N]
   int8_t* emask;       // [T][D][L][2N]: per digit plane, index m <-> Toeplitz offset m - N
   int8_t* ebody;       // [T][D][L][N]
