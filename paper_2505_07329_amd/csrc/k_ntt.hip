@@ -346,22 +346,40 @@ __global__ void __launch_bounds__(kInvThreads) ntt_mask_kernel(Batch) {
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     uint64_t x[NP][8];
-    // pointwise products below 4p each: two blocks stay below 8p, more are reduced
+    // pointwise products below 4p each: two blocks stay below 8p, more are reduced.
+    // One block (K <= N): the loads of every prime are issued together, before any use.
+    if (L == 1) {
+      uint64_t wv[NP][8], av[NP][16];
 #pragma unroll
-    for (int r = 0; r < NP; ++r) {
+      for (int r = 0; r < NP; ++r) {
+        const uint64_t* a = ahat + 2 * (((size_t)t * NP + r) * kN + 8 * tid);
+        const uint64_t* w = what + ((size_t)j * NP + r) * kN + 8 * tid;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) x[r][k] = 0;
-      for (uint32_t i = 0; i < L; ++i) {  // positions 8 tid + k (layout Q1)
-        const uint64_t* a = ahat + 2 * ((((size_t)t * L + i) * NP + r) * kN + 8 * tid);
-        const uint64_t* w = what + (((size_t)j * L + i) * NP + r) * kN + 8 * tid;
-        if (L <= 2) {
+        for (int k = 0; k < 8; ++k) wv[r][k] = w[k];
 #pragma unroll
-          for (int k = 0; k < 8; ++k) x[r][k] += mul_shoup4(w[k], a[2 * k], a[2 * k + 1], md[r].pn);
-        } else {
+        for (int k = 0; k < 16; ++k) av[r][k] = a[k];
+      }
 #pragma unroll
-          for (int k = 0; k < 8; ++k)
-            x[r][k] = reduce_barrett(x[r][k] + mul_shoup4(w[k], a[2 * k], a[2 * k + 1], md[r].pn),
-                                     md[r]);
+      for (int r = 0; r < NP; ++r)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[r][k] = mul_shoup4(wv[r][k], av[r][2 * k], av[r][2 * k + 1], md[r].pn);
+    } else {
+#pragma unroll
+      for (int r = 0; r < NP; ++r) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[r][k] = 0;
+        for (uint32_t i = 0; i < L; ++i) {  // positions 8 tid + k (layout Q1)
+          const uint64_t* a = ahat + 2 * ((((size_t)t * L + i) * NP + r) * kN + 8 * tid);
+          const uint64_t* w = what + (((size_t)j * L + i) * NP + r) * kN + 8 * tid;
+          if (L <= 2) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) x[r][k] += mul_shoup4(w[k], a[2 * k], a[2 * k + 1], md[r].pn);
+          } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+              x[r][k] = reduce_barrett(x[r][k] + mul_shoup4(w[k], a[2 * k], a[2 * k + 1], md[r].pn),
+                                       md[r]);
+          }
         }
       }
     }
