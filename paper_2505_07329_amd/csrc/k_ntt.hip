@@ -311,9 +311,11 @@ __global__ void __launch_bounds__(kThreads) ntt_mask_fwd_kernel(Batch) {
 }
 
 // Product kernel: one workgroup per (row j, tile of kTokTile tokens) of each item;
-// the NP = P primes of a token are transformed together.
-template <bool RAW, int NP>
-__global__ void __launch_bounds__(kInvThreads) ntt_mask_kernel(Batch) {
+// the NP = P primes of a token are transformed together. LC = 2: every item has
+// exactly two input blocks; LC = 0: any number (a launch holds one class).
+template <bool RAW, int NP, int LC>
+__global__ void __launch_bounds__(kInvThreads, LC == 2 ? 4 : 1) ntt_mask_kernel(Batch) {
+  static_assert(LC == 0 || LC == 2, "block classes: exactly two, or any");
   __shared__ uint64_t lds[NP * kInvLdsWords];
   const BatchPtr bt = kernarg_batch();
   const uint32_t blk = linear_block();
@@ -347,22 +349,30 @@ __global__ void __launch_bounds__(kInvThreads) ntt_mask_kernel(Batch) {
     asm volatile("" : "+v"(tid));
     uint64_t x[NP][8];
     // pointwise products below 4p each: two blocks stay below 8p, more are reduced.
-    // One block (K <= N): the loads of every prime are issued together, before any use.
-    if (L == 1) {
-      uint64_t wv[NP][8], av[NP][16];
+    // One block (LC = 0, L = 1) or two (LC = 2): the loads of every prime of a block
+    // are issued together, before any use.
+    if (LC == 2 || L == 1) {
+      constexpr int NB = LC == 2 ? 2 : 1;
 #pragma unroll
-      for (int r = 0; r < NP; ++r) {
-        const uint64_t* a = ahat + 2 * (((size_t)t * NP + r) * kN + 8 * tid);
-        const uint64_t* w = what + ((size_t)j * NP + r) * kN + 8 * tid;
+      for (int i = 0; i < NB; ++i) {
+        uint64_t wv[NP][8], av[NP][16];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) wv[r][k] = w[k];
+        for (int r = 0; r < NP; ++r) {
+          const uint64_t* a = ahat + 2 * ((((size_t)t * NB + i) * NP + r) * kN + 8 * tid);
+          const uint64_t* w = what + (((size_t)j * NB + i) * NP + r) * kN + 8 * tid;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) av[r][k] = a[k];
+          for (int k = 0; k < 8; ++k) wv[r][k] = w[k];
+#pragma unroll
+          for (int k = 0; k < 16; ++k) av[r][k] = a[k];
+        }
+#pragma unroll
+        for (int r = 0; r < NP; ++r)
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const uint64_t v = mul_shoup4(wv[r][k], av[r][2 * k], av[r][2 * k + 1], md[r].pn);
+            x[r][k] = i == 0 ? v : x[r][k] + v;
+          }
       }
-#pragma unroll
-      for (int r = 0; r < NP; ++r)
-#pragma unroll
-        for (int k = 0; k < 8; ++k) x[r][k] = mul_shoup4(wv[r][k], av[r][2 * k], av[r][2 * k + 1], md[r].pn);
     } else {
 #pragma unroll
       for (int r = 0; r < NP; ++r) {
@@ -470,21 +480,29 @@ hipError_t launch_ntt_mask_fwd(const Batch& b, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_ntt_mask(const Batch& b, hipStream_t s) {
+template <int LC>
+void launch_ntt_mask_lc(const Batch& b, dim3 g, hipStream_t s) {
+  if (b.rc.P == 2) {
+    if (b.raw)
+      hipLaunchKernelGGL((ntt_mask_kernel<true, 2, LC>), g, dim3(kInvThreads), 0, s, b);
+    else
+      hipLaunchKernelGGL((ntt_mask_kernel<false, 2, LC>), g, dim3(kInvThreads), 0, s, b);
+  } else {
+    if (b.raw)
+      hipLaunchKernelGGL((ntt_mask_kernel<true, 1, LC>), g, dim3(kInvThreads), 0, s, b);
+    else
+      hipLaunchKernelGGL((ntt_mask_kernel<false, 1, LC>), g, dim3(kInvThreads), 0, s, b);
+  }
+}
+
+hipError_t launch_ntt_mask(const Batch& b, uint32_t lclass, hipStream_t s) {
   const uint32_t blocks = b.mask_start[b.n];
   if (blocks == 0) return hipSuccess;
   const dim3 g = grid_for(blocks);
-  if (b.rc.P == 2) {
-    if (b.raw)
-      hipLaunchKernelGGL((ntt_mask_kernel<true, 2>), g, dim3(kInvThreads), 0, s, b);
-    else
-      hipLaunchKernelGGL((ntt_mask_kernel<false, 2>), g, dim3(kInvThreads), 0, s, b);
-  } else {
-    if (b.raw)
-      hipLaunchKernelGGL((ntt_mask_kernel<true, 1>), g, dim3(kInvThreads), 0, s, b);
-    else
-      hipLaunchKernelGGL((ntt_mask_kernel<false, 1>), g, dim3(kInvThreads), 0, s, b);
-  }
+  if (lclass == 2)
+    launch_ntt_mask_lc<2>(b, g, s);
+  else
+    launch_ntt_mask_lc<0>(b, g, s);
   return hipGetLastError();
 }
 

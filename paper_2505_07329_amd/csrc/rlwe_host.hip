@@ -691,19 +691,22 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
     if (e != hipSuccess) return hip_fail(e, "mask NTT kernel");
   }
   // matrix-core method: one mask launch per distinct number of kept digits;
-  // NTT method: one launch for all its products
+  // NTT method: one launch for the products with two input blocks, one for the rest
+  auto lclass = [](const Item& it) { return it.m.L == 2 ? 2u : 0u; };
   bool done[kMaxBatch] = {};
   for (uint32_t x = 0; x < cnt; ++x) {
     if (done[x]) continue;
     const bool ntt = all.it[x].method == 1;
-    const uint32_t dk = all.it[x].sc.dk;
+    const uint32_t dk = all.it[x].sc.dk, lc = lclass(all.it[x]);
     Batch mb{};
     mb.rc = rc;
     mb.ntt = all.ntt;
     mb.raw = all.raw;
     mb.force_exact = all.force_exact;
     for (uint32_t y = x; y < cnt; ++y) {
-      if (done[y] || (all.it[y].method == 1) != ntt || (!ntt && all.it[y].sc.dk != dk)) continue;
+      if (done[y] || (all.it[y].method == 1) != ntt || (!ntt && all.it[y].sc.dk != dk) ||
+          (ntt && lclass(all.it[y]) != lc))
+        continue;
       done[y] = true;
       const Item& it = all.it[y];
       mb.it[mb.n] = it;
@@ -712,7 +715,8 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
       mb.mask_start[mb.n + 1] = mb.mask_start[mb.n] + blocks;
       ++mb.n;
     }
-    e = timed(ctx, ntt ? K_NTT : K_MASK, s, [&] { return ntt ? launch_ntt_mask(mb, s) : launch_mask(mb, dk, s); });
+    e = timed(ctx, ntt ? K_NTT : K_MASK, s,
+              [&] { return ntt ? launch_ntt_mask(mb, lc, s) : launch_mask(mb, dk, s); });
     if (e != hipSuccess) return hip_fail(e, "mask kernel");
   }
   e = timed(ctx, K_BODY, s, [&] { return launch_body(all, s); });

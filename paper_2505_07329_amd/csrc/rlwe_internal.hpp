@@ -186,7 +186,8 @@ hipError_t launch_prep(const Batch& b, hipStream_t s);
 hipError_t launch_mask(const Batch& b, uint32_t dk, hipStream_t s);
 hipError_t launch_body(const Batch& b, hipStream_t s);
 hipError_t launch_ntt_mask_fwd(const Batch& b, hipStream_t s);
-hipError_t launch_ntt_mask(const Batch& b, hipStream_t s);
+// lclass: every item of b has L = 2 (2), or any L (0)
+hipError_t launch_ntt_mask(const Batch& b, uint32_t lclass, hipStream_t s);
 hipError_t launch_ntt_weights(const MatArgs& m, const NttConst& ntt, const RingConst& rc,
                               uint64_t* what, hipStream_t s);
 hipError_t launch_modswitch(const RingConst& rc, const uint64_t* in, size_t count, uint32_t* out,

@@ -150,12 +150,15 @@ def test_mixed_batch_and_graph():
     g = np.random.default_rng(5)
     W1 = synth.int8_uniform(g, (72, 6000))   # NTT (two blocks)
     W2 = synth.int8_uniform(g, (96, 1000))   # matrix cores
+    W3 = synth.int8_uniform(g, (40, 3000))   # NTT (one block, forced)
     w1 = r.Weights(ctx, dev(W1), r.RLWE_W_FWD | r.RLWE_W_TRANSPOSE)
     w2 = r.Weights(ctx, dev(W2), r.RLWE_W_FWD | r.RLWE_W_TRANSPOSE)
+    w3 = r.Weights(ctx, dev(W3), r.RLWE_W_FWD | r.RLWE_W_NTT)
     assert r.rlwe_weights_method(w1.handle) == r.RLWE_METHOD_NTT
     assert r.rlwe_weights_method(w1.handle, True) == r.RLWE_METHOD_TOEPLITZ
+    # NTT products with one and with two input blocks go out as two launches
     specs = [(w1, False, 6000, 72, 3), (w2, True, 96, 1000, 2), (w1, True, 72, 6000, 2),
-             (w2, False, 1000, 96, 9)]
+             (w2, False, 1000, 96, 9), (w3, False, 3000, 40, 5)]
     items = []
     for s, (w, tr, K, M, T) in enumerate(specs):
         L = (K + N - 1) // N
@@ -182,4 +185,5 @@ def test_mixed_batch_and_graph():
     r.rlwe_graph_destroy(graph)
     w1.close()
     w2.close()
+    w3.close()
     ctx.close()
