@@ -43,7 +43,7 @@ constexpr int kN = kNttN;
 constexpr int kThreads = 256;
 constexpr int kLdsWords = kN + kN / 16;  // padded exchange buffer: position + position / 16
 constexpr int kInvThreads = 512;
-constexpr int kInvLdsWords = kN + kN / 8;  // inverse exchange buffer per prime: position + position / 8
+constexpr int kInvLdsWords = kN + kN / 8;  // inverse exchange buffer per prime (8 blocks of 576 words)
 
 struct Tw {
   uint64_t w, wp;
@@ -197,7 +197,22 @@ struct InvLayout {
                        : tid;
   }
 };
-__device__ __forceinline__ uint32_t pad8(uint32_t pos) { return pos + pos / 8; }
+// Exchange buffer addresses (8-byte words) of position pos in exchange EX (1:
+// Q1 -> Q2, 2: Q2 -> Q3, 3: Q3 -> Q4). 64-bit LDS accesses are served 32 lanes at
+// a time over 32 banks of 8 bytes (measured on gfx950): Q1 and Q2 need the
+// padding of exchange 1, Q3 and Q4 are conflict-free unpadded, and exchange 2
+// swizzles bits 3-4 of the position within a wave's block. Exchanges 1 and 2
+// keep each wave inside its own block of 576 words (no barrier around them);
+// exchange 3 lies between workgroup barriers.
+template <int EX>
+__device__ __forceinline__ uint32_t xaddr(uint32_t pos) {
+  if (EX == 1) return pos + pos / 8;
+  if (EX == 2) {
+    const uint32_t l = pos & 511;
+    return 576 * (pos >> 9) + (l ^ (((l >> 6) & 3) << 3));
+  }
+  return pos;
+}
 
 template <int NP, int PASS, bool END>
 __device__ __forceinline__ void inv_pass(uint64_t (&x)[NP][8], int tid,
@@ -224,21 +239,21 @@ __device__ __forceinline__ void inv_pass(uint64_t (&x)[NP][8], int tid,
       for (int k = 0; k < 2; ++k) x[r][k] = reduce_barrett(x[r][k], md[r]);
   }
 }
-template <int NP, int PASS>
+template <int NP, int PASS, int EX>
 __device__ __forceinline__ void inv_store(uint64_t* lds, const uint64_t (&x)[NP][8], int tid) {
   const uint32_t base = InvLayout<PASS>::base(tid);
 #pragma unroll
   for (int r = 0; r < NP; ++r)
 #pragma unroll
-    for (int k = 0; k < 8; ++k) lds[r * kInvLdsWords + pad8(base + InvLayout<PASS>::S * k)] = x[r][k];
+    for (int k = 0; k < 8; ++k) lds[r * kInvLdsWords + xaddr<EX>(base + InvLayout<PASS>::S * k)] = x[r][k];
 }
-template <int NP, int PASS>
+template <int NP, int PASS, int EX>
 __device__ __forceinline__ void inv_load(const uint64_t* lds, uint64_t (&x)[NP][8], int tid) {
   const uint32_t base = InvLayout<PASS>::base(tid);
 #pragma unroll
   for (int r = 0; r < NP; ++r)
 #pragma unroll
-    for (int k = 0; k < 8; ++k) x[r][k] = lds[r * kInvLdsWords + pad8(base + InvLayout<PASS>::S * k)];
+    for (int k = 0; k < 8; ++k) x[r][k] = lds[r * kInvLdsWords + xaddr<EX>(base + InvLayout<PASS>::S * k)];
 }
 // Orders a wave's LDS stores before its following loads (the exchange partners
 // are lanes of the same wave; the LDS serves one wave's operations in order).
@@ -257,19 +272,19 @@ __device__ __forceinline__ void ntt_inverse(uint64_t (&x)[NP][8], uint64_t* lds,
                                             const InvMod (&md)[NP], int tid) {
   inv_pass<NP, 0, true>(x, tid, tw, md);
   __syncthreads();  // no wave still reads the previous transform's Q4 positions
-  inv_store<NP, 0>(lds, x, tid);
+  inv_store<NP, 0, 1>(lds, x, tid);
   wave_exchange_fence();
-  inv_load<NP, 1>(lds, x, tid);
+  inv_load<NP, 1, 1>(lds, x, tid);
   inv_pass<NP, 1, true>(x, tid, tw, md);
   wave_exchange_fence();  // every lane of the wave has read its Q2 positions
-  inv_store<NP, 1>(lds, x, tid);
+  inv_store<NP, 1, 2>(lds, x, tid);
   wave_exchange_fence();
-  inv_load<NP, 2>(lds, x, tid);
+  inv_load<NP, 2, 2>(lds, x, tid);
   inv_pass<NP, 2, true>(x, tid, tw, md);
-  __syncthreads();  // every wave is done with its own region
-  inv_store<NP, 2>(lds, x, tid);
+  __syncthreads();  // every wave is done with its own block
+  inv_store<NP, 2, 3>(lds, x, tid);
   __syncthreads();
-  inv_load<NP, 3>(lds, x, tid);
+  inv_load<NP, 3, 3>(lds, x, tid);
   inv_pass<NP, 3, false>(x, tid, tw, md);
 }
 
