@@ -67,6 +67,8 @@ def lib() -> ctypes.CDLL:
                                        ctypes.c_size_t, _u32p, ctypes.c_int, _u64p]
         L.orc_modswitch.argtypes = [ctypes.c_uint32, _u64p, ctypes.c_size_t, ctypes.c_uint32,
                                     _u64p, _u32p]
+        L.orc_modswitch_bits.argtypes = [ctypes.c_uint32, _u64p, ctypes.c_size_t, ctypes.c_uint32,
+                                         _u64p, ctypes.c_uint32, _u32p]
         L.orc_crt.argtypes = [ctypes.c_uint32, _u64p, _u64p, _u64p, _u64p]
         L.orc_lwe_phase.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u64p, _i8p,
                                     ctypes.c_size_t, _u64p, _u64p]
@@ -256,6 +258,64 @@ def modswitch(primes, raw: np.ndarray) -> np.ndarray:
     return out.reshape(tuple(lead) + (ln,))
 
 
+def modswitch_bits(primes, raw: np.ndarray, bits: int) -> np.ndarray:
+    """round(c 2^bits / q) mod 2^bits of CRT(raw[..., p, n]), 1 <= bits <= 32, by binary long
+    division (Sec. 3.2, ModulusSwitch to q_out = 2^bits): (..., P, len) -> (..., len) u32."""
+    if not 1 <= bits <= 32:
+        raise ValueError("bits must lie in [1, 32]")
+    pr = _primes(primes)
+    P = len(pr)
+    ln = raw.shape[-1]
+    lead = raw.shape[:-2]
+    count = int(np.prod(lead)) if lead else 1
+    r = np.ascontiguousarray(raw.reshape(count, P, ln), dtype=np.uint64)
+    out = np.empty((count, ln), dtype=np.uint32)
+    lib().orc_modswitch_bits(P, _p(pr, _u64p), count, ln, _p(r, _u64p), bits, _p(out, _u32p))
+    return out.reshape(tuple(lead) + (ln,))
+
+
+def packed_words(length: int, bits: int) -> int:
+    """32-bit words of one ciphertext of `length` coefficients packed at `bits` bits each."""
+    return (length * bits + 31) // 32
+
+
+def pack_bits(values: np.ndarray, bits: int) -> np.ndarray:
+    """Bit-pack the switched coefficients of each ciphertext (Sec. 4.5: the switched output
+    is returned packed into a bit-vector): values (..., len) u32 below 2^bits -> (...,
+    packed_words(len, bits)) u32. Coefficient i of a ciphertext occupies stream bits
+    [i bits, (i + 1) bits), least significant first; stream bit b is bit b mod 32 of word
+    b // 32; unused high bits of the last word are zero. Written with Python integers."""
+    v = np.asarray(values, dtype=np.uint32)
+    if v.size and int(v.max()) >> bits:
+        raise ValueError("a coefficient does not fit in the given bits")
+    ln = v.shape[-1]
+    lead = v.shape[:-1]
+    flat = v.reshape(-1, ln)
+    nw = packed_words(ln, bits)
+    out = np.empty((flat.shape[0], nw), dtype=np.uint32)
+    for c in range(flat.shape[0]):
+        acc = 0
+        for i, x in enumerate(flat[c].tolist()):
+            acc |= x << (i * bits)
+        out[c] = [(acc >> (32 * w)) & 0xFFFFFFFF for w in range(nw)]
+    return out.reshape(tuple(lead) + (nw,))
+
+
+def unpack_bits(words: np.ndarray, bits: int, length: int) -> np.ndarray:
+    """Inverse of pack_bits: (..., packed_words(length, bits)) u32 -> (..., length) u32."""
+    w = np.asarray(words, dtype=np.uint32)
+    lead = w.shape[:-1]
+    flat = w.reshape(-1, w.shape[-1])
+    out = np.empty((flat.shape[0], length), dtype=np.uint32)
+    mask = (1 << bits) - 1
+    for c in range(flat.shape[0]):
+        acc = 0
+        for i, x in enumerate(flat[c].tolist()):
+            acc |= x << (32 * i)
+        out[c] = [(acc >> (i * bits)) & mask for i in range(length)]
+    return out.reshape(tuple(lead) + (length,))
+
+
 def lwe_phase(N: int, primes, S: np.ndarray, lwe: np.ndarray) -> list[int]:
     """Centred phase b - <a, S> mod q of LWE ciphertexts (..., P, N+1), as Python ints."""
     pr = _primes(primes)
@@ -277,6 +337,12 @@ def lwe_phase_u32(N: int, S: np.ndarray, lwe: np.ndarray) -> np.ndarray:
     S_ = np.ascontiguousarray(S, dtype=np.int8)
     lib().orc_lwe_phase_u32(N, _p(S_, _i8p), count, _p(c, _u32p), _p(out, _i64p))
     return out.reshape(lwe.shape[:-1])
+
+
+def lwe_phase_bits(N: int, S: np.ndarray, lwe: np.ndarray, bits: int) -> np.ndarray:
+    """Centred phase modulo 2^bits of LWE ciphertexts switched to 2^bits (..., N+1): int64."""
+    ph = lwe_phase_u32(N, S, lwe).astype(np.int64) % (1 << bits)
+    return np.where(ph >= (1 << (bits - 1)), ph - (1 << bits), ph)
 
 
 def decode(phase: int, delta_: int) -> int:

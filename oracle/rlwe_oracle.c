@@ -325,6 +325,35 @@ static uint32_t switch_one(u128 c, u128 q) {
   return (uint32_t)rounded;
 }
 
+/* round(c * 2^k / q) mod 2^k for 0 <= c < q, 1 <= k <= 32, by binary long
+ * division of c * 2^k by q, one quotient bit per step (remainder < q < 2^110). */
+static uint32_t switch_bits(u128 c, u128 q, uint32_t k) {
+  u128 rem = c;
+  uint64_t quo = 0;
+  for (uint32_t i = 0; i < k; ++i) {
+    rem <<= 1;
+    quo <<= 1;
+    if (rem >= q) {
+      rem -= q;
+      quo |= 1;
+    }
+  }
+  quo += (2 * rem >= q); /* remainder rem/q >= 1/2 rounds up */
+  return (uint32_t)(quo & ((k == 32) ? 0xffffffffull : ((1ull << k) - 1)));
+}
+
+void orc_modswitch_bits(uint32_t P, const uint64_t* primes, size_t count, uint32_t len,
+                        const uint64_t* in, uint32_t k, uint32_t* out) {
+  u128 q = product_q(P, primes);
+#pragma omp parallel for schedule(static)
+  for (size_t c = 0; c < count; ++c) {
+    for (uint32_t n = 0; n < len; ++n) {
+      const uint64_t* r = in + c * (size_t)P * len + n;
+      out[c * len + n] = switch_bits(crt(P, primes, r, len), q, k);
+    }
+  }
+}
+
 void orc_modswitch(uint32_t P, const uint64_t* primes, size_t count, uint32_t len,
                    const uint64_t* in, uint32_t* out) {
   u128 q = product_q(P, primes);

@@ -90,6 +90,10 @@ void orc_matmul_clear(uint32_t N, uint32_t P, const uint64_t* primes, uint32_t d
  * exact long division in two 16-bit steps. */
 void orc_modswitch(uint32_t P, const uint64_t* primes, size_t count, uint32_t len,
                    const uint64_t* in, uint32_t* out);
+/* round(c * 2^k / q) mod 2^k of the CRT value c of every coefficient, 1 <= k <= 32
+ * (binary long division): in u64[count][P][len] -> out u32[count][len]. */
+void orc_modswitch_bits(uint32_t P, const uint64_t* primes, size_t count, uint32_t len,
+                        const uint64_t* in, uint32_t k, uint32_t* out);
 
 /* CRT value of one residue vector, c in [0, q), as two 64-bit halves. */
 void orc_crt(uint32_t P, const uint64_t* primes, const uint64_t* residues, uint64_t* hi,
