@@ -60,7 +60,8 @@ typedef struct rlwe_weights rlwe_weights;
  *   num_primes  P, 1 or 2: q = q_1 ... q_P in RNS form
  *   primes      host pointer to P distinct primes, each < 2^54 and q_p = 1 mod 2N
  *   log2_t      plaintext modulus t = 2^log2_t, 1 <= log2_t <= 32; Delta = floor(q/t)
- *   log2_q_out  modulus of switched outputs; must be 32 */
+ *   log2_q_out  switched outputs are modulo q_out = 2^log2_q_out, 1..32 (the paper
+ *               uses 26 bits, Sec. 4.4); values are returned in uint32 words */
 typedef struct rlwe_params {
   uint32_t N;
   uint32_t num_primes;
@@ -112,7 +113,7 @@ int rlwe_weights_load(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32
 int rlwe_weights_free(rlwe_weights* w);
 
 /* Flags of ct_matmul_clear */
-#define RLWE_OUT_SWITCHED 0u    /* outputs switched to 2^32 (uint32) */
+#define RLWE_OUT_SWITCHED 0u    /* outputs switched to q_out = 2^log2_q_out (uint32) */
 #define RLWE_OUT_RAW_Q 1u       /* outputs modulo q, per prime (uint64) */
 #define RLWE_OUT_FORCE_EXACT 2u /* switched outputs through the slow exact path
                                    for every coefficient (same bits; test hook) */
@@ -131,7 +132,8 @@ int rlwe_weights_free(rlwe_weights* w);
  *          a_n = sum_k w[k] * (A_i[k-n] if k >= n else -A_i[N+k-n]) summed over
  *          blocks (SampleExtract at N-1 of the block products), b = sum_k w[k] B_i[k]
  *            RLWE_OUT_SWITCHED: uint32 [tokens][M][N+1], each coefficient c
- *              replaced by round(c * 2^32 / q) mod 2^32 (ModulusSwitch, Sec. 3.2)
+ *              replaced by round(c * 2^k / q) mod 2^k, k = log2_q_out
+ *              (ModulusSwitch, Sec. 3.2)
  *            RLWE_OUT_RAW_Q:    uint64 [tokens][M][P][N+1], residues mod q_p
  * tokens = 0 is a no-op. Uses the context workspace (grown on demand with
  * hipMalloc unless rlwe_workspace_reserve made it large enough). Asynchronous
@@ -176,13 +178,32 @@ int rlwe_graph_capture_batch(rlwe_ctx* ctx, const ct_matmul_desc* descs, uint32_
 int rlwe_graph_launch(rlwe_graph* g, rlwe_stream_t stream);
 int rlwe_graph_destroy(rlwe_graph* g);
 
-/* ModulusSwitch q -> 2^32 (Sec. 3.2) of `count` vectors of N+1 coefficients:
+/* ModulusSwitch q -> 2^k, k = log2_q_out (Sec. 3.2), of `count` vectors of N+1
+ * coefficients:
  *   in   device, uint64 [count][P][N+1] canonical residues
- *   out  device, uint32 [count][N+1], round(c * 2^32 / q) mod 2^32 with
+ *   out  device, uint32 [count][N+1], round(c * 2^k / q) mod 2^k with
  *        c = CRT(residues) in [0, q) (a tie cannot occur: q is odd)
  * count = 0 is a no-op. Asynchronous on `stream`; no workspace. */
 int ct_modswitch(rlwe_ctx* ctx, const uint64_t* in, size_t count, uint32_t* out,
                  rlwe_stream_t stream);
+
+/* Bit-packing of switched ciphertexts (Sec. 4.5: the switched output is packed
+ * into a bit-vector before it is returned; sizes as in Sec. 4.4):
+ *   in    device, uint32 [count][len], coefficients below 2^k (k = log2_q_out;
+ *         higher bits are ignored), e.g. the switched outputs (len = N + 1)
+ *   out   device, uint32 [count][rlwe_packed_words(len, k)]: coefficient i of a
+ *         ciphertext occupies stream bits [i k, (i + 1) k), least significant
+ *         first; stream bit b is bit b mod 32 of word b / 32; unused high bits of
+ *         the last word are zero. Caller-owned; must not overlap `in`.
+ * count = 0 or len = 0 is a no-op; RLWE_ESHAPE if count * words exceeds 2^39.
+ * Asynchronous on `stream`; no workspace. HBM-bound (4 len bytes read, 4 words
+ * written per ciphertext). */
+int ct_pack_bits(rlwe_ctx* ctx, const uint32_t* in, size_t count, uint32_t len, uint32_t* out,
+                 rlwe_stream_t stream);
+
+/* 32-bit words of one ciphertext of `len` coefficients packed at `bits` bits:
+ * ceil(len * bits / 32); 0 unless 1 <= bits <= 32. */
+size_t rlwe_packed_words(uint32_t len, uint32_t bits);
 
 /* Bytes of workspace ct_matmul_clear needs for this call shape. */
 size_t rlwe_workspace_bytes(const rlwe_ctx* ctx, const rlwe_weights* w, uint32_t transpose,
@@ -200,9 +221,10 @@ int rlwe_workspace_reserve(rlwe_ctx* ctx, size_t bytes);
  * and closes the window. Not for use inside hipGraph capture. */
 typedef struct rlwe_kernel_times {
   /* summed durations: digit preparation and mask transforms (prep), matrix-core
-   * mask products (mask), NTT mask products (ntt), body, standalone switch */
-  double prep_ms, mask_ms, body_ms, modswitch_ms, ntt_ms;
-  uint32_t prep_n, mask_n, body_n, modswitch_n, ntt_n; /* launches recorded */
+   * mask products (mask), NTT mask products (ntt), body, standalone switch,
+   * bit-packing (pack) */
+  double prep_ms, mask_ms, body_ms, modswitch_ms, ntt_ms, pack_ms;
+  uint32_t prep_n, mask_n, body_n, modswitch_n, ntt_n, pack_n; /* launches recorded */
   uint32_t dropped;
 } rlwe_kernel_times;
 

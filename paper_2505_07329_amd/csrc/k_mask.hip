@@ -42,12 +42,13 @@ __host__ __device__ constexpr int copy_base(int s) { return s == 0 ? 0 : s == 1 
 constexpr int kDigitWords = 248 + kCopyWords;  // 328
 constexpr int kWRowWords = kKC / 4 + 4;    // LDS row pitch of the weight tile (dwords)
 
-// round(U * G) mod 2^32 where U is a signed 128-bit integer (u0..u3) and
-// G = g / 2^128 (g < 2^128). Partial products of U*g below bit 96 are dropped
-// (error < 6 * 2^-32 in the result, always downwards), which the caller's
-// uncertainty band absorbs. Sets amb when the fraction is within eps of 1/2.
+// round(U * G * 2^(k - 32)) mod 2^k where U is a signed 128-bit integer (u0..u3),
+// G = g / 2^128 (g < 2^128) and U G = c 2^32 / q mod 2^32. Partial products of U*g
+// below bit 96 are dropped (error < 6 * 2^-32 in U G, always downwards), which
+// the caller's uncertainty band absorbs. Sets amb when the fraction at the
+// rounding position is within eps units of 2^-32 of one half.
 __device__ inline uint32_t fixed_round(uint32_t u0, uint32_t u1, uint32_t u2, uint32_t u3,
-                                       const uint32_t* g, uint32_t eps, bool& amb) {
+                                       const uint32_t* g, uint32_t eps, uint32_t k, bool& amb) {
   auto lo = [](uint32_t a, uint32_t b) -> uint64_t { return (uint32_t)(a * b); };
   auto hi = [](uint32_t a, uint32_t b) -> uint64_t { return __umulhi(a, b); };
   const uint64_t acc3 = hi(u0, g[2]) + hi(u1, g[1]) + hi(u2, g[0]) + lo(u0, g[3]) +
@@ -56,10 +57,10 @@ __device__ inline uint32_t fixed_round(uint32_t u0, uint32_t u1, uint32_t u2, ui
                         hi(u3, g[0]) + lo(u1, g[3]) + lo(u2, g[2]) + lo(u3, g[1]);
   uint64_t w34 = (acc4 << 32) | (uint32_t)acc3;
   if ((int32_t)u3 < 0) w34 -= (uint64_t)g[0] << 32;  // U = U_unsigned - 2^128
-  const uint32_t w3 = (uint32_t)w34, w4 = (uint32_t)(w34 >> 32);
-  const uint32_t dist = w3 - 0x80000000u;  // fraction - 1/2, modulo 2^32
-  amb = (dist + eps) <= 2u * eps;
-  return w4 + (w3 >> 31);
+  int64_t dist;  // fraction - 1/2 in units of 2^-32 of U G
+  const uint32_t res = round_qout(w34, k, dist);
+  amb = (uint64_t)(dist + (int64_t)eps) <= 2ull * eps;
+  return res;
 }
 
 // Exact switched value of element (t, jj, nn), computed by the whole wave: every
@@ -397,7 +398,7 @@ mask_kernel(Batch) {
       } else {
         bool amb;
         uint32_t res = fixed_round((uint32_t)U, (uint32_t)(U >> 32), (uint32_t)(U >> 64),
-                                   (uint32_t)(U >> 96), sc.g, sc.eps, amb);
+                                   (uint32_t)(U >> 96), sc.g, sc.eps, rc.qbits, amb);
         uint64_t pending = __ballot(live && (amb || force_exact));
         while (pending) {
           const int src = __ffsll((unsigned long long)pending) - 1;

@@ -424,15 +424,17 @@ __global__ void __launch_bounds__(kInvThreads, LC == 2 ? 4 : 1) ntt_mask_kernel(
     } else {
       uint32_t* o = (uint32_t*)out + ((size_t)t * rows + j) * (kN + 1);
       uint32_t tie = 0;  // coefficients within 8 units below a rounding tie
+      const uint32_t qbits = bt->rc.qbits;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         uint64_t A = fixed_part(x[0][k], bt->ntt.h[0]);
         if (NP == 2) A += fixed_part(x[NP - 1][k], bt->ntt.h[NP - 1]);
         // A = bits 64..127 of sum_p c_p H_p 2^96 (mod 2^128), at most 7 units low:
-        // integer part A >> 32, fraction A mod 2^32
-        const uint32_t f = (uint32_t)A;
-        if (0x80000000u - f - 1u < 8u) tie |= 1u << k;
-        o[kN - 1 - (tid + 512 * k)] = (uint32_t)(A >> 32) + (f >> 31);
+        // c 2^32 / q mod 2^32 in 32.32 fixed point, rounded to q_out = 2^qbits
+        int64_t dist;
+        const uint32_t res = round_qout(A, qbits, dist);
+        if (dist < 0 && dist >= -8) tie |= 1u << k;
+        o[kN - 1 - (tid + 512 * k)] = res;
       }
       while (tie) {  // rare: exact CRT and switch, rewriting the coefficient
         const int k = __builtin_ctz(tie);

@@ -199,6 +199,41 @@ hipError_t launch_modswitch(const RingConst& rc, const uint64_t* in, size_t coun
   return hipGetLastError();
 }
 
+// Bit-packing of switched ciphertexts (Sec. 4.5: the switched output is returned
+// packed into a bit-vector): in u32[count][len] with values below 2^k -> out
+// u32[count][words], words = ceil(len k / 32). Coefficient i of a ciphertext
+// occupies stream bits [i k, (i + 1) k), least significant first; unused high bits
+// of the last word are zero. One thread per output word gathers the coefficients
+// that touch it (at most ceil(32 / k) + 1); reads and writes are coalesced.
+__global__ void __launch_bounds__(256) pack_bits_kernel(const uint32_t* in, size_t count,
+                                                        uint32_t len, uint32_t k,
+                                                        uint32_t words, uint32_t* out) {
+  const size_t idx = (size_t)linear_block() * blockDim.x + threadIdx.x;
+  if (idx >= count * words) return;
+  const size_t c = idx / words;
+  const uint64_t b0 = 32ull * (idx % words);  // first stream bit of this word
+  const uint32_t* src = in + c * len;
+  const uint32_t mask = qout_mask(k);
+  uint64_t acc = 0;
+  for (uint32_t i = (uint32_t)(b0 / k); i < len && (uint64_t)i * k < b0 + 32; ++i) {
+    const uint64_t v = src[i] & mask;
+    const int64_t sh = (int64_t)i * k - (int64_t)b0;  // in (-k, 32)
+    acc |= sh >= 0 ? v << sh : v >> -sh;
+  }
+  out[idx] = (uint32_t)acc;
+}
+
+hipError_t launch_pack_bits(const uint32_t* in, size_t count, uint32_t len, uint32_t k,
+                            uint32_t* out, hipStream_t s) {
+  const uint32_t words = (uint32_t)(((uint64_t)len * k + 31) / 32);
+  const size_t total = count * words;
+  if (total == 0) return hipSuccess;
+  if ((total + 255) / 256 >= (1ull << 31)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pack_bits_kernel, grid_for((uint32_t)((total + 255) / 256)), dim3(256), 0,
+                     s, in, count, len, k, words, out);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- weight set-up
 
 __global__ void transpose_pad_kernel(const int8_t* src, uint32_t rows, uint32_t cols,

@@ -80,7 +80,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 }  // namespace
 
 namespace {
-enum KernelKind { K_PREP = 0, K_MASK = 1, K_BODY = 2, K_MODSWITCH = 3, K_NTT = 4 };
+enum KernelKind { K_PREP = 0, K_MASK = 1, K_BODY = 2, K_MODSWITCH = 3, K_NTT = 4, K_PACK = 5 };
 constexpr int kMaxProfiled = 4096;
 struct Profiler {
   bool on = false;
@@ -331,7 +331,8 @@ int rlwe_params_init(const rlwe_params* p, int hip_device, rlwe_ctx** out) {
   if (p->num_primes < 1 || p->num_primes > 2)
     return fail(RLWE_EPARAM, "num_primes = %u must be 1 or 2", p->num_primes);
   if (!p->primes) return fail(RLWE_EINVAL, "primes is null");
-  if (p->log2_q_out != 32) return fail(RLWE_EPARAM, "log2_q_out = %u must be 32", p->log2_q_out);
+  if (p->log2_q_out < 1 || p->log2_q_out > 32)
+    return fail(RLWE_EPARAM, "log2_q_out = %u outside [1, 32]", p->log2_q_out);
   if (p->log2_t < 1 || p->log2_t > 32) return fail(RLWE_EPARAM, "log2_t = %u outside [1, 32]", p->log2_t);
   RingConst rc{};
   rc.N = N;
@@ -362,7 +363,8 @@ int rlwe_params_init(const rlwe_params* p, int hip_device, rlwe_ctx** out) {
   const u128 half = (Q - 1) / 2;
   rc.half_lo = (uint64_t)half;
   rc.half_hi = (uint64_t)(half >> 64);
-  rc.inv_q32 = 4294967296.0 / u128_to_double(Q);
+  rc.qbits = p->log2_q_out;
+  rc.inv_qout = ldexp(1.0, (int)rc.qbits) / u128_to_double(Q);
 
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
@@ -408,8 +410,10 @@ int rlwe_profile_end(rlwe_ctx* ctx, rlwe_kernel_times* out) {
   p->on = false;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  double* ms[5] = {&out->prep_ms, &out->mask_ms, &out->body_ms, &out->modswitch_ms, &out->ntt_ms};
-  uint32_t* n[5] = {&out->prep_n, &out->mask_n, &out->body_n, &out->modswitch_n, &out->ntt_n};
+  double* ms[6] = {&out->prep_ms, &out->mask_ms, &out->body_ms, &out->modswitch_ms, &out->ntt_ms,
+                   &out->pack_ms};
+  uint32_t* n[6] = {&out->prep_n, &out->mask_n, &out->body_n, &out->modswitch_n, &out->ntt_n,
+                    &out->pack_n};
   for (int i = 0; i < p->used; ++i) {
     e = hipEventSynchronize(p->ev[i][1]);
     if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
@@ -870,6 +874,25 @@ int ct_modswitch(rlwe_ctx* ctx, const uint64_t* in, size_t count, uint32_t* out,
   hipStream_t s = (hipStream_t)stream;
   e = timed(ctx, K_MODSWITCH, s, [&] { return launch_modswitch(ctx->rc, in, count, out, s); });
   if (e != hipSuccess) return hip_fail(e, "modswitch kernel");
+  return ok();
+}
+
+size_t rlwe_packed_words(uint32_t len, uint32_t bits) {
+  if (bits < 1 || bits > 32) return 0;
+  return ((size_t)len * bits + 31) / 32;
+}
+
+int ct_pack_bits(rlwe_ctx* ctx, const uint32_t* in, size_t count, uint32_t len, uint32_t* out,
+                 rlwe_stream_t stream) {
+  if (!ctx) return fail(RLWE_EINVAL, "ct_pack_bits: null context");
+  if (count == 0 || len == 0) return ok();
+  if (!in || !out) return fail(RLWE_EINVAL, "ct_pack_bits: null buffer");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  e = timed(ctx, K_PACK, s, [&] { return launch_pack_bits(in, count, len, ctx->rc.qbits, out, s); });
+  if (e == hipErrorInvalidValue) return fail(RLWE_ESHAPE, "ct_pack_bits: %zu ciphertexts too many", count);
+  if (e != hipSuccess) return hip_fail(e, "pack kernel");
   return ok();
 }
 

@@ -34,7 +34,8 @@ struct RingConst {
   uint64_t crt_inv_shoup[kMaxPrimes];  // floor(crt_inv * 2^64 / q_p)
   uint64_t Q_lo, Q_hi;             // q = prod q_p as 128-bit
   uint64_t half_lo, half_hi;       // (q - 1) / 2
-  double inv_q32;                  // 2^32 / q (estimate only; results are corrected exactly)
+  uint32_t qbits;                  // switched outputs are modulo q_out = 2^qbits (1..32)
+  double inv_qout;                 // 2^qbits / q (estimate only; results are corrected exactly)
 };
 
 // Constants of the number-theoretic-transform method (N = kNttN only).
@@ -83,20 +84,36 @@ __device__ inline double i128_to_double(i128 v) {
   return (double)hi * 18446744073709551616.0 + (double)lo;
 }
 
-// round(V * 2^32 / q) mod 2^32 for an exact integer V with |V| < 2^127 and
-// |V 2^32 / q| < 2^53. A double estimate is corrected by exact remainder
-// arithmetic modulo 2^128: Z = V 2^32 - F q is computed with wrapping 128-bit
-// operations, which is exact because the true Z lies in [0, 2^128).
+__host__ __device__ inline uint32_t qout_mask(uint32_t k) {
+  return k >= 32 ? 0xffffffffu : (1u << k) - 1u;
+}
+
+// round(V * 2^k / q) mod 2^k (k = rc.qbits) for an exact integer V with
+// |V| < 2^127 and |V 2^k / q| < 2^53. A double estimate is corrected by exact
+// remainder arithmetic modulo 2^128: Z = V 2^k - F q is computed with wrapping
+// 128-bit operations, which is exact because the true Z lies in [0, 2^128).
 __device__ inline uint32_t switch_exact(i128 V, const RingConst& rc) {
   const u128 q = make_u128(rc.Q_hi, rc.Q_lo);
-  const double est = i128_to_double(V) * rc.inv_q32;
-  int64_t f = (int64_t)floor(est) - 8;  // |est - V 2^32/q| < 4 for these magnitudes
-  u128 z = ((u128)V << 32) - (u128)(i128)f * q;
+  const double est = i128_to_double(V) * rc.inv_qout;
+  int64_t f = (int64_t)floor(est) - 8;  // |est - V 2^k/q| < 4 for these magnitudes
+  u128 z = ((u128)V << rc.qbits) - (u128)(i128)f * q;
   for (int it = 0; it < 24 && z >= q; ++it) {
     z -= q;
     ++f;
   }
-  return (uint32_t)(f + (2 * z > q ? 1 : 0));
+  return (uint32_t)(f + (2 * z > q ? 1 : 0)) & qout_mask(rc.qbits);
+}
+
+// Rounding to q_out = 2^k of a value given in 32.32 fixed point: W = x 2^32 with
+// x = c 2^32 / q mod 2^32, so c 2^k / q = W / 2^(64 - k). Returns the rounded value
+// mod 2^k and, in dist, the fraction minus one half in units of W (negative below
+// the tie). With k = 32 this is the integer part W >> 32 and its top fraction bit.
+__device__ inline uint32_t round_qout(uint64_t W, uint32_t k, int64_t& dist) {
+  const uint32_t sh = 64 - k;  // fraction bits, 32..63
+  const uint64_t frac = W & ((1ull << sh) - 1);
+  const uint64_t half = 1ull << (sh - 1);
+  dist = (int64_t)(frac - half);
+  return (uint32_t)((W >> sh) + (frac >= half ? 1 : 0)) & qout_mask(k);
 }
 
 // Shoup multiplication a * w mod q, wp = floor(w 2^64 / q), a < 2^64, q < 2^63.
@@ -190,6 +207,8 @@ hipError_t launch_ntt_mask_fwd(const Batch& b, hipStream_t s);
 hipError_t launch_ntt_mask(const Batch& b, uint32_t lclass, hipStream_t s);
 hipError_t launch_ntt_weights(const MatArgs& m, const NttConst& ntt, const RingConst& rc,
                               uint64_t* what, hipStream_t s);
+hipError_t launch_pack_bits(const uint32_t* in, size_t count, uint32_t len, uint32_t k,
+                            uint32_t* out, hipStream_t s);
 hipError_t launch_modswitch(const RingConst& rc, const uint64_t* in, size_t count, uint32_t* out,
                             hipStream_t s);
 hipError_t launch_transpose_pad(const int8_t* src, uint32_t rows, uint32_t cols, bool transpose,

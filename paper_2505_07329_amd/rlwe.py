@@ -36,7 +36,8 @@ EXPORTS = ("rlwe_params_init", "rlwe_params_destroy", "rlwe_weights_load", "rlwe
            "ct_matmul_clear", "ct_modswitch", "rlwe_workspace_bytes", "rlwe_workspace_reserve",
            "rlwe_profile_begin", "rlwe_profile_end", "rlwe_weights_digits", "ct_matmul_batch",
            "rlwe_batch_workspace_bytes", "rlwe_graph_capture_batch", "rlwe_graph_launch",
-           "rlwe_graph_destroy", "rlwe_weights_method", "rlwe_last_error")
+           "rlwe_graph_destroy", "rlwe_weights_method", "ct_pack_bits", "rlwe_packed_words",
+           "rlwe_last_error")
 
 
 class RlweError(RuntimeError):
@@ -48,10 +49,11 @@ class RlweError(RuntimeError):
 class KernelTimes(ctypes.Structure):
     _fields_ = [("prep_ms", ctypes.c_double), ("mask_ms", ctypes.c_double),
                 ("body_ms", ctypes.c_double), ("modswitch_ms", ctypes.c_double),
-                ("ntt_ms", ctypes.c_double),
+                ("ntt_ms", ctypes.c_double), ("pack_ms", ctypes.c_double),
                 ("prep_n", ctypes.c_uint32), ("mask_n", ctypes.c_uint32),
                 ("body_n", ctypes.c_uint32), ("modswitch_n", ctypes.c_uint32),
-                ("ntt_n", ctypes.c_uint32), ("dropped", ctypes.c_uint32)]
+                ("ntt_n", ctypes.c_uint32), ("pack_n", ctypes.c_uint32),
+                ("dropped", ctypes.c_uint32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -88,6 +90,9 @@ def lib() -> ctypes.CDLL:
     L.ct_matmul_clear.argtypes = [vp, vp, ctypes.c_uint32, vp, ctypes.c_uint32, vp,
                                   ctypes.c_uint32, vp]
     L.ct_modswitch.argtypes = [vp, vp, ctypes.c_size_t, vp, vp]
+    L.ct_pack_bits.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_uint32, vp, vp]
+    L.rlwe_packed_words.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+    L.rlwe_packed_words.restype = ctypes.c_size_t
     L.rlwe_workspace_bytes.argtypes = [vp, vp, ctypes.c_uint32, ctypes.c_uint32]
     L.rlwe_workspace_bytes.restype = ctypes.c_size_t
     L.rlwe_workspace_reserve.argtypes = [vp, ctypes.c_size_t]
@@ -107,7 +112,8 @@ def lib() -> ctypes.CDLL:
     L.rlwe_last_error.argtypes = []
     L.rlwe_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("rlwe_last_error", "rlwe_workspace_bytes", "rlwe_batch_workspace_bytes"):
+        if name not in ("rlwe_last_error", "rlwe_workspace_bytes", "rlwe_batch_workspace_bytes",
+                        "rlwe_packed_words"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -173,6 +179,15 @@ def ct_matmul_clear(ctx: int, w: int, ct, tokens: int, out, transpose: bool = Fa
 def ct_modswitch(ctx: int, raw, count: int, out, stream=None) -> None:
     """raw: int64 [count][P][N+1]; out: int32 [count][N+1]."""
     _check(lib().ct_modswitch(ctx, _ptr(raw), count, _ptr(out), _stream(stream)))
+
+
+def ct_pack_bits(ctx: int, inp, count: int, length: int, out, stream=None) -> None:
+    """inp: int32 [count][length] switched coefficients; out: int32 [count][rlwe_packed_words]."""
+    _check(lib().ct_pack_bits(ctx, _ptr(inp), count, length, _ptr(out), _stream(stream)))
+
+
+def rlwe_packed_words(length: int, bits: int) -> int:
+    return int(lib().rlwe_packed_words(length, bits))
 
 
 def rlwe_workspace_bytes(ctx: int, w: int, transpose: bool, tokens: int) -> int:
@@ -243,10 +258,12 @@ def rlwe_profile_end(ctx: int) -> dict:
 class Context:
     """Owns an rlwe_ctx handle."""
 
-    def __init__(self, N: int, primes: Sequence[int], log2_t: int, device: int = 0):
+    def __init__(self, N: int, primes: Sequence[int], log2_t: int, device: int = 0,
+                 log2_q_out: int = 32):
         self.N, self.primes, self.log2_t = N, tuple(int(p) for p in primes), log2_t
         self.P = len(self.primes)
-        self.handle = rlwe_params_init(N, self.primes, log2_t, device)
+        self.log2_q_out = log2_q_out
+        self.handle = rlwe_params_init(N, self.primes, log2_t, device, log2_q_out)
 
     def close(self) -> None:
         if self.handle:
@@ -291,6 +308,18 @@ def matmul(ctx: Context, w: Weights, ct, transpose: bool = False, raw: bool = Fa
         out = torch.empty(shape, dtype=torch.int64 if raw else torch.int32, device=ct.device)
     flags = (RLWE_OUT_RAW_Q if raw else 0) | (RLWE_OUT_FORCE_EXACT if force_exact else 0)
     ct_matmul_clear(ctx.handle, w.handle, ct, T, out, transpose, flags, stream)
+    return out
+
+
+def pack_bits(ctx: Context, switched, out=None, stream=None):
+    """Bit-pack switched ciphertexts (..., len) int32 -> (..., words) int32 (torch)."""
+    import torch
+    length = switched.shape[-1]
+    count = switched.numel() // length
+    words = rlwe_packed_words(length, ctx.log2_q_out)
+    if out is None:
+        out = torch.empty(switched.shape[:-1] + (words,), dtype=torch.int32, device=switched.device)
+    ct_pack_bits(ctx.handle, switched, count, length, out, stream)
     return out
 
 

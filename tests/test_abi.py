@@ -54,7 +54,8 @@ P4096 = (18014398509309953, 18014398509293569)
     (4096, ((1 << 54) + 1,), 26, 32, -2),           # >= 2^54
     (4096, (40961,), 26, 32, -2),                   # 40961 = 1 mod 8192 is prime but t > q
     (4096, (12289,), 8, 32, -2),                    # 12289 is prime but not 1 mod 8192
-    (4096, P4096, 26, 26, -2),                      # only 2^32 outputs are supported
+    (4096, P4096, 26, 0, -2),                       # q_out = 2^0
+    (4096, P4096, 26, 33, -2),                      # q_out above 2^32
     (4096, P4096, 0, 32, -2),                       # log2_t out of range
     (4096, P4096 + (12289,), 26, 32, -2),           # three primes
 ])
