@@ -117,8 +117,13 @@ def parse():
                     help="target CPU time of the oracle baseline sample (0 disables it)")
     ap.add_argument("--chunk", type=int, default=256, help="mlp: tokens per call")
     ap.add_argument("--method", choices=["auto", "ntt", "toeplitz"], default="auto",
-                    help="mask-product method of every weight matrix (auto: NTT where the "
-                         "contraction spans two or more blocks of N, matrix cores otherwise)")
+                    help="mask-product method of every weight matrix (auto: the library's choice "
+                         "by estimated time per output)")
+    ap.add_argument("--q-out-bits", type=int, default=32,
+                    help="attn: switched outputs modulo 2^K (the paper's output modulus is 26 bits)")
+    ap.add_argument("--pack", action="store_true",
+                    help="attn: every step also bit-packs the switched outputs (ct_pack_bits), "
+                         "reported with its own HBM roofline")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="attn: before the timed region, run one plain elementwise copy kernel "
                          "(int32 bitwise not) reading and writing GIB GiB each, as the known-size "
@@ -580,16 +585,21 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    ctx = rlwe.Context(N, primes, log2_t, device=0)
+    qbits = args.q_out_bits
+    ctx = rlwe.Context(N, primes, log2_t, device=0, log2_q_out=qbits)
     w = rlwe.Weights(ctx, torch.from_numpy(W).to(dev), rlwe.RLWE_W_FWD | method_flag(args))
     ct = torch.from_numpy(ct_np.view(np.int64)).to(dev)
     out = torch.empty((T, d_out, N + 1), dtype=torch.int32, device=dev)
+    words = rlwe.rlwe_packed_words(N + 1, qbits)
+    packed = torch.empty((T, d_out, words), dtype=torch.int32, device=dev) if args.pack else None
     rlwe.rlwe_workspace_reserve(ctx.handle, rlwe.rlwe_workspace_bytes(ctx.handle, w.handle, False, T))
     kept, total = rlwe.rlwe_weights_digits(w.handle)
     stream = torch.cuda.current_stream()
 
     def step():
         rlwe.ct_matmul_clear(ctx.handle, w.handle, ct, T, out, False, rlwe.RLWE_OUT_SWITCHED, stream)
+        if args.pack:
+            rlwe.ct_pack_bits(ctx.handle, out, T * d_out, N + 1, packed, stream)
 
     for _ in range(args.warmup):
         step()
@@ -623,8 +633,17 @@ def main():
     is_ntt = rlwe.rlwe_weights_method(w.handle) == rlwe.RLWE_METHOD_NTT
     roof, _ = roofline([dict(T=T, M=d_out, K=d_in, kept=kept, ntt=is_ntt)], one, N, len(primes),
                        traffic={"mfma": kernel_traffic("mask"), "alu": kernel_traffic("ntt")})
+    pack_roof = None
+    if args.pack and kt["pack_n"]:
+        pack_ms = kt["pack_ms"] / kt["pack_n"]
+        moved = T * d_out * 4 * ((N + 1) + words)  # switched words read once, packed words written
+        gbs = moved / (pack_ms * 1e-3) / 1e9
+        pack_roof = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+                     "frac": gbs / 8000.0, "traffic": None, "ms": pack_ms,
+                     "bytes_out_per_lwe": 4 * words}
+    switched = f"switched to 2^{qbits}" + (" and bit-packed" if args.pack else "")
     result = {
-        "metric": "encrypted MACs/s (d_in*d_out*tokens/s), W.[x]_HE with outputs switched to 2^32",
+        "metric": f"encrypted MACs/s (d_in*d_out*tokens/s), W.[x]_HE with outputs {switched}",
         "value": value,
         "unit": "MAC/s",
         "n_gpus": 1,
@@ -637,7 +656,8 @@ def main():
         "dtype": "int8",
         "data": "synthetic (seeded uniform int8 weights, uniform ciphertext residues)",
         "config": {"workload": cfg["name"], "d_in": d_in, "d_out": d_out, "tokens": T, "N": N,
-                   "primes": len(primes), "log2_t": log2_t, "q_out": "2^32",
+                   "primes": len(primes), "log2_t": log2_t, "q_out": f"2^{qbits}",
+                   "packed": bool(args.pack),
                    "method": "ntt" if is_ntt else "toeplitz",
                    "digits_on_matrix_cores": None if is_ntt else f"{kept}/{total}"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
@@ -646,6 +666,9 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
+    if pack_roof:
+        result["kernels_ms"]["pack"] = pack_roof.pop("ms")
+        result["roofline_pack"] = pack_roof
     w.close()
     ctx.close()
     if args.cpu_seconds > 0:

@@ -203,34 +203,64 @@ hipError_t launch_modswitch(const RingConst& rc, const uint64_t* in, size_t coun
 // packed into a bit-vector): in u32[count][len] with values below 2^k -> out
 // u32[count][words], words = ceil(len k / 32). Coefficient i of a ciphertext
 // occupies stream bits [i k, (i + 1) k), least significant first; unused high bits
-// of the last word are zero. One thread per output word gathers the coefficients
-// that touch it (at most ceil(32 / k) + 1); reads and writes are coalesced.
+// of the last word are zero. HBM-bound: a workgroup owns a tile of consecutive
+// output words of one ciphertext, stages the coefficients they touch in LDS (sized
+// for k at launch; every thread has several independent lane-consecutive loads in
+// flight) and assembles up to eight words per thread, each store instruction
+// lane-consecutive. The first coefficient of word w is floor(32 w / k) =
+// umulhi(32 w, ceil(2^32 / k)), exact for 32 w < 2^21 and k >= 2.
+// Words per workgroup tile: 2048 (eight per thread) for k >= 16, 1024 for k >= 8,
+// else 256, so the staged coefficients stay below 33 KB of LDS.
+__host__ __device__ inline uint32_t pack_tile_words(uint32_t k) {
+  return k >= 16 ? 2048u : k >= 8 ? 1024u : 256u;
+}
+__host__ __device__ inline uint32_t pack_tile_coeffs(uint32_t k) {
+  return (pack_tile_words(k) * 32 + k - 1) / k + 2;  // coefficients touching one tile, at most
+}
+
 __global__ void __launch_bounds__(256) pack_bits_kernel(const uint32_t* in, size_t count,
-                                                        uint32_t len, uint32_t k,
-                                                        uint32_t words, uint32_t* out) {
-  const size_t idx = (size_t)linear_block() * blockDim.x + threadIdx.x;
-  if (idx >= count * words) return;
-  const size_t c = idx / words;
-  const uint64_t b0 = 32ull * (idx % words);  // first stream bit of this word
-  const uint32_t* src = in + c * len;
+                                                        uint32_t len, uint32_t k, uint32_t kinv,
+                                                        uint32_t words, uint32_t tiles,
+                                                        uint32_t* out) {
+  extern __shared__ uint32_t coeff[];
+  const uint32_t tw = pack_tile_words(k);
+  const uint32_t blk = linear_block();
+  const uint32_t c = blk / tiles;
+  if (c >= count) return;
+  const uint32_t w0 = (blk - c * tiles) * tw;
+  const uint32_t w1 = min(words, w0 + tw);
+  const uint32_t i0 = k == 1 ? 32 * w0 : __umulhi(32 * w0, kinv);
+  const uint32_t i1 = min(len, (32 * w1 + k - 1) / k);
+  const uint32_t* src = in + (size_t)c * len;
   const uint32_t mask = qout_mask(k);
-  uint64_t acc = 0;
-  for (uint32_t i = (uint32_t)(b0 / k); i < len && (uint64_t)i * k < b0 + 32; ++i) {
-    const uint64_t v = src[i] & mask;
-    const int64_t sh = (int64_t)i * k - (int64_t)b0;  // in (-k, 32)
-    acc |= sh >= 0 ? v << sh : v >> -sh;
+#pragma unroll 8
+  for (uint32_t i = i0 + threadIdx.x; i < i1; i += 256) coeff[i - i0] = src[i] & mask;
+  __syncthreads();
+  uint32_t* dst = out + (size_t)c * words;
+  for (uint32_t w = w0 + threadIdx.x; w < w1; w += 256) {
+    const uint32_t b0 = 32 * w;  // first stream bit of this word
+    const uint32_t first = k == 1 ? b0 : __umulhi(b0, kinv);
+    uint64_t acc = 0;
+    for (uint32_t i = first, sh0 = i * k; i < i1 && sh0 < b0 + 32; ++i, sh0 += k) {
+      const uint64_t v = coeff[i - i0];
+      acc |= sh0 >= b0 ? v << (sh0 - b0) : v >> (b0 - sh0);  // shifts below 64
+    }
+    dst[w] = (uint32_t)acc;
   }
-  out[idx] = (uint32_t)acc;
 }
 
 hipError_t launch_pack_bits(const uint32_t* in, size_t count, uint32_t len, uint32_t k,
                             uint32_t* out, hipStream_t s) {
   const uint32_t words = (uint32_t)(((uint64_t)len * k + 31) / 32);
-  const size_t total = count * words;
-  if (total == 0) return hipSuccess;
-  if ((total + 255) / 256 >= (1ull << 31)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(pack_bits_kernel, grid_for((uint32_t)((total + 255) / 256)), dim3(256), 0,
-                     s, in, count, len, k, words, out);
+  if (count == 0 || words == 0) return hipSuccess;
+  if (32ull * words >= (1ull << 21)) return hipErrorInvalidValue;  // len * k < 2^21 bits
+  const uint32_t tiles = (words + pack_tile_words(k) - 1) / pack_tile_words(k);
+  const uint64_t blocks = (uint64_t)count * tiles;
+  if (blocks >= (1ull << 31)) return hipErrorInvalidValue;
+  const uint32_t kinv = k == 1 ? 0u : (uint32_t)(((1ull << 32) + k - 1) / k);  // ceil(2^32 / k)
+  const size_t lds = (size_t)pack_tile_coeffs(k) * 4;  // 33 KB at k = 1, 5 KB at k = 26
+  hipLaunchKernelGGL(pack_bits_kernel, grid_for((uint32_t)blocks), dim3(256), lds, s, in, count,
+                     len, k, kinv, words, tiles, out);
   return hipGetLastError();
 }
 
