@@ -69,6 +69,12 @@ def lib() -> ctypes.CDLL:
                                     _u64p, _u32p]
         L.orc_modswitch_bits.argtypes = [ctypes.c_uint32, _u64p, ctypes.c_size_t, ctypes.c_uint32,
                                          _u64p, ctypes.c_uint32, _u32p]
+        L.orc_splitmix64_at.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_splitmix64_at.restype = ctypes.c_uint64
+        L.orc_mask_coeff.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                     ctypes.c_uint32, ctypes.c_uint64]
+        L.orc_mask_coeff.restype = ctypes.c_uint64
+        L.orc_expand_mask.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _u64p, _u64p]
         L.orc_crt.argtypes = [ctypes.c_uint32, _u64p, _u64p, _u64p, _u64p]
         L.orc_lwe_phase.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u64p, _i8p,
                                     ctypes.c_size_t, _u64p, _u64p]
@@ -197,6 +203,38 @@ def encrypt_tokens(N: int, primes, log2_t: int, S: np.ndarray, x: np.ndarray, A:
     ct[:, :, 0] = A
     ct[:, :, 1] = B
     return ct
+
+
+def splitmix64_at(seed: int, ctr: int) -> int:
+    return int(lib().orc_splitmix64_at(seed, ctr))
+
+
+def mask_coeff(seed: int, N: int, p: int, n: int, q: int) -> int:
+    return int(lib().orc_mask_coeff(seed, N, p, n, q))
+
+
+def expand_masks(seeds: np.ndarray, N: int, primes) -> np.ndarray:
+    """Masks of seeded ciphertexts (Sec. 3.1): seeds (...) u64 -> A (..., P, N) u64."""
+    pr = _primes(primes)
+    sd = np.asarray(seeds, dtype=np.uint64)
+    out = np.empty(sd.shape + (len(pr), N), dtype=np.uint64)
+    flat = out.reshape(-1, len(pr) * N)
+    for c, s_ in enumerate(sd.reshape(-1).tolist()):
+        row = np.empty(len(pr) * N, dtype=np.uint64)
+        lib().orc_expand_mask(s_, N, len(pr), _p(pr, _u64p), _p(row, _u64p))
+        flat[c] = row
+    return out
+
+
+def seeded_layout(ct: np.ndarray, seeds: np.ndarray) -> np.ndarray:
+    """The seeded input layout of ciphertexts whose masks are expand_masks(seeds):
+    ct (T, L, 2, P, N) -> (T, L, P N + 2) u64 = [seed, 0, B residues]; about half the
+    bytes of the full layout (Sec. 4.4: a seed and the body are sent)."""
+    T, L, _, P, N = ct.shape
+    out = np.zeros((T, L, P * N + 2), dtype=np.uint64)
+    out[:, :, 0] = np.asarray(seeds, dtype=np.uint64)
+    out[:, :, 2:] = ct[:, :, 1].reshape(T, L, P * N)
+    return out
 
 
 def rlwe_phase(N: int, primes, S: np.ndarray, A: np.ndarray, B: np.ndarray) -> np.ndarray:

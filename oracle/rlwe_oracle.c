@@ -288,6 +288,40 @@ void orc_matmul_clear(uint32_t N, uint32_t P, const uint64_t* primes, uint32_t d
   }
 }
 
+/* ------------------------------------------------------------ seeded masks */
+
+/* SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) used as a counter-based
+ * generator: output `ctr` under `seed` is the (ctr + 1)-th output of the
+ * sequential generator whose state starts at `seed` (state += golden gamma,
+ * then the published 64-bit finalizer). */
+static uint64_t splitmix64_at(uint64_t seed, uint64_t ctr) {
+  uint64_t z = seed + (ctr + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+uint64_t orc_splitmix64_at(uint64_t seed, uint64_t ctr) { return splitmix64_at(seed, ctr); }
+
+/* Mask coefficient n of prime p (modulus q < 2^54) of the ciphertext with this
+ * seed: the top 54 bits of draws (p N + n) 16 + j, j = 0..15, the first below q
+ * (rejection sampling: uniform on [0, q)); if all 16 are rejected (probability
+ * below 2^-200 for the primes used here), the first draw reduced mod q. */
+uint64_t orc_mask_coeff(uint64_t seed, uint32_t N, uint32_t p, uint32_t n, uint64_t q) {
+  const uint64_t base = ((uint64_t)p * N + n) << 4;
+  for (uint32_t j = 0; j < 16; ++j) {
+    const uint64_t v = splitmix64_at(seed, base | j) >> 10;
+    if (v < q) return v;
+  }
+  return (splitmix64_at(seed, base) >> 10) % q;
+}
+
+/* The mask A of one ciphertext expanded from its seed: A[p][n], P primes. */
+void orc_expand_mask(uint64_t seed, uint32_t N, uint32_t P, const uint64_t* primes, uint64_t* A) {
+  for (uint32_t p = 0; p < P; ++p)
+    for (uint32_t n = 0; n < N; ++n) A[(size_t)p * N + n] = orc_mask_coeff(seed, N, p, n, primes[p]);
+}
+
 /* ------------------------------------------------------------ modulus switch */
 
 static u128 crt(uint32_t P, const uint64_t* primes, const uint64_t* r, size_t stride) {

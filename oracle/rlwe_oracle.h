@@ -111,4 +111,11 @@ void orc_lwe_phase_u32(uint32_t N, const int8_t* S, size_t count, const uint32_t
 #ifdef __cplusplus
 }
 #endif
+
+/* Seeded masks (Sec. 3.1: the mask is generated from a seed sent by the client):
+ * SplitMix64 output `ctr` under `seed`; mask coefficient n of prime p (rejection
+ * sampling onto [0, q) from 54-bit draws); the whole mask A[P][N] of a seed. */
+uint64_t orc_splitmix64_at(uint64_t seed, uint64_t ctr);
+uint64_t orc_mask_coeff(uint64_t seed, uint32_t N, uint32_t p, uint32_t n, uint64_t q);
+void orc_expand_mask(uint64_t seed, uint32_t N, uint32_t P, const uint64_t* primes, uint64_t* A);
 #endif
