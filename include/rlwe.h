@@ -117,6 +117,7 @@ int rlwe_weights_free(rlwe_weights* w);
 #define RLWE_OUT_RAW_Q 1u       /* outputs modulo q, per prime (uint64) */
 #define RLWE_OUT_FORCE_EXACT 2u /* switched outputs through the slow exact path
                                    for every coefficient (same bits; test hook) */
+#define RLWE_IN_SEEDED 4u       /* inputs in the seeded layout (masks expanded on the GPU) */
 
 /* The encrypted clear-weight product of Eq. (LWEdot) for `tokens` inputs.
  * With transpose = 0 it computes W.[x] (d_in -> d_out); with transpose = 1,
@@ -126,7 +127,14 @@ int rlwe_weights_free(rlwe_weights* w);
  *   ct_in  device, uint64 [tokens][L][2][P][N]: for token t and block i,
  *          ct_in[t][i][0] = A and ct_in[t][i][1] = B of RLWE(x_hat_i), each
  *          per prime p in canonical residues; x_hat_i holds inputs iN .. iN+N-1
- *          (zero past K)
+ *          (zero past K). With RLWE_IN_SEEDED, uint64 [tokens][L][P*N + 2]:
+ *          [seed, 0, B residues [P][N]] per block (Sec. 3.1: the client sends a
+ *          seed for the uniform mask; Sec. 4.4), about half the bytes; the GPU
+ *          expands A[p][n] as the top 54 bits of the first of the SplitMix64
+ *          outputs (p N + n) 16 + j, j < 16, under the seed that lies below q_p
+ *          (the first output mod q_p if none does). SplitMix64 output c under
+ *          seed s: z = s + (c + 1) 0x9E3779B97F4A7C15, z = (z ^ z >> 30)
+ *          0xBF58476D1CE4E5B9, z = (z ^ z >> 27) 0x94D049BB133111EB, z ^ z >> 31.
  *   out    device; one LWE ciphertext per (token, output) under the key
  *          (S_0 .. S_{N-1}): mask a_0 .. a_{N-1} then body b, with
  *          a_n = sum_k w[k] * (A_i[k-n] if k >= n else -A_i[N+k-n]) summed over

@@ -306,11 +306,18 @@ __global__ void __launch_bounds__(kThreads) ntt_mask_fwd_kernel(Batch) {
   const uint32_t p_idx = loc % P, ti = loc / P;
   const uint64_t p = bt->rc.q[p_idx];
   const uint64_t* tw = bt->ntt.fwd[p_idx];
-  const uint64_t* A = bt->it[ii].ct + ((size_t)ti * 2 * P + p_idx) * kN;
+  const bool seeded = bt->seeded != 0;
+  const uint64_t* blk_in = bt->it[ii].ct + ti * ct_block_words(P, kN, seeded);
   const int tid = threadIdx.x;
   uint64_t x[16];
+  if (seeded) {
+    const uint64_t seed = blk_in[0];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) x[k] = A[tid + 256 * k];
+    for (int k = 0; k < 16; ++k) x[k] = seeded_mask(seed, kN, p_idx, tid + 256 * k, p);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = blk_in[(size_t)p_idx * kN + tid + 256 * k];
+  }
   ntt_forward(x, lds, tw, p, tid);
   uint64_t* dst = bt->it[ii].ahat + 2 * ((size_t)loc * kN + 16 * tid);
   const uint64_t r1 = bt->ntt.rq[p_idx][0], r0 = bt->ntt.rq[p_idx][1];

@@ -74,10 +74,20 @@ __global__ void __launch_bounds__(256) prep_kernel(Batch) {
   if (ti >= a.T * L || k >= N) return;
   const uint32_t i = ti % L;
   const uint32_t t = ti / L;
-  const uint64_t* A = a.ct + (ti * 2 + 0) * P * N;
-  const uint64_t* B = a.ct + (ti * 2 + 1) * P * N;
+  const bool seeded = bt->seeded != 0;
+  const uint64_t* blk_in = a.ct + ti * ct_block_words(P, N, seeded);
+  const uint64_t* B = blk_in + (seeded ? 2 : (size_t)P * N);
+  uint64_t a0, a1 = 0;
+  if (seeded) {
+    const uint64_t seed = blk_in[0];
+    a0 = seeded_mask(seed, N, 0, k, rc.q[0]);
+    if (P > 1) a1 = seeded_mask(seed, N, 1, k, rc.q[1]);
+  } else {
+    a0 = blk_in[k];
+    if (P > 1) a1 = blk_in[N + k];
+  }
   int8_t da[D], db[D];
-  digits255<D>(lift_centered(rc, A[k], P > 1 ? A[N + k] : 0), da);
+  digits255<D>(lift_centered(rc, a0, a1), da);
   digits255<D>(lift_centered(rc, B[k], P > 1 ? B[N + k] : 0), db);
 #pragma unroll
   for (int l = 0; l < D; ++l) {

@@ -661,6 +661,7 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
   all.ntt = ctx->ntt;
   all.raw = raw;
   all.force_exact = (flags & RLWE_OUT_FORCE_EXACT) ? 1 : 0;
+  all.seeded = (flags & RLWE_IN_SEEDED) ? 1 : 0;
   size_t off = 0;
   for (uint32_t x = 0; x < cnt; ++x) {
     const ct_matmul_desc& dd = d[order[x]];
@@ -733,7 +734,7 @@ int ct_matmul_batch(rlwe_ctx* ctx, const ct_matmul_desc* descs, uint32_t n, uint
   if (!ctx) return fail(RLWE_EINVAL, "ct_matmul_batch: null context");
   if (n == 0) return ok();
   if (!descs) return fail(RLWE_EINVAL, "ct_matmul_batch: null descriptors");
-  if (flags & ~(RLWE_OUT_RAW_Q | RLWE_OUT_FORCE_EXACT))
+  if (flags & ~(RLWE_OUT_RAW_Q | RLWE_OUT_FORCE_EXACT | RLWE_IN_SEEDED))
     return fail(RLWE_EINVAL, "ct_matmul_batch: unknown flags 0x%x", flags);
   for (uint32_t i = 0; i < n; ++i) {
     const Mat* m;
@@ -797,7 +798,7 @@ int rlwe_graph_capture_batch(rlwe_ctx* ctx, const ct_matmul_desc* descs, uint32_
                              uint32_t flags, rlwe_graph** out) {
   if (!ctx || !descs || !out || n == 0) return fail(RLWE_EINVAL, "rlwe_graph_capture_batch: bad argument");
   *out = nullptr;
-  if (flags & ~(RLWE_OUT_RAW_Q | RLWE_OUT_FORCE_EXACT))
+  if (flags & ~(RLWE_OUT_RAW_Q | RLWE_OUT_FORCE_EXACT | RLWE_IN_SEEDED))
     return fail(RLWE_EINVAL, "rlwe_graph_capture_batch: unknown flags 0x%x", flags);
   for (uint32_t i = 0; i < n; ++i) {
     const Mat* m;

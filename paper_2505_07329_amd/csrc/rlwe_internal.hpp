@@ -84,6 +84,33 @@ __device__ inline double i128_to_double(i128 v) {
   return (double)hi * 18446744073709551616.0 + (double)lo;
 }
 
+// Seeded masks (Sec. 3.1: the client sends a seed in place of the uniform mask).
+// SplitMix64 (Steele, Lea and Flood, 2014) as a counter-based generator: output
+// ctr under seed is the finalizer applied to seed + (ctr + 1) * golden gamma.
+__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t ctr) {
+  uint64_t z = seed + (ctr + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+// Mask coefficient n of prime p (q_p < 2^54): the top 54 bits of the first of the
+// draws (p N + n) 16 + j, j < 16, that lies below q_p; if none does (probability
+// below 2^-200), the first draw mod q_p.
+__device__ inline uint64_t seeded_mask(uint64_t seed, uint32_t N, uint32_t p, uint32_t n,
+                                       uint64_t q) {
+  const uint64_t base = ((uint64_t)p * N + n) << 4;
+  for (uint32_t j = 0; j < 16; ++j) {
+    const uint64_t v = splitmix64_at(seed, base | j) >> 10;
+    if (v < q) return v;
+  }
+  return (splitmix64_at(seed, base) >> 10) % q;
+}
+// Words of one input block: the full layout [A, B] (2 P N) or the seeded one
+// [seed, 0, B] (P N + 2).
+__host__ __device__ inline size_t ct_block_words(uint32_t P, uint32_t N, bool seeded) {
+  return seeded ? (size_t)P * N + 2 : (size_t)2 * P * N;
+}
+
 __host__ __device__ inline uint32_t qout_mask(uint32_t k) {
   return k >= 32 ? 0xffffffffu : (1u << k) - 1u;
 }
@@ -157,6 +184,7 @@ struct Batch {
   uint32_t n;
   uint32_t raw;
   uint32_t force_exact;
+  uint32_t seeded;  // inputs in the seeded layout: per block [seed, 0, B residues]
   NttConst ntt;
   uint32_t prep_start[kMaxBatch + 1];  // blocks of 256 threads over T*L*N coefficients
   uint32_t fwd_start[kMaxBatch + 1];   // NTT method: one transform per (token, block, prime)

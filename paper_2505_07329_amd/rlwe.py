@@ -31,6 +31,7 @@ RLWE_METHOD_NTT = 1
 RLWE_OUT_SWITCHED = 0
 RLWE_OUT_RAW_Q = 1
 RLWE_OUT_FORCE_EXACT = 2
+RLWE_IN_SEEDED = 4
 
 EXPORTS = ("rlwe_params_init", "rlwe_params_destroy", "rlwe_weights_load", "rlwe_weights_free",
            "ct_matmul_clear", "ct_modswitch", "rlwe_workspace_bytes", "rlwe_workspace_reserve",
@@ -298,8 +299,9 @@ class Weights:
 
 
 def matmul(ctx: Context, w: Weights, ct, transpose: bool = False, raw: bool = False,
-           force_exact: bool = False, out=None, stream=None):
-    """Allocate the output (torch, on ct's device) and run ct_matmul_clear."""
+           force_exact: bool = False, out=None, stream=None, seeded: bool = False):
+    """Allocate the output (torch, on ct's device) and run ct_matmul_clear. seeded: ct is
+    in the seeded layout (tokens, L, P N + 2)."""
     import torch
     T = ct.shape[0]
     M = w.out_rows(transpose)
@@ -307,6 +309,7 @@ def matmul(ctx: Context, w: Weights, ct, transpose: bool = False, raw: bool = Fa
         shape = (T, M, ctx.P, ctx.N + 1) if raw else (T, M, ctx.N + 1)
         out = torch.empty(shape, dtype=torch.int64 if raw else torch.int32, device=ct.device)
     flags = (RLWE_OUT_RAW_Q if raw else 0) | (RLWE_OUT_FORCE_EXACT if force_exact else 0)
+    flags |= RLWE_IN_SEEDED if seeded else 0
     ct_matmul_clear(ctx.handle, w.handle, ct, T, out, transpose, flags, stream)
     return out
 
