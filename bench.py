@@ -121,6 +121,9 @@ def parse():
                          "by estimated time per output)")
     ap.add_argument("--q-out-bits", type=int, default=32,
                     help="attn: switched outputs modulo 2^K (the paper's output modulus is 26 bits)")
+    ap.add_argument("--seeded", action="store_true",
+                    help="attn: inputs in the seeded layout [seed, 0, B] per block; the masks are "
+                         "expanded on the GPU")
     ap.add_argument("--pack", action="store_true",
                     help="attn: every step also bit-packs the switched outputs (ct_pack_bits), "
                          "reported with its own HBM roofline")
@@ -582,13 +585,21 @@ def main():
     L = (d_in + N - 1) // N
     W = synth.int8_uniform(synth.rng(2, synth.P_WEIGHTS), (d_out, d_in))
     ct_np = synth.uniform_mod_primes(synth.rng(2, synth.P_MASK), primes, (T, L, 2), N)
+    if args.seeded:  # [seed, 0, B] per block; seeds and bodies seeded and uniform
+        g = synth.rng(2, synth.P_MISC)
+        in_np = np.zeros((T, L, len(primes) * N + 2), dtype=np.uint64)
+        in_np[:, :, 0] = g.integers(0, 2**63, size=(T, L), dtype=np.uint64)
+        in_np[:, :, 2:] = ct_np[:, :, 1].reshape(T, L, len(primes) * N)
+    else:
+        in_np = ct_np
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     qbits = args.q_out_bits
     ctx = rlwe.Context(N, primes, log2_t, device=0, log2_q_out=qbits)
     w = rlwe.Weights(ctx, torch.from_numpy(W).to(dev), rlwe.RLWE_W_FWD | method_flag(args))
-    ct = torch.from_numpy(ct_np.view(np.int64)).to(dev)
+    ct = torch.from_numpy(in_np.view(np.int64)).to(dev)
+    in_flags = rlwe.RLWE_IN_SEEDED if args.seeded else 0
     out = torch.empty((T, d_out, N + 1), dtype=torch.int32, device=dev)
     words = rlwe.rlwe_packed_words(N + 1, qbits)
     packed = torch.empty((T, d_out, words), dtype=torch.int32, device=dev) if args.pack else None
@@ -597,7 +608,8 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step():
-        rlwe.ct_matmul_clear(ctx.handle, w.handle, ct, T, out, False, rlwe.RLWE_OUT_SWITCHED, stream)
+        rlwe.ct_matmul_clear(ctx.handle, w.handle, ct, T, out, False,
+                             rlwe.RLWE_OUT_SWITCHED | in_flags, stream)
         if args.pack:
             rlwe.ct_pack_bits(ctx.handle, out, T * d_out, N + 1, packed, stream)
 
@@ -657,7 +669,8 @@ def main():
         "data": "synthetic (seeded uniform int8 weights, uniform ciphertext residues)",
         "config": {"workload": cfg["name"], "d_in": d_in, "d_out": d_out, "tokens": T, "N": N,
                    "primes": len(primes), "log2_t": log2_t, "q_out": f"2^{qbits}",
-                   "packed": bool(args.pack),
+                   "packed": bool(args.pack), "seeded_input": bool(args.seeded),
+                   "input_bytes": int(in_np.nbytes),
                    "method": "ntt" if is_ntt else "toeplitz",
                    "digits_on_matrix_cores": None if is_ntt else f"{kept}/{total}"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
