@@ -283,6 +283,61 @@ def matmul_clear(N: int, primes, W: np.ndarray, ct: np.ndarray,
     return out
 
 
+def rows_per_product(d_in: int, N: int) -> int:
+    """Rows sharing one weight polynomial under multi-row packing: floor(N / d_in)."""
+    if not 1 <= d_in <= N:
+        raise ValueError("multi-row packing needs 1 <= d_in <= N")
+    return N // d_in
+
+
+def rowpack_weights(W: np.ndarray, N: int) -> np.ndarray:
+    """Multi-row packing of the weights (the coefficient packing of Sec. 4.5, as in Cheetah):
+    the n_o = floor(N / K) rows g n_o + rho (rho < n_o) of group g share one polynomial,
+    w_g[rho K + K - 1 - k] = W[g n_o + rho, k] (each row reversed in its own slot of K
+    coefficients; zero past the last row). W (d_out, K) -> (ceil(d_out / n_o), N) int64."""
+    W = np.asarray(W, dtype=np.int64)
+    d_out, K = W.shape
+    n_o = rows_per_product(K, N)
+    G = -(-d_out // n_o)
+    out = np.zeros((G, N), dtype=np.int64)
+    for j in range(d_out):
+        g, rho = divmod(j, n_o)
+        out[g, rho * K:(rho + 1) * K] = W[j, ::-1]
+    return out
+
+
+def matmul_rowpacked(N: int, primes, W: np.ndarray, ct: np.ndarray) -> np.ndarray:
+    """LWE(x . w_j) under multi-row packing (d_in = K <= N, one input block): the output of row
+    j = g n_o + rho is SampleExtract at h = (rho + 1) K - 1 of RLWE(x_hat) . w_g (Sec. 3.2),
+    whose message coefficient h is sum_k x[k] w_j[k]. W int8 (d_out, K); ct (T, 1, 2, P, N)
+    -> uint64 (T, d_out, P, N+1). Products by the oracle's negacyclic NTT."""
+    pr = _primes(primes)
+    P = len(pr)
+    W = np.asarray(W)
+    d_out, K = W.shape
+    T = ct.shape[0]
+    assert ct.shape == (T, 1, 2, P, N)
+    n_o = rows_per_product(K, N)
+    Wg = rowpack_weights(W, N)
+    out = np.empty((T, d_out, P, N + 1), dtype=np.uint64)
+    for p, q in enumerate(pr.tolist()):
+        psi = find_psi(N, q)
+        wq = [np.ascontiguousarray(w % q, dtype=np.uint64) for w in Wg]
+        for t in range(T):
+            A, B = ct[t, 0, 0, p], ct[t, 0, 1, p]
+            for g, w in enumerate(wq):
+                CA = poly_mul_ntt(A, w, q, psi)
+                CB = poly_mul_ntt(B, w, q, psi)
+                for rho in range(n_o):
+                    j = g * n_o + rho
+                    if j >= d_out:
+                        break
+                    a, b = sample_extract(CA, CB, q, (rho + 1) * K - 1)
+                    out[t, j, p, :N] = a
+                    out[t, j, p, N] = b
+    return out
+
+
 def modswitch(primes, raw: np.ndarray) -> np.ndarray:
     """round(c 2^32 / q) mod 2^32 of CRT(raw[..., p, n]): (..., P, len) -> (..., len) u32."""
     pr = _primes(primes)

@@ -57,6 +57,27 @@ def matmul_clear(q, N, W, cts):
     return res
 
 
+def matmul_rowpacked(q, N, W, ct):
+    """Multi-row packing for one block (K = len(W[0]) <= N): rows g n_o + rho share the
+    polynomial with row rho reversed in slot rho; row j's output is SampleExtract at
+    (rho + 1) K - 1. ct = (A, B) of one token. Returns [(a, b)] per row."""
+    K = len(W[0])
+    n_o = N // K
+    A, B = ct
+    res = []
+    for j, w in enumerate(W):
+        g, rho = divmod(j, n_o)
+        wg = [0] * N
+        for r in range(n_o):
+            if g * n_o + r < len(W):
+                for k in range(K):
+                    wg[r * K + K - 1 - k] = W[g * n_o + r][k]
+        CA = negacyclic_mul(A, wg, q)
+        CB = negacyclic_mul(B, wg, q)
+        res.append(sample_extract(CA, CB, q, (rho + 1) * K - 1))
+    return res
+
+
 def modswitch(c, q, bits=32):
     """round(c 2^bits / q) mod 2^bits, half up."""
     return ((c * (1 << (bits + 1)) + q) // (2 * q)) % (1 << bits)
