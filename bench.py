@@ -44,25 +44,29 @@ NTT_PEAK_GBFLY = 256 * 4 * 16 * 2.4e9 / 17 / 1e9
 
 def method_flag(args):
     from paper_2505_07329_amd import rlwe
-    return {"auto": 0, "ntt": rlwe.RLWE_W_NTT, "toeplitz": rlwe.RLWE_W_TOEPLITZ}[args.method]
+    flag = {"auto": 0, "ntt": rlwe.RLWE_W_NTT, "toeplitz": rlwe.RLWE_W_TOEPLITZ}[args.method]
+    return flag | (rlwe.RLWE_W_ROWPACK if getattr(args, "rowpack", False) else 0)
 
 
 def product_info(rlwe, w, tr, T, M, K):
     kept, _ = rlwe.rlwe_weights_digits(w.handle, tr)
     ntt = rlwe.rlwe_weights_method(w.handle, tr) == rlwe.RLWE_METHOD_NTT
-    return dict(T=T, M=M, K=K, kept=kept, ntt=ntt)
+    n_o = rlwe.rlwe_weights_rows_per_product(w.handle, tr)
+    return dict(T=T, M=M, K=K, kept=kept, ntt=ntt, n_o=n_o)
 
 
 def roofline(products, kt, N, P, traffic=None):
     """Roofline of the dominant mask kernel of a set of products, each a dict with
-    T, M (outputs per token), K, kept (digits on the matrix cores), ntt (method).
-    Matrix cores: 2 T M N K kept int8 ops; NTT: per output and prime one inverse
-    transform ((N/2) log2 N butterflies) and L N pointwise products. traffic: measured
+    T, M (outputs per token), K, kept (digits on the matrix cores), ntt (method), n_o
+    (outputs per weight polynomial, 1 unless rows are packed). Matrix cores: 2 T M N K
+    kept int8 ops; NTT: per weight polynomial, token and prime one inverse transform
+    ((N/2) log2 N butterflies) and L N pointwise products. traffic: measured
     HBM bytes per launch by kernel kind ("mfma", "alu"), where known."""
     traffic = traffic or {}
     import math
     mf_ops = sum(2.0 * p["T"] * p["M"] * N * p["K"] * p["kept"] for p in products if not p["ntt"])
-    nt_ops = sum(p["T"] * p["M"] * P * ((N // 2) * math.log2(N) + ((p["K"] + N - 1) // N) * N)
+    nt_ops = sum(p["T"] * -(-p["M"] // p.get("n_o", 1)) * P
+                 * ((N // 2) * math.log2(N) + ((p["K"] + N - 1) // N) * N)
                  for p in products if p["ntt"])
     parts = {}
     if mf_ops and kt["mask_ms"] > 0:
@@ -127,6 +131,9 @@ def parse():
     ap.add_argument("--pack", action="store_true",
                     help="attn: every step also bit-packs the switched outputs (ct_pack_bits), "
                          "reported with its own HBM roofline")
+    ap.add_argument("--rowpack", action="store_true",
+                    help="load every weight matrix with RLWE_W_ROWPACK (floor(N / K) rows per "
+                         "weight polynomial where the contraction length K <= N/2; NTT method)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="attn: before the timed region, run one plain elementwise copy kernel "
                          "(int32 bitwise not) reading and writing GIB GiB each, as the known-size "
@@ -153,8 +160,9 @@ def parse():
     return args
 
 
-def cpu_baseline(W, ct_np, N, primes, T, d_out, d_in, target_s):
-    """The oracle (NTT mode + exact modulus switch) on sampled (token, row) outputs."""
+def cpu_baseline(W, ct_np, N, primes, T, d_out, d_in, target_s, n_o=1):
+    """The oracle (NTT mode + exact modulus switch) on sampled (token, row) outputs; with
+    packed rows (n_o > 1), on sampled (token, group of n_o rows) products."""
     import numpy as np
 
     from oracle import oracle as orc
@@ -163,7 +171,18 @@ def cpu_baseline(W, ct_np, N, primes, T, d_out, d_in, target_s):
     done = 0
     t0 = time.perf_counter()
     batch = 64
+    groups = -(-d_out // n_o)
     while True:
+        if n_o > 1:
+            t, gr = int(g.integers(0, T)), int(g.integers(0, groups))
+            rows = W[gr * n_o:(gr + 1) * n_o]
+            raw = orc.matmul_rowpacked(N, primes, rows, ct_np[t:t + 1])
+            orc.modswitch(primes, raw)
+            done += rows.shape[0]
+            el = time.perf_counter() - t0
+            if el >= target_s:
+                break
+            continue
         pairs = np.stack([g.integers(0, T, batch), g.integers(0, d_out, batch)], 1).astype(np.uint32)
         raw = orc.matmul_clear(N, primes, W, ct_np, pairs=pairs, mode=1)
         orc.modswitch(primes, raw)
@@ -174,8 +193,10 @@ def cpu_baseline(W, ct_np, N, primes, T, d_out, d_in, target_s):
         batch = min(4096, batch * 2)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": done * d_in / el, "unit": "encrypted MAC/s", "cores": cores, "kind": "oracle",
-            "sample": f"{done} (token, row) outputs of the same workload, NTT-mode oracle plus exact "
-                      f"switch, {el:.1f} s on {cores} threads, scaled per MAC"}
+            "sample": f"{done} (token, row) outputs of the same workload"
+                      + (f" in groups of {n_o} packed rows" if n_o > 1 else "")
+                      + f", NTT-mode oracle plus exact switch, {el:.1f} s on {cores} threads, "
+                        f"scaled per MAC"}
 
 
 LAYER_BUDGET = 250e9  # output bytes per captured graph
@@ -643,8 +664,11 @@ def main():
     per_launch = {k: kt[k] / max(1, kt[k.replace("_ms", "_n")]) for k in ("prep_ms", "mask_ms", "ntt_ms", "body_ms")}
     one = dict(kt, mask_ms=per_launch["mask_ms"], ntt_ms=per_launch["ntt_ms"])
     is_ntt = rlwe.rlwe_weights_method(w.handle) == rlwe.RLWE_METHOD_NTT
-    roof, _ = roofline([dict(T=T, M=d_out, K=d_in, kept=kept, ntt=is_ntt)], one, N, len(primes),
-                       traffic={"mfma": kernel_traffic("mask"), "alu": kernel_traffic("ntt")})
+    n_o = rlwe.rlwe_weights_rows_per_product(w.handle)
+    roof, _ = roofline([dict(T=T, M=d_out, K=d_in, kept=kept, ntt=is_ntt, n_o=n_o)], one, N,
+                       len(primes),
+                       traffic={"mfma": kernel_traffic("mask"),
+                                "alu": kernel_traffic("ntt") if n_o == 1 else None})
     pack_roof = None
     if args.pack and kt["pack_n"]:
         pack_ms = kt["pack_ms"] / kt["pack_n"]
@@ -671,7 +695,7 @@ def main():
                    "primes": len(primes), "log2_t": log2_t, "q_out": f"2^{qbits}",
                    "packed": bool(args.pack), "seeded_input": bool(args.seeded),
                    "input_bytes": int(in_np.nbytes),
-                   "method": "ntt" if is_ntt else "toeplitz",
+                   "method": "ntt" if is_ntt else "toeplitz", "rows_per_product": n_o,
                    "digits_on_matrix_cores": None if is_ntt else f"{kept}/{total}"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "kernels_ms": {"prep": per_launch["prep_ms"], "mask": per_launch["mask_ms"],
@@ -685,7 +709,8 @@ def main():
     w.close()
     ctx.close()
     if args.cpu_seconds > 0:
-        result["cpu_baseline"] = cpu_baseline(W, ct_np, N, primes, T, d_out, d_in, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(W, ct_np, N, primes, T, d_out, d_in, args.cpu_seconds,
+                                              n_o)
     print(json.dumps(result), flush=True)
 
 

@@ -83,6 +83,7 @@ int rlwe_params_destroy(rlwe_ctx* ctx);
 #define RLWE_W_TRANSPOSE 2u /* keep W^T for products W^T.[g] (backward pass) */
 #define RLWE_W_NTT 4u       /* mask product by number-theoretic transforms (N = 4096 only) */
 #define RLWE_W_TOEPLITZ 8u  /* mask product on the int8 matrix cores (digit planes) */
+#define RLWE_W_ROWPACK 16u  /* several rows per weight polynomial where K <= N/2 (NTT) */
 
 /* Mask-product methods (rlwe_weights_method). Both give the same bits. */
 #define RLWE_METHOD_TOEPLITZ 0u
@@ -100,10 +101,18 @@ int rlwe_params_destroy(rlwe_ctx* ctx);
  *           output: matrix cores 8 + 0.0033 K dk ns (K the contraction length,
  *           dk the digit planes kept, rlwe_weights_digits), transforms
  *           (12.75 + 11.25 L) P ns (L = ceil(K / N) blocks, P primes), fitted to
- *           MI355X timings; at other N the matrix-core method
+ *           MI355X timings; at other N the matrix-core method.
+ *           RLWE_W_ROWPACK (N = 4096, not with RLWE_W_TOEPLITZ): an orientation
+ *           whose contraction length K is at most N/2 packs n_o = floor(N / K)
+ *           rows into each weight polynomial, row g n_o + rho reversed in
+ *           coefficients [rho K, rho K + K) (the coefficient packing of Sec.
+ *           4.3.1, as in Cheetah), with the NTT method: one polynomial product
+ *           per n_o outputs. Other orientations load as without the flag. The
+ *           outputs decrypt to the same values; their ciphertexts differ (see
+ *           ct_matmul_clear). NTT memory: ceil(rows / n_o) * P * N * 8 bytes
  * Validation: 1 <= d_out, d_in <= 65536; the exact 128-bit accumulation needs
  * 127 * d * q / 2 < 2^127 for the contraction length d (d_in forward, d_out
- * transposed) -> RLWE_ESHAPE. Overflow: returns RLWE_EOVERFLOW if 127 times the
+ * transposed; n_o d when rows are packed) -> RLWE_ESHAPE. Overflow: returns RLWE_EOVERFLOW if 127 times the
  * largest row 1-norm (column 1-norm for W^T) reaches t/2, since W.x could then
  * wrap modulo t (Sec. 4.4). Synchronises `stream` (set-up call). */
 int rlwe_weights_load(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32_t d_in,
@@ -143,6 +152,12 @@ int rlwe_weights_free(rlwe_weights* w);
  *              replaced by round(c * 2^k / q) mod 2^k, k = log2_q_out
  *              (ModulusSwitch, Sec. 3.2)
  *            RLWE_OUT_RAW_Q:    uint64 [tokens][M][P][N+1], residues mod q_p
+ *          With packed rows (RLWE_W_ROWPACK, n_o > 1; one block), output j = g n_o
+ *          + rho is SampleExtract at h = (rho + 1) K - 1 of w_hat_g.(A, B), w_hat_g
+ *          the polynomial of rows g n_o .. g n_o + n_o - 1: with c = w_hat_g A
+ *          mod X^N + 1, a_n = c[h-n] for n <= h and -c[N+h-n] for n > h;
+ *          b = sum_r sum_k w_{g n_o + r}[k] * B~[(rho - r) K + k], B~[-i] = -B[N-i]
+ *          (the standard outputs are the case h = N - 1 of the same rule)
  * tokens = 0 is a no-op. Uses the context workspace (grown on demand with
  * hipMalloc unless rlwe_workspace_reserve made it large enough). Asynchronous
  * on `stream`. */
@@ -249,6 +264,11 @@ int rlwe_weights_digits(const rlwe_weights* w, uint32_t transpose, uint32_t* kep
  * or RLWE_METHOD_NTT (host pointer). RLWE_EINVAL for null arguments or an
  * orientation that was not loaded. */
 int rlwe_weights_method(const rlwe_weights* w, uint32_t transpose, uint32_t* method);
+
+/* Outputs per weight polynomial of one loaded orientation (host pointer): n_o =
+ * floor(N / K) when it was loaded with RLWE_W_ROWPACK and K <= N/2, else 1.
+ * RLWE_EINVAL for null arguments or an orientation that was not loaded. */
+int rlwe_weights_rows_per_product(const rlwe_weights* w, uint32_t transpose, uint32_t* n_o);
 
 /* Description of the last error on this thread ("" if none). */
 const char* rlwe_last_error(void);

@@ -291,7 +291,7 @@ def rows_per_product(d_in: int, N: int) -> int:
 
 
 def rowpack_weights(W: np.ndarray, N: int) -> np.ndarray:
-    """Multi-row packing of the weights (the coefficient packing of Sec. 4.5, as in Cheetah):
+    """Multi-row packing of the weights (the coefficient packing of Sec. 4.3.1, as in Cheetah):
     the n_o = floor(N / K) rows g n_o + rho (rho < n_o) of group g share one polynomial,
     w_g[rho K + K - 1 - k] = W[g n_o + rho, k] (each row reversed in its own slot of K
     coefficients; zero past the last row). W (d_out, K) -> (ceil(d_out / n_o), N) int64."""

@@ -345,10 +345,13 @@ __global__ void __launch_bounds__(kInvThreads, LC == 2 ? 4 : 1) ntt_mask_kernel(
   if (blk >= bt->mask_start[nb]) return;
   const uint32_t ii = find_item(bt->mask_start, nb, blk);
   const uint32_t L = bt->it[ii].m.L, rows = bt->it[ii].m.rows, T = bt->it[ii].T;
+  // rows sharing one weight polynomial (1 unless rows are packed) and their slot size
+  const uint32_t n_o = bt->it[ii].m.n_o, slot = bt->it[ii].m.slot;
+  const uint32_t groups = (rows + n_o - 1) / n_o;
   const uint32_t loc = blk - bt->mask_start[ii];
-  const uint32_t j = loc % rows, t0 = (loc / rows) * kTokTile;
+  const uint32_t j = loc % groups, t0 = (loc / groups) * kTokTile;  // j: the weight polynomial
   const uint64_t* ahat = bt->it[ii].ahat;
-  const uint64_t* what = bt->it[ii].what;  // [rows][L][P][N] residues
+  const uint64_t* what = bt->it[ii].what;  // [groups][L][P][N] residues
   void* out = bt->it[ii].out;
   // per-prime constants, indexed by compile-time prime numbers only (ring
   // constants are read in place: a local copy indexed at run time would live in
@@ -416,20 +419,37 @@ __global__ void __launch_bounds__(kInvThreads, LC == 2 ? 4 : 1) ntt_mask_kernel(
       }
     }
     ntt_inverse<NP>(x, lds, tw, md, tid);
-    // coefficient m = tid + 512 k of C (layout Q4); a'[N - 1 - m]
+    // Coefficient m = tid + 512 k of C (layout Q4). Row rho of the group (row
+    // j n_o + rho) is SampleExtract at h = (rho + 1) slot - 1 (Sec. 3.2): a'[n] =
+    // C[h - n] for n <= h, -C[N + h - n] otherwise, so C[m] lands at n = h - m, or
+    // negated at n = h - m + N. Unpacked rows: n_o = 1, slot = N, h = N - 1.
     if (RAW) {
+      uint64_t c[NP][8];
 #pragma unroll
-      for (int r = 0; r < NP; ++r) {
-        uint64_t* o = (uint64_t*)out + ((size_t)t * rows + j) * NP * (kN + 1) + r * (kN + 1);
+      for (int r = 0; r < NP; ++r)
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-          const uint32_t m = tid + 512 * k;
-          const uint64_t c = mul_shoup(x[r][k], bt->ntt.ninv[r], bt->ntt.ninv_shoup[r], p[r]);
-          o[kN - 1 - m] = c >= p[r] ? c - p[r] : c;
+          const uint64_t v = mul_shoup(x[r][k], bt->ntt.ninv[r], bt->ntt.ninv_shoup[r], p[r]);
+          c[r][k] = v >= p[r] ? v - p[r] : v;
+        }
+      for (uint32_t rho = 0; rho < n_o && j * n_o + rho < rows; ++rho) {
+        const uint32_t h = (rho + 1) * slot - 1;
+#pragma unroll
+        for (int r = 0; r < NP; ++r) {
+          uint64_t* o = (uint64_t*)out + ((size_t)t * rows + j * n_o + rho) * NP * (kN + 1) +
+                        r * (kN + 1);
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const uint32_t m = tid + 512 * k;
+            if (m <= h)
+              o[h - m] = c[r][k];
+            else
+              o[h + kN - m] = c[r][k] ? p[r] - c[r][k] : 0;
+          }
         }
       }
     } else {
-      uint32_t* o = (uint32_t*)out + ((size_t)t * rows + j) * (kN + 1);
+      uint32_t res[8];
       uint32_t tie = 0;  // coefficients within 8 units below a rounding tie
       const uint32_t qbits = bt->rc.qbits;
 #pragma unroll
@@ -439,11 +459,10 @@ __global__ void __launch_bounds__(kInvThreads, LC == 2 ? 4 : 1) ntt_mask_kernel(
         // A = bits 64..127 of sum_p c_p H_p 2^96 (mod 2^128), at most 7 units low:
         // c 2^32 / q mod 2^32 in 32.32 fixed point, rounded to q_out = 2^qbits
         int64_t dist;
-        const uint32_t res = round_qout(A, qbits, dist);
+        res[k] = round_qout(A, qbits, dist);
         if (dist < 0 && dist >= -8) tie |= 1u << k;
-        o[kN - 1 - (tid + 512 * k)] = res;
       }
-      while (tie) {  // rare: exact CRT and switch, rewriting the coefficient
+      while (tie) {  // rare: exact CRT and switch of the coefficient
         const int k = __builtin_ctz(tie);
         tie &= tie - 1;
         uint64_t c[NP];
@@ -466,14 +485,33 @@ __global__ void __launch_bounds__(kInvThreads, LC == 2 ? 4 : 1) ntt_mask_kernel(
           v = (u128)y[0] * p[NP - 1] + (u128)y[NP - 1] * p[0];
           v = v >= Q ? v - Q : v;
         }
-        o[kN - 1 - (tid + 512 * k)] = switch_exact((i128)v, rc);
+        const uint32_t e = switch_exact((i128)v, rc);
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) res[kk] = k == kk ? e : res[kk];
+      }
+      // the switch of -c is -(switch of c) mod 2^qbits (q is odd: no ties)
+      const uint32_t qmask = qout_mask(qbits);
+      for (uint32_t rho = 0; rho < n_o && j * n_o + rho < rows; ++rho) {
+        const uint32_t h = (rho + 1) * slot - 1;
+        uint32_t* o = (uint32_t*)out + ((size_t)t * rows + j * n_o + rho) * (kN + 1);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t m = tid + 512 * k;
+          if (m <= h)
+            o[h - m] = res[k];
+          else
+            o[h + kN - m] = (0u - res[k]) & qmask;
+        }
       }
     }
   }
 }
 
-// NTT-domain weights: one workgroup per (row j, block i, prime p). Block i of row
-// j is encoded reversed, w_hat[k] = w_j[iN + N - 1 - k] (zero past K), Sec. 4.3.
+// NTT-domain weights: one workgroup per (weight polynomial j, block i, prime p).
+// Unpacked (n_o = 1, slot = N), block i of row j is encoded reversed, w_hat[k] =
+// w_j[iN + N - 1 - k] (zero past K), Sec. 4.3. Packed (one block, slot = K), row
+// j n_o + rho of the group fills coefficients [rho K, rho K + K) reversed:
+// w_hat[rho K + K - 1 - k] = w_{j n_o + rho}[k] (zero past the last row and N).
 // what[((j L + i) P + p) N + pos], bit-reversed order, residues in [0, p).
 __global__ void __launch_bounds__(kThreads) ntt_weights_kernel(MatArgs m, NttConst ntt,
                                                                RingConst rc, uint64_t* what) {
@@ -487,8 +525,10 @@ __global__ void __launch_bounds__(kThreads) ntt_weights_kernel(MatArgs m, NttCon
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const uint32_t pos = tid + 256 * k;
-    const uint32_t col = i * kN + kN - 1 - pos;
-    const int v = col < m.k ? (int)m.w[(size_t)j * m.kw + col] : 0;
+    const uint32_t rho = pos / m.slot, row = j * m.n_o + rho;
+    const uint32_t col = i * kN + m.slot - 1 - (pos - rho * m.slot);
+    const bool in = rho < m.n_o && row < m.rows && col < m.k;
+    const int v = in ? (int)m.w[(size_t)row * m.kw + col] : 0;
     x[k] = v < 0 ? p - (uint64_t)(-v) : (uint64_t)v;
   }
   ntt_forward(x, lds, ntt.fwd[p_idx], p, tid);
@@ -532,7 +572,7 @@ hipError_t launch_ntt_mask(const Batch& b, uint32_t lclass, hipStream_t s) {
 
 hipError_t launch_ntt_weights(const MatArgs& m, const NttConst& ntt, const RingConst& rc,
                               uint64_t* what, hipStream_t s) {
-  const uint32_t blocks = m.rows * m.L * rc.P;
+  const uint32_t blocks = (m.rows + m.n_o - 1) / m.n_o * m.L * rc.P;
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(ntt_weights_kernel, dim3(blocks), dim3(kThreads), 0, s, m, ntt, rc, what);
   return hipGetLastError();

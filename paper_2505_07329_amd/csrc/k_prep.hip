@@ -113,6 +113,14 @@ hipError_t launch_prep(const Batch& b, hipStream_t s) {
 
 // ---------------------------------------------------------------- body
 
+// Sum of the 16 int8 products of two 16-byte vectors, added to acc.
+__device__ inline int32_t dot16(int4 w, int4 e, int32_t acc) {
+  acc = __builtin_amdgcn_sdot4(w.x, e.x, acc, false);
+  acc = __builtin_amdgcn_sdot4(w.y, e.y, acc, false);
+  acc = __builtin_amdgcn_sdot4(w.z, e.z, acc, false);
+  return __builtin_amdgcn_sdot4(w.w, e.w, acc, false);
+}
+
 template <int D, bool RAW>
 __global__ void __launch_bounds__(256) body_kernel(Batch) {
   const BatchPtr bt = kernarg_batch();
@@ -123,27 +131,78 @@ __global__ void __launch_bounds__(256) body_kernel(Batch) {
   const RingConst rc = kernarg_load(&bt->rc);
   const Item a = kernarg_load(&bt->it[ii]);
   const MatArgs& m = a.m;
-  // blocks of one token: ceil(rows / 256)
-  const uint32_t per = (m.rows + 255) / 256;
+  // blocks of one token: body_blocks_per_token (rows, or the packed slot-major order)
+  const uint32_t per = body_blocks_per_token(m);
   const uint32_t loc = blk - bt->body_start[ii];
   const uint32_t t = loc / per;
-  const uint32_t j = (loc - t * per) * 256 + threadIdx.x;
-  if (t >= a.T || j >= m.rows) return;
+  const uint32_t v = (loc - t * per) * 256 + threadIdx.x;
+  if (t >= a.T) return;
   const uint32_t N = rc.N;
+  uint32_t j = v;  // output row
   int32_t S[D];
 #pragma unroll
   for (int l = 0; l < D; ++l) S[l] = 0;
-  for (uint32_t i = 0; i < m.L; ++i) {
+  if (m.n_o > 1) {
+    // Multi-row packing (one block): row j = g n_o + rho is the coefficient h = (rho
+    // + 1) K - 1 of w_hat_g B, w_hat_g holding row g n_o + r reversed in [r K, r K +
+    // K). Term r: sum_k w_{g n_o + r}[k] B[(rho - r) K + k], with B[-i] = -B[N - i]
+    // (X^N = -1); every term lies on one side of the wrap. Threads run slot-major
+    // (v = rho gpad + g, gpad a multiple of 64), so rho, and with it the offset into
+    // B of every term, is the same across a wave: the digit loads stay uniform.
+    const uint32_t K = m.k, gpad = body_group_pad(m);
+    const uint32_t rho = __builtin_amdgcn_readfirstlane(v / gpad), g = v - rho * gpad;
+    j = g * m.n_o + rho;
+    if (rho >= m.n_o || j >= m.rows) return;
+    const int8_t* eb = a.ebody + (size_t)t * D * N;
+    for (uint32_t r = 0; r < m.n_o; ++r) {
+      const uint32_t wr = g * m.n_o + r;
+      const int8_t* wrow = m.w + (size_t)min(wr, m.rows - 1) * m.kw;
+      const int wmask = wr < m.rows ? -1 : 0;  // rows past the last one are zero
+      const bool neg = r > rho;
+      const uint32_t base = neg ? N - (r - rho) * K : (rho - r) * K;
+      int32_t U[D];
+#pragma unroll
+      for (int l = 0; l < D; ++l) U[l] = 0;
+      if ((K & 15) == 0) {  // base is a multiple of 16: 16-byte loads stay aligned
+        for (uint32_t k = 0; k < K; k += 16) {
+          int4 w16 = *(const int4*)(wrow + k);
+          w16.x &= wmask;
+          w16.y &= wmask;
+          w16.z &= wmask;
+          w16.w &= wmask;
+#pragma unroll
+          for (int l = 0; l < D; ++l) U[l] = dot16(w16, *(const int4*)(eb + (size_t)l * N + base + k), U[l]);
+        }
+      } else if ((K & 3) == 0) {  // word loads stay aligned
+        for (uint32_t k = 0; k < K; k += 4) {
+          const int w4 = *(const int*)(wrow + k) & wmask;
+#pragma unroll
+          for (int l = 0; l < D; ++l)
+            U[l] = __builtin_amdgcn_sdot4(w4, *(const int*)(eb + (size_t)l * N + base + k), U[l],
+                                          false);
+        }
+      } else {
+        for (uint32_t k = 0; k < K; ++k) {
+          const int w1 = (int)wrow[k] & wmask;
+#pragma unroll
+          for (int l = 0; l < D; ++l) U[l] += w1 * (int)eb[(size_t)l * N + base + k];
+        }
+      }
+#pragma unroll
+      for (int l = 0; l < D; ++l) S[l] = neg ? S[l] - U[l] : S[l] + U[l];
+    }
+  } else if (j >= m.rows) {
+    return;
+  }
+  for (uint32_t i = 0; i < m.L && m.n_o == 1; ++i) {
     const uint32_t kb = min(N, m.k - i * N);
     const uint32_t kp = (kb + 31u) & ~31u;
     const int8_t* wrow = m.w + (size_t)j * m.kw + (size_t)i * N;
-    for (uint32_t k = 0; k < kp; k += 4) {
-      const int w4 = *(const int*)(wrow + k);
+    for (uint32_t k = 0; k < kp; k += 16) {
+      const int4 w16 = *(const int4*)(wrow + k);
 #pragma unroll
-      for (int l = 0; l < D; ++l) {
-        const int e4 = *(const int*)(a.ebody + (((size_t)t * D + l) * m.L + i) * N + k);
-        S[l] = __builtin_amdgcn_sdot4(w4, e4, S[l], false);
-      }
+      for (int l = 0; l < D; ++l)
+        S[l] = dot16(w16, *(const int4*)(a.ebody + (((size_t)t * D + l) * m.L + i) * N + k), S[l]);
     }
   }
   i128 V = 0;
@@ -152,7 +211,7 @@ __global__ void __launch_bounds__(256) body_kernel(Batch) {
   const size_t row = (size_t)t * m.rows + j;
   if (RAW) {
     uint64_t* o = (uint64_t*)a.out;
-    for (uint32_t p = 0; p < rc.P; ++p) o[(row * rc.P + p) * (N + 1) + N] = mod_i128(V, rc.q[p]);
+    for (uint32_t p = 0; p < rc.P; ++p) o[(row * rc.P + p) * (N + 1) + N] = mod_i128(V, bt->rc.q[p]);
   } else {
     ((uint32_t*)a.out)[row * (N + 1) + N] = switch_exact(V, rc);
   }

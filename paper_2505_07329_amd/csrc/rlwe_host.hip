@@ -463,7 +463,7 @@ static void free_mat(Mat& m) {
 }
 
 static int load_mat(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32_t d_in,
-                    bool transpose, int method, hipStream_t s, Mat& m) {
+                    bool transpose, int method, bool rowpack, hipStream_t s, Mat& m) {
   const RingConst& rc = ctx->rc;
   MatArgs& a = m.args;
   a.rows = transpose ? d_in : d_out;
@@ -471,9 +471,13 @@ static int load_mat(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32_t
   a.kw = (uint32_t)align_up(a.k, 64);
   a.rows_pad = (uint32_t)align_up(a.rows, 64);
   a.L = (a.k + rc.N - 1) / rc.N;
-  // exact 128-bit accumulation: 127 * K * (q-1)/2 < 2^127
+  // multi-row packing where two or more rows fit one polynomial (Sec. 4.3.1)
+  a.n_o = rowpack && 2 * a.k <= rc.N ? rc.N / a.k : 1;
+  a.slot = a.n_o > 1 ? a.k : rc.N;
+  // exact 128-bit accumulation: 127 * K' * (q-1)/2 < 2^127, K' the weights one
+  // output sums over (n_o K with packing)
   const u128 Q = make_u128(rc.Q_hi, rc.Q_lo);
-  const u128 lim = ((u128)1 << 127) / ((u128)127 * a.k);
+  const u128 lim = ((u128)1 << 127) / ((u128)127 * a.k * a.n_o);
   if ((Q - 1) / 2 >= lim)
     return fail(RLWE_ESHAPE, "contraction length %u too long for exact 128-bit sums at this q", a.k);
   hipError_t e = hipMalloc(&m.w, (size_t)a.rows_pad * a.kw);
@@ -512,15 +516,16 @@ static int load_mat(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32_t
   // kept, the transform cost with the blocks L only; the constants are fitted to
   // MI355X timings of both kernels at N = 4096 with two primes (K = 512 .. 8192),
   // the transform cost taken per prime.
-  m.ntt = method == 1;
-  if (method == 0 && ctx->ntt_ok) {
+  m.ntt = method == 1 || a.n_o > 1;
+  if (method == 0 && a.n_o == 1 && ctx->ntt_ok) {
     const double mfma_ns = 8.0 + 0.0033 * (double)a.k * m.sc.dk;
     const double ntt_ns = (12.75 + 11.25 * a.L) * rc.P;
     m.ntt = ntt_ns < mfma_ns;
   }
   if (m.ntt) {
     if (!ctx->ntt_ok) return fail(RLWE_EPARAM, "the NTT method needs N = %u", kNttN);
-    const size_t bytes = (size_t)a.rows * a.L * rc.P * rc.N * 8;
+    const size_t groups = (a.rows + a.n_o - 1) / a.n_o;
+    const size_t bytes = groups * a.L * rc.P * rc.N * 8;
     e = hipMalloc(&m.what, bytes);
     if (e != hipSuccess) return fail(RLWE_ENOMEM, "hipMalloc(NTT weights, %zu bytes): %s", bytes, hipGetErrorString(e));
     e = launch_ntt_weights(a, ctx->ntt, rc, m.what, s);
@@ -536,11 +541,13 @@ int rlwe_weights_load(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32
   if (!ctx || !W_dev || !out) return fail(RLWE_EINVAL, "rlwe_weights_load: null argument");
   *out = nullptr;
   if ((flags & (RLWE_W_FWD | RLWE_W_TRANSPOSE)) == 0 ||
-      (flags & ~(RLWE_W_FWD | RLWE_W_TRANSPOSE | RLWE_W_NTT | RLWE_W_TOEPLITZ)) ||
-      ((flags & RLWE_W_NTT) && (flags & RLWE_W_TOEPLITZ)))
+      (flags & ~(RLWE_W_FWD | RLWE_W_TRANSPOSE | RLWE_W_NTT | RLWE_W_TOEPLITZ | RLWE_W_ROWPACK)) ||
+      ((flags & RLWE_W_NTT) && (flags & RLWE_W_TOEPLITZ)) ||
+      ((flags & RLWE_W_ROWPACK) && (flags & RLWE_W_TOEPLITZ)))
     return fail(RLWE_EINVAL, "rlwe_weights_load: flags 0x%x invalid", flags);
-  if ((flags & RLWE_W_NTT) && !ctx->ntt_ok)
-    return fail(RLWE_EPARAM, "RLWE_W_NTT needs N = %u (N = %u)", kNttN, ctx->rc.N);
+  if ((flags & (RLWE_W_NTT | RLWE_W_ROWPACK)) && !ctx->ntt_ok)
+    return fail(RLWE_EPARAM, "RLWE_W_NTT and RLWE_W_ROWPACK need N = %u (N = %u)", kNttN,
+                ctx->rc.N);
   const int method = (flags & RLWE_W_NTT) ? 1 : (flags & RLWE_W_TOEPLITZ) ? 2 : 0;
   if (d_out < 1 || d_in < 1 || d_out > 65536 || d_in > 65536)
     return fail(RLWE_ESHAPE, "d_out = %u, d_in = %u must lie in [1, 65536]", d_out, d_in);
@@ -551,9 +558,10 @@ int rlwe_weights_load(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32
   w->ctx = ctx;
   hipStream_t s = (hipStream_t)stream;
   int r = RLWE_OK;
-  if (flags & RLWE_W_FWD) r = load_mat(ctx, W_dev, d_out, d_in, false, method, s, w->fwd);
+  const bool rowpack = flags & RLWE_W_ROWPACK;
+  if (flags & RLWE_W_FWD) r = load_mat(ctx, W_dev, d_out, d_in, false, method, rowpack, s, w->fwd);
   if (r == RLWE_OK && (flags & RLWE_W_TRANSPOSE))
-    r = load_mat(ctx, W_dev, d_out, d_in, true, method, s, w->tr);
+    r = load_mat(ctx, W_dev, d_out, d_in, true, method, rowpack, s, w->tr);
   if (r != RLWE_OK) {
     std::string msg = g_err;
     hipStreamSynchronize(s);
@@ -599,6 +607,14 @@ int rlwe_weights_method(const rlwe_weights* w, uint32_t transpose, uint32_t* met
   const Mat& m = transpose ? w->tr : w->fwd;
   if (!m.present) return fail(RLWE_EINVAL, "rlwe_weights_method: orientation not loaded");
   *method = m.ntt ? RLWE_METHOD_NTT : RLWE_METHOD_TOEPLITZ;
+  return ok();
+}
+
+int rlwe_weights_rows_per_product(const rlwe_weights* w, uint32_t transpose, uint32_t* n_o) {
+  if (!w || !n_o) return fail(RLWE_EINVAL, "rlwe_weights_rows_per_product: null argument");
+  const Mat& m = transpose ? w->tr : w->fwd;
+  if (!m.present) return fail(RLWE_EINVAL, "rlwe_weights_rows_per_product: orientation not loaded");
+  *n_o = m.args.n_o;
   return ok();
 }
 
@@ -686,7 +702,7 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
     const uint32_t prep_per = rc.N >= 256 ? rc.N / 256 : 1;
     all.prep_start[x + 1] = all.prep_start[x] + dd.tokens * m.args.L * prep_per;
     all.fwd_start[x + 1] = all.fwd_start[x] + (m.ntt ? dd.tokens * m.args.L * rc.P : 0);
-    all.body_start[x + 1] = all.body_start[x] + dd.tokens * ((m.args.rows + 255) / 256);
+    all.body_start[x + 1] = all.body_start[x] + dd.tokens * body_blocks_per_token(m.args);
   }
   all.n = cnt;
   hipError_t e = timed(ctx, K_PREP, s, [&] { return launch_prep(all, s); });
@@ -715,7 +731,8 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
       done[y] = true;
       const Item& it = all.it[y];
       mb.it[mb.n] = it;
-      const uint32_t blocks = ntt ? it.m.rows * ((it.T + kTokTile - 1) / kTokTile)
+      const uint32_t groups = (it.m.rows + it.m.n_o - 1) / it.m.n_o;
+      const uint32_t blocks = ntt ? groups * ((it.T + kTokTile - 1) / kTokTile)
                                   : it.T * (it.m.rows_pad / 32) * (rc.N / 64);
       mb.mask_start[mb.n + 1] = mb.mask_start[mb.n] + blocks;
       ++mb.n;

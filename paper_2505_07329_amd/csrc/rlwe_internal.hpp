@@ -159,7 +159,22 @@ struct MatArgs {
   uint32_t k;           // contraction length K
   uint32_t kw;          // row pitch: K rounded up to 64
   uint32_t L;           // input blocks
+  // Rows per weight polynomial and the slot each occupies (NTT method): 1 and N for
+  // the reversed encoding of Sec. 4.3; with multi-row packing (K <= N/2, one block)
+  // floor(N / K) rows, row rho of a group reversed in coefficients [rho K, rho K + K)
+  uint32_t n_o;
+  uint32_t slot;
 };
+
+// Body launch geometry (256 threads per block). Unpacked rows: one thread per row.
+// Packed rows: threads in slot-major order v = rho gpad + g over the groups g padded
+// to a multiple of 64, so that every wave holds a single slot rho.
+__host__ __device__ inline uint32_t body_group_pad(const MatArgs& m) {
+  return ((m.rows + m.n_o - 1) / m.n_o + 63) / 64 * 64;
+}
+__host__ __device__ inline uint32_t body_blocks_per_token(const MatArgs& m) {
+  return m.n_o > 1 ? (m.n_o * body_group_pad(m) + 255) / 256 : (m.rows + 255) / 256;
+}
 
 // One product of a batch: weights, input ciphertexts, workspace planes, output.
 struct Item {

@@ -26,6 +26,7 @@ RLWE_W_FWD = 1
 RLWE_W_TRANSPOSE = 2
 RLWE_W_NTT = 4
 RLWE_W_TOEPLITZ = 8
+RLWE_W_ROWPACK = 16
 RLWE_METHOD_TOEPLITZ = 0
 RLWE_METHOD_NTT = 1
 RLWE_OUT_SWITCHED = 0
@@ -38,7 +39,7 @@ EXPORTS = ("rlwe_params_init", "rlwe_params_destroy", "rlwe_weights_load", "rlwe
            "rlwe_profile_begin", "rlwe_profile_end", "rlwe_weights_digits", "ct_matmul_batch",
            "rlwe_batch_workspace_bytes", "rlwe_graph_capture_batch", "rlwe_graph_launch",
            "rlwe_graph_destroy", "rlwe_weights_method", "ct_pack_bits", "rlwe_packed_words",
-           "rlwe_last_error")
+           "rlwe_weights_rows_per_product", "rlwe_last_error")
 
 
 class RlweError(RuntimeError):
@@ -102,6 +103,7 @@ def lib() -> ctypes.CDLL:
     L.rlwe_weights_digits.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
                                       ctypes.POINTER(ctypes.c_uint32)]
     L.rlwe_weights_method.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
+    L.rlwe_weights_rows_per_product.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
     L.ct_matmul_batch.argtypes = [vp, ctypes.POINTER(CtMatmulDesc), ctypes.c_uint32,
                                   ctypes.c_uint32, vp]
     L.rlwe_batch_workspace_bytes.argtypes = [vp, ctypes.POINTER(CtMatmulDesc), ctypes.c_uint32]
@@ -209,6 +211,12 @@ def rlwe_weights_method(w: int, transpose: bool = False) -> int:
     m = ctypes.c_uint32()
     _check(lib().rlwe_weights_method(w, int(bool(transpose)), ctypes.byref(m)))
     return m.value
+
+
+def rlwe_weights_rows_per_product(w: int, transpose: bool = False) -> int:
+    n = ctypes.c_uint32()
+    _check(lib().rlwe_weights_rows_per_product(w, int(bool(transpose)), ctypes.byref(n)))
+    return n.value
 
 
 def _descs(items):

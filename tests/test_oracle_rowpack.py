@@ -1,4 +1,4 @@
-"""Pins of the oracle's multi-row packing (the coefficient packing of Sec. 4.5, as in
+"""Pins of the oracle's multi-row packing (the coefficient packing of Sec. 4.3.1, as in
 Cheetah): for d_in = K <= N, the n_o = floor(N / K) rows of a group share one weight
 polynomial with row rho reversed in slot rho, and row rho's output is SampleExtract
 (Sec. 3.2) at h = (rho + 1) K - 1.
