@@ -94,8 +94,8 @@ def roofline(products, kt, N, P, traffic=None):
 KERNEL_TRAFFIC = {
     "mask": {"source": "k_mask.hip", "fetch_bytes": 4382392135, "write_bytes": 4766662645,
              "sha256": "b71d09264e517098c1179f16657d1e4fa62f1eaae851294a6d0fdb5115986154"},
-    "ntt": {"source": "k_ntt.hip", "fetch_bytes": 17634446603, "write_bytes": 4385097669,
-            "sha256": "de766d99f7c8bc3356de272d5df76d288796b1225439d0cf55078e4a7f08d75d"},
+    "ntt": {"source": "k_ntt.hip", "fetch_bytes": 5067261677, "write_bytes": 4365784442,
+            "sha256": "e251e3a5e2d22e750b5e4fd1bb6d2335346f7d096c8a45e3df630253c67ce817"},
 }
 
 
