@@ -79,6 +79,14 @@ def lib() -> ctypes.CDLL:
         L.orc_lwe_phase.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u64p, _i8p,
                                     ctypes.c_size_t, _u64p, _u64p]
         L.orc_lwe_phase_u32.argtypes = [ctypes.c_uint32, _i8p, ctypes.c_size_t, _u32p, _i64p]
+        L.orc_decomp.argtypes = [ctypes.c_uint32, _u64p, ctypes.c_size_t, _u64p, ctypes.c_uint32,
+                                 ctypes.c_uint32, _i64p]
+        L.orc_gadget.argtypes = [ctypes.c_uint32, _u64p, ctypes.c_uint32, ctypes.c_uint32, _u64p]
+        L.orc_ksk_gen.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u64p, ctypes.c_uint32,
+                                  ctypes.c_uint32, _i8p, _i8p, _u64p, _i64p, _u64p]
+        L.orc_keyswitch_pack.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u64p, ctypes.c_uint32,
+                                         ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _u64p,
+                                         _u64p, ctypes.c_int, _u64p]
     return _lib
 
 
@@ -441,3 +449,122 @@ def lwe_phase_bits(N: int, S: np.ndarray, lwe: np.ndarray, bits: int) -> np.ndar
 def decode(phase: int, delta_: int) -> int:
     """Round a centred phase to the nearest multiple of Delta: the decrypted message."""
     return (2 * phase + delta_) // (2 * delta_)
+
+
+# ------------------------------------------------------------------ KeySwitch packing
+
+def check_gadget(primes, beta: int, ell: int) -> None:
+    """Decomposition parameters the oracle accepts: K = beta ell <= 64 rounding bits, at most
+    8 levels, and signed digits below every prime (2^(beta-1) < q_p)."""
+    if not (1 <= beta <= 54 and 1 <= ell <= 8 and beta * ell <= 64):
+        raise ValueError("need 1 <= beta <= 54, 1 <= ell <= 8, beta * ell <= 64")
+    if any((1 << (beta - 1)) >= int(p) for p in primes):
+        raise ValueError("digits must lie below every prime")
+
+
+def decomp(primes, residues: np.ndarray, beta: int, ell: int) -> np.ndarray:
+    """Gadget decomposition of TFHE (Decomp of KeySwitching, Sec. 3.2) of every coefficient
+    given by its residues: (..., P) u64 -> (..., ell) int64 signed base-2^beta digits of
+    round(c 2^K / q) mod 2^K, K = beta ell, most significant first."""
+    check_gadget(primes, beta, ell)
+    pr = _primes(primes)
+    P = len(pr)
+    r = np.ascontiguousarray(residues, dtype=np.uint64)
+    assert r.shape[-1] == P
+    lead = r.shape[:-1]
+    count = int(np.prod(lead)) if lead else 1
+    out = np.empty((count, ell), dtype=np.int64)
+    lib().orc_decomp(P, _p(pr, _u64p), count, _p(r.reshape(count, P), _u64p), beta, ell,
+                     _p(out, _i64p))
+    return out.reshape(tuple(lead) + (ell,))
+
+
+def gadget(primes, beta: int, ell: int) -> np.ndarray:
+    """Residues of the gadget values g_m = round(q / 2^(beta (m + 1))): (ell, P) u64."""
+    check_gadget(primes, beta, ell)
+    pr = _primes(primes)
+    out = np.empty((ell, len(pr)), dtype=np.uint64)
+    lib().orc_gadget(len(pr), _p(pr, _u64p), beta, ell, _p(out, _u64p))
+    return out
+
+
+def ksk_gen(N: int, primes, beta: int, ell: int, S_src: np.ndarray, S_dst: np.ndarray,
+            A: np.ndarray, E: np.ndarray) -> np.ndarray:
+    """Key-switching key KSK_{i,m} = RLWE_{S_dst}(S_src[i] g_m) (message in the constant
+    coefficient; Sec. 3.2). A (N, ell, P, N) uniform residues, E (N, ell, N) errors ->
+    (N, ell, 2, P, N) u64: A, then B = A S_dst + E + S_src[i] g_m."""
+    check_gadget(primes, beta, ell)
+    pr = _primes(primes)
+    P = len(pr)
+    A_ = np.ascontiguousarray(A, dtype=np.uint64)
+    E_ = np.ascontiguousarray(E, dtype=np.int64)
+    assert A_.shape == (N, ell, P, N) and E_.shape == (N, ell, N)
+    out = np.empty((N, ell, 2, P, N), dtype=np.uint64)
+    Ss = np.ascontiguousarray(S_src, dtype=np.int8)
+    Sd = np.ascontiguousarray(S_dst, dtype=np.int8)
+    lib().orc_ksk_gen(N, P, _p(pr, _u64p), beta, ell, _p(Ss, _i8p), _p(Sd, _i8p), _p(A_, _u64p),
+                      _p(E_, _i64p), _p(out, _u64p))
+    return out
+
+
+def packed_count(M: int, n_pack: int) -> int:
+    """RLWE ciphertexts that M LWE ciphertexts fill at n_pack slots each."""
+    return -(-M // n_pack)
+
+
+def keyswitch_pack(N: int, primes, beta: int, ell: int, lwe: np.ndarray, ksk: np.ndarray,
+                   n_pack: int | None = None, mode: int = 1) -> np.ndarray:
+    """Eq. (pack_rotate) without the final switch: LWE ciphertexts (M, P, N+1) -> packed RLWE
+    ciphertexts (ceil(M / n_pack), 2, P, N) u64, LWE g n_pack + s rotated into slot s of
+    output g after KeySwitching. mode 0: the definition, one LWE at a time (tiny rings);
+    mode 1: the same sums regrouped by input coefficient, products by NTT."""
+    check_gadget(primes, beta, ell)
+    pr = _primes(primes)
+    P = len(pr)
+    n_pack = N if n_pack is None else int(n_pack)
+    if not 1 <= n_pack <= N:
+        raise ValueError("n_pack must lie in [1, N]")
+    lw = np.ascontiguousarray(lwe, dtype=np.uint64).reshape(-1, P, N + 1)
+    M = lw.shape[0]
+    k = np.ascontiguousarray(ksk, dtype=np.uint64)
+    assert k.shape == (N, ell, 2, P, N)
+    out = np.empty((packed_count(M, n_pack), 2, P, N), dtype=np.uint64)
+    lib().orc_keyswitch_pack(N, P, _p(pr, _u64p), beta, ell, M, n_pack, _p(lw, _u64p),
+                             _p(k, _u64p), int(mode), _p(out, _u64p))
+    return out
+
+
+def rlwe_modswitch_bits(primes, rlwe: np.ndarray, bits: int) -> np.ndarray:
+    """ModulusSwitch of packed RLWE ciphertexts (G, 2, P, N) to 2^bits, coefficient by
+    coefficient (Eq. (pack_rotate)): -> (G, 2, N) u32."""
+    G, two, P, N = rlwe.shape
+    return modswitch_bits(primes, np.ascontiguousarray(rlwe), bits).reshape(G, two, N)
+
+
+def rlwe_decrypt_slots(N: int, primes, S: np.ndarray, rlwe: np.ndarray) -> list[list[int]]:
+    """Centred phase B - A S mod q of packed RLWE ciphertexts (G, 2, P, N), per coefficient,
+    as Python ints: [G][N]."""
+    G = rlwe.shape[0]
+    ph = rlwe_phase(N, primes, S, rlwe[:, 0], rlwe[:, 1])  # (G, P, N)
+    q = modulus(primes)
+    return [[centered(crt(primes, ph[g, :, n]), q) for n in range(N)] for g in range(G)]
+
+
+def rlwe_phase_bits(S: np.ndarray, rlwe: np.ndarray, bits: int) -> np.ndarray:
+    """Centred phase B - A S mod 2^bits of switched RLWE ciphertexts (G, 2, N) u32: (G, N)."""
+    Sv = np.asarray(S, dtype=np.int64)
+    G, _, N = rlwe.shape
+    mod = 1 << bits
+    out = np.empty((G, N), dtype=np.int64)
+    for g in range(G):
+        A = rlwe[g, 0].astype(np.int64)
+        B = rlwe[g, 1].astype(np.int64)
+        # negacyclic product A S modulo 2^bits (S ternary, |terms| < N 2^bits < 2^63)
+        AS = np.zeros(N, dtype=np.int64)
+        for k in np.nonzero(Sv)[0]:
+            sh = np.roll(A, int(k))
+            sh[:k] = -sh[:k]
+            AS += sh * Sv[k]
+        ph = (B - AS) % mod
+        out[g] = np.where(ph >= mod // 2, ph - mod, ph)
+    return out

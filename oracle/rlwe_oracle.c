@@ -427,3 +427,212 @@ void orc_lwe_phase_u32(uint32_t N, const int8_t* S, size_t count, const uint32_t
     out[c] = (int64_t)(int32_t)(lwe[N] - dot);
   }
 }
+
+/* ------------------------------------------------------------ KeySwitch packing */
+
+/* round(c * 2^K / q) mod 2^K for 0 <= c < q < 2^110, 1 <= K <= 64, by binary long
+ * division of c * 2^K by q, one quotient bit per step (remainder < q). */
+static uint64_t round_to_2k(u128 c, u128 q, uint32_t K) {
+  u128 rem = c;
+  uint64_t quo = 0;
+  for (uint32_t i = 0; i < K; ++i) {
+    rem <<= 1;
+    quo <<= 1;
+    if (rem >= q) {
+      rem -= q;
+      quo |= 1;
+    }
+  }
+  quo += (2 * rem >= q); /* rem / q >= 1/2 rounds up; no tie for odd q */
+  return K == 64 ? quo : quo & ((1ull << K) - 1);
+}
+
+/* Gadget decomposition of TFHE (the Decomp of KeySwitching, Sec. 3.2) of the
+ * coefficient whose residues are r[p * stride]: the torus value c / q is rounded
+ * to K = beta * ell bits, a~ = round(c 2^K / q) mod 2^K, and a~ is written in
+ * signed base 2^beta, a~ = sum_m d_m 2^(beta (ell - 1 - m)) mod 2^K with every
+ * d_m in [-2^(beta-1), 2^(beta-1)); d_0 is the most significant digit. The carry
+ * out of d_0 is dropped (a multiple of 2^K stands for a multiple of q). */
+static void decomp_one(uint32_t P, const uint64_t* primes, const uint64_t* r, size_t stride,
+                       uint32_t beta, uint32_t ell, int64_t* d) {
+  const u128 q = product_q(P, primes);
+  const uint64_t at = round_to_2k(crt(P, primes, r, stride), q, beta * ell);
+  const uint64_t base = beta == 64 ? 0 : 1ull << beta; /* beta <= 54 in practice */
+  const int64_t half = (int64_t)1 << (beta - 1);
+  uint64_t carry = 0;
+  for (uint32_t k = 0; k < ell; ++k) { /* least significant digit first */
+    const uint32_t m = ell - 1 - k;
+    uint64_t v = ((at >> (beta * k)) & (base - 1)) + carry;
+    if ((int64_t)v >= half) {
+      d[m] = (int64_t)v - (int64_t)base;
+      carry = 1;
+    } else {
+      d[m] = (int64_t)v;
+      carry = 0;
+    }
+  }
+}
+
+void orc_decomp(uint32_t P, const uint64_t* primes, size_t count, const uint64_t* in,
+                uint32_t beta, uint32_t ell, int64_t* out) {
+#pragma omp parallel for schedule(static)
+  for (size_t c = 0; c < count; ++c) decomp_one(P, primes, in + c * P, 1, beta, ell, out + c * ell);
+}
+
+/* Gadget values g_m = round(q / 2^(beta (m + 1))) as residues mod every prime:
+ * out[m][p]. Together with decomp_one, sum_m d_m g_m = c mod q up to
+ * q / 2^(K+1) + ell 2^(beta-2) (the rounding of c / q and of the g_m). */
+void orc_gadget(uint32_t P, const uint64_t* primes, uint32_t beta, uint32_t ell, uint64_t* out) {
+  const u128 q = product_q(P, primes);
+  for (uint32_t m = 0; m < ell; ++m) {
+    const uint32_t sh = beta * (m + 1);
+    const u128 g = sh >= 128 ? 0 : (q + ((u128)1 << (sh - 1))) >> sh;
+    for (uint32_t p = 0; p < P; ++p) out[m * P + p] = (uint64_t)(g % primes[p]);
+  }
+}
+
+/* Key-switching key (Sec. 3.2, KeySwitching): KSK_{i,m} = RLWE_{S_dst}(s_i g_m), the
+ * message in the constant coefficient, for every LWE key coefficient i < N
+ * (s = S_src, the key SampleExtract leaves) and gadget level m < ell.
+ *   A   [N][ell][P][N] uniform residues, E [N][ell][N] errors
+ *   ksk [N][ell][2][P][N] (out): A, then B = A S_dst + E + s_i g_m */
+void orc_ksk_gen(uint32_t N, uint32_t P, const uint64_t* primes, uint32_t beta, uint32_t ell,
+                 const int8_t* S_src, const int8_t* S_dst, const uint64_t* A, const int64_t* E,
+                 uint64_t* ksk) {
+  uint64_t g[8 * 2];
+  orc_gadget(P, primes, beta, ell, g);
+#pragma omp parallel for schedule(dynamic) collapse(3)
+  for (uint32_t i = 0; i < N; ++i) {
+    for (uint32_t m = 0; m < ell; ++m) {
+      for (uint32_t p = 0; p < P; ++p) {
+        const uint64_t q = primes[p];
+        uint64_t* s = (uint64_t*)malloc(sizeof(uint64_t) * N);
+        uint64_t* as = (uint64_t*)malloc(sizeof(uint64_t) * N);
+        for (uint32_t k = 0; k < N; ++k) s[k] = mod_i64(S_dst[k], q);
+        const uint64_t* a = A + (((size_t)i * ell + m) * P + p) * N;
+        poly_mul(a, s, N, q, 1, as);
+        uint64_t* ka = ksk + ((((size_t)i * ell + m) * 2 + 0) * P + p) * N;
+        uint64_t* kb = ksk + ((((size_t)i * ell + m) * 2 + 1) * P + p) * N;
+        const uint64_t msg = orc_mulmod(mod_i64(S_src[i], q), g[m * P + p], q);
+        for (uint32_t k = 0; k < N; ++k) {
+          u128 v = (u128)as[k] + mod_i64(E[((size_t)i * ell + m) * N + k], q);
+          if (k == 0) v += msg;
+          ka[k] = a[k];
+          kb[k] = (uint64_t)(v % q);
+        }
+        free(s);
+        free(as);
+      }
+    }
+  }
+}
+
+/* Packing of M LWE ciphertexts into G = ceil(M / n_pack) RLWE ciphertexts,
+ * Eq. (pack_rotate): output g = sum over slots s < n_pack (LWE g n_pack + s, while
+ * below M) of Rotate(KeySwitching(LWE), s), where
+ *   KeySwitching(a, b) = (0, b) - sum_i sum_m Decomp_m(a_i) KSK_{i,m}   (Sec. 3.2)
+ * and Rotate by s multiplies both polynomials by X^s in Z_q[X]/(X^N + 1).
+ *   lwe  [M][P][N+1] residues (mask, then body), ksk [N][ell][2][P][N]
+ *   out  [G][2][P][N]: A, then B of every packed ciphertext
+ * mode 0 follows that definition literally, one LWE at a time (N^2 ell 2 P
+ * products per LWE: tiny rings only). mode 1 uses the linearity of both steps:
+ *   A_g = -sum_i sum_m D_{i,m} KSK_{i,m}.A,  B_g = sum_s b_s X^s - sum_i sum_m D_{i,m} KSK_{i,m}.B
+ * with the digit polynomials D_{i,m} = sum_s Decomp_m(a_{g n_pack + s, i}) X^s, each
+ * product by the oracle's negacyclic NTT. */
+void orc_keyswitch_pack(uint32_t N, uint32_t P, const uint64_t* primes, uint32_t beta,
+                        uint32_t ell, uint32_t M, uint32_t n_pack, const uint64_t* lwe,
+                        const uint64_t* ksk, int mode, uint64_t* out) {
+  const uint32_t G = (M + n_pack - 1) / n_pack;
+  const size_t lw = (size_t)P * (N + 1);
+  memset(out, 0, sizeof(uint64_t) * (size_t)G * 2 * P * N);
+  /* digits of every mask coefficient: dg[(j N + i) ell + m] */
+  int64_t* dg = (int64_t*)malloc(sizeof(int64_t) * (size_t)M * N * ell);
+#pragma omp parallel for schedule(static)
+  for (size_t ji = 0; ji < (size_t)M * N; ++ji) {
+    const size_t j = ji / N, i = ji % N;
+    decomp_one(P, primes, lwe + j * lw + i, N + 1, beta, ell, dg + ji * ell);
+  }
+  if (mode == 0) {
+#pragma omp parallel for schedule(dynamic)
+    for (uint32_t g = 0; g < G; ++g) {
+      uint64_t* ks = (uint64_t*)malloc(sizeof(uint64_t) * 2 * P * N);
+      for (uint32_t s = 0; s < n_pack && (size_t)g * n_pack + s < M; ++s) {
+        const size_t j = (size_t)g * n_pack + s;
+        /* KeySwitching(LWE_j), starting from the trivial (0, b) */
+        for (uint32_t r = 0; r < P; ++r)
+          for (uint32_t n = 0; n < N; ++n) {
+            ks[(0 * P + r) * N + n] = 0;
+            ks[(1 * P + r) * N + n] = n == 0 ? lwe[j * lw + (size_t)r * (N + 1) + N] : 0;
+          }
+        for (uint32_t i = 0; i < N; ++i)
+          for (uint32_t m = 0; m < ell; ++m) {
+            const int64_t d = dg[(j * N + i) * ell + m];
+            if (d == 0) continue;
+            for (uint32_t c = 0; c < 2; ++c)
+              for (uint32_t r = 0; r < P; ++r) {
+                const uint64_t q = primes[r], dq = mod_i64(d, q);
+                const uint64_t* k = ksk + ((((size_t)i * ell + m) * 2 + c) * P + r) * N;
+                uint64_t* o = ks + ((size_t)c * P + r) * N;
+                for (uint32_t n = 0; n < N; ++n)
+                  o[n] = (uint64_t)(((u128)o[n] + q - orc_mulmod(dq, k[n], q)) % q);
+              }
+          }
+        /* Rotate by s and add: X^s X^n = X^(n+s), or -X^(n+s-N) past the degree */
+        for (uint32_t c = 0; c < 2; ++c)
+          for (uint32_t r = 0; r < P; ++r) {
+            const uint64_t q = primes[r];
+            const uint64_t* src = ks + ((size_t)c * P + r) * N;
+            uint64_t* dst = out + (((size_t)g * 2 + c) * P + r) * N;
+            for (uint32_t n = 0; n < N; ++n) {
+              const uint32_t e = n + s;
+              if (e < N)
+                dst[e] = (dst[e] + src[n]) % q;
+              else
+                dst[e - N] = (dst[e - N] + q - src[n]) % q;
+            }
+          }
+      }
+      free(ks);
+    }
+  } else {
+    for (uint32_t g = 0; g < G; ++g) {
+      for (uint32_t r = 0; r < P; ++r) {
+        const uint64_t q = primes[r];
+        const uint64_t psi = orc_find_psi(N, q);
+        uint64_t* acc[2] = {out + (((size_t)g * 2 + 0) * P + r) * N,
+                            out + (((size_t)g * 2 + 1) * P + r) * N};
+        /* the terms (i, m) are summed in per-thread copies, then added up */
+#pragma omp parallel
+        {
+          uint64_t* D = (uint64_t*)malloc(sizeof(uint64_t) * N);
+          uint64_t* prod = (uint64_t*)malloc(sizeof(uint64_t) * N);
+          uint64_t* part = (uint64_t*)calloc(2 * (size_t)N, sizeof(uint64_t));
+#pragma omp for schedule(dynamic)
+          for (uint32_t im = 0; im < N * ell; ++im) {
+            const uint32_t i = im / ell, m = im % ell;
+            for (uint32_t s = 0; s < N; ++s) {
+              const size_t j = (size_t)g * n_pack + s;
+              D[s] = (s < n_pack && j < M) ? mod_i64(dg[(j * N + i) * ell + m], q) : 0;
+            }
+            for (uint32_t c = 0; c < 2; ++c) {
+              const uint64_t* k = ksk + ((((size_t)i * ell + m) * 2 + c) * P + r) * N;
+              orc_poly_mul_ntt(D, k, N, q, psi, prod);
+              for (uint32_t n = 0; n < N; ++n) part[c * N + n] = (part[c * N + n] + prod[n]) % q;
+            }
+          }
+#pragma omp critical
+          for (uint32_t c = 0; c < 2; ++c)
+            for (uint32_t n = 0; n < N; ++n) acc[c][n] = (acc[c][n] + q - part[c * N + n]) % q;
+          free(D);
+          free(prod);
+          free(part);
+        }
+        for (uint32_t s = 0; s < n_pack && s < N && (size_t)g * n_pack + s < M; ++s) {
+          const size_t j = (size_t)g * n_pack + s;
+          acc[1][s] = (acc[1][s] + lwe[j * lw + (size_t)r * (N + 1) + N]) % q;
+        }
+      }
+    }
+  }
+  free(dg);
+}

@@ -118,4 +118,26 @@ void orc_lwe_phase_u32(uint32_t N, const int8_t* S, size_t count, const uint32_t
 uint64_t orc_splitmix64_at(uint64_t seed, uint64_t ctr);
 uint64_t orc_mask_coeff(uint64_t seed, uint32_t N, uint32_t p, uint32_t n, uint64_t q);
 void orc_expand_mask(uint64_t seed, uint32_t N, uint32_t P, const uint64_t* primes, uint64_t* A);
+
+
+/* KeySwitch packing (Sec. 3.2 KeySwitching and Rotate; Sec. 4.3 Eq. (pack_rotate)).
+ * Decomp is the gadget decomposition of TFHE: a~ = round(c 2^K / q) mod 2^K with K =
+ * beta ell, then ell signed base-2^beta digits d_0 (most significant) .. d_{ell-1} in
+ * [-2^(beta-1), 2^(beta-1)); gadget g_m = round(q / 2^(beta (m+1))).
+ *   orc_decomp          in [count][P] residues -> out [count][ell] digits
+ *   orc_gadget          out [ell][P] residues of g_m
+ *   orc_ksk_gen         KSK_{i,m} = RLWE_{S_dst}(S_src[i] g_m): A [N][ell][P][N],
+ *                       E [N][ell][N] -> ksk [N][ell][2][P][N]
+ *   orc_keyswitch_pack  M LWEs [M][P][N+1] -> ceil(M / n_pack) RLWEs [G][2][P][N];
+ *                       LWE g n_pack + s lands in slot s of output g. mode 0: the
+ *                       definition one LWE at a time; 1: digit polynomials by NTT */
+void orc_decomp(uint32_t P, const uint64_t* primes, size_t count, const uint64_t* in,
+                uint32_t beta, uint32_t ell, int64_t* out);
+void orc_gadget(uint32_t P, const uint64_t* primes, uint32_t beta, uint32_t ell, uint64_t* out);
+void orc_ksk_gen(uint32_t N, uint32_t P, const uint64_t* primes, uint32_t beta, uint32_t ell,
+                 const int8_t* S_src, const int8_t* S_dst, const uint64_t* A, const int64_t* E,
+                 uint64_t* ksk);
+void orc_keyswitch_pack(uint32_t N, uint32_t P, const uint64_t* primes, uint32_t beta,
+                        uint32_t ell, uint32_t M, uint32_t n_pack, const uint64_t* lwe,
+                        const uint64_t* ksk, int mode, uint64_t* out);
 #endif

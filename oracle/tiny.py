@@ -5,7 +5,8 @@ split, no CRT inside the products), so agreement with the C oracle on tiny
 inputs checks the residue-wise C code against an independent route.
 
 Passages: Sec. 3.1 (RLWE encryption), Sec. 3.2 (SampleExtract, ModulusSwitch),
-Sec. 4.3 (block split, reversed weights, Eq. (LWEdot)).
+Sec. 4.3 (block split, reversed weights, Eq. (LWEdot), Eq. (pack_rotate)); the
+Decomp of KeySwitching is the gadget decomposition of TFHE.
 """
 
 from __future__ import annotations
@@ -86,3 +87,56 @@ def modswitch(c, q, bits=32):
 def lwe_phase(a, b, S, q):
     ph = (b - sum(x * s for x, s in zip(a, S))) % q
     return ph - q if ph > q // 2 else ph
+
+
+def decomp(c, q, beta, ell):
+    """TFHE gadget decomposition of c mod q: signed base-2^beta digits, most significant first,
+    of round(c 2^(beta ell) / q) mod 2^(beta ell)."""
+    K = beta * ell
+    at = ((c % q) * (1 << (K + 1)) + q) // (2 * q) % (1 << K)
+    d = []
+    for k in range(ell):  # least significant first, balanced
+        v = at % (1 << beta)
+        at //= 1 << beta
+        if v >= 1 << (beta - 1):
+            v -= 1 << beta
+            at += 1
+        d.append(v)
+    return d[::-1]
+
+
+def gadget(q, beta, ell):
+    return [(q + (1 << (beta * (m + 1) - 1))) >> (beta * (m + 1)) for m in range(ell)]
+
+
+def keyswitch(a, b, ksk, q, beta, ell):
+    """KeySwitching(a, b) = (0, b) - sum_i sum_m Decomp_m(a_i) KSK[i][m], KSK[i][m] = (A, B)."""
+    N = len(a)
+    A = [0] * N
+    B = [b % q] + [0] * (N - 1)
+    for i in range(N):
+        for m, d in enumerate(decomp(a[i], q, beta, ell)):
+            KA, KB = ksk[i][m]
+            A = [(x - d * y) % q for x, y in zip(A, KA)]
+            B = [(x - d * y) % q for x, y in zip(B, KB)]
+    return A, B
+
+
+def rotate(P, s, q):
+    """P(X) X^s in Z_q[X]/(X^N + 1)."""
+    N = len(P)
+    X = [0] * N
+    X[s] = 1
+    return negacyclic_mul(P, X, q)
+
+
+def keyswitch_pack(lwes, ksk, q, beta, ell):
+    """Eq. (pack_rotate) before the switch: sum_s Rotate(KeySwitching(lwes[s]), s)."""
+    N = len(lwes[0][0])
+    A = [0] * N
+    B = [0] * N
+    for s, (a, b) in enumerate(lwes):
+        KA, KB = keyswitch(a, b, ksk, q, beta, ell)
+        A = [(x + y) % q for x, y in zip(A, rotate(KA, s, q))]
+        B = [(x + y) % q for x, y in zip(B, rotate(KB, s, q))]
+    return A, B
