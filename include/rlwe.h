@@ -245,10 +245,13 @@ int rlwe_workspace_reserve(rlwe_ctx* ctx, size_t bytes);
 typedef struct rlwe_kernel_times {
   /* summed durations: digit preparation and mask transforms (prep), matrix-core
    * mask products (mask), NTT mask products (ntt), body, standalone switch,
-   * bit-packing (pack) */
+   * bit-packing (pack), KeySwitch packing: gadget digits (ksdig), transforms and
+   * key products (ksacc), inverse transforms and outputs (ksfin) */
   double prep_ms, mask_ms, body_ms, modswitch_ms, ntt_ms, pack_ms;
   uint32_t prep_n, mask_n, body_n, modswitch_n, ntt_n, pack_n; /* launches recorded */
   uint32_t dropped;
+  double ksdig_ms, ksacc_ms, ksfin_ms;
+  uint32_t ksdig_n, ksacc_n, ksfin_n;
 } rlwe_kernel_times;
 
 int rlwe_profile_begin(rlwe_ctx* ctx);
@@ -269,6 +272,63 @@ int rlwe_weights_method(const rlwe_weights* w, uint32_t transpose, uint32_t* met
  * floor(N / K) when it was loaded with RLWE_W_ROWPACK and K <= N/2, else 1.
  * RLWE_EINVAL for null arguments or an orientation that was not loaded. */
 int rlwe_weights_rows_per_product(const rlwe_weights* w, uint32_t transpose, uint32_t* n_o);
+
+/* KeySwitch packing (Sec. 3.2 KeySwitching and Rotate; Sec. 4.3 Eq. (pack_rotate)):
+ * the LWE outputs of ct_matmul_clear are key-switched to RLWE ciphertexts and
+ * rotated into the slots of packed RLWE ciphertexts, which are then switched to
+ * q_out; N = 4096 only.
+ *
+ * Decomp (the gadget decomposition of TFHE, to which Sec. 3.2 refers): a mask
+ * coefficient c in [0, q) is rounded to K = log2_base * levels bits, a~ =
+ * round(c 2^K / q) mod 2^K, and a~ = sum_m d_m 2^(log2_base (levels - 1 - m))
+ * mod 2^K with signed digits d_m in [-2^(log2_base-1), 2^(log2_base-1)), d_0 the
+ * most significant; the gadget values are g_m = round(q / 2^(log2_base (m+1))).
+ * The key-switching key (a client-side secret product: it is built with both
+ * secret keys) is KSK_{i,m} = RLWE_{S'}(s_i g_m) for i < N, m < levels, the
+ * message in the constant coefficient, s the LWE key of the outputs (the
+ * coefficients of the input key S) and S' the key of the packed outputs.
+ *
+ * rlwe_ksk_load: make the key resident in the NTT domain (N levels P 2 N 8 bytes).
+ *   ksk_dev    device, uint64 [N][levels][2][P][N] canonical residues: A, then B of
+ *              KSK_{i,m}; read during the call only
+ *   log2_base  digit bits, 1 <= log2_base <= 54, 2^(log2_base-1) below every prime
+ *   levels     1 <= levels <= 4, log2_base * levels <= 64 (e.g. 54 and 1 for two
+ *              54-bit primes; 12 and 3 for one)
+ * Errors: RLWE_EINVAL (null), RLWE_EPARAM (N != 4096, bad gadget), RLWE_ENOMEM.
+ * Synchronises `stream` (set-up call). */
+typedef struct rlwe_ksk rlwe_ksk;
+int rlwe_ksk_load(rlwe_ctx* ctx, const uint64_t* ksk_dev, uint32_t log2_base, uint32_t levels,
+                  rlwe_stream_t stream, rlwe_ksk** out);
+
+/* Release a key (after all work that uses it has completed). NULL ok. */
+int rlwe_ksk_free(rlwe_ksk* k);
+
+/* Packed ciphertexts for `count` LWE ciphertexts at n_pack slots each:
+ * ceil(count / n_pack) (0 if n_pack = 0). */
+size_t rlwe_packed_count(size_t count, uint32_t n_pack);
+
+/* Workspace bytes of ct_keyswitch_pack for this shape (0 on bad input); calls
+ * within rlwe_workspace_reserve(that many) allocate nothing. */
+size_t rlwe_keyswitch_workspace_bytes(const rlwe_ctx* ctx, const rlwe_ksk* k, size_t count,
+                                      uint32_t n_pack);
+
+/* Eq. (pack_rotate): packed output g = sum over slots s < n_pack of
+ * Rotate(KeySwitching(LWE_{g n_pack + s}), s) (while g n_pack + s < count), with
+ * KeySwitching(a, b) = (0, b) - sum_i sum_m Decomp_m(a_i) KSK_{i,m} and Rotate by
+ * s the product with X^s in Z_q[X]/(X^N + 1); then, unless RLWE_OUT_RAW_Q, the
+ * ModulusSwitch of every coefficient to q_out = 2^log2_q_out. Coefficient s of
+ * output g decrypts under S' to the message of LWE g n_pack + s (e.g. n_pack =
+ * d_out packs one token's outputs of W.[x] per ciphertext when d_out <= N;
+ * n_pack = N fills every slot).
+ *   lwe_in  device, uint64 [count][P][N+1]: LWE ciphertexts modulo q (mask, then
+ *           body), e.g. the RLWE_OUT_RAW_Q output of ct_matmul_clear
+ *   out     device: RLWE_OUT_SWITCHED uint32 [G][2][N] (A, then B, switched);
+ *           RLWE_OUT_RAW_Q uint64 [G][2][P][N] residues; G = rlwe_packed_count
+ * count = 0 is a no-op; RLWE_ESHAPE unless 1 <= n_pack <= N. Uses the context
+ * workspace (grown with hipMalloc unless reserved; refused while the stream is
+ * captured). Asynchronous on `stream`. */
+int ct_keyswitch_pack(rlwe_ctx* ctx, const rlwe_ksk* k, const uint64_t* lwe_in, size_t count,
+                      uint32_t n_pack, void* out, uint32_t flags, rlwe_stream_t stream);
 
 /* Description of the last error on this thread ("" if none). */
 const char* rlwe_last_error(void);

@@ -1,0 +1,390 @@
+// KeySwitch packing of LWE outputs into RLWE ciphertexts (Sec. 3.2 KeySwitching and
+// Rotate, Sec. 4.3 Eq. (pack_rotate)), N = 4096.
+//
+// LWE ciphertext g n_pack + s (mask a, body b) goes to slot s of packed output g:
+//   out_g = sum_s X^s ((0, b_s) - sum_i sum_m Decomp_m(a_s[i]) KSK_{i,m}).
+// Both KeySwitching and the rotation are linear in the digits, so the sums are
+// regrouped by key coefficient i and level m: with the digit polynomials
+// D_{i,m}(X) = sum_s Decomp_m(a_s[i]) X^s,
+//   A_g = -sum_{i,m} D_{i,m} KSK_{i,m}.A,   B_g = sum_s b_s X^s - sum_{i,m} D_{i,m} KSK_{i,m}.B
+// in Z_q[X]/(X^N + 1), per prime. The key is resident in the NTT domain, so each
+// D_{i,m} costs one forward transform per prime and two pointwise products; a
+// group needs N ell transforms per prime and two inverse transforms per prime.
+//
+// Decomp is the gadget decomposition of TFHE: the coefficient c (CRT of its
+// residues) is rounded to K = beta ell bits, a~ = round(c 2^K / q) mod 2^K, and
+// a~ is written in signed base 2^beta (digits in [-2^(beta-1), 2^(beta-1)), most
+// significant first). The rounding is exact: with y_p = c_p (q/q_p)^-1 mod q_p,
+// c 2^K / q = sum_p y_p 2^K / q_p - kappa 2^K, and each y_p 2^K / q_p is split
+// into its integer part and remainder through 2^K = f_p q_p + g_p. The signed
+// digits are those of a~ + H, H = sum_m 2^(beta-1) 2^(beta m), less 2^(beta-1).
+//
+// Kernels (one pass covers up to kKsGroups output groups):
+//   ks_digits_kernel  raw LWE masks [M][P][N+1] -> digits [group][i][m][slot]
+//                     (int64), a 64 x 64 tile transpose through LDS
+//   ks_accum_kernel   per (group, chunk of 64 key coefficients, prime): forward
+//                     transforms of the digit polynomials, pointwise products
+//                     with the resident key, partial sums [group][chunk][p][2][N]
+//   ks_finish_kernel  per group: sum of the partials, inverse transforms, the
+//                     factor 1/N, negation, bodies, optional switch to 2^k
+#include "ntt_device.hpp"
+
+namespace rlwe {
+
+namespace {
+
+constexpr uint32_t kKsChunk = 64;                 // key coefficients per accumulate workgroup
+constexpr uint32_t kKsChunks = kNttN / kKsChunk;  // chunks per group
+constexpr uint32_t kTile = 64;                    // digit transpose tile (coefficients x slots)
+
+typedef const __attribute__((address_space(4))) KsArgs* KsPtr;
+__device__ __forceinline__ KsPtr ks_args() { return (KsPtr)__builtin_amdgcn_kernarg_segment_ptr(); }
+
+// Signed base-2^beta digits of round(c 2^K / q) mod 2^K for the coefficient with
+// residues c0 (prime 0) and c1 (prime 1, NP = 2), into d[0..ell).
+template <int NP, int ELL>
+__device__ __forceinline__ void decompose(KsPtr a, uint64_t c0, uint64_t c1, int64_t (&d)[ELL]) {
+  uint64_t at;
+  {
+    const uint64_t cs[2] = {c0, c1};
+    uint64_t u[NP], rem[NP];
+#pragma unroll
+    for (int r = 0; r < NP; ++r) {
+      const uint64_t p = a->rc.q[r];
+      const uint64_t y = NP == 1 ? cs[r] : mulmod_shoup(cs[r], a->rc.crt_inv[r], a->rc.crt_inv_shoup[r], p);
+      // y 2^K = y f q_p + y g: floor(y g / q_p) is qh or qh + 1
+      const uint64_t qh = __umul64hi(y, a->kc.g_shoup[r]);
+      uint64_t rr = y * a->kc.g[r] - qh * p;  // in [0, 2 q_p)
+      u[r] = y * a->kc.f[r] + qh;
+      if (rr >= p) {
+        rr -= p;
+        ++u[r];
+      }
+      rem[r] = rr;
+    }
+    if (NP == 1) {
+      at = u[0] + (2 * rem[0] >= a->rc.q[0] ? 1 : 0);
+    } else {
+      // fraction rem_0 / q_0 + rem_1 / q_1 in [0, 2) against 1/2 and 3/2
+      const u128 Q = make_u128(a->rc.Q_hi, a->rc.Q_lo);
+      const u128 F = 2 * ((u128)rem[0] * a->rc.q[NP - 1] + (u128)rem[NP - 1] * a->rc.q[0]);
+      at = u[0] + u[NP - 1] + (F >= Q ? 1 : 0) + (F >= 3 * Q ? 1 : 0);
+    }
+  }
+  const uint32_t beta = a->kc.beta;
+  const uint64_t v = (at & a->kc.kmask) + a->kc.H;
+  const uint64_t bmask = (1ull << beta) - 1, half = 1ull << (beta - 1);
+#pragma unroll
+  for (int m = 0; m < ELL; ++m) {
+    const uint32_t sh = beta * (ELL - 1 - m);
+    d[m] = (int64_t)((v >> sh) & bmask) - (int64_t)half;
+  }
+}
+
+
+// Forward pass of the 512-thread transform in layout PASS (InvLayout): three
+// Cooley-Tukey stages, spans 4S, 2S, S, inputs and outputs below 4p.
+template <int PASS>
+__device__ __forceinline__ void fwd512_pass(uint64_t (&x)[1][8], int tid, const uint64_t* tw,
+                                            uint64_t p) {
+  constexpr int S = InvLayout<PASS>::S;
+  const uint32_t base = InvLayout<PASS>::base(tid);
+#pragma unroll
+  for (int st = 0; st < 3; ++st) {
+    const int sp = 4 >> st;
+    const uint32_t t = S * sp;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (k & sp) continue;
+      const uint32_t pos = base + S * k;
+      ct_bfly(x[0][k], x[0][k + sp], ld_tw(tw, kN / (2 * t) + pos / (2 * t)), p);
+    }
+  }
+}
+
+// Forward transform on 512 threads, one prime: x in layout Q4 (positions tid +
+// 512 k), natural order, below 4p -> layout Q1 (8 tid + k), bit-reversed order,
+// below 4p. The mirror of the inverse: Q4 -> Q3 crosses waves (buffer lx, between
+// barriers), Q3 -> Q2 and Q2 -> Q1 stay inside each wave's block of lw.
+__device__ __forceinline__ void ntt_forward512(uint64_t (&x)[1][8], uint64_t* lx, uint64_t* lw,
+                                               const uint64_t* tw, uint64_t p, int tid) {
+  fwd512_pass<3>(x, tid, tw, p);
+  __syncthreads();  // no wave still reads the previous transform's Q3 positions
+  inv_store<1, 3, 3>(lx, x, tid);
+  __syncthreads();
+  inv_load<1, 2, 3>(lx, x, tid);
+  fwd512_pass<2>(x, tid, tw, p);
+  wave_exchange_fence();  // every lane of the wave has read its Q2 positions of the last transform
+  inv_store<1, 2, 2>(lw, x, tid);
+  wave_exchange_fence();
+  inv_load<1, 1, 2>(lw, x, tid);
+  fwd512_pass<1>(x, tid, tw, p);
+  wave_exchange_fence();
+  inv_store<1, 1, 1>(lw, x, tid);
+  wave_exchange_fence();
+  inv_load<1, 0, 1>(lw, x, tid);
+  fwd512_pass<0>(x, tid, tw, p);
+}
+
+}  // namespace
+
+// Digits: one workgroup per (group of the pass, tile of 64 key coefficients i,
+// tile of 64 slots s). Loads run along i (coalesced rows of an LWE mask), stores
+// along s (coalesced rows of a digit polynomial).
+template <int NP, int ELL>
+__global__ void __launch_bounds__(256) ks_digits_kernel(KsArgs) {
+  __shared__ int64_t tile[kTile][kTile + 1];
+  const KsPtr a = ks_args();
+  const uint32_t N = kN;
+  const uint32_t tiles = N / kTile;
+  const uint32_t blk = linear_block();
+  const uint32_t gb = blk / (tiles * tiles);
+  if (gb >= a->GB) return;
+  const uint32_t it = (blk / tiles) % tiles, st = blk % tiles;
+  const uint32_t i0 = it * kTile, s0 = st * kTile;
+  const uint32_t g = a->g0 + gb;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  constexpr uint32_t ell = ELL;
+  int64_t d[16][ELL];
+#pragma unroll
+  for (int rep = 0; rep < 16; ++rep) {
+    const uint32_t s = s0 + ty + 4 * rep;
+    const uint64_t j = (uint64_t)g * a->n_pack + s;
+    if (s < a->n_pack && j < a->M) {
+      const uint64_t* row = a->lwe + j * NP * (N + 1) + i0 + tx;
+      decompose<NP, ELL>(a, row[0], NP == 2 ? row[N + 1] : 0, d[rep]);
+    } else {
+#pragma unroll
+      for (int m = 0; m < ELL; ++m) d[rep][m] = 0;
+    }
+  }
+  int64_t* dst = a->dig + (size_t)gb * N * ell * N;
+#pragma unroll
+  for (int m = 0; m < ELL; ++m) {
+    if (m) __syncthreads();  // the previous level's tile has been written out
+#pragma unroll
+    for (int rep = 0; rep < 16; ++rep) tile[tx][ty + 4 * rep] = d[rep][m];  // [i][s]
+    __syncthreads();
+#pragma unroll
+    for (int rep = 0; rep < 16; ++rep) {
+      const uint32_t il = ty + 4 * rep;
+      dst[((size_t)(i0 + il) * ell + m) * N + s0 + tx] = tile[il][tx];
+    }
+  }
+}
+
+// Accumulation: one workgroup per (group of the pass, chunk of kKsChunk key
+// coefficients, prime). Block b runs on XCD b mod 8; the mapping keeps every
+// (chunk, prime) on one XCD with the groups varying fastest, so the workgroups
+// that run together on an XCD read the same key polynomials from its L2.
+__global__ void __launch_bounds__(kInvThreads, 4) ks_accum_kernel(KsArgs) {
+  __shared__ uint64_t lx[kN];
+  __shared__ uint64_t lw[kInvLdsWords];
+  const KsPtr a = ks_args();
+  const uint32_t P = a->rc.P, GB = a->GB, ell = a->kc.ell;
+  const uint32_t blk = linear_block();
+  const uint32_t rest = blk >> 3, xcd = blk & 7;
+  const uint32_t gb = rest % GB, cp = (rest / GB) * 8 + xcd;
+  if (cp >= kKsChunks * P) return;
+  const uint32_t chunk = cp / P, r = cp % P;
+  const uint64_t p = a->rc.q[r];
+  const uint64_t pn = 0 - p;
+  const InvMod md{pn, 8 * p, a->ntt.bm[r]};
+  const uint64_t* tw = a->ntt.fwd[r];
+  const uint64_t r1 = a->ntt.rq[r][0], r0 = a->ntt.rq[r][1];
+  const int tid0 = threadIdx.x;
+  uint64_t accA[8], accB[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) accA[k] = accB[k] = 0;
+  const int64_t* dig = a->dig + (size_t)gb * kN * ell * kN;
+  for (uint32_t il = 0; il < kKsChunk; ++il) {
+    const uint32_t i = chunk * kKsChunk + il;
+    for (uint32_t m = 0; m < ell; ++m) {
+      int tid = tid0;
+      asm volatile("" : "+v"(tid));
+      uint64_t x[1][8];
+      const int64_t* dsrc = dig + ((size_t)i * ell + m) * kN + tid;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int64_t v = dsrc[512 * k];
+        x[0][k] = v < 0 ? (uint64_t)(v + (int64_t)p) : (uint64_t)v;
+      }
+      ntt_forward512(x, lx, lw, tw, p, tid);
+      const uint64_t* kh = a->khat + (((size_t)i * ell + m) * P + r) * 2 * kN + 8 * tid;
+      uint64_t ka[8], kb[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        ka[k] = kh[k];
+        kb[k] = kh[kN + k];
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint64_t v = reduce4(x[0][k], p);
+        // Shoup companion floor(v 2^64 / p): v floor(2^128 / p) / 2^64 is at most 1 low
+        uint64_t c = v * r1 + __umul64hi(v, r0);
+        c += (0 - c * p) >= p ? 1 : 0;
+        accA[k] += mul_shoup4(ka[k], v, c, pn);
+        accB[k] += mul_shoup4(kb[k], v, c, pn);
+      }
+    }
+    if ((il & 15) == 15) {  // at most 64 products below 4p since the last reduction
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        accA[k] = reduce_barrett(accA[k], md);
+        accB[k] = reduce_barrett(accB[k], md);
+      }
+    }
+  }
+  uint64_t* dst = a->part + (((size_t)gb * kKsChunks + chunk) * P + r) * 2 * kN + 8 * tid0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    dst[k] = reduce4(reduce_barrett(accA[k], md), p);
+    dst[kN + k] = reduce4(reduce_barrett(accB[k], md), p);
+  }
+}
+
+// Finish: one workgroup per group of the pass; the primes are transformed together.
+template <bool RAW, int NP>
+__global__ void __launch_bounds__(kInvThreads) ks_finish_kernel(KsArgs) {
+  __shared__ uint64_t lds[NP * kInvLdsWords];
+  const KsPtr a = ks_args();
+  const uint32_t gb = linear_block();
+  if (gb >= a->GB) return;
+  const uint32_t g = a->g0 + gb;
+  uint64_t p[NP];
+  InvMod md[NP];
+  const uint64_t* tw[NP];
+#pragma unroll
+  for (int r = 0; r < NP; ++r) {
+    p[r] = a->rc.q[r];
+    md[r] = InvMod{0 - p[r], 8 * p[r], a->ntt.bm[r]};
+    tw[r] = a->ntt.inv[r];
+  }
+  const int tid = threadIdx.x;
+  const uint32_t N = kN;
+  for (uint32_t c = 0; c < 2; ++c) {
+    uint64_t x[NP][8];
+#pragma unroll
+    for (int r = 0; r < NP; ++r) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) x[r][k] = 0;
+      for (uint32_t ch = 0; ch < kKsChunks; ++ch) {
+        const uint64_t* src =
+            a->part + ((((size_t)gb * kKsChunks + ch) * NP + r) * 2 + c) * kN + 8 * tid;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[r][k] += src[k];  // 64 terms below p
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) x[r][k] = reduce_barrett(x[r][k], md[r]);
+    }
+    if (c) __syncthreads();  // the first component's transforms are done with lds
+    ntt_inverse<NP>(x, lds, tw, md, tid);
+    // coefficient n = tid + 512 k, natural order
+    uint64_t v[NP][8];
+#pragma unroll
+    for (int r = 0; r < NP; ++r)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        uint64_t t = mul_shoup(x[r][k], a->ntt.ninv[r], a->ntt.ninv_shoup[r], p[r]);
+        t = t >= p[r] ? t - p[r] : t;
+        uint64_t b = 0;
+        if (c == 1) {
+          const uint32_t s = tid + 512 * k;
+          const uint64_t j = (uint64_t)g * a->n_pack + s;
+          if (s < a->n_pack && j < a->M) b = a->lwe[(j * NP + r) * (N + 1) + N];
+        }
+        v[r][k] = b >= t ? b - t : b + p[r] - t;  // (b - sum) mod p; b = 0 for the mask
+      }
+    if (RAW) {
+      uint64_t* o = (uint64_t*)a->out + (((size_t)g * 2 + c) * NP) * N;
+#pragma unroll
+      for (int r = 0; r < NP; ++r)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) o[(size_t)r * N + tid + 512 * k] = v[r][k];
+    } else {
+      uint32_t* o = (uint32_t*)a->out + ((size_t)g * 2 + c) * N;
+      const RingConst rc = kernarg_load(&a->rc);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        u128 V = v[0][k];
+        if (NP == 2) {
+          const uint64_t y0 = mulmod_shoup(v[0][k], rc.crt_inv[0], rc.crt_inv_shoup[0], p[0]);
+          const uint64_t y1 = mulmod_shoup(v[NP - 1][k], rc.crt_inv[NP - 1], rc.crt_inv_shoup[NP - 1], p[NP - 1]);
+          V = (u128)y0 * p[NP - 1] + (u128)y1 * p[0];
+          const u128 Q = make_u128(rc.Q_hi, rc.Q_lo);
+          if (V >= Q) V -= Q;
+        }
+        o[tid + 512 * k] = switch_exact((i128)V, rc);
+      }
+    }
+  }
+}
+
+// Key in the NTT domain: one workgroup per polynomial (i, m, c, p) of the key
+// [N][ell][2][P][N] -> khat[((i ell + m) P + p) 2 + c][N], bit-reversed, in [0, p).
+__global__ void __launch_bounds__(kThreads) ksk_fwd_kernel(KsArgs) {
+  __shared__ uint64_t lds[kLdsWords];
+  const KsPtr a = ks_args();
+  const uint32_t P = a->rc.P;
+  const uint32_t loc = linear_block();  // ((i ell + m) 2 + c) P + p
+  if (loc >= kN * a->kc.ell * 2 * P) return;
+  const uint32_t r = loc % P, c = (loc / P) % 2, im = loc / (2 * P);
+  const uint64_t p = a->rc.q[r];
+  const int tid = threadIdx.x;
+  const uint64_t* src = a->ksk_in + (size_t)loc * kN;
+  uint64_t x[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) x[k] = src[tid + 256 * k];
+  ntt_forward(x, lds, a->ntt.fwd[r], p, tid);
+  uint64_t* dst = a->khat_out + (((size_t)im * P + r) * 2 + c) * kN + 16 * tid;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) dst[k] = reduce4(x[k], p);
+}
+
+hipError_t launch_ksk_fwd(const KsArgs& a, hipStream_t s) {
+  const uint32_t blocks = kN * a.kc.ell * 2 * a.rc.P;
+  hipLaunchKernelGGL(ksk_fwd_kernel, grid_for(blocks), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ks_digits(const KsArgs& a, hipStream_t s) {
+  const uint32_t tiles = kN / kTile;
+  const uint32_t blocks = a.GB * tiles * tiles;
+  const dim3 g = grid_for(blocks);
+  switch (a.rc.P * 8 + a.kc.ell) {
+    case 9: hipLaunchKernelGGL((ks_digits_kernel<1, 1>), g, dim3(256), 0, s, a); break;
+    case 10: hipLaunchKernelGGL((ks_digits_kernel<1, 2>), g, dim3(256), 0, s, a); break;
+    case 11: hipLaunchKernelGGL((ks_digits_kernel<1, 3>), g, dim3(256), 0, s, a); break;
+    case 12: hipLaunchKernelGGL((ks_digits_kernel<1, 4>), g, dim3(256), 0, s, a); break;
+    case 17: hipLaunchKernelGGL((ks_digits_kernel<2, 1>), g, dim3(256), 0, s, a); break;
+    case 18: hipLaunchKernelGGL((ks_digits_kernel<2, 2>), g, dim3(256), 0, s, a); break;
+    case 19: hipLaunchKernelGGL((ks_digits_kernel<2, 3>), g, dim3(256), 0, s, a); break;
+    case 20: hipLaunchKernelGGL((ks_digits_kernel<2, 4>), g, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ks_accum(const KsArgs& a, hipStream_t s) {
+  const uint32_t blocks = a.GB * kKsChunks * a.rc.P;  // kKsChunks P is a multiple of 8
+  hipLaunchKernelGGL(ks_accum_kernel, grid_for(blocks), dim3(kInvThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ks_finish(const KsArgs& a, hipStream_t s) {
+  const dim3 g = grid_for(a.GB);
+  if (a.rc.P == 2) {
+    if (a.raw)
+      hipLaunchKernelGGL((ks_finish_kernel<true, 2>), g, dim3(kInvThreads), 0, s, a);
+    else
+      hipLaunchKernelGGL((ks_finish_kernel<false, 2>), g, dim3(kInvThreads), 0, s, a);
+  } else {
+    if (a.raw)
+      hipLaunchKernelGGL((ks_finish_kernel<true, 1>), g, dim3(kInvThreads), 0, s, a);
+    else
+      hipLaunchKernelGGL((ks_finish_kernel<false, 1>), g, dim3(kInvThreads), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rlwe

@@ -80,7 +80,10 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 }  // namespace
 
 namespace {
-enum KernelKind { K_PREP = 0, K_MASK = 1, K_BODY = 2, K_MODSWITCH = 3, K_NTT = 4, K_PACK = 5 };
+enum KernelKind {
+  K_PREP = 0, K_MASK = 1, K_BODY = 2, K_MODSWITCH = 3, K_NTT = 4, K_PACK = 5,
+  K_KSDIG = 6, K_KSACC = 7, K_KSFIN = 8, K_KINDS = 9
+};
 constexpr int kMaxProfiled = 4096;
 struct Profiler {
   bool on = false;
@@ -410,10 +413,12 @@ int rlwe_profile_end(rlwe_ctx* ctx, rlwe_kernel_times* out) {
   p->on = false;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  double* ms[6] = {&out->prep_ms, &out->mask_ms, &out->body_ms, &out->modswitch_ms, &out->ntt_ms,
-                   &out->pack_ms};
-  uint32_t* n[6] = {&out->prep_n, &out->mask_n, &out->body_n, &out->modswitch_n, &out->ntt_n,
-                    &out->pack_n};
+  double* ms[K_KINDS] = {&out->prep_ms,  &out->mask_ms,  &out->body_ms,
+                         &out->modswitch_ms, &out->ntt_ms, &out->pack_ms,
+                         &out->ksdig_ms, &out->ksacc_ms, &out->ksfin_ms};
+  uint32_t* n[K_KINDS] = {&out->prep_n,  &out->mask_n,  &out->body_n,
+                          &out->modswitch_n, &out->ntt_n, &out->pack_n,
+                          &out->ksdig_n, &out->ksacc_n, &out->ksfin_n};
   for (int i = 0; i < p->used; ++i) {
     e = hipEventSynchronize(p->ev[i][1]);
     if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
@@ -911,6 +916,158 @@ int ct_pack_bits(rlwe_ctx* ctx, const uint32_t* in, size_t count, uint32_t len, 
   e = timed(ctx, K_PACK, s, [&] { return launch_pack_bits(in, count, len, ctx->rc.qbits, out, s); });
   if (e == hipErrorInvalidValue) return fail(RLWE_ESHAPE, "ct_pack_bits: %zu ciphertexts too many", count);
   if (e != hipSuccess) return hip_fail(e, "pack kernel");
+  return ok();
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ KeySwitch packing
+
+struct rlwe_ksk {
+  rlwe_ctx* ctx = nullptr;
+  uint64_t* khat = nullptr;  // [N][ell][P][2][N], NTT domain, bit-reversed
+  KsConst kc{};
+};
+
+namespace {
+KsArgs ks_args_base(const rlwe_ctx* ctx) {
+  KsArgs a{};
+  a.rc = ctx->rc;
+  a.ntt = ctx->ntt;
+  return a;
+}
+// Output groups per pass and the workspace of one pass.
+uint32_t ks_pass_groups(size_t M, uint32_t n_pack) {
+  const size_t G = (M + n_pack - 1) / n_pack;
+  return (uint32_t)std::min<size_t>(G, kKsGroups);
+}
+size_t ks_ws_bytes(const rlwe_ctx* ctx, const rlwe_ksk* k, size_t M, uint32_t n_pack) {
+  const size_t N = ctx->rc.N, GB = ks_pass_groups(M, n_pack);
+  const size_t dig = GB * N * k->kc.ell * N * 8;
+  const size_t part = GB * (N / 64) * ctx->rc.P * 2 * N * 8;
+  return align_up(dig, 256) + part;
+}
+}  // namespace
+
+extern "C" {
+
+int rlwe_ksk_load(rlwe_ctx* ctx, const uint64_t* ksk_dev, uint32_t log2_base, uint32_t levels,
+                  rlwe_stream_t stream, rlwe_ksk** out) {
+  if (!ctx || !ksk_dev || !out) return fail(RLWE_EINVAL, "rlwe_ksk_load: null argument");
+  *out = nullptr;
+  const RingConst& rc = ctx->rc;
+  if (!ctx->ntt_ok) return fail(RLWE_EPARAM, "KeySwitch packing needs N = %u", kNttN);
+  if (levels < 1 || levels > kMaxLevels)
+    return fail(RLWE_EPARAM, "levels = %u outside [1, %u]", levels, kMaxLevels);
+  if (log2_base < 1 || log2_base * levels > 64)
+    return fail(RLWE_EPARAM, "log2_base = %u: need 1 <= log2_base and log2_base * levels <= 64", log2_base);
+  for (uint32_t r = 0; r < rc.P; ++r)
+    if (log2_base > 54 || (1ull << (log2_base - 1)) >= rc.q[r])
+      return fail(RLWE_EPARAM, "digits of %u bits do not lie below prime %llu", log2_base,
+                  (unsigned long long)rc.q[r]);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  rlwe_ksk* k = new (std::nothrow) rlwe_ksk;
+  if (!k) return fail(RLWE_ENOMEM, "out of host memory");
+  k->ctx = ctx;
+  KsConst& kc = k->kc;
+  kc.beta = log2_base;
+  kc.ell = levels;
+  kc.K = log2_base * levels;
+  kc.kmask = kc.K == 64 ? ~0ull : (1ull << kc.K) - 1;
+  kc.H = 0;
+  for (uint32_t m = 0; m < levels; ++m) kc.H += (1ull << (log2_base - 1)) << (log2_base * m);
+  for (uint32_t r = 0; r < rc.P; ++r) {
+    const u128 two_k = (u128)1 << kc.K, q = rc.q[r];
+    kc.f[r] = (uint64_t)(two_k / q);  // mod 2^64 (exact unless K = 64 and q = 1)
+    kc.g[r] = (uint64_t)(two_k % q);
+    kc.g_shoup[r] = (uint64_t)(((u128)kc.g[r] << 64) / q);
+  }
+  const size_t N = rc.N;
+  const size_t bytes = N * levels * rc.P * 2 * N * 8;
+  e = hipMalloc(&k->khat, bytes);
+  if (e != hipSuccess) {
+    delete k;
+    return fail(RLWE_ENOMEM, "hipMalloc(key, %zu bytes): %s", bytes, hipGetErrorString(e));
+  }
+  KsArgs a = ks_args_base(ctx);
+  a.kc = kc;
+  a.ksk_in = ksk_dev;
+  a.khat_out = k->khat;
+  hipStream_t s = (hipStream_t)stream;
+  e = launch_ksk_fwd(a, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    hipFree(k->khat);
+    delete k;
+    return hip_fail(e, "key transform");
+  }
+  *out = k;
+  return ok();
+}
+
+int rlwe_ksk_free(rlwe_ksk* k) {
+  if (!k) return ok();
+  hipSetDevice(k->ctx->device);
+  if (k->khat) hipFree(k->khat);
+  delete k;
+  return ok();
+}
+
+size_t rlwe_keyswitch_workspace_bytes(const rlwe_ctx* ctx, const rlwe_ksk* k, size_t count,
+                                      uint32_t n_pack) {
+  if (!ctx || !k || count == 0 || n_pack < 1 || n_pack > ctx->rc.N) return 0;
+  return ks_ws_bytes(ctx, k, count, n_pack);
+}
+
+size_t rlwe_packed_count(size_t count, uint32_t n_pack) {
+  return n_pack ? (count + n_pack - 1) / n_pack : 0;
+}
+
+int ct_keyswitch_pack(rlwe_ctx* ctx, const rlwe_ksk* k, const uint64_t* lwe_in, size_t count,
+                      uint32_t n_pack, void* out, uint32_t flags, rlwe_stream_t stream) {
+  if (!ctx || !k) return fail(RLWE_EINVAL, "ct_keyswitch_pack: null context or key");
+  if (k->ctx != ctx) return fail(RLWE_EINVAL, "ct_keyswitch_pack: key of another context");
+  if (flags & ~RLWE_OUT_RAW_Q) return fail(RLWE_EINVAL, "ct_keyswitch_pack: unknown flags 0x%x", flags);
+  if (n_pack < 1 || n_pack > ctx->rc.N)
+    return fail(RLWE_ESHAPE, "n_pack = %u outside [1, N]", n_pack);
+  if (count == 0) return ok();
+  if (!lwe_in || !out) return fail(RLWE_EINVAL, "ct_keyswitch_pack: null buffer");
+  const size_t G = (count + n_pack - 1) / n_pack;
+  if (G >= (1ull << 31)) return fail(RLWE_ESHAPE, "ct_keyswitch_pack: %zu ciphertexts too many", count);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  const size_t need = ks_ws_bytes(ctx, k, count, n_pack);
+  if (need > ctx->ws_bytes) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+      return fail(RLWE_EINVAL, "workspace must be reserved (rlwe_workspace_reserve) before capture");
+    const int r = ensure_ws(ctx, need, s);
+    if (r != RLWE_OK) return r;
+  }
+  const uint32_t GBmax = ks_pass_groups(count, n_pack);
+  KsArgs a = ks_args_base(ctx);
+  a.kc = k->kc;
+  a.lwe = lwe_in;
+  a.M = count;
+  a.n_pack = n_pack;
+  a.raw = (flags & RLWE_OUT_RAW_Q) ? 1 : 0;
+  a.khat = k->khat;
+  a.dig = (int64_t*)ctx->ws;
+  a.part = (uint64_t*)((unsigned char*)ctx->ws +
+                       align_up((size_t)GBmax * ctx->rc.N * k->kc.ell * ctx->rc.N * 8, 256));
+  a.out = out;
+  for (size_t g0 = 0; g0 < G; g0 += GBmax) {
+    a.g0 = (uint32_t)g0;
+    a.GB = (uint32_t)std::min<size_t>(GBmax, G - g0);
+    e = timed(ctx, K_KSDIG, s, [&] { return launch_ks_digits(a, s); });
+    if (e != hipSuccess) return hip_fail(e, "KeySwitch digits kernel");
+    e = timed(ctx, K_KSACC, s, [&] { return launch_ks_accum(a, s); });
+    if (e != hipSuccess) return hip_fail(e, "KeySwitch accumulate kernel");
+    e = timed(ctx, K_KSFIN, s, [&] { return launch_ks_finish(a, s); });
+    if (e != hipSuccess) return hip_fail(e, "KeySwitch finish kernel");
+  }
   return ok();
 }
 

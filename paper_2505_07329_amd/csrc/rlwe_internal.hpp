@@ -208,6 +208,35 @@ struct Batch {
   Item it[kMaxBatch];
 };
 
+// KeySwitch packing (Sec. 3.2 KeySwitching, Eq. (pack_rotate)); N = kNttN only.
+constexpr uint32_t kMaxLevels = 4;   // gadget levels ell
+constexpr uint32_t kKsGroups = 64;   // packed outputs per pass of the kernels
+struct KsConst {
+  uint32_t beta, ell, K;             // digit bits, levels, K = beta ell rounding bits (<= 64)
+  uint64_t kmask;                    // 2^K - 1
+  uint64_t H;                        // sum_m 2^(beta-1) 2^(beta m) mod 2^64
+  uint64_t f[kMaxPrimes];            // floor(2^K / q_p) mod 2^64
+  uint64_t g[kMaxPrimes];            // 2^K mod q_p
+  uint64_t g_shoup[kMaxPrimes];      // floor(g 2^64 / q_p)
+};
+// Arguments of the KeySwitch kernels (read in place through the kernarg segment).
+struct KsArgs {
+  RingConst rc;
+  NttConst ntt;
+  KsConst kc;
+  const uint64_t* lwe;   // [M][P][N+1] LWE ciphertexts, residues
+  uint64_t M;
+  uint32_t n_pack;       // slots filled per packed output
+  uint32_t g0, GB;       // first output group of this pass, groups in the pass
+  uint32_t raw;          // outputs modulo q per prime (else switched to 2^qbits)
+  int64_t* dig;          // workspace: digits [GB][N][ell][N]
+  const uint64_t* khat;  // key in the NTT domain [N][ell][P][2][N]
+  uint64_t* part;        // workspace: partial sums [GB][N / 64][P][2][N]
+  void* out;             // [G][2][P][N] u64 or [G][2][N] u32
+  const uint64_t* ksk_in;  // key load: [N][ell][2][P][N] canonical residues
+  uint64_t* khat_out;      // key load: destination of the transformed key
+};
+
 // Kernels take the Batch as their only argument and read it in place through the
 // kernarg segment pointer (constant address space, uniform scalar loads); indexing
 // the by-value parameter directly would make every thread copy it to scratch.
@@ -257,6 +286,10 @@ hipError_t launch_modswitch(const RingConst& rc, const uint64_t* in, size_t coun
 hipError_t launch_transpose_pad(const int8_t* src, uint32_t rows, uint32_t cols, bool transpose,
                                 int8_t* dst, uint32_t dst_rows_pad, uint32_t dst_kw,
                                 hipStream_t s);
+hipError_t launch_ksk_fwd(const KsArgs& a, hipStream_t s);
+hipError_t launch_ks_digits(const KsArgs& a, hipStream_t s);
+hipError_t launch_ks_accum(const KsArgs& a, hipStream_t s);
+hipError_t launch_ks_finish(const KsArgs& a, hipStream_t s);
 hipError_t launch_row_l1(const int8_t* w, uint32_t rows, uint32_t kw, uint32_t* out,
                          hipStream_t s);
 

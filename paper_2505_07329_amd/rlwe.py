@@ -39,7 +39,9 @@ EXPORTS = ("rlwe_params_init", "rlwe_params_destroy", "rlwe_weights_load", "rlwe
            "rlwe_profile_begin", "rlwe_profile_end", "rlwe_weights_digits", "ct_matmul_batch",
            "rlwe_batch_workspace_bytes", "rlwe_graph_capture_batch", "rlwe_graph_launch",
            "rlwe_graph_destroy", "rlwe_weights_method", "ct_pack_bits", "rlwe_packed_words",
-           "rlwe_weights_rows_per_product", "rlwe_last_error")
+           "rlwe_weights_rows_per_product", "rlwe_ksk_load", "rlwe_ksk_free",
+           "rlwe_packed_count", "rlwe_keyswitch_workspace_bytes", "ct_keyswitch_pack",
+           "rlwe_last_error")
 
 
 class RlweError(RuntimeError):
@@ -55,7 +57,10 @@ class KernelTimes(ctypes.Structure):
                 ("prep_n", ctypes.c_uint32), ("mask_n", ctypes.c_uint32),
                 ("body_n", ctypes.c_uint32), ("modswitch_n", ctypes.c_uint32),
                 ("ntt_n", ctypes.c_uint32), ("pack_n", ctypes.c_uint32),
-                ("dropped", ctypes.c_uint32)]
+                ("dropped", ctypes.c_uint32),
+                ("ksdig_ms", ctypes.c_double), ("ksacc_ms", ctypes.c_double),
+                ("ksfin_ms", ctypes.c_double), ("ksdig_n", ctypes.c_uint32),
+                ("ksacc_n", ctypes.c_uint32), ("ksfin_n", ctypes.c_uint32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -112,11 +117,20 @@ def lib() -> ctypes.CDLL:
                                            ctypes.c_uint32, ctypes.POINTER(vp)]
     L.rlwe_graph_launch.argtypes = [vp, vp]
     L.rlwe_graph_destroy.argtypes = [vp]
+    L.rlwe_ksk_load.argtypes = [vp, vp, ctypes.c_uint32, ctypes.c_uint32, vp, ctypes.POINTER(vp)]
+    L.rlwe_ksk_free.argtypes = [vp]
+    L.rlwe_packed_count.argtypes = [ctypes.c_size_t, ctypes.c_uint32]
+    L.rlwe_packed_count.restype = ctypes.c_size_t
+    L.rlwe_keyswitch_workspace_bytes.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_uint32]
+    L.rlwe_keyswitch_workspace_bytes.restype = ctypes.c_size_t
+    L.ct_keyswitch_pack.argtypes = [vp, vp, vp, ctypes.c_size_t, ctypes.c_uint32, vp,
+                                    ctypes.c_uint32, vp]
     L.rlwe_last_error.argtypes = []
     L.rlwe_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name not in ("rlwe_last_error", "rlwe_workspace_bytes", "rlwe_batch_workspace_bytes",
-                        "rlwe_packed_words"):
+                        "rlwe_packed_words", "rlwe_packed_count",
+                        "rlwe_keyswitch_workspace_bytes"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -252,6 +266,33 @@ def rlwe_graph_destroy(graph: int) -> None:
     _check(lib().rlwe_graph_destroy(graph))
 
 
+def rlwe_ksk_load(ctx: int, ksk, log2_base: int, levels: int, stream=None) -> int:
+    """ksk: int64 CUDA tensor [N][levels][2][P][N] (uint64 residues of KSK_{i,m})."""
+    h = ctypes.c_void_p()
+    _check(lib().rlwe_ksk_load(ctx, _ptr(ksk), log2_base, levels, _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def rlwe_ksk_free(k: int) -> None:
+    _check(lib().rlwe_ksk_free(k))
+
+
+def rlwe_packed_count(count: int, n_pack: int) -> int:
+    return int(lib().rlwe_packed_count(count, n_pack))
+
+
+def rlwe_keyswitch_workspace_bytes(ctx: int, k: int, count: int, n_pack: int) -> int:
+    return int(lib().rlwe_keyswitch_workspace_bytes(ctx, k, count, n_pack))
+
+
+def ct_keyswitch_pack(ctx: int, k: int, lwe, count: int, n_pack: int, out,
+                      flags: int = RLWE_OUT_SWITCHED, stream=None) -> None:
+    """lwe: int64 [count][P][N+1] raw LWE ciphertexts; out: int32 [G][2][N] (switched) or
+    int64 [G][2][P][N] (RLWE_OUT_RAW_Q), G = rlwe_packed_count(count, n_pack)."""
+    _check(lib().ct_keyswitch_pack(ctx, k, _ptr(lwe), count, n_pack, _ptr(out), flags,
+                                   _stream(stream)))
+
+
 def rlwe_profile_begin(ctx: int) -> None:
     _check(lib().rlwe_profile_begin(ctx))
 
@@ -340,4 +381,34 @@ def modswitch(ctx: Context, raw, out=None, stream=None):
     if out is None:
         out = torch.empty(raw.shape[:-2] + (ctx.N + 1,), dtype=torch.int32, device=raw.device)
     ct_modswitch(ctx.handle, raw, count, out, stream)
+    return out
+
+
+class KeySwitchKey:
+    """Owns an rlwe_ksk handle: the key-switching key made resident in the NTT domain."""
+
+    def __init__(self, ctx: Context, ksk, log2_base: int, levels: int, stream=None):
+        self.ctx = ctx
+        self.log2_base, self.levels = log2_base, levels
+        self.handle = rlwe_ksk_load(ctx.handle, ksk, log2_base, levels, stream)
+
+    def close(self) -> None:
+        if self.handle:
+            rlwe_ksk_free(self.handle)
+            self.handle = 0
+
+
+def keyswitch_pack(ctx: Context, k: KeySwitchKey, lwe, n_pack: int | None = None,
+                   raw: bool = False, out=None, stream=None):
+    """Pack raw LWE ciphertexts (..., P, N+1) int64 into RLWE ciphertexts (torch): (G, 2, N)
+    int32 switched, or (G, 2, P, N) int64 with raw=True."""
+    import torch
+    n_pack = ctx.N if n_pack is None else int(n_pack)
+    count = lwe.numel() // (ctx.P * (ctx.N + 1))
+    G = rlwe_packed_count(count, n_pack)
+    if out is None:
+        shape = (G, 2, ctx.P, ctx.N) if raw else (G, 2, ctx.N)
+        out = torch.empty(shape, dtype=torch.int64 if raw else torch.int32, device=lwe.device)
+    ct_keyswitch_pack(ctx.handle, k.handle, lwe, count, n_pack, out,
+                      RLWE_OUT_RAW_Q if raw else RLWE_OUT_SWITCHED, stream)
     return out

@@ -74,3 +74,14 @@ def test_null_arguments_rejected():
     assert L.rlwe_params_destroy(None) == 0
     assert L.rlwe_weights_free(None) == 0
     assert b"null" in L.rlwe_last_error() or L.rlwe_last_error() == b""
+
+
+def test_keyswitch_entry_points_reject_null_arguments():
+    L = rlwe.lib()
+    assert L.rlwe_ksk_load(None, None, 54, 1, None, None) == -1
+    assert L.ct_keyswitch_pack(None, None, None, 0, 1, None, 0, None) == -1
+    assert L.rlwe_ksk_free(None) == 0
+    assert L.rlwe_keyswitch_workspace_bytes(None, None, 1, 1) == 0
+    assert L.rlwe_packed_count(10, 4) == 3
+    assert L.rlwe_packed_count(8192, 4096) == 2
+    assert L.rlwe_packed_count(10, 0) == 0

@@ -1,0 +1,179 @@
+"""KeySwitch packing on the GPU (Sec. 3.2 KeySwitching and Rotate, Eq. (pack_rotate))
+against the oracle, bit for bit, through the C ABI.
+
+Covered: two primes with one gadget level (54-bit digits) and with 2 and 4 levels,
+one prime with three 12-bit levels, raw and switched outputs (2^32 and 2^26), ragged
+last groups and n_pack below N, two calls in a row with different shapes, the
+full attention shape (262144 LWE ciphertexts of the 2048 x 2048, 128-token product
+into 64 packed ciphertexts) on sampled groups, and end-to-end decryption of packed
+real products computed on the GPU.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2505_07329_amd import synth
+from tests.cases import make_case
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N = 4096
+P2 = synth.PRIMES_4096
+P1 = synth.PRIMES_4096[:1]
+
+
+def rl():
+    from paper_2505_07329_amd import rlwe
+    return rlwe
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a.view(np.int64) if a.dtype == np.uint64 else a)).cuda()
+
+
+def host_u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def uniform(primes, lead, n, salt):
+    return synth.uniform_mod_primes(synth.rng(0, synth.P_MISC, 300 + salt), primes, lead, n)
+
+
+def random_key(primes, ell, salt):
+    """Uniform residues in the key layout [N][ell][2][P][N] (parity does not need a real key)."""
+    return uniform(primes, (N, ell, 2), N, salt)
+
+
+@pytest.mark.parametrize("primes,beta,ell,M,n_pack", [
+    (P2, 54, 1, N + 300, N),
+    (P2, 27, 2, 700, 500),
+    (P2, 16, 4, 300, N),
+    (P1, 12, 3, 1000, 700),
+])
+def test_pack_matches_oracle(primes, beta, ell, M, n_pack):
+    print(f"case: keyswitch P={len(primes)} beta={beta} ell={ell} M={M} n_pack={n_pack}", flush=True)
+    r = rl()
+    lwe = uniform(primes, (M,), N + 1, M)
+    ksk = random_key(primes, ell, beta)
+    want = orc.keyswitch_pack(N, primes, beta, ell, lwe, ksk, n_pack)
+    G = want.shape[0]
+    with r.Context(N, primes, 26, log2_q_out=32) as ctx:
+        k = r.KeySwitchKey(ctx, dev(ksk), beta, ell)
+        got = r.keyswitch_pack(ctx, k, dev(lwe), n_pack, raw=True)
+        sw = r.keyswitch_pack(ctx, k, dev(lwe), n_pack)
+        torch.cuda.synchronize()
+        assert got.shape == (G, 2, len(primes), N)
+        g = host_u64(got)
+        assert np.array_equal(g, want), f"{int((g != want).sum())} residues differ"
+        s = sw.cpu().numpy().view(np.uint32)
+        assert np.array_equal(s, orc.rlwe_modswitch_bits(primes, want, 32))
+        k.close()
+    with r.Context(N, primes, 26, log2_q_out=26) as ctx:
+        k = r.KeySwitchKey(ctx, dev(ksk), beta, ell)
+        sw = r.keyswitch_pack(ctx, k, dev(lwe), n_pack)
+        torch.cuda.synchronize()
+        assert np.array_equal(sw.cpu().numpy().view(np.uint32),
+                              orc.rlwe_modswitch_bits(primes, want, 26))
+        k.close()
+
+
+def test_calls_in_a_row_and_edge_cases():
+    """A larger call, then a smaller one, on one context and key; count = 0 is a no-op;
+    invalid shapes and gadgets are refused."""
+    print("case: keyswitch calls in a row, edge cases", flush=True)
+    r = rl()
+    ksk = random_key(P2, 1, 7)
+    a = uniform(P2, (N + 5,), N + 1, 11)
+    b = uniform(P2, (3,), N + 1, 12)
+    with r.Context(N, P2, 26) as ctx:
+        k = r.KeySwitchKey(ctx, dev(ksk), 54, 1)
+        ga = r.keyswitch_pack(ctx, k, dev(a), raw=True)
+        gb = r.keyswitch_pack(ctx, k, dev(b), raw=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(host_u64(ga), orc.keyswitch_pack(N, P2, 54, 1, a, ksk))
+        assert np.array_equal(host_u64(gb), orc.keyswitch_pack(N, P2, 54, 1, b, ksk))
+        dummy = torch.zeros(1, dtype=torch.int64, device="cuda")
+        r.ct_keyswitch_pack(ctx.handle, k.handle, dummy, 0, N, dummy)  # no-op
+        for n_pack in (0, N + 1):
+            with pytest.raises(r.RlweError) as ei:
+                r.ct_keyswitch_pack(ctx.handle, k.handle, dummy, 1, n_pack, dummy)
+            assert ei.value.code == r.RLWE_ESHAPE
+        for beta, ell in ((55, 1), (20, 5), (33, 2), (0, 1)):
+            with pytest.raises(r.RlweError) as ei:
+                r.KeySwitchKey(ctx, dev(ksk), beta, ell)
+            assert ei.value.code == r.RLWE_EPARAM
+        k.close()
+    with r.Context(2048, synth.PRIMES_2048, 24) as ctx:
+        with pytest.raises(r.RlweError) as ei:
+            r.KeySwitchKey(ctx, dev(ksk[:1]), 12, 3)
+        assert ei.value.code == r.RLWE_EPARAM
+
+
+def test_attention_shape_sampled_groups():
+    """The launch configuration of the benchmark: 128 tokens x 2048 outputs = 262144 LWE
+    ciphertexts into 64 packed ciphertexts (n_pack = N); groups 0 and 63 against the
+    oracle, and the switched output of every group against the raw one."""
+    print("case: keyswitch attention shape, M=262144, sampled groups", flush=True)
+    r = rl()
+    T, d_out = 128, 2048
+    M = T * d_out
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(synth.SEED_BASE + 2000 + 77)
+    lwe = torch.empty((M, 2, N + 1), dtype=torch.int64, device="cuda")
+    for p, q in enumerate(P2):
+        lwe[:, p].random_(0, q, generator=gen)
+    ksk = random_key(P2, 1, 13)
+    with r.Context(N, P2, 26) as ctx:
+        k = r.KeySwitchKey(ctx, dev(ksk), 54, 1)
+        raw = r.keyswitch_pack(ctx, k, lwe, N, raw=True)
+        sw = r.keyswitch_pack(ctx, k, lwe, N)
+        torch.cuda.synchronize()
+        assert raw.shape == (64, 2, 2, N)
+        for g in (0, 63):
+            part = host_u64(lwe[g * N:(g + 1) * N])
+            want = orc.keyswitch_pack(N, P2, 54, 1, part, ksk)
+            assert np.array_equal(host_u64(raw[g:g + 1]), want), f"group {g}"
+        rr = host_u64(raw)
+        assert np.array_equal(sw.cpu().numpy().view(np.uint32), orc.rlwe_modswitch_bits(P2, rr, 32))
+        k.close()
+    del lwe, raw, sw
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("method", ["ntt", "toeplitz"])
+def test_packed_gpu_products_decrypt(method):
+    """Product on the GPU (raw outputs), then packing on the GPU with a real key: every
+    slot decrypts under the packing key to W x, the empty slots to 0, and the packed
+    ciphertexts equal the oracle's packing of the same LWE ciphertexts."""
+    print(f"case: keyswitch end to end, {method}", flush=True)
+    r = rl()
+    d_in, d_out, T, log2_t = 2048, 1500, 2, 26
+    case = make_case(N, P2, log2_t, d_out, d_in, T, config=2, salt=31)
+    g_a = synth.rng(2, synth.P_MASK, 40)
+    g_s = synth.rng(2, synth.P_SECRET, 40)
+    g_e = synth.rng(2, synth.P_ERROR, 40)
+    A = synth.uniform_mod_primes(g_a, P2, (N, 1), N)
+    E = synth.rounded_gaussian(g_e, (N, 1, N))
+    S_dst = synth.ternary(g_s, N)
+    ksk = orc.ksk_gen(N, P2, 54, 1, case.S, S_dst, A, E)
+    flag = r.RLWE_W_NTT if method == "ntt" else r.RLWE_W_TOEPLITZ
+    with r.Context(N, P2, log2_t) as ctx:
+        w = r.Weights(ctx, dev(case.W), r.RLWE_W_FWD | flag)
+        lwe = r.matmul(ctx, w, dev(case.ct), raw=True)  # (T, d_out, P, N+1)
+        k = r.KeySwitchKey(ctx, dev(ksk), 54, 1)
+        packed = r.keyswitch_pack(ctx, k, lwe, d_out, raw=True)  # one token per ciphertext
+        torch.cuda.synchronize()
+        lw = host_u64(lwe)
+        pk = host_u64(packed)
+        w.close()
+        k.close()
+    assert np.array_equal(lw, orc.matmul_clear(N, P2, case.W, case.ct))
+    assert np.array_equal(pk, orc.keyswitch_pack(N, P2, 54, 1, lw.reshape(-1, 2, N + 1), ksk, d_out))
+    y = case.x.astype(np.int64) @ case.W.astype(np.int64).T
+    ph = orc.rlwe_decrypt_slots(N, P2, S_dst, pk)
+    for t in range(T):
+        dec = [orc.decode(v, case.delta) for v in ph[t]]
+        assert dec[:d_out] == [int(v) for v in y[t]]
+        assert all(v == 0 for v in dec[d_out:])
