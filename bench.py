@@ -92,11 +92,48 @@ def roofline(products, kt, N, P, traffic=None):
 # (--copy-calibration). Valid for the kernel source it was taken on (sha256); for any
 # other source the roofline reports traffic as null.
 KERNEL_TRAFFIC = {
-    "mask": {"source": "k_mask.hip", "fetch_bytes": 4382392135, "write_bytes": 4766662645,
+    "mask": {"sources": ["k_mask.hip"], "fetch_bytes": 4382392135, "write_bytes": 4766662645,
              "sha256": "b71d09264e517098c1179f16657d1e4fa62f1eaae851294a6d0fdb5115986154"},
-    "ntt": {"source": "k_ntt.hip", "fetch_bytes": 5067261677, "write_bytes": 4365784442,
+    "ntt": {"sources": ["k_ntt.hip", "ntt_device.hpp"], "fetch_bytes": 5067261677,
+            "write_bytes": 4365784442,
             "sha256": "e251e3a5e2d22e750b5e4fd1bb6d2335346f7d096c8a45e3df630253c67ce817"},
 }
+
+
+def keyswitch_roofline(M, N, P, ell, acc_s):
+    """Roofline of the KeySwitch accumulate kernel for M LWE ciphertexts packed N per RLWE
+    ciphertext: per packed ciphertext, key coefficient, level and prime one forward
+    transform ((N/2) log2 N butterflies) and 2 N pointwise products (mask and body of the
+    key), each counted as one butterfly."""
+    import math
+    G = -(-M // N)
+    work = G * N * ell * P * ((N // 2) * math.log2(N) + 2 * N)
+    a = work / acc_s / 1e9
+    return {"bound": "alu", "achieved": a, "peak": NTT_PEAK_GBFLY,
+            "unit": "G butterfly/s (54-bit lazy Shoup, KeySwitch transforms)",
+            "frac": a / NTT_PEAK_GBFLY, "traffic": None}
+
+
+def keyswitch_cpu_baseline(prod, N, primes, d_in, beta, ell):
+    """Oracle rate of the whole path: the product rate measured by cpu_baseline and the
+    oracle's packing (digits, NTT-form KeySwitch, Rotate) timed on one packed ciphertext
+    of N uniform LWE ciphertexts; combined per encrypted MAC."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    from paper_2505_07329_amd import synth
+    g = synth.rng(2, synth.P_MISC, 5)
+    lwe = synth.uniform_mod_primes(g, primes, (N,), N + 1)
+    ksk = synth.uniform_mod_primes(g, primes, (N, ell, 2), N)
+    t0 = time.perf_counter()
+    orc.keyswitch_pack(N, primes, beta, ell, lwe, ksk, N)
+    el = time.perf_counter() - t0
+    pack_rate = N * d_in / el  # MAC/s of the outputs packed per second
+    value = 1.0 / (1.0 / prod["value"] + 1.0 / pack_rate)
+    return {"value": value, "unit": "encrypted MAC/s", "cores": prod["cores"], "kind": "oracle",
+            "sample": prod["sample"] + f"; plus the oracle's packing of {N} LWE ciphertexts "
+                      f"into one RLWE ciphertext ({el:.1f} s, {N * d_in / el:.3g} MAC/s of outputs "
+                      "packed); rates combined per MAC"}
 
 
 def kernel_traffic(kind):
@@ -104,11 +141,27 @@ def kernel_traffic(kind):
     rec = KERNEL_TRAFFIC.get(kind)
     if not rec:
         return None
-    src = os.path.join(ROOT, "paper_2505_07329_amd", "csrc", rec["source"])
-    with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
-            return None
+    h = hashlib.sha256()
+    for name in rec["sources"]:
+        with open(os.path.join(ROOT, "paper_2505_07329_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sha256"]:
+        return None
     return rec["fetch_bytes"] + rec["write_bytes"]
+
+
+def source_sha256(kind):
+    """sha256 of the sources a traffic record is tied to (printed by --print-hashes)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES[kind]:
+        with open(os.path.join(ROOT, "paper_2505_07329_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+KERNEL_SOURCES = {"mask": ["k_mask.hip"], "ntt": ["k_ntt.hip", "ntt_device.hpp"],
+                  "ksacc": ["k_keyswitch.hip", "ntt_device.hpp"]}
 
 
 def parse():
@@ -131,9 +184,16 @@ def parse():
     ap.add_argument("--pack", action="store_true",
                     help="attn: every step also bit-packs the switched outputs (ct_pack_bits), "
                          "reported with its own HBM roofline")
+    ap.add_argument("--keyswitch", action="store_true",
+                    help="attn: pack the outputs into RLWE ciphertexts (KeySwitch and Rotate, "
+                         "Eq. (pack_rotate)), N per ciphertext, switched to 2^q-out-bits")
+    ap.add_argument("--ks-base-bits", type=int, default=54, help="KeySwitch: digit bits")
+    ap.add_argument("--ks-levels", type=int, default=1, help="KeySwitch: gadget levels")
     ap.add_argument("--rowpack", action="store_true",
                     help="load every weight matrix with RLWE_W_ROWPACK (floor(N / K) rows per "
                          "weight polynomial where the contraction length K <= N/2; NTT method)")
+    ap.add_argument("--print-hashes", action="store_true",
+                    help="print the sha256 of each kernel's sources and exit")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="attn: before the timed region, run one plain elementwise copy kernel "
                          "(int32 bitwise not) reading and writing GIB GiB each, as the known-size "
@@ -581,6 +641,9 @@ def serve_cpu_baseline(reqs, N, primes, target_s):
 
 def main():
     args = parse()
+    if args.print_hashes:
+        print(json.dumps({k: source_sha256(k) for k in KERNEL_SOURCES}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the encrypted product shards by tokens or output "
               "rows with no exchange, and it is measured on one MI355X; use --gpus 1.",
@@ -621,14 +684,42 @@ def main():
     w = rlwe.Weights(ctx, torch.from_numpy(W).to(dev), rlwe.RLWE_W_FWD | method_flag(args))
     ct = torch.from_numpy(in_np.view(np.int64)).to(dev)
     in_flags = rlwe.RLWE_IN_SEEDED if args.seeded else 0
-    out = torch.empty((T, d_out, N + 1), dtype=torch.int32, device=dev)
-    words = rlwe.rlwe_packed_words(N + 1, qbits)
-    packed = torch.empty((T, d_out, words), dtype=torch.int32, device=dev) if args.pack else None
-    rlwe.rlwe_workspace_reserve(ctx.handle, rlwe.rlwe_workspace_bytes(ctx.handle, w.handle, False, T))
+    P = len(primes)
+    ks = args.keyswitch
+    if ks:  # raw LWE outputs, packed N per RLWE ciphertext, switched
+        out = torch.empty((T, d_out, P, N + 1), dtype=torch.int64, device=dev)
+        G = rlwe.rlwe_packed_count(T * d_out, N)
+        rlwe_out = torch.empty((G, 2, N), dtype=torch.int32, device=dev)
+        # a key of uniform residues: the kernels are data-oblivious (the tests use real keys)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(synth.SEED_BASE + 2000 + synth.P_MISC)
+        ksk_t = torch.empty((N, args.ks_levels, 2, P, N), dtype=torch.int64, device=dev)
+        for p_, q_ in enumerate(primes):
+            ksk_t[:, :, :, p_].random_(0, q_, generator=gen)
+        key = rlwe.KeySwitchKey(ctx, ksk_t, args.ks_base_bits, args.ks_levels)
+        del ksk_t
+        words = rlwe.rlwe_packed_words(N, qbits)
+        packed = torch.empty((G, 2, words), dtype=torch.int32, device=dev) if args.pack else None
+    else:
+        out = torch.empty((T, d_out, N + 1), dtype=torch.int32, device=dev)
+        words = rlwe.rlwe_packed_words(N + 1, qbits)
+        packed = torch.empty((T, d_out, words), dtype=torch.int32, device=dev) if args.pack else None
+    ws = rlwe.rlwe_workspace_bytes(ctx.handle, w.handle, False, T)
+    if ks:
+        ws = max(ws, rlwe.rlwe_keyswitch_workspace_bytes(ctx.handle, key.handle, T * d_out, N))
+    rlwe.rlwe_workspace_reserve(ctx.handle, ws)
     kept, total = rlwe.rlwe_weights_digits(w.handle)
     stream = torch.cuda.current_stream()
 
     def step():
+        if ks:
+            rlwe.ct_matmul_clear(ctx.handle, w.handle, ct, T, out, False,
+                                 rlwe.RLWE_OUT_RAW_Q | in_flags, stream)
+            rlwe.ct_keyswitch_pack(ctx.handle, key.handle, out, T * d_out, N, rlwe_out,
+                                   rlwe.RLWE_OUT_SWITCHED, stream)
+            if args.pack:
+                rlwe.ct_pack_bits(ctx.handle, rlwe_out, G * 2, N, packed, stream)
+            return
         rlwe.ct_matmul_clear(ctx.handle, w.handle, ct, T, out, False,
                              rlwe.RLWE_OUT_SWITCHED | in_flags, stream)
         if args.pack:
@@ -667,17 +758,30 @@ def main():
     n_o = rlwe.rlwe_weights_rows_per_product(w.handle)
     roof, _ = roofline([dict(T=T, M=d_out, K=d_in, kept=kept, ntt=is_ntt, n_o=n_o)], one, N,
                        len(primes),
-                       traffic={"mfma": kernel_traffic("mask"),
-                                "alu": kernel_traffic("ntt") if n_o == 1 else None})
+                       traffic={"mfma": None if ks else kernel_traffic("mask"),
+                                "alu": kernel_traffic("ntt") if n_o == 1 and not ks else None})
+    ks_roof = None
+    if ks and kt["ksacc_n"]:
+        ks_ms = {k: kt[f"ks{k}_ms"] / max(1, kt[f"ks{k}_n"]) * kt[f"ks{k}_n"] / args.steps
+                 for k in ("dig", "acc", "fin")}  # per step (a step may hold several passes)
+        ks_roof = keyswitch_roofline(T * d_out, N, P, args.ks_levels, ks_ms["acc"] * 1e-3)
+        ks_roof["traffic"] = kernel_traffic("ksacc")
+        ks_roof["digits_hbm_gbs"] = (T * d_out * (P * 8 * (N + 1) + args.ks_levels * 8 * N)
+                                     / (ks_ms["dig"] * 1e-3) / 1e9)
     pack_roof = None
     if args.pack and kt["pack_n"]:
         pack_ms = kt["pack_ms"] / kt["pack_n"]
-        moved = T * d_out * 4 * ((N + 1) + words)  # switched words read once, packed words written
+        n_ct, ln = (G * 2, N) if ks else (T * d_out, N + 1)
+        moved = n_ct * 4 * (ln + words)  # switched words read once, packed words written
         gbs = moved / (pack_ms * 1e-3) / 1e9
         pack_roof = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
                      "frac": gbs / 8000.0, "traffic": None, "ms": pack_ms,
                      "bytes_out_per_lwe": 4 * words}
+        if ks:
+            pack_roof["bytes_out_per_rlwe"] = pack_roof.pop("bytes_out_per_lwe") * 2
     switched = f"switched to 2^{qbits}" + (" and bit-packed" if args.pack else "")
+    if ks:
+        switched = (f"packed {N} per RLWE ciphertext (KeySwitch + Rotate), " + switched)
     result = {
         "metric": f"encrypted MACs/s (d_in*d_out*tokens/s), W.[x]_HE with outputs {switched}",
         "value": value,
@@ -696,7 +800,10 @@ def main():
                    "packed": bool(args.pack), "seeded_input": bool(args.seeded),
                    "input_bytes": int(in_np.nbytes),
                    "method": "ntt" if is_ntt else "toeplitz", "rows_per_product": n_o,
-                   "digits_on_matrix_cores": None if is_ntt else f"{kept}/{total}"},
+                   "digits_on_matrix_cores": None if is_ntt else f"{kept}/{total}",
+                   "keyswitch": ({"n_pack": N, "log2_base": args.ks_base_bits,
+                                  "levels": args.ks_levels, "packed_ciphertexts": G}
+                                 if ks else None)},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "kernels_ms": {"prep": per_launch["prep_ms"], "mask": per_launch["mask_ms"],
                        "ntt": per_launch["ntt_ms"], "body": per_launch["body_ms"]},
@@ -706,11 +813,23 @@ def main():
     if pack_roof:
         result["kernels_ms"]["pack"] = pack_roof.pop("ms")
         result["roofline_pack"] = pack_roof
+    if ks_roof:
+        result["kernels_ms"].update({"ks_digits": ks_ms["dig"], "ks_accum": ks_ms["acc"],
+                                     "ks_finish": ks_ms["fin"]})
+        # the dominant kernel of the step carries the headline roofline
+        if roof is None or ks_ms["acc"] > max(per_launch["ntt_ms"], per_launch["mask_ms"]):
+            result["roofline"], result["roofline_product"] = ks_roof, roof
+        else:
+            result["roofline_keyswitch"] = ks_roof
+        key.close()
     w.close()
     ctx.close()
     if args.cpu_seconds > 0:
-        result["cpu_baseline"] = cpu_baseline(W, ct_np, N, primes, T, d_out, d_in, args.cpu_seconds,
-                                              n_o)
+        result["cpu_baseline"] = cpu_baseline(W, ct_np, N, primes, T, d_out, d_in,
+                                              args.cpu_seconds / 2 if ks else args.cpu_seconds, n_o)
+        if ks:
+            result["cpu_baseline"] = keyswitch_cpu_baseline(result["cpu_baseline"], N, primes, d_in,
+                                                            args.ks_base_bits, args.ks_levels)
     print(json.dumps(result), flush=True)
 
 

@@ -174,9 +174,10 @@ __global__ void __launch_bounds__(256) ks_digits_kernel(KsArgs) {
 }
 
 // Accumulation: one workgroup per (group of the pass, chunk of kKsChunk key
-// coefficients, prime). Block b runs on XCD b mod 8; the mapping keeps every
-// (chunk, prime) on one XCD with the groups varying fastest, so the workgroups
-// that run together on an XCD read the same key polynomials from its L2.
+// coefficients, prime). Block b runs on XCD b mod 8; the mapping keeps every chunk
+// on one XCD with the primes, then the groups varying fastest, so the workgroups
+// that run together on an XCD read the same key polynomials from its L2, and the
+// two primes of a group read each digit polynomial from HBM once.
 __global__ void __launch_bounds__(kInvThreads, 4) ks_accum_kernel(KsArgs) {
   __shared__ uint64_t lx[kN];
   __shared__ uint64_t lw[kInvLdsWords];
@@ -184,9 +185,9 @@ __global__ void __launch_bounds__(kInvThreads, 4) ks_accum_kernel(KsArgs) {
   const uint32_t P = a->rc.P, GB = a->GB, ell = a->kc.ell;
   const uint32_t blk = linear_block();
   const uint32_t rest = blk >> 3, xcd = blk & 7;
-  const uint32_t gb = rest % GB, cp = (rest / GB) * 8 + xcd;
-  if (cp >= kKsChunks * P) return;
-  const uint32_t chunk = cp / P, r = cp % P;
+  const uint32_t r = rest % P, gb = (rest / P) % GB, cq = rest / P / GB;
+  if (cq >= kKsChunks / 8) return;
+  const uint32_t chunk = cq * 8 + xcd;
   const uint64_t p = a->rc.q[r];
   const uint64_t pn = 0 - p;
   const InvMod md{pn, 8 * p, a->ntt.bm[r]};
@@ -210,21 +211,27 @@ __global__ void __launch_bounds__(kInvThreads, 4) ks_accum_kernel(KsArgs) {
         x[0][k] = v < 0 ? (uint64_t)(v + (int64_t)p) : (uint64_t)v;
       }
       ntt_forward512(x, lx, lw, tw, p, tid);
+      asm volatile("" ::: "memory");  // the key loads stay after the transform (register pressure)
       const uint64_t* kh = a->khat + (((size_t)i * ell + m) * P + r) * 2 * kN + 8 * tid;
-      uint64_t ka[8], kb[8];
+      // two halves of four positions: the key loads of one half are in flight at a time
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        ka[k] = kh[k];
-        kb[k] = kh[kN + k];
-      }
+      for (int h = 0; h < 2; ++h) {
+        uint64_t ka[4], kb[4];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const uint64_t v = reduce4(x[0][k], p);
-        // Shoup companion floor(v 2^64 / p): v floor(2^128 / p) / 2^64 is at most 1 low
-        uint64_t c = v * r1 + __umul64hi(v, r0);
-        c += (0 - c * p) >= p ? 1 : 0;
-        accA[k] += mul_shoup4(ka[k], v, c, pn);
-        accB[k] += mul_shoup4(kb[k], v, c, pn);
+        for (int k = 0; k < 4; ++k) {
+          ka[k] = kh[4 * h + k];
+          kb[k] = kh[kN + 4 * h + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint64_t v = reduce4(x[0][4 * h + k], p);
+          // Shoup companion floor(v 2^64 / p): v floor(2^128 / p) / 2^64 is at most 1 low
+          uint64_t c = v * r1 + __umul64hi(v, r0);
+          c += (0 - c * p) >= p ? 1 : 0;
+          accA[4 * h + k] += mul_shoup4(ka[k], v, c, pn);
+          accB[4 * h + k] += mul_shoup4(kb[k], v, c, pn);
+        }
+        if (h == 0) asm volatile("" ::: "memory");  // keep the second half's loads here
       }
     }
     if ((il & 15) == 15) {  // at most 64 products below 4p since the last reduction
