@@ -288,7 +288,8 @@ int rlwe_weights_rows_per_product(const rlwe_weights* w, uint32_t transpose, uin
  * message in the constant coefficient, s the LWE key of the outputs (the
  * coefficients of the input key S) and S' the key of the packed outputs.
  *
- * rlwe_ksk_load: make the key resident in the NTT domain (N levels P 2 N 8 bytes).
+ * rlwe_ksk_load: make the key resident in the NTT domain (N levels P 2 N 16 bytes:
+ * residues and their Shoup companions).
  *   ksk_dev    device, uint64 [N][levels][2][P][N] canonical residues: A, then B of
  *              KSK_{i,m}; read during the call only
  *   log2_base  digit bits, 1 <= log2_base <= 54, 2^(log2_base-1) below every prime

@@ -24,7 +24,8 @@
 //                     (int64), a 64 x 64 tile transpose through LDS
 //   ks_accum_kernel   per (group, chunk of 64 key coefficients, prime): forward
 //                     transforms of the digit polynomials, pointwise products
-//                     with the resident key, partial sums [group][chunk][p][2][N]
+//                     with the resident key (value, Shoup companion pairs), partial
+//                     sums [group][chunk][p][2][N]
 //   ks_finish_kernel  per group: sum of the partials, inverse transforms, the
 //                     factor 1/N, negation, bodies, optional switch to 2^k
 #include "ntt_device.hpp"
@@ -82,13 +83,24 @@ __device__ __forceinline__ void decompose(KsPtr a, uint64_t c0, uint64_t c1, int
 }
 
 
+// Forward butterfly without reductions (Harvey's lazy form, one step further): the
+// product w Y mod p is taken below 4p for any 64-bit Y (truncated-quotient Shoup),
+// so X, Y < B give X + wY and X + 4p - wY, both below B + 4p. From canonical inputs
+// the twelve stages end below 49p < 2^60.
+__device__ __forceinline__ void ct_bfly_lazy(uint64_t& X, uint64_t& Y, const Tw& t, uint64_t p4,
+                                             uint64_t pn) {
+  const uint64_t v = mul_shoup4(Y, t.w, t.wp, pn);
+  const uint64_t x = X;
+  X = x + v;
+  Y = x + p4 - v;
+}
+
 // Forward pass of the 512-thread transform in layout PASS (InvLayout): three
-// Cooley-Tukey stages, spans 4S, 2S, S, inputs and outputs below 4p.
+// Cooley-Tukey stages, spans 4S, 2S, S (twiddles as in the inverse, tw512).
 template <int PASS>
 __device__ __forceinline__ void fwd512_pass(uint64_t (&x)[1][8], int tid, const uint64_t* tw,
-                                            uint64_t p) {
+                                            uint64_t p4, uint64_t pn) {
   constexpr int S = InvLayout<PASS>::S;
-  const uint32_t base = InvLayout<PASS>::base(tid);
 #pragma unroll
   for (int st = 0; st < 3; ++st) {
     const int sp = 4 >> st;
@@ -96,34 +108,35 @@ __device__ __forceinline__ void fwd512_pass(uint64_t (&x)[1][8], int tid, const 
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       if (k & sp) continue;
-      const uint32_t pos = base + S * k;
-      ct_bfly(x[0][k], x[0][k + sp], ld_tw(tw, kN / (2 * t) + pos / (2 * t)), p);
+      const Tw w = tw512<PASS>(tw, t, k, tid);
+      ct_bfly_lazy(x[0][k], x[0][k + sp], w, p4, pn);
     }
   }
 }
 
 // Forward transform on 512 threads, one prime: x in layout Q4 (positions tid +
-// 512 k), natural order, below 4p -> layout Q1 (8 tid + k), bit-reversed order,
-// below 4p. The mirror of the inverse: Q4 -> Q3 crosses waves (buffer lx, between
+// 512 k), natural order, canonical -> layout Q1 (8 tid + k), bit-reversed order,
+// below 49p. The mirror of the inverse: Q4 -> Q3 crosses waves (buffer lx, between
 // barriers), Q3 -> Q2 and Q2 -> Q1 stay inside each wave's block of lw.
 __device__ __forceinline__ void ntt_forward512(uint64_t (&x)[1][8], uint64_t* lx, uint64_t* lw,
                                                const uint64_t* tw, uint64_t p, int tid) {
-  fwd512_pass<3>(x, tid, tw, p);
+  const uint64_t p4 = 4 * p, pn = 0 - p;
+  fwd512_pass<3>(x, tid, tw, p4, pn);
   __syncthreads();  // no wave still reads the previous transform's Q3 positions
   inv_store<1, 3, 3>(lx, x, tid);
   __syncthreads();
   inv_load<1, 2, 3>(lx, x, tid);
-  fwd512_pass<2>(x, tid, tw, p);
+  fwd512_pass<2>(x, tid, tw, p4, pn);
   wave_exchange_fence();  // every lane of the wave has read its Q2 positions of the last transform
   inv_store<1, 2, 2>(lw, x, tid);
   wave_exchange_fence();
   inv_load<1, 1, 2>(lw, x, tid);
-  fwd512_pass<1>(x, tid, tw, p);
+  fwd512_pass<1>(x, tid, tw, p4, pn);
   wave_exchange_fence();
   inv_store<1, 1, 1>(lw, x, tid);
   wave_exchange_fence();
   inv_load<1, 0, 1>(lw, x, tid);
-  fwd512_pass<0>(x, tid, tw, p);
+  fwd512_pass<0>(x, tid, tw, p4, pn);
 }
 
 }  // namespace
@@ -178,11 +191,13 @@ __global__ void __launch_bounds__(256) ks_digits_kernel(KsArgs) {
 // on one XCD with the primes, then the groups varying fastest, so the workgroups
 // that run together on an XCD read the same key polynomials from its L2, and the
 // two primes of a group read each digit polynomial from HBM once.
+template <int ELL>
 __global__ void __launch_bounds__(kInvThreads, 4) ks_accum_kernel(KsArgs) {
   __shared__ uint64_t lx[kN];
   __shared__ uint64_t lw[kInvLdsWords];
   const KsPtr a = ks_args();
-  const uint32_t P = a->rc.P, GB = a->GB, ell = a->kc.ell;
+  constexpr uint32_t ell = ELL;
+  const uint32_t P = a->rc.P, GB = a->GB;
   const uint32_t blk = linear_block();
   const uint32_t rest = blk >> 3, xcd = blk & 7;
   const uint32_t r = rest % P, gb = (rest / P) % GB, cq = rest / P / GB;
@@ -192,7 +207,6 @@ __global__ void __launch_bounds__(kInvThreads, 4) ks_accum_kernel(KsArgs) {
   const uint64_t pn = 0 - p;
   const InvMod md{pn, 8 * p, a->ntt.bm[r]};
   const uint64_t* tw = a->ntt.fwd[r];
-  const uint64_t r1 = a->ntt.rq[r][0], r0 = a->ntt.rq[r][1];
   const int tid0 = threadIdx.x;
   uint64_t accA[8], accB[8];
 #pragma unroll
@@ -211,27 +225,22 @@ __global__ void __launch_bounds__(kInvThreads, 4) ks_accum_kernel(KsArgs) {
         x[0][k] = v < 0 ? (uint64_t)(v + (int64_t)p) : (uint64_t)v;
       }
       ntt_forward512(x, lx, lw, tw, p, tid);
-      asm volatile("" ::: "memory");  // the key loads stay after the transform (register pressure)
-      const uint64_t* kh = a->khat + (((size_t)i * ell + m) * P + r) * 2 * kN + 8 * tid;
-      // two halves of four positions: the key loads of one half are in flight at a time
+      // key (value, Shoup companion) pairs of mask and body at positions 8 tid + k; the
+      // transformed digits (below 49p) are the free operand of the Shoup products
+      const uint64_t* kh = a->khat + (((size_t)i * ell + m) * P + r) * 4 * kN + 16 * tid;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        uint64_t ka[4], kb[4];
+      for (int h = 0; h < 4; ++h) {
+        Tw ka[2], kb[2];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          ka[k] = kh[4 * h + k];
-          kb[k] = kh[kN + 4 * h + k];
+        for (int k = 0; k < 2; ++k) {
+          ka[k] = ld_tw(kh, 2 * h + k);
+          kb[k] = ld_tw(kh + 2 * kN, 2 * h + k);
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const uint64_t v = reduce4(x[0][4 * h + k], p);
-          // Shoup companion floor(v 2^64 / p): v floor(2^128 / p) / 2^64 is at most 1 low
-          uint64_t c = v * r1 + __umul64hi(v, r0);
-          c += (0 - c * p) >= p ? 1 : 0;
-          accA[4 * h + k] += mul_shoup4(ka[k], v, c, pn);
-          accB[4 * h + k] += mul_shoup4(kb[k], v, c, pn);
+        for (int k = 0; k < 2; ++k) {
+          accA[2 * h + k] += mul_shoup4(x[0][2 * h + k], ka[k].w, ka[k].wp, pn);
+          accB[2 * h + k] += mul_shoup4(x[0][2 * h + k], kb[k].w, kb[k].wp, pn);
         }
-        if (h == 0) asm volatile("" ::: "memory");  // keep the second half's loads here
       }
     }
     if ((il & 15) == 15) {  // at most 64 products below 4p since the last reduction
@@ -328,7 +337,8 @@ __global__ void __launch_bounds__(kInvThreads) ks_finish_kernel(KsArgs) {
 }
 
 // Key in the NTT domain: one workgroup per polynomial (i, m, c, p) of the key
-// [N][ell][2][P][N] -> khat[((i ell + m) P + p) 2 + c][N], bit-reversed, in [0, p).
+// [N][ell][2][P][N] -> khat[((i ell + m) P + p) 2 + c][N][2]: bit-reversed order,
+// residue in [0, p) and its Shoup companion floor(v 2^64 / p).
 __global__ void __launch_bounds__(kThreads) ksk_fwd_kernel(KsArgs) {
   __shared__ uint64_t lds[kLdsWords];
   const KsPtr a = ks_args();
@@ -343,9 +353,17 @@ __global__ void __launch_bounds__(kThreads) ksk_fwd_kernel(KsArgs) {
 #pragma unroll
   for (int k = 0; k < 16; ++k) x[k] = src[tid + 256 * k];
   ntt_forward(x, lds, a->ntt.fwd[r], p, tid);
-  uint64_t* dst = a->khat_out + (((size_t)im * P + r) * 2 + c) * kN + 16 * tid;
+  uint64_t* dst = a->khat_out + ((((size_t)im * P + r) * 2 + c) * kN + 16 * tid) * 2;
+  const uint64_t r1 = a->ntt.rq[r][0], r0 = a->ntt.rq[r][1];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) dst[k] = reduce4(x[k], p);
+  for (int k = 0; k < 16; ++k) {
+    const uint64_t v = reduce4(x[k], p);
+    // v floor(2^128 / p) / 2^64 is at most 1 below floor(v 2^64 / p)
+    uint64_t cp = v * r1 + __umul64hi(v, r0);
+    cp += (0 - cp * p) >= p ? 1 : 0;
+    dst[2 * k] = v;
+    dst[2 * k + 1] = cp;
+  }
 }
 
 hipError_t launch_ksk_fwd(const KsArgs& a, hipStream_t s) {
@@ -374,7 +392,14 @@ hipError_t launch_ks_digits(const KsArgs& a, hipStream_t s) {
 
 hipError_t launch_ks_accum(const KsArgs& a, hipStream_t s) {
   const uint32_t blocks = a.GB * kKsChunks * a.rc.P;  // kKsChunks P is a multiple of 8
-  hipLaunchKernelGGL(ks_accum_kernel, grid_for(blocks), dim3(kInvThreads), 0, s, a);
+  const dim3 g = grid_for(blocks);
+  switch (a.kc.ell) {
+    case 1: hipLaunchKernelGGL(ks_accum_kernel<1>, g, dim3(kInvThreads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(ks_accum_kernel<2>, g, dim3(kInvThreads), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(ks_accum_kernel<3>, g, dim3(kInvThreads), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(ks_accum_kernel<4>, g, dim3(kInvThreads), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -220,11 +220,28 @@ __device__ __forceinline__ uint32_t xaddr(uint32_t pos) {
   return pos;
 }
 
+// Twiddle of the butterfly with lower element k of a thread in 512-thread layout
+// PASS (InvLayout), span t: entry N / (2t) + pos / (2t). In layouts Q4 and Q3 it is
+// the same on every lane of a wave: positions tid + 512 k give pos / (2t) = 512 k /
+// (2t) for t >= 512 (tid < 512), and positions 512 w + l + 64 k (wave w, lane l < 64)
+// give (512 w + 64 k) / (2t) for t >= 64, since l never carries; those are read with
+// scalar loads, the others per lane.
+typedef const __attribute__((address_space(4))) uint64_t* TwScalarPtr;
+template <int PASS>
+__device__ __forceinline__ Tw tw512(const uint64_t* tw, uint32_t t, int k, int tid) {
+  if (PASS >= 2) {
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane(tid) >> 6;
+    const uint32_t upos = PASS == 3 ? 512u * k : 512u * wave + 64u * k;
+    const uint32_t idx = kN / (2 * t) + upos / (2 * t);
+    return Tw{((TwScalarPtr)tw)[2 * idx], ((TwScalarPtr)tw)[2 * idx + 1]};
+  }
+  return ld_tw(tw, kN / (2 * t) + (InvLayout<PASS>::base(tid) + InvLayout<PASS>::S * k) / (2 * t));
+}
+
 template <int NP, int PASS, bool END>
 __device__ __forceinline__ void inv_pass(uint64_t (&x)[NP][8], int tid,
                                          const uint64_t* const (&tw)[NP], const InvMod (&md)[NP]) {
   constexpr int S = InvLayout<PASS>::S;
-  const uint32_t base = InvLayout<PASS>::base(tid);
 #pragma unroll
   for (int st = 0; st < 3; ++st) {
     const int sp = 1 << st;
@@ -232,10 +249,9 @@ __device__ __forceinline__ void inv_pass(uint64_t (&x)[NP][8], int tid,
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       if (k & sp) continue;
-      const uint32_t idx = kN / (2 * t) + (base + S * k) / (2 * t);
 #pragma unroll
       for (int r = 0; r < NP; ++r)
-        gs_bfly(x[r][k], x[r][k + sp], ld_tw(tw[r], idx), md[r].p8 << st, md[r].pn);
+        gs_bfly(x[r][k], x[r][k + sp], tw512<PASS>(tw[r], t, k, tid), md[r].p8 << st, md[r].pn);
     }
   }
   if (END) {

@@ -925,7 +925,7 @@ int ct_pack_bits(rlwe_ctx* ctx, const uint32_t* in, size_t count, uint32_t len, 
 
 struct rlwe_ksk {
   rlwe_ctx* ctx = nullptr;
-  uint64_t* khat = nullptr;  // [N][ell][P][2][N], NTT domain, bit-reversed
+  uint64_t* khat = nullptr;  // [N][ell][P][2][N][2], NTT domain, bit-reversed, with companions
   KsConst kc{};
 };
 
@@ -984,7 +984,7 @@ int rlwe_ksk_load(rlwe_ctx* ctx, const uint64_t* ksk_dev, uint32_t log2_base, ui
     kc.g_shoup[r] = (uint64_t)(((u128)kc.g[r] << 64) / q);
   }
   const size_t N = rc.N;
-  const size_t bytes = N * levels * rc.P * 2 * N * 8;
+  const size_t bytes = N * levels * rc.P * 2 * N * 16;
   e = hipMalloc(&k->khat, bytes);
   if (e != hipSuccess) {
     delete k;

@@ -230,7 +230,7 @@ struct KsArgs {
   uint32_t g0, GB;       // first output group of this pass, groups in the pass
   uint32_t raw;          // outputs modulo q per prime (else switched to 2^qbits)
   int64_t* dig;          // workspace: digits [GB][N][ell][N]
-  const uint64_t* khat;  // key in the NTT domain [N][ell][P][2][N]
+  const uint64_t* khat;  // key in the NTT domain [N][ell][P][2][N][2] (value, Shoup companion)
   uint64_t* part;        // workspace: partial sums [GB][N / 64][P][2][N]
   void* out;             // [G][2][P][N] u64 or [G][2][N] u32
   const uint64_t* ksk_in;  // key load: [N][ell][2][P][N] canonical residues
