@@ -94,9 +94,12 @@ def roofline(products, kt, N, P, traffic=None):
 KERNEL_TRAFFIC = {
     "mask": {"sources": ["k_mask.hip"], "fetch_bytes": 4382392135, "write_bytes": 4766662645,
              "sha256": "b71d09264e517098c1179f16657d1e4fa62f1eaae851294a6d0fdb5115986154"},
-    "ntt": {"sources": ["k_ntt.hip", "ntt_device.hpp"], "fetch_bytes": 5067261677,
-            "write_bytes": 4365784442,
-            "sha256": "e251e3a5e2d22e750b5e4fd1bb6d2335346f7d096c8a45e3df630253c67ce817"},
+    "ntt": {"sources": ["k_ntt.hip", "ntt_device.hpp"], "fetch_bytes": 5397402760,
+            "write_bytes": 4325817385,
+            "sha256": "8a9fb76ae0be760fb20f2939998f49ce57013adcd497b8cb1e60d410a79a3f7e"},
+    "ksacc": {"sources": ["k_keyswitch.hip", "ntt_device.hpp"], "fetch_bytes": 13262158387,
+              "write_bytes": 539077652,
+              "sha256": "0e6f6cbc7e937e0a412a725a6d9f2fc808760543c85f927d73ec1fdf29a66419"},
 }
 
 
