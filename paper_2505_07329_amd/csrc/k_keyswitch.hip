@@ -25,7 +25,7 @@
 //   ks_accum_kernel   per (group, chunk of 64 key coefficients, prime): forward
 //                     transforms of the digit polynomials, pointwise products
 //                     with the resident key (value, Shoup companion pairs), partial
-//                     sums [group][chunk][p][2][N]
+//                     sums [group][chunk][p][2][N] (lane-major positions)
 //   ks_finish_kernel  per group: sum of the partials, inverse transforms, the
 //                     factor 1/N, negation, bodies, optional switch to 2^k
 #include "ntt_device.hpp"
@@ -227,14 +227,15 @@ __global__ void __launch_bounds__(kInvThreads, 4) ks_accum_kernel(KsArgs) {
       ntt_forward512(x, lx, lw, tw, p, tid);
       // key (value, Shoup companion) pairs of mask and body at positions 8 tid + k; the
       // transformed digits (below 49p) are the free operand of the Shoup products
-      const uint64_t* kh = a->khat + (((size_t)i * ell + m) * P + r) * 4 * kN + 16 * tid;
+      // lane-major key layout (lane_major): each load covers 1 KB across a wave
+      const uint64_t* kh = a->khat + (((size_t)i * ell + m) * P + r) * 4 * kN;
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
         Tw ka[2], kb[2];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-          ka[k] = ld_tw(kh, 2 * h + k);
-          kb[k] = ld_tw(kh + 2 * kN, 2 * h + k);
+          ka[k] = ld_tw(kh, (2 * h + k) * 512 + tid);
+          kb[k] = ld_tw(kh + 2 * kN, (2 * h + k) * 512 + tid);
         }
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -251,11 +252,11 @@ __global__ void __launch_bounds__(kInvThreads, 4) ks_accum_kernel(KsArgs) {
       }
     }
   }
-  uint64_t* dst = a->part + (((size_t)gb * kKsChunks + chunk) * P + r) * 2 * kN + 8 * tid0;
+  uint64_t* dst = a->part + (((size_t)gb * kKsChunks + chunk) * P + r) * 2 * kN + tid0;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    dst[k] = reduce4(reduce_barrett(accA[k], md), p);
-    dst[kN + k] = reduce4(reduce_barrett(accB[k], md), p);
+  for (int k = 0; k < 8; ++k) {  // lane-major: position 8 tid + k at k 512 + tid
+    dst[512 * k] = reduce4(reduce_barrett(accA[k], md), p);
+    dst[kN + 512 * k] = reduce4(reduce_barrett(accB[k], md), p);
   }
 }
 
@@ -286,9 +287,9 @@ __global__ void __launch_bounds__(kInvThreads) ks_finish_kernel(KsArgs) {
       for (int k = 0; k < 8; ++k) x[r][k] = 0;
       for (uint32_t ch = 0; ch < kKsChunks; ++ch) {
         const uint64_t* src =
-            a->part + ((((size_t)gb * kKsChunks + ch) * NP + r) * 2 + c) * kN + 8 * tid;
+            a->part + ((((size_t)gb * kKsChunks + ch) * NP + r) * 2 + c) * kN + tid;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) x[r][k] += src[k];  // 64 terms below p
+        for (int k = 0; k < 8; ++k) x[r][k] += src[512 * k];  // 64 terms below p
       }
 #pragma unroll
       for (int k = 0; k < 8; ++k) x[r][k] = reduce_barrett(x[r][k], md[r]);
@@ -337,8 +338,9 @@ __global__ void __launch_bounds__(kInvThreads) ks_finish_kernel(KsArgs) {
 }
 
 // Key in the NTT domain: one workgroup per polynomial (i, m, c, p) of the key
-// [N][ell][2][P][N] -> khat[((i ell + m) P + p) 2 + c][N][2]: bit-reversed order,
-// residue in [0, p) and its Shoup companion floor(v 2^64 / p).
+// [N][ell][2][P][N] -> khat[((i ell + m) P + p) 2 + c][lane_major(pos)][2] for
+// bit-reversed position pos: residue in [0, p) and its Shoup companion
+// floor(v 2^64 / p).
 __global__ void __launch_bounds__(kThreads) ksk_fwd_kernel(KsArgs) {
   __shared__ uint64_t lds[kLdsWords];
   const KsPtr a = ks_args();
@@ -353,7 +355,7 @@ __global__ void __launch_bounds__(kThreads) ksk_fwd_kernel(KsArgs) {
 #pragma unroll
   for (int k = 0; k < 16; ++k) x[k] = src[tid + 256 * k];
   ntt_forward(x, lds, a->ntt.fwd[r], p, tid);
-  uint64_t* dst = a->khat_out + ((((size_t)im * P + r) * 2 + c) * kN + 16 * tid) * 2;
+  uint64_t* dst = a->khat_out + (((size_t)im * P + r) * 2 + c) * kN * 2;
   const uint64_t r1 = a->ntt.rq[r][0], r0 = a->ntt.rq[r][1];
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
@@ -361,8 +363,9 @@ __global__ void __launch_bounds__(kThreads) ksk_fwd_kernel(KsArgs) {
     // v floor(2^128 / p) / 2^64 is at most 1 below floor(v 2^64 / p)
     uint64_t cp = v * r1 + __umul64hi(v, r0);
     cp += (0 - cp * p) >= p ? 1 : 0;
-    dst[2 * k] = v;
-    dst[2 * k + 1] = cp;
+    const uint32_t at = 2 * lane_major(16 * tid + k);
+    dst[at] = v;
+    dst[at + 1] = cp;
   }
 }
 

@@ -6,9 +6,10 @@ namespace rlwe {
 
 
 // NTT of the masks of every NTT-method product: one workgroup per (token, block,
-// prime). ahat[(((t L + i) P + p) N + pos) * 2 + {0, 1}], bit-reversed order:
-// residue in [0, p) and its Shoup companion (the mask side carries the companions,
-// computed once per token, so the resident weights need only their residues).
+// prime). ahat[(((t L + i) P + p) N + lane_major(pos)) * 2 + {0, 1}], bit-reversed
+// position pos: residue in [0, p) and its Shoup companion (the mask side carries
+// the companions, computed once per token, so the resident weights need only their
+// residues).
 __global__ void __launch_bounds__(kThreads) ntt_mask_fwd_kernel(Batch) {
   __shared__ uint64_t lds[kLdsWords];
   const BatchPtr bt = kernarg_batch();
@@ -34,7 +35,7 @@ __global__ void __launch_bounds__(kThreads) ntt_mask_fwd_kernel(Batch) {
     for (int k = 0; k < 16; ++k) x[k] = blk_in[(size_t)p_idx * kN + tid + 256 * k];
   }
   ntt_forward(x, lds, tw, p, tid);
-  uint64_t* dst = bt->it[ii].ahat + 2 * ((size_t)loc * kN + 16 * tid);
+  uint64_t* dst = bt->it[ii].ahat + 2 * (size_t)loc * kN;
   const uint64_t r1 = bt->ntt.rq[p_idx][0], r0 = bt->ntt.rq[p_idx][1];
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
@@ -42,8 +43,9 @@ __global__ void __launch_bounds__(kThreads) ntt_mask_fwd_kernel(Batch) {
     // Shoup companion floor(v 2^64 / p): v floor(2^128 / p) / 2^64 is at most 1 low
     uint64_t c = v * r1 + __umul64hi(v, r0);
     c += (0 - c * p) >= p ? 1 : 0;
-    dst[2 * k] = v;
-    dst[2 * k + 1] = c;
+    const uint32_t at = 2 * lane_major(16 * tid + k);
+    dst[at] = v;
+    dst[at + 1] = c;
   }
 }
 
@@ -103,12 +105,16 @@ __global__ void __launch_bounds__(kInvThreads, LC == 2 ? 4 : 1) ntt_mask_kernel(
         uint64_t wv[NP][8], av[NP][16];
 #pragma unroll
         for (int r = 0; r < NP; ++r) {
-          const uint64_t* a = ahat + 2 * ((((size_t)t * NB + i) * NP + r) * kN + 8 * tid);
-          const uint64_t* w = what + (((size_t)j * NB + i) * NP + r) * kN + 8 * tid;
+          // lane-major operands: position 8 tid + k at k 512 + tid
+          const uint64_t* a = ahat + 2 * ((((size_t)t * NB + i) * NP + r) * kN + tid);
+          const uint64_t* w = what + (((size_t)j * NB + i) * NP + r) * kN + tid;
 #pragma unroll
-          for (int k = 0; k < 8; ++k) wv[r][k] = w[k];
+          for (int k = 0; k < 8; ++k) wv[r][k] = w[512 * k];
 #pragma unroll
-          for (int k = 0; k < 16; ++k) av[r][k] = a[k];
+          for (int k = 0; k < 8; ++k) {
+            av[r][2 * k] = a[1024 * k];
+            av[r][2 * k + 1] = a[1024 * k + 1];
+          }
         }
 #pragma unroll
         for (int r = 0; r < NP; ++r)
@@ -124,16 +130,17 @@ __global__ void __launch_bounds__(kInvThreads, LC == 2 ? 4 : 1) ntt_mask_kernel(
 #pragma unroll
         for (int k = 0; k < 8; ++k) x[r][k] = 0;
         for (uint32_t i = 0; i < L; ++i) {  // positions 8 tid + k (layout Q1)
-          const uint64_t* a = ahat + 2 * ((((size_t)t * L + i) * NP + r) * kN + 8 * tid);
-          const uint64_t* w = what + (((size_t)j * L + i) * NP + r) * kN + 8 * tid;
+          const uint64_t* a = ahat + 2 * ((((size_t)t * L + i) * NP + r) * kN + tid);
+          const uint64_t* w = what + (((size_t)j * L + i) * NP + r) * kN + tid;
           if (L <= 2) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) x[r][k] += mul_shoup4(w[k], a[2 * k], a[2 * k + 1], md[r].pn);
+            for (int k = 0; k < 8; ++k)
+              x[r][k] += mul_shoup4(w[512 * k], a[1024 * k], a[1024 * k + 1], md[r].pn);
           } else {
 #pragma unroll
             for (int k = 0; k < 8; ++k)
-              x[r][k] = reduce_barrett(x[r][k] + mul_shoup4(w[k], a[2 * k], a[2 * k + 1], md[r].pn),
-                                       md[r]);
+              x[r][k] = reduce_barrett(
+                  x[r][k] + mul_shoup4(w[512 * k], a[1024 * k], a[1024 * k + 1], md[r].pn), md[r]);
           }
         }
       }
@@ -232,7 +239,8 @@ __global__ void __launch_bounds__(kInvThreads, LC == 2 ? 4 : 1) ntt_mask_kernel(
 // w_j[iN + N - 1 - k] (zero past K), Sec. 4.3. Packed (one block, slot = K), row
 // j n_o + rho of the group fills coefficients [rho K, rho K + K) reversed:
 // w_hat[rho K + K - 1 - k] = w_{j n_o + rho}[k] (zero past the last row and N).
-// what[((j L + i) P + p) N + pos], bit-reversed order, residues in [0, p).
+// what[((j L + i) P + p) N + lane_major(pos)], bit-reversed position pos, residues
+// in [0, p).
 __global__ void __launch_bounds__(kThreads) ntt_weights_kernel(MatArgs m, NttConst ntt,
                                                                RingConst rc, uint64_t* what) {
   __shared__ uint64_t lds[kLdsWords];
@@ -252,9 +260,9 @@ __global__ void __launch_bounds__(kThreads) ntt_weights_kernel(MatArgs m, NttCon
     x[k] = v < 0 ? p - (uint64_t)(-v) : (uint64_t)v;
   }
   ntt_forward(x, lds, ntt.fwd[p_idx], p, tid);
-  uint64_t* dst = what + (size_t)loc * kN + 16 * tid;
+  uint64_t* dst = what + (size_t)loc * kN;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) dst[k] = reduce4(x[k], p);
+  for (int k = 0; k < 16; ++k) dst[lane_major(16 * tid + k)] = reduce4(x[k], p);
 }
 
 hipError_t launch_ntt_mask_fwd(const Batch& b, hipStream_t s) {

@@ -125,6 +125,13 @@ __device__ __forceinline__ void gs_bfly(uint64_t& X, uint64_t& Y, const Tw& t, u
   Y = mul_shoup4(d, t.w, t.wp, pn);
 }
 
+// Storage index of bit-reversed position pos in the lane-major layout of operands
+// read by the 512-thread kernels, whose thread t holds positions 8 t .. 8 t + 7
+// (layout Q1): position 8 t + k is stored at k 512 + t, so each of a wave's loads
+// of one k covers consecutive words.
+__host__ __device__ __forceinline__ uint32_t lane_major(uint32_t pos) {
+  return (pos % 8) * 512 + pos / 8;
+}
 __device__ __forceinline__ uint32_t pad(uint32_t pos) { return pos + pos / 16; }
 
 // Four stages of one pass on x[16] at positions base + STRIDE * k. The twiddle

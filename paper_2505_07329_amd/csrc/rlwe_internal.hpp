@@ -181,8 +181,8 @@ struct Item {
   MatArgs m;
   SwitchConst sc;
   uint32_t method;     // 0: digit planes on the matrix cores, 1: NTT
-  const uint64_t* what;  // NTT method: [rows][L][P][N] transformed weight blocks
-  uint64_t* ahat;        // NTT method: [T][L][P][N] (mask, Shoup companion) pairs (workspace)
+  const uint64_t* what;  // NTT method: [rows][L][P][N] transformed weight blocks (lane-major)
+  uint64_t* ahat;        // NTT method: [T][L][P][N] (mask, Shoup companion) pairs, lane-major (workspace)
   const uint64_t* ct;  // [T][L][2][P][N]
   int8_t* emask;       // [T][D][L][2N]: per digit plane, index m <-> Toeplitz offset m - N
   int8_t* ebody;       // [T][D][L][N]
@@ -230,7 +230,7 @@ struct KsArgs {
   uint32_t g0, GB;       // first output group of this pass, groups in the pass
   uint32_t raw;          // outputs modulo q per prime (else switched to 2^qbits)
   int64_t* dig;          // workspace: digits [GB][N][ell][N]
-  const uint64_t* khat;  // key in the NTT domain [N][ell][P][2][N][2] (value, Shoup companion)
+  const uint64_t* khat;  // key in the NTT domain [N][ell][P][2][N][2] (value, Shoup companion), lane-major
   uint64_t* part;        // workspace: partial sums [GB][N / 64][P][2][N]
   void* out;             // [G][2][P][N] u64 or [G][2][N] u32
   const uint64_t* ksk_in;  // key load: [N][ell][2][P][N] canonical residues
