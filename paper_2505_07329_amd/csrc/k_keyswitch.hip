@@ -95,10 +95,11 @@ __device__ __forceinline__ void ct_bfly_lazy(uint64_t& X, uint64_t& Y, const Tw&
   Y = x + p4 - v;
 }
 
-// Forward pass of the 512-thread transform in layout PASS (InvLayout): three
-// Cooley-Tukey stages, spans 4S, 2S, S (twiddles as in the inverse, tw512).
-template <int PASS>
-__device__ __forceinline__ void fwd512_pass(uint64_t (&x)[1][8], int tid, const uint64_t* tw,
+// Forward pass of the 512-thread transform in layout PASS (InvLayout) on NC
+// transforms of one prime at once: three Cooley-Tukey stages, spans 4S, 2S, S
+// (twiddles as in the inverse, tw512, shared by the NC chains).
+template <int NC, int PASS>
+__device__ __forceinline__ void fwd512_pass(uint64_t (&x)[NC][8], int tid, const uint64_t* tw,
                                             uint64_t p4, uint64_t pn) {
   constexpr int S = InvLayout<PASS>::S;
 #pragma unroll
@@ -109,34 +110,38 @@ __device__ __forceinline__ void fwd512_pass(uint64_t (&x)[1][8], int tid, const 
     for (int k = 0; k < 8; ++k) {
       if (k & sp) continue;
       const Tw w = tw512<PASS>(tw, t, k, tid);
-      ct_bfly_lazy(x[0][k], x[0][k + sp], w, p4, pn);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) ct_bfly_lazy(x[c][k], x[c][k + sp], w, p4, pn);
     }
   }
 }
 
-// Forward transform on 512 threads, one prime: x in layout Q4 (positions tid +
-// 512 k), natural order, canonical -> layout Q1 (8 tid + k), bit-reversed order,
-// below 49p. The mirror of the inverse: Q4 -> Q3 crosses waves (buffer lx, between
-// barriers), Q3 -> Q2 and Q2 -> Q1 stay inside each wave's block of lw.
-__device__ __forceinline__ void ntt_forward512(uint64_t (&x)[1][8], uint64_t* lx, uint64_t* lw,
+// NC forward transforms of one prime on 512 threads: x[c] in layout Q4 (positions tid
+// + 512 k), natural order, canonical -> layout Q1 (8 tid + k), bit-reversed order,
+// below 49p. The mirror of the inverse: Q4 -> Q3 crosses waves (between barriers),
+// Q3 -> Q2 and Q2 -> Q1 stay inside each wave's block; lds holds NC exchange buffers
+// of kInvLdsWords words, and a third barrier separates the Q3 loads of every wave
+// from the wave-local stores that reuse the buffer.
+template <int NC>
+__device__ __forceinline__ void ntt_forward512(uint64_t (&x)[NC][8], uint64_t* lds,
                                                const uint64_t* tw, uint64_t p, int tid) {
   const uint64_t p4 = 4 * p, pn = 0 - p;
-  fwd512_pass<3>(x, tid, tw, p4, pn);
-  __syncthreads();  // no wave still reads the previous transform's Q3 positions
-  inv_store<1, 3, 3>(lx, x, tid);
+  fwd512_pass<NC, 3>(x, tid, tw, p4, pn);
+  __syncthreads();  // no wave still reads the previous transforms' Q1 positions
+  inv_store<NC, 3, 3>(lds, x, tid);
   __syncthreads();
-  inv_load<1, 2, 3>(lx, x, tid);
-  fwd512_pass<2>(x, tid, tw, p4, pn);
-  wave_exchange_fence();  // every lane of the wave has read its Q2 positions of the last transform
-  inv_store<1, 2, 2>(lw, x, tid);
+  inv_load<NC, 2, 3>(lds, x, tid);
+  fwd512_pass<NC, 2>(x, tid, tw, p4, pn);
+  __syncthreads();  // every wave has read its Q3 positions
+  inv_store<NC, 2, 2>(lds, x, tid);
   wave_exchange_fence();
-  inv_load<1, 1, 2>(lw, x, tid);
-  fwd512_pass<1>(x, tid, tw, p4, pn);
+  inv_load<NC, 1, 2>(lds, x, tid);
+  fwd512_pass<NC, 1>(x, tid, tw, p4, pn);
   wave_exchange_fence();
-  inv_store<1, 1, 1>(lw, x, tid);
+  inv_store<NC, 1, 1>(lds, x, tid);
   wave_exchange_fence();
-  inv_load<1, 0, 1>(lw, x, tid);
-  fwd512_pass<0>(x, tid, tw, p4, pn);
+  inv_load<NC, 0, 1>(lds, x, tid);
+  fwd512_pass<NC, 0>(x, tid, tw, p4, pn);
 }
 
 }  // namespace
@@ -193,8 +198,8 @@ __global__ void __launch_bounds__(256) ks_digits_kernel(KsArgs) {
 // two primes of a group read each digit polynomial from HBM once.
 template <int ELL>
 __global__ void __launch_bounds__(kInvThreads, 4) ks_accum_kernel(KsArgs) {
-  __shared__ uint64_t lx[kN];
-  __shared__ uint64_t lw[kInvLdsWords];
+  constexpr int NC = 2;  // key coefficients i, i + 1 transformed together (two chains)
+  __shared__ uint64_t lds[NC * kInvLdsWords];
   const KsPtr a = ks_args();
   constexpr uint32_t ell = ELL;
   const uint32_t P = a->rc.P, GB = a->GB;
@@ -212,39 +217,44 @@ __global__ void __launch_bounds__(kInvThreads, 4) ks_accum_kernel(KsArgs) {
 #pragma unroll
   for (int k = 0; k < 8; ++k) accA[k] = accB[k] = 0;
   const int64_t* dig = a->dig + (size_t)gb * kN * ell * kN;
-  for (uint32_t il = 0; il < kKsChunk; ++il) {
+  for (uint32_t il = 0; il < kKsChunk; il += NC) {
     const uint32_t i = chunk * kKsChunk + il;
     for (uint32_t m = 0; m < ell; ++m) {
       int tid = tid0;
       asm volatile("" : "+v"(tid));
-      uint64_t x[1][8];
-      const int64_t* dsrc = dig + ((size_t)i * ell + m) * kN + tid;
+      uint64_t x[NC][8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int64_t v = dsrc[512 * k];
-        x[0][k] = v < 0 ? (uint64_t)(v + (int64_t)p) : (uint64_t)v;
+      for (int c = 0; c < NC; ++c) {
+        const int64_t* dsrc = dig + ((size_t)(i + c) * ell + m) * kN + tid;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int64_t v = dsrc[512 * k];
+          x[c][k] = v < 0 ? (uint64_t)(v + (int64_t)p) : (uint64_t)v;
+        }
       }
-      ntt_forward512(x, lx, lw, tw, p, tid);
+      ntt_forward512<NC>(x, lds, tw, p, tid);
       // key (value, Shoup companion) pairs of mask and body at positions 8 tid + k; the
       // transformed digits (below 49p) are the free operand of the Shoup products
-      // lane-major key layout (lane_major): each load covers 1 KB across a wave
-      const uint64_t* kh = a->khat + (((size_t)i * ell + m) * P + r) * 4 * kN;
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
-        Tw ka[2], kb[2];
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          ka[k] = ld_tw(kh, (2 * h + k) * 512 + tid);
-          kb[k] = ld_tw(kh + 2 * kN, (2 * h + k) * 512 + tid);
-        }
+        for (int c = 0; c < NC; ++c) {
+          const uint64_t* kh = a->khat + (((size_t)(i + c) * ell + m) * P + r) * 4 * kN;
+          Tw ka[2], kb[2];
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          accA[2 * h + k] += mul_shoup4(x[0][2 * h + k], ka[k].w, ka[k].wp, pn);
-          accB[2 * h + k] += mul_shoup4(x[0][2 * h + k], kb[k].w, kb[k].wp, pn);
+          for (int k = 0; k < 2; ++k) {  // lane-major key layout (lane_major)
+            ka[k] = ld_tw(kh, (2 * h + k) * 512 + tid);
+            kb[k] = ld_tw(kh + 2 * kN, (2 * h + k) * 512 + tid);
+          }
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            accA[2 * h + k] += mul_shoup4(x[c][2 * h + k], ka[k].w, ka[k].wp, pn);
+            accB[2 * h + k] += mul_shoup4(x[c][2 * h + k], kb[k].w, kb[k].wp, pn);
+          }
         }
       }
     }
-    if ((il & 15) == 15) {  // at most 64 products below 4p since the last reduction
+    if ((il & 15) == 16 - NC) {  // at most 64 products below 4p since the last reduction
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         accA[k] = reduce_barrett(accA[k], md);
