@@ -163,18 +163,25 @@ __global__ void __launch_bounds__(256) ks_digits_kernel(KsArgs) {
   const uint32_t g = a->g0 + gb;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   constexpr uint32_t ell = ELL;
-  int64_t d[16][ELL];
+  // every load is issued before any decomposition: rows past the last LWE ciphertext
+  // (or past n_pack) read LWE 0 and are zeroed afterwards
+  uint64_t c0[16], c1[16];
+  bool ok[16];
 #pragma unroll
   for (int rep = 0; rep < 16; ++rep) {
     const uint32_t s = s0 + ty + 4 * rep;
     const uint64_t j = (uint64_t)g * a->n_pack + s;
-    if (s < a->n_pack && j < a->M) {
-      const uint64_t* row = a->lwe + j * NP * (N + 1) + i0 + tx;
-      decompose<NP, ELL>(a, row[0], NP == 2 ? row[N + 1] : 0, d[rep]);
-    } else {
+    ok[rep] = s < a->n_pack && j < a->M;
+    const uint64_t* row = a->lwe + (ok[rep] ? j : 0) * NP * (N + 1) + i0 + tx;
+    c0[rep] = row[0];
+    c1[rep] = NP == 2 ? row[N + 1] : 0;
+  }
+  int64_t d[16][ELL];
 #pragma unroll
-      for (int m = 0; m < ELL; ++m) d[rep][m] = 0;
-    }
+  for (int rep = 0; rep < 16; ++rep) {
+    decompose<NP, ELL>(a, c0[rep], c1[rep], d[rep]);
+#pragma unroll
+    for (int m = 0; m < ELL; ++m) d[rep][m] = ok[rep] ? d[rep][m] : 0;
   }
   int64_t* dst = a->dig + (size_t)gb * N * ell * N;
 #pragma unroll
