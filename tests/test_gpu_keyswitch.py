@@ -5,8 +5,10 @@ Covered: two primes with one gadget level (54-bit digits) and with 2 and 4 level
 one prime with three 12-bit levels, raw and switched outputs (2^32 and 2^26), ragged
 last groups and n_pack below N, two calls in a row with different shapes, the
 full attention shape (262144 LWE ciphertexts of the 2048 x 2048, 128-token product
-into 64 packed ciphertexts) on sampled groups, and end-to-end decryption of packed
-real products computed on the GPU.
+into 64 packed ciphertexts) on sampled groups, more than one pass of the kernels (66
+packed ciphertexts), one slot per ciphertext, a single ciphertext, replays of a
+captured graph, and end-to-end decryption of packed real products computed on the
+GPU.
 """
 
 import numpy as np
@@ -177,3 +179,58 @@ def test_packed_gpu_products_decrypt(method):
         dec = [orc.decode(v, case.delta) for v in ph[t]]
         assert dec[:d_out] == [int(v) for v in y[t]]
         assert all(v == 0 for v in dec[d_out:])
+
+
+def test_several_passes_and_graph_replay():
+    """More than 64 packed ciphertexts (two passes of the kernels, the second starting at
+    group 64) against the oracle on groups 0, 64 and 65; n_pack = 1 and a single LWE
+    ciphertext; the call captured in a HIP graph after the workspace is reserved, replayed
+    three times with eager work in between, each replay equal to the eager result."""
+    print("case: keyswitch two passes, n_pack 1, graph replay", flush=True)
+    r = rl()
+    M = 65 * N + 100  # 66 packed ciphertexts
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(synth.SEED_BASE + 2000 + 78)
+    lwe = torch.empty((M, 2, N + 1), dtype=torch.int64, device="cuda")
+    for p, q in enumerate(P2):
+        lwe[:, p].random_(0, q, generator=gen)
+    ksk = random_key(P2, 1, 14)
+    with r.Context(N, P2, 26) as ctx:
+        k = r.KeySwitchKey(ctx, dev(ksk), 54, 1)
+        raw = r.keyswitch_pack(ctx, k, lwe, N, raw=True)
+        torch.cuda.synchronize()
+        assert raw.shape == (66, 2, 2, N)
+        for g in (0, 64, 65):
+            part = host_u64(lwe[g * N:(g + 1) * N])
+            want = orc.keyswitch_pack(N, P2, 54, 1, part, ksk)
+            assert np.array_equal(host_u64(raw[g:g + 1]), want), f"group {g}"
+        # one slot per ciphertext, and a single ciphertext
+        few = lwe[:3]
+        one = r.keyswitch_pack(ctx, k, few, 1, raw=True)
+        single = r.keyswitch_pack(ctx, k, lwe[:1], N, raw=True)
+        torch.cuda.synchronize()
+        fh = host_u64(few)
+        assert np.array_equal(host_u64(one), orc.keyswitch_pack(N, P2, 54, 1, fh, ksk, 1))
+        assert np.array_equal(host_u64(single), orc.keyswitch_pack(N, P2, 54, 1, fh[:1], ksk, N))
+        # graph capture and replay
+        small = lwe[:2 * N + 10].clone()
+        r.rlwe_workspace_reserve(ctx.handle, r.rlwe_keyswitch_workspace_bytes(
+            ctx.handle, k.handle, small.shape[0], N))
+        eager = r.keyswitch_pack(ctx, k, small, N)
+        torch.cuda.synchronize()
+        out = torch.zeros_like(eager)
+        s = torch.cuda.Stream()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=s):
+            r.keyswitch_pack(ctx, k, small, N, out=out, stream=s)
+        for rep in range(3):
+            out.zero_()
+            graph.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(out, eager), f"replay {rep}"
+            r.keyswitch_pack(ctx, k, lwe[:5], N)  # eager work between replays
+            torch.cuda.synchronize()
+        del graph
+        k.close()
+    del lwe, raw
+    torch.cuda.empty_cache()
