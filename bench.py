@@ -94,12 +94,12 @@ def roofline(products, kt, N, P, traffic=None):
 KERNEL_TRAFFIC = {
     "mask": {"sources": ["k_mask.hip"], "fetch_bytes": 4382392135, "write_bytes": 4766662645,
              "sha256": "b71d09264e517098c1179f16657d1e4fa62f1eaae851294a6d0fdb5115986154"},
-    "ntt": {"sources": ["k_ntt.hip", "ntt_device.hpp"], "fetch_bytes": 5397402760,
-            "write_bytes": 4325817385,
-            "sha256": "8a9fb76ae0be760fb20f2939998f49ce57013adcd497b8cb1e60d410a79a3f7e"},
-    "ksacc": {"sources": ["k_keyswitch.hip", "ntt_device.hpp"], "fetch_bytes": 13262158387,
-              "write_bytes": 539077652,
-              "sha256": "0e6f6cbc7e937e0a412a725a6d9f2fc808760543c85f927d73ec1fdf29a66419"},
+    "ntt": {"sources": ["k_ntt.hip", "ntt_device.hpp"], "fetch_bytes": 5235432167,
+            "write_bytes": 4353380721,
+            "sha256": "907e84ae099765681a079616d1259f2bb3353d5d693e563e9c65c36da68b6166"},
+    "ksacc": {"sources": ["k_keyswitch.hip", "ntt_device.hpp"], "fetch_bytes": 13028230194,
+              "write_bytes": 536870912,
+              "sha256": "c053fe10c49fefbd3c6f4717a8ab487da7073624ee1fa55500764d173b7cad11"},
 }
 
 
