@@ -14,10 +14,8 @@
 // Decomp is the gadget decomposition of TFHE: the coefficient c (CRT of its
 // residues) is rounded to K = beta ell bits, a~ = round(c 2^K / q) mod 2^K, and
 // a~ is written in signed base 2^beta (digits in [-2^(beta-1), 2^(beta-1)), most
-// significant first). The rounding is exact: with y_p = c_p (q/q_p)^-1 mod q_p,
-// c 2^K / q = sum_p y_p 2^K / q_p - kappa 2^K, and each y_p 2^K / q_p is split
-// into its integer part and remainder through 2^K = f_p q_p + g_p. The signed
-// digits are those of a~ + H, H = sum_m 2^(beta-1) 2^(beta m), less 2^(beta-1).
+// significant first). The rounding is exact (decompose, below). The signed digits
+// are those of a~ + H, H = sum_m 2^(beta-1) 2^(beta m), less 2^(beta-1).
 //
 // Kernels (one pass covers up to kKsGroups output groups):
 //   ks_digits_kernel  raw LWE masks [M][P][N+1] -> digits [group][i][m][slot]
@@ -43,34 +41,51 @@ __device__ __forceinline__ KsPtr ks_args() { return (KsPtr)__builtin_amdgcn_kern
 
 // Signed base-2^beta digits of round(c 2^K / q) mod 2^K for the coefficient with
 // residues c0 (prime 0) and c1 (prime 1, NP = 2), into d[0..ell).
+//
+// With y_p = c_p inv_p mod q_p (inv_p = (q/q_p)^-1 mod q_p, 1 for one prime),
+// c 2^K / q = sum_p y_p 2^K / q_p - kappa 2^K, and y_p 2^K / q_p is congruent mod 2^K
+// to c_p inv_p 2^K / q_p = c_p IH_p + c_p G_p / q_p with IH_p = floor(inv_p 2^K / q_p)
+// and G_p = inv_p 2^K mod q_p. So each prime contributes the integer c_p IH_p +
+// floor(c_p G_p / q_p) (one Shoup product) and the fraction rem_p / q_p, rem_p =
+// c_p G_p mod q_p; a~ adds the rounding of the fractions' sum (in [0, P)). That sum is
+// compared with 1/2 (and 3/2) in double precision, error below 2^-50; within 2^-40 of a
+// boundary the comparison is redone exactly in 128-bit integers (a tie is impossible
+// for odd q).
 template <int NP, int ELL>
 __device__ __forceinline__ void decompose(KsPtr a, uint64_t c0, uint64_t c1, int64_t (&d)[ELL]) {
-  uint64_t at;
+  uint64_t at = 0;
   {
     const uint64_t cs[2] = {c0, c1};
-    uint64_t u[NP], rem[NP];
+    uint64_t rem[NP];
+    double fr = 0.0;
 #pragma unroll
     for (int r = 0; r < NP; ++r) {
       const uint64_t p = a->rc.q[r];
-      const uint64_t y = NP == 1 ? cs[r] : mulmod_shoup(cs[r], a->rc.crt_inv[r], a->rc.crt_inv_shoup[r], p);
-      // y 2^K = y f q_p + y g: floor(y g / q_p) is qh or qh + 1
-      const uint64_t qh = __umul64hi(y, a->kc.g_shoup[r]);
-      uint64_t rr = y * a->kc.g[r] - qh * p;  // in [0, 2 q_p)
-      u[r] = y * a->kc.f[r] + qh;
+      const uint64_t c = cs[r];
+      const uint64_t qh = __umul64hi(c, a->kc.g_shoup[r]);  // floor(c G / q_p) or 1 less
+      uint64_t rr = c * a->kc.g[r] - qh * p;                 // in [0, 2 q_p)
+      uint64_t u = c * a->kc.f[r] + qh;
       if (rr >= p) {
         rr -= p;
-        ++u[r];
+        ++u;
       }
       rem[r] = rr;
+      at += u;
+      fr += (double)rr * a->kc.rq[r];
     }
-    if (NP == 1) {
-      at = u[0] + (2 * rem[0] >= a->rc.q[0] ? 1 : 0);
-    } else {
-      // fraction rem_0 / q_0 + rem_1 / q_1 in [0, 2) against 1/2 and 3/2
-      const u128 Q = make_u128(a->rc.Q_hi, a->rc.Q_lo);
-      const u128 F = 2 * ((u128)rem[0] * a->rc.q[NP - 1] + (u128)rem[NP - 1] * a->rc.q[0]);
-      at = u[0] + u[NP - 1] + (F >= Q ? 1 : 0) + (F >= 3 * Q ? 1 : 0);
+    // round(fraction sum): + 1 from 1/2, + 1 more from 3/2 (two primes)
+    uint32_t up = (fr >= 0.5 ? 1u : 0u) + (NP == 2 && fr >= 1.5 ? 1u : 0u);
+    const bool near = fabs(fr - 0.5) < 0x1p-40 || (NP == 2 && fabs(fr - 1.5) < 0x1p-40);
+    if (near) {  // exact: compare 2 sum_p rem_p (q / q_p) with q and 3q
+      if (NP == 1) {
+        up = 2 * rem[0] >= a->rc.q[0] ? 1u : 0u;
+      } else {
+        const u128 Q = make_u128(a->rc.Q_hi, a->rc.Q_lo);
+        const u128 F = 2 * ((u128)rem[0] * a->rc.q[NP - 1] + (u128)rem[NP - 1] * a->rc.q[0]);
+        up = (F >= Q ? 1u : 0u) + (F >= 3 * Q ? 1u : 0u);
+      }
     }
+    at += up;
   }
   const uint32_t beta = a->kc.beta;
   const uint64_t v = (at & a->kc.kmask) + a->kc.H;
@@ -81,7 +96,6 @@ __device__ __forceinline__ void decompose(KsPtr a, uint64_t c0, uint64_t c1, int
     d[m] = (int64_t)((v >> sh) & bmask) - (int64_t)half;
   }
 }
-
 
 // Forward butterfly without reductions (Harvey's lazy form, one step further): the
 // product w Y mod p is taken below 4p for any 64-bit Y (truncated-quotient Shoup),

@@ -978,10 +978,12 @@ int rlwe_ksk_load(rlwe_ctx* ctx, const uint64_t* ksk_dev, uint32_t log2_base, ui
   kc.H = 0;
   for (uint32_t m = 0; m < levels; ++m) kc.H += (1ull << (log2_base - 1)) << (log2_base * m);
   for (uint32_t r = 0; r < rc.P; ++r) {
-    const u128 two_k = (u128)1 << kc.K, q = rc.q[r];
-    kc.f[r] = (uint64_t)(two_k / q);  // mod 2^64 (exact unless K = 64 and q = 1)
-    kc.g[r] = (uint64_t)(two_k % q);
+    // inv_p 2^K = f q_p + g (inv_p < 2^54, so the product fits in 118 bits)
+    const u128 x = (u128)(rc.P == 1 ? 1 : rc.crt_inv[r]) << kc.K, q = rc.q[r];
+    kc.f[r] = (uint64_t)(x / q);  // mod 2^64
+    kc.g[r] = (uint64_t)(x % q);
     kc.g_shoup[r] = (uint64_t)(((u128)kc.g[r] << 64) / q);
+    kc.rq[r] = 1.0 / (double)q;
   }
   const size_t N = rc.N;
   const size_t bytes = N * levels * rc.P * 2 * N * 16;

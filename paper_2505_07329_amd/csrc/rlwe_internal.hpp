@@ -215,9 +215,11 @@ struct KsConst {
   uint32_t beta, ell, K;             // digit bits, levels, K = beta ell rounding bits (<= 64)
   uint64_t kmask;                    // 2^K - 1
   uint64_t H;                        // sum_m 2^(beta-1) 2^(beta m) mod 2^64
-  uint64_t f[kMaxPrimes];            // floor(2^K / q_p) mod 2^64
-  uint64_t g[kMaxPrimes];            // 2^K mod q_p
+  // with inv_p = (q / q_p)^-1 mod q_p (1 for one prime):
+  uint64_t f[kMaxPrimes];            // floor(inv_p 2^K / q_p) mod 2^64
+  uint64_t g[kMaxPrimes];            // inv_p 2^K mod q_p
   uint64_t g_shoup[kMaxPrimes];      // floor(g 2^64 / q_p)
+  double rq[kMaxPrimes];             // 1 / q_p (estimate only; near ties are redone exactly)
 };
 // Arguments of the KeySwitch kernels (read in place through the kernarg segment).
 struct KsArgs {

@@ -234,3 +234,47 @@ def test_several_passes_and_graph_replay():
         k.close()
     del lwe, raw
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("primes,beta,ell", [(P2, 54, 1), (P2, 27, 2), (P1, 12, 3)])
+def test_decomposition_near_rounding_ties(primes, beta, ell):
+    """Mask coefficients whose scaled value c 2^K / q lies within 2^-40 of a rounding tie
+    (x + 1/2), where the GPU's double-precision test hands over to exact integer
+    arithmetic: the packed outputs equal the oracle's."""
+    print(f"case: keyswitch near ties P={len(primes)} beta={beta} ell={ell}", flush=True)
+    r = rl()
+    q = orc.modulus(primes)
+    K = beta * ell
+    g = np.random.default_rng(4242 + K)
+    vals = []
+    for v in g.integers(0, 1 << min(K, 62), size=N, dtype=np.uint64).tolist():
+        # c 2^K / q just below v + 1/2 (and the next integer just above it)
+        c = ((2 * v + 1) * q) >> (K + 1)
+        vals += [c % q, (c + 1) % q]
+    # the two coefficients next to the tie of the fraction itself, c 2^K = (q -+ 1)/2 mod q
+    inv2k = pow(pow(2, K, q), -1, q)
+    vals += [((q - 1) // 2) * inv2k % q, ((q + 1) // 2) * inv2k % q]
+    M = 3
+    lwe = np.zeros((M, len(primes), N + 1), dtype=np.uint64)
+    flat = vals[:M * N]
+    for j in range(M):
+        for i in range(N):
+            c = flat[(j * N + i) % len(flat)]
+            lwe[j, :, i] = [c % p for p in primes]
+    lwe[:, :, N] = uniform(primes, (M,), 1, K)[:, :, 0]
+    lwe[M - 1, :, :2] = np.array([[vals[-2] % p, vals[-1] % p] for p in primes], dtype=np.uint64)
+    # these values really are near a tie (one prime: only the last two can be, as c 2^K / q
+    # moves by 2^K / q = 2^-18 per unit of c)
+    near = 0
+    for c in flat[:64] + vals[-2:]:
+        frac = (c * (1 << (K + 1))) % (2 * q)  # 2 q frac(c 2^K / q)
+        near += abs(frac - q) * (1 << 40) < 2 * q
+    assert near >= (2 if len(primes) == 1 else 32)
+    ksk = random_key(primes, ell, 90 + K)
+    want = orc.keyswitch_pack(N, primes, beta, ell, lwe, ksk, N)
+    with r.Context(N, primes, 26) as ctx:
+        k = r.KeySwitchKey(ctx, dev(ksk), beta, ell)
+        got = r.keyswitch_pack(ctx, k, dev(lwe), N, raw=True)
+        torch.cuda.synchronize()
+        k.close()
+    assert np.array_equal(host_u64(got), want)
