@@ -139,6 +139,36 @@ def keyswitch_cpu_baseline(prod, N, primes, d_in, beta, ell):
                       "packed); rates combined per MAC"}
 
 
+def clear_gemm_context(torch, dev, T, d_in, d_out, he_value):
+    """Context only: the same product on clear int8 data (torch._int_mm, int32 results) on the
+    same GPU, and the encrypted product's slowdown against it (the HE overhead factor)."""
+    try:
+        a = torch.randint(-127, 128, (T, d_in), dtype=torch.int8, device=dev)
+        b = torch.randint(-127, 128, (d_in, d_out), dtype=torch.int8, device=dev)
+        kind = "int8 torch._int_mm"
+        f = lambda: torch._int_mm(a, b)  # noqa: E731
+        f()
+    except Exception:  # no int8 GEMM in this build of torch: half precision instead
+        a = torch.randn((T, d_in), dtype=torch.float16, device=dev)
+        b = torch.randn((d_in, d_out), dtype=torch.float16, device=dev)
+        kind = "fp16 torch.matmul (no int8 GEMM available)"
+        f = lambda: a @ b  # noqa: E731
+    for _ in range(5):
+        f()
+    reps = 200
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        f()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    value = T * d_in * d_out / (ms * 1e-3)
+    return {"kind": kind, "value": value, "unit": "MAC/s", "ms": ms,
+            "he_overhead": value / he_value}
+
+
 def kernel_traffic(kind):
     import hashlib
     rec = KERNEL_TRAFFIC.get(kind)
@@ -816,6 +846,7 @@ def main():
     if pack_roof:
         result["kernels_ms"]["pack"] = pack_roof.pop("ms")
         result["roofline_pack"] = pack_roof
+    result["clear_gemm_context"] = clear_gemm_context(torch, dev, T, d_in, d_out, macs * args.steps / wall)
     if ks_roof:
         result["kernels_ms"].update({"ks_digits": ks_ms["dig"], "ks_accum": ks_ms["acc"],
                                      "ks_finish": ks_ms["fin"]})
