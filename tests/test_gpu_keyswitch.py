@@ -144,11 +144,12 @@ def test_attention_shape_sampled_groups():
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("method", ["ntt", "toeplitz"])
+@pytest.mark.parametrize("method", ["ntt", "toeplitz", "rowpack"])
 def test_packed_gpu_products_decrypt(method):
-    """Product on the GPU (raw outputs), then packing on the GPU with a real key: every
-    slot decrypts under the packing key to W x, the empty slots to 0, and the packed
-    ciphertexts equal the oracle's packing of the same LWE ciphertexts."""
+    """Product on the GPU (raw outputs; both mask methods, and packed rows), then packing on
+    the GPU with a real key: every slot decrypts under the packing key to W x, the empty
+    slots to 0, and the packed ciphertexts equal the oracle's packing of the same LWE
+    ciphertexts."""
     print(f"case: keyswitch end to end, {method}", flush=True)
     r = rl()
     d_in, d_out, T, log2_t = 2048, 1500, 2, 26
@@ -160,7 +161,8 @@ def test_packed_gpu_products_decrypt(method):
     E = synth.rounded_gaussian(g_e, (N, 1, N))
     S_dst = synth.ternary(g_s, N)
     ksk = orc.ksk_gen(N, P2, 54, 1, case.S, S_dst, A, E)
-    flag = r.RLWE_W_NTT if method == "ntt" else r.RLWE_W_TOEPLITZ
+    flag = {"ntt": r.RLWE_W_NTT, "toeplitz": r.RLWE_W_TOEPLITZ,
+            "rowpack": r.RLWE_W_NTT | r.RLWE_W_ROWPACK}[method]
     with r.Context(N, P2, log2_t) as ctx:
         w = r.Weights(ctx, dev(case.W), r.RLWE_W_FWD | flag)
         lwe = r.matmul(ctx, w, dev(case.ct), raw=True)  # (T, d_out, P, N+1)
@@ -171,7 +173,10 @@ def test_packed_gpu_products_decrypt(method):
         pk = host_u64(packed)
         w.close()
         k.close()
-    assert np.array_equal(lw, orc.matmul_clear(N, P2, case.W, case.ct))
+    if method == "rowpack":  # two rows per weight polynomial (K = N/2)
+        assert np.array_equal(lw, orc.matmul_rowpacked(N, P2, case.W, case.ct))
+    else:
+        assert np.array_equal(lw, orc.matmul_clear(N, P2, case.W, case.ct))
     assert np.array_equal(pk, orc.keyswitch_pack(N, P2, 54, 1, lw.reshape(-1, 2, N + 1), ksk, d_out))
     y = case.x.astype(np.int64) @ case.W.astype(np.int64).T
     ph = orc.rlwe_decrypt_slots(N, P2, S_dst, pk)
