@@ -156,8 +156,7 @@ __global__ void __launch_bounds__(kInvThreads, LC == 2 ? 4 : 1) ntt_mask_kernel(
       for (int r = 0; r < NP; ++r)
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-          const uint64_t v = mul_shoup(x[r][k], bt->ntt.ninv[r], bt->ntt.ninv_shoup[r], p[r]);
-          c[r][k] = v >= p[r] ? v - p[r] : v;
+          c[r][k] = reduce4(reduce_barrett(x[r][k], md[r]), p[r]);  // 1/N is in the weights
         }
       for (uint32_t rho = 0; rho < n_o && j * n_o + rho < rows; ++rho) {
         const uint32_t h = (rho + 1) * slot - 1;
@@ -240,7 +239,7 @@ __global__ void __launch_bounds__(kInvThreads, LC == 2 ? 4 : 1) ntt_mask_kernel(
 // j n_o + rho of the group fills coefficients [rho K, rho K + K) reversed:
 // w_hat[rho K + K - 1 - k] = w_{j n_o + rho}[k] (zero past the last row and N).
 // what[((j L + i) P + p) N + lane_major(pos)], bit-reversed position pos, residues
-// in [0, p).
+// in [0, p), multiplied by N^-1 (the factor of the inverse transform).
 __global__ void __launch_bounds__(kThreads) ntt_weights_kernel(MatArgs m, NttConst ntt,
                                                                RingConst rc, uint64_t* what) {
   __shared__ uint64_t lds[kLdsWords];
@@ -261,8 +260,10 @@ __global__ void __launch_bounds__(kThreads) ntt_weights_kernel(MatArgs m, NttCon
   }
   ntt_forward(x, lds, ntt.fwd[p_idx], p, tid);
   uint64_t* dst = what + (size_t)loc * kN;
+  const uint64_t ninv = ntt.ninv[p_idx], ninv_shoup = ntt.ninv_shoup[p_idx];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) dst[lane_major(16 * tid + k)] = reduce4(x[k], p);
+  for (int k = 0; k < 16; ++k)  // the inverse transform's factor 1/N, applied once here
+    dst[lane_major(16 * tid + k)] = mulmod_shoup(reduce4(x[k], p), ninv, ninv_shoup, p);
 }
 
 hipError_t launch_ntt_mask_fwd(const Batch& b, hipStream_t s) {

@@ -9,7 +9,8 @@
 // root of unity): a Cooley-Tukey forward transform from natural to bit-reversed
 // order and a Gentleman-Sande inverse from bit-reversed to natural order, both
 // with the twist folded into their twiddles psi^(+-bitrev(k)); the factor 1/N
-// of the inverse is folded into the output constants. For token t and output
+// of the inverse is folded into the resident weights (product) or applied at the
+// end (KeySwitch packing). For token t and output
 // row j the polynomial C = sum_i A_{t,i} * w_hat_ij (Sec. 4.3, reversed weight
 // encoding) gives the SampleExtract mask at N - 1 as a'[n] = C[N - 1 - n]
 // (Sec. 3.2), so a'[n] is the inverse transform's coefficient N - 1 - n. The two

@@ -275,7 +275,7 @@ int build_ntt(rlwe_ctx* ctx) {
     ctx->ntt.rq[pi][0] = (uint64_t)(rq >> 64);
     ctx->ntt.rq[pi][1] = (uint64_t)rq;
     ctx->ntt.ninv_shoup[pi] = (uint64_t)(((u128)ninv << 64) / q);
-    const uint64_t c = mulmod_h(ninv, rc.crt_inv[pi], q);
+    const uint64_t c = rc.crt_inv[pi];  // N^-1 is folded into the transformed weights
     ctx->ntt.crt[pi] = c;
     ctx->ntt.crt_shoup[pi] = (uint64_t)(((u128)c << 64) / q);
     // h = floor(c 2^128 / q) mod 2^128 = c floor(2^128 / q) + floor(c (2^128 mod q) / q)

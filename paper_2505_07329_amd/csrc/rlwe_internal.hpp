@@ -44,7 +44,8 @@ constexpr uint32_t kTokTile = 8;  // tokens per workgroup of the NTT product ker
 struct NttConst {
   const uint64_t* fwd[kMaxPrimes];  // [N] (psi^bitrev(k), Shoup companion), device
   const uint64_t* inv[kMaxPrimes];  // [N] (psi^-bitrev(k), Shoup companion), device
-  uint64_t crt[kMaxPrimes];         // N^-1 (q / q_p)^-1 mod q_p (N^-1 mod q_0 for one prime)
+  uint64_t crt[kMaxPrimes];         // (q / q_p)^-1 mod q_p (1 for one prime); the factor N^-1 of
+                                    // the inverse transform is folded into the NTT weights
   uint64_t crt_shoup[kMaxPrimes];
   uint64_t ninv[kMaxPrimes];        // N^-1 mod q_p
   uint64_t ninv_shoup[kMaxPrimes];
