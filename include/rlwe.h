@@ -276,7 +276,7 @@ int rlwe_weights_rows_per_product(const rlwe_weights* w, uint32_t transpose, uin
 /* KeySwitch packing (Sec. 3.2 KeySwitching and Rotate; Sec. 4.3 Eq. (pack_rotate)):
  * the LWE outputs of ct_matmul_clear are key-switched to RLWE ciphertexts and
  * rotated into the slots of packed RLWE ciphertexts, which are then switched to
- * q_out; N = 4096 only.
+ * q_out; N <= 4096 (tuned kernels at N = 4096, plain ones below).
  *
  * Decomp (the gadget decomposition of TFHE, to which Sec. 3.2 refers): a mask
  * coefficient c in [0, q) is rounded to K = log2_base * levels bits, a~ =
@@ -295,7 +295,7 @@ int rlwe_weights_rows_per_product(const rlwe_weights* w, uint32_t transpose, uin
  *   log2_base  digit bits, 1 <= log2_base <= 54, 2^(log2_base-1) below every prime
  *   levels     1 <= levels <= 4, log2_base * levels <= 64 (e.g. 54 and 1 for two
  *              54-bit primes; 12 and 3 for one)
- * Errors: RLWE_EINVAL (null), RLWE_EPARAM (N != 4096, bad gadget), RLWE_ENOMEM.
+ * Errors: RLWE_EINVAL (null), RLWE_EPARAM (N > 4096, bad gadget), RLWE_ENOMEM.
  * Synchronises `stream` (set-up call). */
 typedef struct rlwe_ksk rlwe_ksk;
 int rlwe_ksk_load(rlwe_ctx* ctx, const uint64_t* ksk_dev, uint32_t log2_base, uint32_t levels,

@@ -1,5 +1,6 @@
 // KeySwitch packing of LWE outputs into RLWE ciphertexts (Sec. 3.2 KeySwitching and
-// Rotate, Sec. 4.3 Eq. (pack_rotate)), N = 4096.
+// Rotate, Sec. 4.3 Eq. (pack_rotate)): tuned kernels for N = 4096, plain ones for
+// other ring degrees up to 4096.
 //
 // LWE ciphertext g n_pack + s (mask a, body b) goes to slot s of packed output g:
 //   out_g = sum_s X^s ((0, b_s) - sum_i sum_m Decomp_m(a_s[i]) KSK_{i,m}).
@@ -167,7 +168,7 @@ template <int NP, int ELL>
 __global__ void __launch_bounds__(256) ks_digits_kernel(KsArgs) {
   __shared__ int64_t tile[kTile][kTile + 1];
   const KsPtr a = ks_args();
-  const uint32_t N = kN;
+  const uint32_t N = a->rc.N;  // any N that is a multiple of 64
   const uint32_t tiles = N / kTile;
   const uint32_t blk = linear_block();
   const uint32_t gb = blk / (tiles * tiles);
@@ -400,14 +401,200 @@ __global__ void __launch_bounds__(kThreads) ksk_fwd_kernel(KsArgs) {
   }
 }
 
+// ---------------------------------------------------------------- other ring degrees
+// For N != 4096 (64 <= N <= 4096) the same computation runs on 256 threads with
+// plain radix-2 transforms in LDS, one stage per barrier, exact Shoup products (values
+// below 4p forward, below 2p inverse), the key in natural bit-reversed order. These
+// serve small rings (N = 2048 for one 54-bit prime); speed is not their aim.
+namespace {
+constexpr int kGenThreads = 256;
+
+// Cooley-Tukey, natural -> bit-reversed order, in place in LDS; inputs and outputs
+// below 4p. Ends with a barrier.
+__device__ void gen_forward(uint64_t* x, uint32_t N, const uint64_t* tw, uint64_t p) {
+  for (uint32_t t = N / 2; t >= 1; t >>= 1) {
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < N / 2; j += kGenThreads) {
+      const uint32_t pos = (j / t) * 2 * t + (j % t);
+      uint64_t X = x[pos], Y = x[pos + t];
+      ct_bfly(X, Y, ld_tw(tw, N / (2 * t) + pos / (2 * t)), p);
+      x[pos] = X;
+      x[pos + t] = Y;
+    }
+  }
+  __syncthreads();
+}
+
+// Gentleman-Sande, bit-reversed -> natural order, without the factor 1/N, in place
+// in LDS; inputs and outputs below 2p. Ends with a barrier.
+__device__ void gen_inverse(uint64_t* x, uint32_t N, const uint64_t* tw, uint64_t p) {
+  const uint64_t p2 = 2 * p;
+  for (uint32_t t = 1; t < N; t <<= 1) {
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < N / 2; j += kGenThreads) {
+      const uint32_t pos = (j / t) * 2 * t + (j % t);
+      const uint64_t X = x[pos], Y = x[pos + t];
+      const Tw w = ld_tw(tw, N / (2 * t) + pos / (2 * t));
+      const uint64_t sum = X + Y;
+      x[pos] = sum >= p2 ? sum - p2 : sum;
+      x[pos + t] = mul_shoup(X + p2 - Y, w.w, w.wp, p);
+    }
+  }
+  __syncthreads();
+}
+}  // namespace
+
+// Key in the NTT domain, any N: khat[((i ell + m) P + p) 2 + c][pos][2], natural
+// bit-reversed position order, residue and Shoup companion.
+__global__ void __launch_bounds__(kGenThreads) ksk_fwd_generic(KsArgs) {
+  __shared__ uint64_t x[kN];
+  const KsPtr a = ks_args();
+  const uint32_t N = a->rc.N, P = a->rc.P;
+  const uint32_t loc = linear_block();  // ((i ell + m) 2 + c) P + p
+  if (loc >= N * a->kc.ell * 2 * P) return;
+  const uint32_t r = loc % P, c = (loc / P) % 2, im = loc / (2 * P);
+  const uint64_t p = a->rc.q[r];
+  const uint64_t* src = a->ksk_in + (size_t)loc * N;
+  for (uint32_t n = threadIdx.x; n < N; n += kGenThreads) x[n] = src[n];
+  gen_forward(x, N, a->ntt.fwd[r], p);
+  uint64_t* dst = a->khat_out + (((size_t)im * P + r) * 2 + c) * N * 2;
+  const uint64_t r1 = a->ntt.rq[r][0], r0 = a->ntt.rq[r][1];
+  for (uint32_t n = threadIdx.x; n < N; n += kGenThreads) {
+    const uint64_t v = reduce4(x[n], p);
+    uint64_t cp = v * r1 + __umul64hi(v, r0);
+    cp += (0 - cp * p) >= p ? 1 : 0;
+    dst[2 * n] = v;
+    dst[2 * n + 1] = cp;
+  }
+}
+
+// Accumulation, any N: one workgroup per (group of the pass, chunk of 64 key
+// coefficients, prime); thread t holds positions t + 256 e, e < N / 256.
+__global__ void __launch_bounds__(kGenThreads) ks_accum_generic(KsArgs) {
+  __shared__ uint64_t x[kN];
+  const KsPtr a = ks_args();
+  const uint32_t N = a->rc.N, P = a->rc.P, GB = a->GB, ell = a->kc.ell;
+  const uint32_t chunks = N / kKsChunk;
+  const uint32_t blk = linear_block();
+  const uint32_t r = blk % P, chunk = (blk / P) % chunks, gb = blk / P / chunks;
+  if (gb >= GB) return;
+  const uint64_t p = a->rc.q[r], pn = 0 - p;
+  const InvMod md{pn, 8 * p, a->ntt.bm[r]};
+  const uint64_t* tw = a->ntt.fwd[r];
+  const uint32_t per = (N + kGenThreads - 1) / kGenThreads;  // at most 16
+  const uint32_t tid = threadIdx.x;
+  uint64_t accA[16], accB[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) accA[e] = accB[e] = 0;
+  const int64_t* dig = a->dig + (size_t)gb * N * ell * N;
+  for (uint32_t il = 0; il < kKsChunk; ++il) {
+    const uint32_t i = chunk * kKsChunk + il;
+    for (uint32_t m = 0; m < ell; ++m) {
+      __syncthreads();  // the previous transform's products have read x
+      const int64_t* dsrc = dig + ((size_t)i * ell + m) * N;
+      for (uint32_t n = tid; n < N; n += kGenThreads) {
+        const int64_t v = dsrc[n];
+        x[n] = v < 0 ? (uint64_t)(v + (int64_t)p) : (uint64_t)v;
+      }
+      gen_forward(x, N, tw, p);
+      const uint64_t* kh = a->khat + (((size_t)i * ell + m) * P + r) * 4 * N;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const uint32_t pos = tid + kGenThreads * e;
+        if ((uint32_t)e < per && pos < N) {
+          const Tw ka = ld_tw(kh, pos), kb = ld_tw(kh + 2 * N, pos);
+          accA[e] += mul_shoup4(x[pos], ka.w, ka.wp, pn);
+          accB[e] += mul_shoup4(x[pos], kb.w, kb.wp, pn);
+        }
+      }
+    }
+    if ((il & 15) == 15) {  // at most 64 products below 4p since the last reduction
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        accA[e] = reduce_barrett(accA[e], md);
+        accB[e] = reduce_barrett(accB[e], md);
+      }
+    }
+  }
+  uint64_t* dst = a->part + (((size_t)gb * chunks + chunk) * P + r) * 2 * N;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const uint32_t pos = tid + kGenThreads * e;
+    if ((uint32_t)e < per && pos < N) {
+      dst[pos] = reduce4(reduce_barrett(accA[e], md), p);
+      dst[N + pos] = reduce4(reduce_barrett(accB[e], md), p);
+    }
+  }
+}
+
+// Finish, any N: one workgroup per group of the pass.
+template <bool RAW, int NP>
+__global__ void __launch_bounds__(kGenThreads) ks_finish_generic(KsArgs) {
+  __shared__ uint64_t x[NP][kN];
+  const KsPtr a = ks_args();
+  const uint32_t gb = linear_block();
+  if (gb >= a->GB) return;
+  const uint32_t g = a->g0 + gb, N = a->rc.N, chunks = N / kKsChunk;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t c = 0; c < 2; ++c) {
+    __syncthreads();  // the previous component's outputs have been read
+#pragma unroll
+    for (int r = 0; r < NP; ++r) {
+      const uint64_t p = a->rc.q[r];
+      const InvMod md{0 - p, 8 * p, a->ntt.bm[r]};
+      for (uint32_t n = tid; n < N; n += kGenThreads) {
+        uint64_t v = 0;
+        for (uint32_t ch = 0; ch < chunks; ++ch)  // at most 64 terms below p
+          v += a->part[((((size_t)gb * chunks + ch) * NP + r) * 2 + c) * N + n];
+        x[r][n] = reduce4(reduce_barrett(v, md), p);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NP; ++r) gen_inverse(x[r], N, a->ntt.inv[r], a->rc.q[r]);
+    for (uint32_t n = tid; n < N; n += kGenThreads) {
+      uint64_t v[NP];
+#pragma unroll
+      for (int r = 0; r < NP; ++r) {
+        const uint64_t p = a->rc.q[r];
+        uint64_t t = mul_shoup(x[r][n], a->ntt.ninv[r], a->ntt.ninv_shoup[r], p);
+        t = t >= p ? t - p : t;
+        uint64_t b = 0;
+        const uint64_t j = (uint64_t)g * a->n_pack + n;
+        if (c == 1 && n < a->n_pack && j < a->M) b = a->lwe[(j * NP + r) * (N + 1) + N];
+        v[r] = b >= t ? b - t : b + p - t;  // (b - sum) mod p; b = 0 for the mask
+      }
+      if (RAW) {
+        uint64_t* o = (uint64_t*)a->out + (((size_t)g * 2 + c) * NP) * N;
+#pragma unroll
+        for (int r = 0; r < NP; ++r) o[(size_t)r * N + n] = v[r];
+      } else {
+        const RingConst rc = kernarg_load(&a->rc);
+        u128 V = v[0];
+        if (NP == 2) {
+          const uint64_t y0 = mulmod_shoup(v[0], rc.crt_inv[0], rc.crt_inv_shoup[0], rc.q[0]);
+          const uint64_t y1 =
+              mulmod_shoup(v[NP - 1], rc.crt_inv[NP - 1], rc.crt_inv_shoup[NP - 1], rc.q[NP - 1]);
+          V = (u128)y0 * rc.q[NP - 1] + (u128)y1 * rc.q[0];
+          const u128 Q = make_u128(rc.Q_hi, rc.Q_lo);
+          if (V >= Q) V -= Q;
+        }
+        ((uint32_t*)a->out)[((size_t)g * 2 + c) * N + n] = switch_exact((i128)V, rc);
+      }
+    }
+  }
+}
+
 hipError_t launch_ksk_fwd(const KsArgs& a, hipStream_t s) {
-  const uint32_t blocks = kN * a.kc.ell * 2 * a.rc.P;
-  hipLaunchKernelGGL(ksk_fwd_kernel, grid_for(blocks), dim3(kThreads), 0, s, a);
+  const uint32_t blocks = a.rc.N * a.kc.ell * 2 * a.rc.P;
+  if (a.rc.N == kN)
+    hipLaunchKernelGGL(ksk_fwd_kernel, grid_for(blocks), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(ksk_fwd_generic, grid_for(blocks), dim3(kGenThreads), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_ks_digits(const KsArgs& a, hipStream_t s) {
-  const uint32_t tiles = kN / kTile;
+  const uint32_t tiles = a.rc.N / kTile;
   const uint32_t blocks = a.GB * tiles * tiles;
   const dim3 g = grid_for(blocks);
   switch (a.rc.P * 8 + a.kc.ell) {
@@ -425,6 +612,11 @@ hipError_t launch_ks_digits(const KsArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_ks_accum(const KsArgs& a, hipStream_t s) {
+  if (a.rc.N != kN) {
+    const uint32_t blocks = a.GB * (a.rc.N / kKsChunk) * a.rc.P;
+    hipLaunchKernelGGL(ks_accum_generic, grid_for(blocks), dim3(kGenThreads), 0, s, a);
+    return hipGetLastError();
+  }
   const uint32_t blocks = a.GB * kKsChunks * a.rc.P;  // kKsChunks P is a multiple of 8
   const dim3 g = grid_for(blocks);
   switch (a.kc.ell) {
@@ -439,6 +631,20 @@ hipError_t launch_ks_accum(const KsArgs& a, hipStream_t s) {
 
 hipError_t launch_ks_finish(const KsArgs& a, hipStream_t s) {
   const dim3 g = grid_for(a.GB);
+  if (a.rc.N != kN) {
+    if (a.rc.P == 2) {
+      if (a.raw)
+        hipLaunchKernelGGL((ks_finish_generic<true, 2>), g, dim3(kGenThreads), 0, s, a);
+      else
+        hipLaunchKernelGGL((ks_finish_generic<false, 2>), g, dim3(kGenThreads), 0, s, a);
+    } else {
+      if (a.raw)
+        hipLaunchKernelGGL((ks_finish_generic<true, 1>), g, dim3(kGenThreads), 0, s, a);
+      else
+        hipLaunchKernelGGL((ks_finish_generic<false, 1>), g, dim3(kGenThreads), 0, s, a);
+    }
+    return hipGetLastError();
+  }
   if (a.rc.P == 2) {
     if (a.raw)
       hipLaunchKernelGGL((ks_finish_kernel<true, 2>), g, dim3(kInvThreads), 0, s, a);

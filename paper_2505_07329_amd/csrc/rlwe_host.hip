@@ -103,6 +103,7 @@ struct rlwe_ctx {
   size_t ws_bytes = 0;
   Profiler* prof = nullptr;
   bool ntt_ok = false;      // the NTT method is available (N = kNttN)
+  bool tw_ok = false;       // twiddle tables built (N <= kNttN): KeySwitch packing available
   NttConst ntt{};
   uint64_t* ntt_tables = nullptr;
 };
@@ -296,7 +297,8 @@ int build_ntt(rlwe_ctx* ctx) {
     ctx->ntt.fwd[pi] = ctx->ntt_tables + (2 * pi) * per;
     ctx->ntt.inv[pi] = ctx->ntt_tables + (2 * pi + 1) * per;
   }
-  ctx->ntt_ok = true;
+  ctx->ntt_ok = N == kNttN;  // the tuned transforms of the product are written for N = 4096
+  ctx->tw_ok = true;
   return RLWE_OK;
 }
 
@@ -381,7 +383,7 @@ int rlwe_params_init(const rlwe_params* p, int hip_device, rlwe_ctx** out) {
   ctx->device = hip_device;
   ctx->log2_t = p->log2_t;
   ctx->rc = rc;
-  if (N == kNttN) {
+  if (N <= kNttN) {
     const int r = build_ntt(ctx);
     if (r != RLWE_OK) {
       if (ctx->ntt_tables) hipFree(ctx->ntt_tables);
@@ -956,7 +958,7 @@ int rlwe_ksk_load(rlwe_ctx* ctx, const uint64_t* ksk_dev, uint32_t log2_base, ui
   if (!ctx || !ksk_dev || !out) return fail(RLWE_EINVAL, "rlwe_ksk_load: null argument");
   *out = nullptr;
   const RingConst& rc = ctx->rc;
-  if (!ctx->ntt_ok) return fail(RLWE_EPARAM, "KeySwitch packing needs N = %u", kNttN);
+  if (!ctx->tw_ok) return fail(RLWE_EPARAM, "KeySwitch packing needs N <= %u", kNttN);
   if (levels < 1 || levels > kMaxLevels)
     return fail(RLWE_EPARAM, "levels = %u outside [1, %u]", levels, kMaxLevels);
   if (log2_base < 1 || log2_base * levels > 64)

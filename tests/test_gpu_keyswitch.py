@@ -107,10 +107,10 @@ def test_calls_in_a_row_and_edge_cases():
                 r.KeySwitchKey(ctx, dev(ksk), beta, ell)
             assert ei.value.code == r.RLWE_EPARAM
         k.close()
-    with r.Context(2048, synth.PRIMES_2048, 24) as ctx:
+    with r.Context(8192, (18014398508400641,), 24) as ctx:  # prime, = 1 mod 16384: a valid ring
         with pytest.raises(r.RlweError) as ei:
             r.KeySwitchKey(ctx, dev(ksk[:1]), 12, 3)
-        assert ei.value.code == r.RLWE_EPARAM
+        assert ei.value.code == r.RLWE_EPARAM  # packing is offered up to N = 4096
 
 
 def test_attention_shape_sampled_groups():
@@ -283,3 +283,66 @@ def test_decomposition_near_rounding_ties(primes, beta, ell):
         torch.cuda.synchronize()
         k.close()
     assert np.array_equal(host_u64(got), want)
+
+
+@pytest.mark.parametrize("N_,primes,beta,ell,M,n_pack", [
+    (2048, synth.PRIMES_2048, 12, 3, 2048 + 300, 2048),
+    (2048, synth.PRIMES_2048, 18, 2, 700, 256),
+    (256, P2, 54, 1, 600, 256),
+    (64, P2, 27, 2, 100, 50),
+])
+def test_pack_smaller_rings_matches_oracle(N_, primes, beta, ell, M, n_pack):
+    """The plain kernels for N below 4096 against the oracle: raw and switched outputs."""
+    print(f"case: keyswitch N={N_} P={len(primes)} beta={beta} ell={ell} M={M}", flush=True)
+    r = rl()
+    g = synth.rng(0, synth.P_MISC, 500 + N_)
+    lwe = synth.uniform_mod_primes(g, primes, (M,), N_ + 1)
+    ksk = synth.uniform_mod_primes(g, primes, (N_, ell, 2), N_)
+    want = orc.keyswitch_pack(N_, primes, beta, ell, lwe, ksk, n_pack)
+    with r.Context(N_, primes, 24) as ctx:
+        k = r.KeySwitchKey(ctx, dev(ksk), beta, ell)
+        got = r.keyswitch_pack(ctx, k, dev(lwe), n_pack, raw=True)
+        sw = r.keyswitch_pack(ctx, k, dev(lwe), n_pack)
+        torch.cuda.synchronize()
+        k.close()
+    assert np.array_equal(host_u64(got), want)
+    assert np.array_equal(sw.cpu().numpy().view(np.uint32), orc.rlwe_modswitch_bits(primes, want, 32))
+
+
+def test_config1_products_packed_and_decrypted():
+    """The 256 x 256 workload at N = 2048, one prime, t = 2^24, 16 tokens: product on the GPU
+    (matrix cores, raw outputs), packing of each token's 256 outputs into one RLWE ciphertext
+    with a real key, switch to 2^32: every slot decrypts to W x after the switch, and the
+    packed ciphertexts equal the oracle's."""
+    print("case: keyswitch config 1 end to end", flush=True)
+    r = rl()
+    N1, primes, log2_t, beta, ell = 2048, synth.PRIMES_2048, 24, 12, 3
+    case = make_case(N1, primes, log2_t, 256, 256, 16, config=1, salt=32)
+    g_a = synth.rng(1, synth.P_MASK, 41)
+    g_s = synth.rng(1, synth.P_SECRET, 41)
+    g_e = synth.rng(1, synth.P_ERROR, 41)
+    A = synth.uniform_mod_primes(g_a, primes, (N1, ell), N1)
+    E = synth.rounded_gaussian(g_e, (N1, ell, N1))
+    S_dst = synth.ternary(g_s, N1)
+    ksk = orc.ksk_gen(N1, primes, beta, ell, case.S, S_dst, A, E)
+    with r.Context(N1, primes, log2_t) as ctx:
+        w = r.Weights(ctx, dev(case.W))
+        lwe = r.matmul(ctx, w, dev(case.ct), raw=True)  # (16, 256, 1, N+1)
+        k = r.KeySwitchKey(ctx, dev(ksk), beta, ell)
+        packed = r.keyswitch_pack(ctx, k, lwe, 256, raw=True)
+        switched = r.keyswitch_pack(ctx, k, lwe, 256)
+        torch.cuda.synchronize()
+        lw = host_u64(lwe)
+        pk = host_u64(packed)
+        sw = switched.cpu().numpy().view(np.uint32)
+        w.close()
+        k.close()
+    assert np.array_equal(lw, orc.matmul_clear(N1, primes, case.W, case.ct))
+    want = orc.keyswitch_pack(N1, primes, beta, ell, lw.reshape(-1, 1, N1 + 1), ksk, 256)
+    assert np.array_equal(pk, want)
+    assert np.array_equal(sw, orc.rlwe_modswitch_bits(primes, want, 32))
+    y = case.x.astype(np.int64) @ case.W.astype(np.int64).T  # (16, 256)
+    ph = orc.rlwe_phase_bits(S_dst, sw, 32)
+    dec = np.floor_divide(2 * ph + 256, 2 * 256)  # Delta' = 2^32 / 2^24
+    assert np.array_equal(dec[:, :256], y)
+    assert not dec[:, 256:].any()
