@@ -94,12 +94,12 @@ def roofline(products, kt, N, P, traffic=None):
 KERNEL_TRAFFIC = {
     "mask": {"sources": ["k_mask.hip"], "fetch_bytes": 4382392135, "write_bytes": 4766662645,
              "sha256": "b71d09264e517098c1179f16657d1e4fa62f1eaae851294a6d0fdb5115986154"},
-    "ntt": {"sources": ["k_ntt.hip", "ntt_device.hpp"], "fetch_bytes": 5235432167,
-            "write_bytes": 4353380721,
-            "sha256": "907e84ae099765681a079616d1259f2bb3353d5d693e563e9c65c36da68b6166"},
-    "ksacc": {"sources": ["k_keyswitch.hip", "ntt_device.hpp"], "fetch_bytes": 13028230194,
+    "ntt": {"sources": ["k_ntt.hip", "ntt_device.hpp"], "fetch_bytes": 5229068197,
+            "write_bytes": 4353263073,
+            "sha256": "5940a3bc95d060bc17cb8c97bb71eac99c2dc47ccb3a55101a7b0f99ea1a3184"},
+    "ksacc": {"sources": ["k_keyswitch.hip", "ntt_device.hpp"], "fetch_bytes": 13024574302,
               "write_bytes": 536870912,
-              "sha256": "c053fe10c49fefbd3c6f4717a8ab487da7073624ee1fa55500764d173b7cad11"},
+              "sha256": "a3b7e0769e8f43109b006a44a3a6a099f51728e1743497e52c6a70a19a93380e"},
 }
 
 
