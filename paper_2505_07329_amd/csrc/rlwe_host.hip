@@ -386,7 +386,7 @@ int rlwe_params_init(const rlwe_params* p, int hip_device, rlwe_ctx** out) {
   if (N <= kNttN) {
     const int r = build_ntt(ctx);
     if (r != RLWE_OK) {
-      if (ctx->ntt_tables) hipFree(ctx->ntt_tables);
+      if (ctx->ntt_tables) (void)hipFree(ctx->ntt_tables);
       delete ctx;
       return r;
     }
@@ -438,19 +438,19 @@ int rlwe_profile_end(rlwe_ctx* ctx, rlwe_kernel_times* out) {
 int rlwe_params_destroy(rlwe_ctx* ctx) {
   if (!ctx) return ok();
   if (ctx->prof) {
-    hipSetDevice(ctx->device);
+    (void)hipSetDevice(ctx->device);
     for (int i = 0; i < ctx->prof->created; ++i) {
-      hipEventDestroy(ctx->prof->ev[i][0]);
-      hipEventDestroy(ctx->prof->ev[i][1]);
+      (void)hipEventDestroy(ctx->prof->ev[i][0]);
+      (void)hipEventDestroy(ctx->prof->ev[i][1]);
     }
     delete ctx->prof;
   }
   if (ctx->ntt_tables) {
-    hipSetDevice(ctx->device);
-    hipFree(ctx->ntt_tables);
+    (void)hipSetDevice(ctx->device);
+    (void)hipFree(ctx->ntt_tables);
   }
   if (ctx->ws) {
-    hipSetDevice(ctx->device);
+    (void)hipSetDevice(ctx->device);
     hipError_t e = hipFree(ctx->ws);
     if (e != hipSuccess) {
       delete ctx;
@@ -462,8 +462,8 @@ int rlwe_params_destroy(rlwe_ctx* ctx) {
 }
 
 static void free_mat(Mat& m) {
-  if (m.w) hipFree(m.w);
-  if (m.what) hipFree(m.what);
+  if (m.w) (void)hipFree(m.w);
+  if (m.what) (void)hipFree(m.what);
   m.w = nullptr;
   m.what = nullptr;
   m.present = false;
@@ -500,7 +500,7 @@ static int load_mat(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32_t
   uint32_t* host = new (std::nothrow) uint32_t[a.rows];
   if (e == hipSuccess && host) e = hipMemcpyAsync(host, norms, sizeof(uint32_t) * a.rows, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  hipFree(norms);
+  (void)hipFree(norms);
   if (!host) return fail(RLWE_ENOMEM, "out of host memory");
   if (e != hipSuccess) {
     delete[] host;
@@ -571,7 +571,7 @@ int rlwe_weights_load(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32
     r = load_mat(ctx, W_dev, d_out, d_in, true, method, rowpack, s, w->tr);
   if (r != RLWE_OK) {
     std::string msg = g_err;
-    hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(s);
     free_mat(w->fwd);
     free_mat(w->tr);
     delete w;
@@ -584,7 +584,7 @@ int rlwe_weights_load(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32
 
 int rlwe_weights_free(rlwe_weights* w) {
   if (!w) return ok();
-  hipSetDevice(w->ctx->device);
+  (void)hipSetDevice(w->ctx->device);
   free_mat(w->fwd);
   free_mat(w->tr);
   delete w;
@@ -857,12 +857,12 @@ int rlwe_graph_capture_batch(rlwe_ctx* ctx, const ct_matmul_desc* descs, uint32_
   }
   if (prof) prof->on = was_on;
   if (r == RLWE_OK && e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
-  if (cs) hipStreamDestroy(cs);
+  if (cs) (void)hipStreamDestroy(cs);
   if (r != RLWE_OK || e != hipSuccess) {
     const std::string msg = r != RLWE_OK ? g_err : std::string("graph capture: ") + hipGetErrorString(e);
-    if (g->exec) hipGraphExecDestroy(g->exec);
-    if (g->graph) hipGraphDestroy(g->graph);
-    if (g->ws) hipFree(g->ws);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->ws) (void)hipFree(g->ws);
     delete g;
     g_err = msg;
     return r != RLWE_OK ? r : RLWE_EHIP;
@@ -881,10 +881,10 @@ int rlwe_graph_launch(rlwe_graph* g, rlwe_stream_t stream) {
 
 int rlwe_graph_destroy(rlwe_graph* g) {
   if (!g) return ok();
-  hipSetDevice(g->ctx->device);
-  if (g->exec) hipGraphExecDestroy(g->exec);
-  if (g->graph) hipGraphDestroy(g->graph);
-  if (g->ws) hipFree(g->ws);
+  (void)hipSetDevice(g->ctx->device);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->ws) (void)hipFree(g->ws);
   delete g;
   return ok();
 }
@@ -1002,7 +1002,7 @@ int rlwe_ksk_load(rlwe_ctx* ctx, const uint64_t* ksk_dev, uint32_t log2_base, ui
   e = launch_ksk_fwd(a, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
-    hipFree(k->khat);
+    (void)hipFree(k->khat);
     delete k;
     return hip_fail(e, "key transform");
   }
@@ -1012,8 +1012,8 @@ int rlwe_ksk_load(rlwe_ctx* ctx, const uint64_t* ksk_dev, uint32_t log2_base, ui
 
 int rlwe_ksk_free(rlwe_ksk* k) {
   if (!k) return ok();
-  hipSetDevice(k->ctx->device);
-  if (k->khat) hipFree(k->khat);
+  (void)hipSetDevice(k->ctx->device);
+  if (k->khat) (void)hipFree(k->khat);
   delete k;
   return ok();
 }
