@@ -193,8 +193,8 @@ def source_sha256(kind):
     return h.hexdigest()
 
 
-KERNEL_SOURCES = {"mask": ["k_mask.hip"], "ntt": ["k_ntt.hip", "ntt_device.hpp"],
-                  "ksacc": ["k_keyswitch.hip", "ntt_device.hpp"]}
+KERNEL_SOURCES = {"mask": ["k_mask.hip"], "ntt": ["k_ntt.hip", "ntt_device.hpp", "ks_round.hpp"],
+                  "ksacc": ["k_keyswitch.hip", "ntt_device.hpp", "ks_round.hpp"]}
 
 
 def parse():
@@ -719,8 +719,7 @@ def main():
     in_flags = rlwe.RLWE_IN_SEEDED if args.seeded else 0
     P = len(primes)
     ks = args.keyswitch
-    if ks:  # raw LWE outputs, packed N per RLWE ciphertext, switched
-        out = torch.empty((T, d_out, P, N + 1), dtype=torch.int64, device=dev)
+    if ks:  # the product's LWE outputs packed N per RLWE ciphertext, switched (one call)
         G = rlwe.rlwe_packed_count(T * d_out, N)
         rlwe_out = torch.empty((G, 2, N), dtype=torch.int32, device=dev)
         # a key of uniform residues: the kernels are data-oblivious (the tests use real keys)
@@ -739,17 +738,16 @@ def main():
         packed = torch.empty((T, d_out, words), dtype=torch.int32, device=dev) if args.pack else None
     ws = rlwe.rlwe_workspace_bytes(ctx.handle, w.handle, False, T)
     if ks:
-        ws = max(ws, rlwe.rlwe_keyswitch_workspace_bytes(ctx.handle, key.handle, T * d_out, N))
+        ws = max(ws, rlwe.rlwe_matmul_pack_workspace_bytes(ctx.handle, w.handle, False, T,
+                                                           key.handle, N))
     rlwe.rlwe_workspace_reserve(ctx.handle, ws)
     kept, total = rlwe.rlwe_weights_digits(w.handle)
     stream = torch.cuda.current_stream()
 
     def step():
         if ks:
-            rlwe.ct_matmul_clear(ctx.handle, w.handle, ct, T, out, False,
-                                 rlwe.RLWE_OUT_RAW_Q | in_flags, stream)
-            rlwe.ct_keyswitch_pack(ctx.handle, key.handle, out, T * d_out, N, rlwe_out,
-                                   rlwe.RLWE_OUT_SWITCHED, stream)
+            rlwe.ct_matmul_pack(ctx.handle, w.handle, ct, T, key.handle, N, rlwe_out, False,
+                                rlwe.RLWE_OUT_SWITCHED | in_flags, stream)
             if args.pack:
                 rlwe.ct_pack_bits(ctx.handle, rlwe_out, G * 2, N, packed, stream)
             return
@@ -799,7 +797,9 @@ def main():
                  for k in ("dig", "acc", "fin")}  # per step (a step may hold several passes)
         ks_roof = keyswitch_roofline(T * d_out, N, P, args.ks_levels, ks_ms["acc"] * 1e-3)
         ks_roof["traffic"] = kernel_traffic("ksacc")
-        ks_roof["digits_hbm_gbs"] = (T * d_out * (P * 8 * (N + 1) + args.ks_levels * 8 * N)
+        # the digit kernel reads the rounded masks (NTT method) or the raw residues
+        read = 8 * N if is_ntt else P * 8 * (N + 1)
+        ks_roof["digits_hbm_gbs"] = (T * d_out * (read + args.ks_levels * 8 * N)
                                      / (ks_ms["dig"] * 1e-3) / 1e9)
     pack_roof = None
     if args.pack and kt["pack_n"]:

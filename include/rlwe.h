@@ -331,6 +331,33 @@ size_t rlwe_keyswitch_workspace_bytes(const rlwe_ctx* ctx, const rlwe_ksk* k, si
 int ct_keyswitch_pack(rlwe_ctx* ctx, const rlwe_ksk* k, const uint64_t* lwe_in, size_t count,
                       uint32_t n_pack, void* out, uint32_t flags, rlwe_stream_t stream);
 
+/* Workspace bytes of ct_matmul_pack for this shape (0 on bad input); calls within
+ * rlwe_workspace_reserve(that many) allocate nothing. */
+size_t rlwe_matmul_pack_workspace_bytes(const rlwe_ctx* ctx, const rlwe_weights* w,
+                                        uint32_t transpose, uint32_t tokens, const rlwe_ksk* k,
+                                        uint32_t n_pack);
+
+/* The product of ct_matmul_clear followed by ct_keyswitch_pack of its LWE outputs
+ * (Eq. (LWEdot), then Eq. (pack_rotate)): output g packs the LWE outputs g n_pack +
+ * s, s < n_pack, in the order (token, row) of ct_matmul_clear. The result is the
+ * same, bit for bit, as the two calls. With the NTT method the product kernel
+ * rounds every mask coefficient to 2^K for Decomp itself (K = log2_base * levels of
+ * the key), so that only a~ (8 bytes) instead of P residues passes between the two
+ * steps; with the matrix-core method the raw residues do.
+ *   ct_in, tokens, transpose, w   as for ct_matmul_clear (flag RLWE_IN_SEEDED)
+ *   k, n_pack, out                as for ct_keyswitch_pack (flag RLWE_OUT_RAW_Q);
+ *                                 count = tokens * (rows of the product)
+ *   RLWE_OUT_FORCE_EXACT          every rounding through the slow exact path (same
+ *                                 bits; test hook)
+ * tokens = 0 is a no-op. Errors as for the two calls. Uses the context workspace
+ * (rlwe_matmul_pack_workspace_bytes: the product's, the LWE outputs between the
+ * steps, M (N + P) 8 bytes with the NTT method, and ct_keyswitch_pack's; grown with
+ * hipMalloc unless reserved; refused while the stream is captured). Asynchronous
+ * on `stream`. */
+int ct_matmul_pack(rlwe_ctx* ctx, const rlwe_weights* w, uint32_t transpose, const uint64_t* ct_in,
+                   uint32_t tokens, const rlwe_ksk* k, uint32_t n_pack, void* out, uint32_t flags,
+                   rlwe_stream_t stream);
+
 /* Description of the last error on this thread ("" if none). */
 const char* rlwe_last_error(void);
 

@@ -15,11 +15,12 @@
 // Decomp is the gadget decomposition of TFHE: the coefficient c (CRT of its
 // residues) is rounded to K = beta ell bits, a~ = round(c 2^K / q) mod 2^K, and
 // a~ is written in signed base 2^beta (digits in [-2^(beta-1), 2^(beta-1)), most
-// significant first). The rounding is exact (decompose, below). The signed digits
+// significant first). The rounding is exact (round_fast and round_exact, below). The signed digits
 // are those of a~ + H, H = sum_m 2^(beta-1) 2^(beta m), less 2^(beta-1).
 //
 // Kernels (one pass covers up to kKsGroups output groups):
-//   ks_digits_kernel  raw LWE masks [M][P][N+1] -> digits [group][i][m][slot]
+//   ks_digits_kernel  raw LWE masks [M][P][N+1] (or masks already rounded to 2^K by
+//                     the product kernel, [M][N+P]) -> digits [group][i][m][slot]
 //                     (int64), a 64 x 64 tile transpose through LDS
 //   ks_accum_kernel   per (group, chunk of 64 key coefficients, prime): forward
 //                     transforms of the digit polynomials, pointwise products
@@ -27,6 +28,7 @@
 //                     sums [group][chunk][p][2][N] (lane-major positions)
 //   ks_finish_kernel  per group: sum of the partials, inverse transforms, the
 //                     factor 1/N, negation, bodies, optional switch to 2^k
+#include "ks_round.hpp"
 #include "ntt_device.hpp"
 
 namespace rlwe {
@@ -40,54 +42,15 @@ constexpr uint32_t kTile = 64;                    // digit transpose tile (coeff
 typedef const __attribute__((address_space(4))) KsArgs* KsPtr;
 __device__ __forceinline__ KsPtr ks_args() { return (KsPtr)__builtin_amdgcn_kernarg_segment_ptr(); }
 
-// Signed base-2^beta digits of round(c 2^K / q) mod 2^K for the coefficient with
-// residues c0 (prime 0) and c1 (prime 1, NP = 2), into d[0..ell).
-//
-// With y_p = c_p inv_p mod q_p (inv_p = (q/q_p)^-1 mod q_p, 1 for one prime),
-// c 2^K / q = sum_p y_p 2^K / q_p - kappa 2^K, and y_p 2^K / q_p is congruent mod 2^K
-// to c_p inv_p 2^K / q_p = c_p IH_p + c_p G_p / q_p with IH_p = floor(inv_p 2^K / q_p)
-// and G_p = inv_p 2^K mod q_p. So each prime contributes the integer c_p IH_p +
-// floor(c_p G_p / q_p) (one Shoup product) and the fraction rem_p / q_p, rem_p =
-// c_p G_p mod q_p; a~ adds the rounding of the fractions' sum (in [0, P)). That sum is
-// compared with 1/2 (and 3/2) in double precision, error below 2^-50; within 2^-40 of a
-// boundary the comparison is redone exactly in 128-bit integers (a tie is impossible
-// for odd q).
-template <int NP, int ELL>
-__device__ __forceinline__ void decompose(KsPtr a, uint64_t c0, uint64_t c1, int64_t (&d)[ELL]) {
-  uint64_t at = 0;
-  {
-    const uint64_t cs[2] = {c0, c1};
-    uint64_t rem[NP];
-    double fr = 0.0;
-#pragma unroll
-    for (int r = 0; r < NP; ++r) {
-      const uint64_t p = a->rc.q[r];
-      const uint64_t c = cs[r];
-      const uint64_t qh = __umul64hi(c, a->kc.g_shoup[r]);  // floor(c G / q_p) or 1 less
-      uint64_t rr = c * a->kc.g[r] - qh * p;                 // in [0, 2 q_p)
-      uint64_t u = c * a->kc.f[r] + qh;
-      if (rr >= p) {
-        rr -= p;
-        ++u;
-      }
-      rem[r] = rr;
-      at += u;
-      fr += (double)rr * a->kc.rq[r];
-    }
-    // round(fraction sum): + 1 from 1/2, + 1 more from 3/2 (two primes)
-    uint32_t up = (fr >= 0.5 ? 1u : 0u) + (NP == 2 && fr >= 1.5 ? 1u : 0u);
-    const bool near = fabs(fr - 0.5) < 0x1p-40 || (NP == 2 && fabs(fr - 1.5) < 0x1p-40);
-    if (near) {  // exact: compare 2 sum_p rem_p (q / q_p) with q and 3q
-      if (NP == 1) {
-        up = 2 * rem[0] >= a->rc.q[0] ? 1u : 0u;
-      } else {
-        const u128 Q = make_u128(a->rc.Q_hi, a->rc.Q_lo);
-        const u128 F = 2 * ((u128)rem[0] * a->rc.q[NP - 1] + (u128)rem[NP - 1] * a->rc.q[0]);
-        up = (F >= Q ? 1u : 0u) + (F >= 3 * Q ? 1u : 0u);
-      }
-    }
-    at += up;
-  }
+// Index of LWE ciphertext j's body residue for prime r in the input.
+__device__ __forceinline__ size_t body_index(KsPtr a, uint64_t j, uint32_t r) {
+  const size_t N = a->rc.N, P = a->rc.P;
+  return a->pre ? j * (N + P) + N + r : (j * P + r) * (N + 1) + N;
+}
+
+// Signed digits of a~ (most significant first): those of a~ + H less 2^(beta-1).
+template <int ELL>
+__device__ __forceinline__ void digits_of(KsPtr a, uint64_t at, int64_t (&d)[ELL]) {
   const uint32_t beta = a->kc.beta;
   const uint64_t v = (at & a->kc.kmask) + a->kc.H;
   const uint64_t bmask = (1ull << beta) - 1, half = 1ull << (beta - 1);
@@ -164,7 +127,7 @@ __device__ __forceinline__ void ntt_forward512(uint64_t (&x)[NC][8], uint64_t* l
 // Digits: one workgroup per (group of the pass, tile of 64 key coefficients i,
 // tile of 64 slots s). Loads run along i (coalesced rows of an LWE mask), stores
 // along s (coalesced rows of a digit polynomial).
-template <int NP, int ELL>
+template <int NP, int ELL, bool PRE>
 __global__ void __launch_bounds__(256) ks_digits_kernel(KsArgs) {
   __shared__ int64_t tile[kTile][kTile + 1];
   const KsPtr a = ks_args();
@@ -178,25 +141,51 @@ __global__ void __launch_bounds__(256) ks_digits_kernel(KsArgs) {
   const uint32_t g = a->g0 + gb;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   constexpr uint32_t ell = ELL;
-  // every load is issued before any decomposition: rows past the last LWE ciphertext
-  // (or past n_pack) read LWE 0 and are zeroed afterwards
+  // LWE ciphertext j: raw residues [P][N+1], or (PRE) the rounded mask a~ [N] and the
+  // bodies. Every load is issued before any rounding: rows past the last LWE
+  // ciphertext (or past n_pack) read LWE 0 and are zeroed afterwards.
+  const size_t stride = PRE ? N + NP : NP * (N + 1);
   uint64_t c0[16], c1[16];
-  bool ok[16];
+  uint32_t okm = 0;
 #pragma unroll
   for (int rep = 0; rep < 16; ++rep) {
     const uint32_t s = s0 + ty + 4 * rep;
     const uint64_t j = (uint64_t)g * a->n_pack + s;
-    ok[rep] = s < a->n_pack && j < a->M;
-    const uint64_t* row = a->lwe + (ok[rep] ? j : 0) * NP * (N + 1) + i0 + tx;
+    const bool ok = s < a->n_pack && j < a->M;
+    okm |= (ok ? 1u : 0u) << rep;
+    const uint64_t* row = a->lwe + (ok ? j : 0) * stride + i0 + tx;
     c0[rep] = row[0];
-    c1[rep] = NP == 2 ? row[N + 1] : 0;
+    c1[rep] = NP == 2 && !PRE ? row[N + 1] : 0;
+  }
+  uint64_t at[16];
+  if (PRE) {
+#pragma unroll
+    for (int rep = 0; rep < 16; ++rep) at[rep] = c0[rep];
+  } else {
+    uint32_t nearm = 0;
+#pragma unroll
+    for (int rep = 0; rep < 16; ++rep) {
+      bool nr;
+      at[rep] = round_fast<NP>(&a->kc.rd, c0[rep], c1[rep], nr);
+      nearm |= (nr ? 1u : 0u) << rep;
+    }
+    nearm &= okm;
+    while (nearm) {  // rare: the exact rounding, residues read again
+      const int k = __builtin_ctz(nearm);
+      nearm &= nearm - 1;
+      const uint64_t j = (uint64_t)g * a->n_pack + s0 + ty + 4 * k;
+      const uint64_t* row = a->lwe + j * stride + i0 + tx;
+      const uint64_t e = round_exact<NP>(&a->kc.rd, row[0], NP == 2 ? row[N + 1] : 0);
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) at[kk] = k == kk ? e : at[kk];
+    }
   }
   int64_t d[16][ELL];
 #pragma unroll
   for (int rep = 0; rep < 16; ++rep) {
-    decompose<NP, ELL>(a, c0[rep], c1[rep], d[rep]);
+    digits_of<ELL>(a, at[rep], d[rep]);
 #pragma unroll
-    for (int m = 0; m < ELL; ++m) d[rep][m] = ok[rep] ? d[rep][m] : 0;
+    for (int m = 0; m < ELL; ++m) d[rep][m] = (okm >> rep) & 1 ? d[rep][m] : 0;
   }
   int64_t* dst = a->dig + (size_t)gb * N * ell * N;
 #pragma unroll
@@ -340,7 +329,7 @@ __global__ void __launch_bounds__(kInvThreads) ks_finish_kernel(KsArgs) {
         if (c == 1) {
           const uint32_t s = tid + 512 * k;
           const uint64_t j = (uint64_t)g * a->n_pack + s;
-          if (s < a->n_pack && j < a->M) b = a->lwe[(j * NP + r) * (N + 1) + N];
+          if (s < a->n_pack && j < a->M) b = a->lwe[body_index(a, j, r)];
         }
         v[r][k] = b >= t ? b - t : b + p[r] - t;  // (b - sum) mod p; b = 0 for the mask
       }
@@ -560,7 +549,7 @@ __global__ void __launch_bounds__(kGenThreads) ks_finish_generic(KsArgs) {
         t = t >= p ? t - p : t;
         uint64_t b = 0;
         const uint64_t j = (uint64_t)g * a->n_pack + n;
-        if (c == 1 && n < a->n_pack && j < a->M) b = a->lwe[(j * NP + r) * (N + 1) + N];
+        if (c == 1 && n < a->n_pack && j < a->M) b = a->lwe[body_index(a, j, r)];
         v[r] = b >= t ? b - t : b + p - t;  // (b - sum) mod p; b = 0 for the mask
       }
       if (RAW) {
@@ -593,22 +582,27 @@ hipError_t launch_ksk_fwd(const KsArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <bool PRE>
+hipError_t launch_ks_digits_pre(const KsArgs& a, dim3 g, hipStream_t s) {
+  switch (a.rc.P * 8 + a.kc.ell) {
+    case 9: hipLaunchKernelGGL((ks_digits_kernel<1, 1, PRE>), g, dim3(256), 0, s, a); break;
+    case 10: hipLaunchKernelGGL((ks_digits_kernel<1, 2, PRE>), g, dim3(256), 0, s, a); break;
+    case 11: hipLaunchKernelGGL((ks_digits_kernel<1, 3, PRE>), g, dim3(256), 0, s, a); break;
+    case 12: hipLaunchKernelGGL((ks_digits_kernel<1, 4, PRE>), g, dim3(256), 0, s, a); break;
+    case 17: hipLaunchKernelGGL((ks_digits_kernel<2, 1, PRE>), g, dim3(256), 0, s, a); break;
+    case 18: hipLaunchKernelGGL((ks_digits_kernel<2, 2, PRE>), g, dim3(256), 0, s, a); break;
+    case 19: hipLaunchKernelGGL((ks_digits_kernel<2, 3, PRE>), g, dim3(256), 0, s, a); break;
+    case 20: hipLaunchKernelGGL((ks_digits_kernel<2, 4, PRE>), g, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_ks_digits(const KsArgs& a, hipStream_t s) {
   const uint32_t tiles = a.rc.N / kTile;
   const uint32_t blocks = a.GB * tiles * tiles;
   const dim3 g = grid_for(blocks);
-  switch (a.rc.P * 8 + a.kc.ell) {
-    case 9: hipLaunchKernelGGL((ks_digits_kernel<1, 1>), g, dim3(256), 0, s, a); break;
-    case 10: hipLaunchKernelGGL((ks_digits_kernel<1, 2>), g, dim3(256), 0, s, a); break;
-    case 11: hipLaunchKernelGGL((ks_digits_kernel<1, 3>), g, dim3(256), 0, s, a); break;
-    case 12: hipLaunchKernelGGL((ks_digits_kernel<1, 4>), g, dim3(256), 0, s, a); break;
-    case 17: hipLaunchKernelGGL((ks_digits_kernel<2, 1>), g, dim3(256), 0, s, a); break;
-    case 18: hipLaunchKernelGGL((ks_digits_kernel<2, 2>), g, dim3(256), 0, s, a); break;
-    case 19: hipLaunchKernelGGL((ks_digits_kernel<2, 3>), g, dim3(256), 0, s, a); break;
-    case 20: hipLaunchKernelGGL((ks_digits_kernel<2, 4>), g, dim3(256), 0, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return a.pre ? launch_ks_digits_pre<true>(a, g, s) : launch_ks_digits_pre<false>(a, g, s);
 }
 
 hipError_t launch_ks_accum(const KsArgs& a, hipStream_t s) {

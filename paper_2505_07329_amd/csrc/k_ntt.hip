@@ -1,5 +1,6 @@
 // The mask part of Eq. (LWEdot) by number-theoretic transforms, for N = 4096
 // (transform layouts and arithmetic: ntt_device.hpp).
+#include "ks_round.hpp"
 #include "ntt_device.hpp"
 
 namespace rlwe {
@@ -52,7 +53,9 @@ __global__ void __launch_bounds__(kThreads) ntt_mask_fwd_kernel(Batch) {
 // Product kernel: one workgroup per (row j, tile of kTokTile tokens) of each item;
 // the NP = P primes of a token are transformed together. LC = 2: every item has
 // exactly two input blocks; LC = 0: any number (a launch holds one class).
-template <bool RAW, int NP, int LC>
+// OUT: 0 switched to 2^qbits (u32), 1 raw residues (u64 per prime), 2 masks rounded
+// to 2^K for the gadget decomposition (u64, bodies written by the body kernel).
+template <int OUT, int NP, int LC>
 __global__ void __launch_bounds__(kInvThreads, LC == 2 ? 4 : 1) ntt_mask_kernel(Batch) {
   static_assert(LC == 0 || LC == 2, "block classes: exactly two, or any");
   __shared__ uint64_t lds[NP * kInvLdsWords];
@@ -150,7 +153,49 @@ __global__ void __launch_bounds__(kInvThreads, LC == 2 ? 4 : 1) ntt_mask_kernel(
     // j n_o + rho) is SampleExtract at h = (rho + 1) slot - 1 (Sec. 3.2): a'[n] =
     // C[h - n] for n <= h, -C[N + h - n] otherwise, so C[m] lands at n = h - m, or
     // negated at n = h - m + N. Unpacked rows: n_o = 1, slot = N, h = N - 1.
-    if (RAW) {
+    if (OUT == 2) {
+      // a~ = round(c 2^K / q) mod 2^K of every coefficient (Decomp's rounding, for
+      // KeySwitch packing); the switch of -c is -(switch of c) (q is odd: no ties)
+      uint64_t c[NP][8];
+#pragma unroll
+      for (int r = 0; r < NP; ++r)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c[r][k] = reduce4(reduce_barrett(x[r][k], md[r]), p[r]);
+      uint64_t av[8];
+      uint32_t nearm = bt->force_exact ? 0xffu : 0u;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        bool nr;
+        av[k] = round_fast<NP>(&bt->kr, c[0][k], c[NP - 1][k], nr);
+        nearm |= (nr ? 1u : 0u) << k;
+      }
+      while (nearm) {  // rare: exact rounding of the coefficient
+        const int k = __builtin_ctz(nearm);
+        nearm &= nearm - 1;
+        uint64_t c0 = c[0][0], c1 = c[NP - 1][0];
+#pragma unroll
+        for (int kk = 1; kk < 8; ++kk) {
+          c0 = k == kk ? c[0][kk] : c0;
+          c1 = k == kk ? c[NP - 1][kk] : c1;
+        }
+        const uint64_t e = round_exact<NP>(&bt->kr, c0, NP == 2 ? c1 : 0);
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) av[kk] = k == kk ? e : av[kk];
+      }
+      const uint64_t km = bt->kmask;
+      for (uint32_t rho = 0; rho < n_o && j * n_o + rho < rows; ++rho) {
+        const uint32_t h = (rho + 1) * slot - 1;
+        uint64_t* o = (uint64_t*)out + ((size_t)t * rows + j * n_o + rho) * (kN + NP);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t m = tid + 512 * k;
+          if (m <= h)
+            o[h - m] = av[k] & km;
+          else
+            o[h + kN - m] = (0 - av[k]) & km;
+        }
+      }
+    } else if (OUT == 1) {
       uint64_t c[NP][8];
 #pragma unroll
       for (int r = 0; r < NP; ++r)
@@ -273,19 +318,22 @@ hipError_t launch_ntt_mask_fwd(const Batch& b, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int OUT, int LC>
+void launch_ntt_mask_out(const Batch& b, dim3 g, hipStream_t s) {
+  if (b.rc.P == 2)
+    hipLaunchKernelGGL((ntt_mask_kernel<OUT, 2, LC>), g, dim3(kInvThreads), 0, s, b);
+  else
+    hipLaunchKernelGGL((ntt_mask_kernel<OUT, 1, LC>), g, dim3(kInvThreads), 0, s, b);
+}
+
 template <int LC>
 void launch_ntt_mask_lc(const Batch& b, dim3 g, hipStream_t s) {
-  if (b.rc.P == 2) {
-    if (b.raw)
-      hipLaunchKernelGGL((ntt_mask_kernel<true, 2, LC>), g, dim3(kInvThreads), 0, s, b);
-    else
-      hipLaunchKernelGGL((ntt_mask_kernel<false, 2, LC>), g, dim3(kInvThreads), 0, s, b);
-  } else {
-    if (b.raw)
-      hipLaunchKernelGGL((ntt_mask_kernel<true, 1, LC>), g, dim3(kInvThreads), 0, s, b);
-    else
-      hipLaunchKernelGGL((ntt_mask_kernel<false, 1, LC>), g, dim3(kInvThreads), 0, s, b);
-  }
+  if (b.gadget)
+    launch_ntt_mask_out<2, LC>(b, g, s);
+  else if (b.raw)
+    launch_ntt_mask_out<1, LC>(b, g, s);
+  else
+    launch_ntt_mask_out<0, LC>(b, g, s);
 }
 
 hipError_t launch_ntt_mask(const Batch& b, uint32_t lclass, hipStream_t s) {

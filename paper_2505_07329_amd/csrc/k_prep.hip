@@ -211,7 +211,10 @@ __global__ void __launch_bounds__(256) body_kernel(Batch) {
   const size_t row = (size_t)t * m.rows + j;
   if (RAW) {
     uint64_t* o = (uint64_t*)a.out;
-    for (uint32_t p = 0; p < rc.P; ++p) o[(row * rc.P + p) * (N + 1) + N] = mod_i128(V, bt->rc.q[p]);
+    // raw [T][M][P][N+1], or after rounded masks (gadget output) [T][M][N+P]
+    for (uint32_t p = 0; p < rc.P; ++p)
+      o[bt->gadget ? row * (N + rc.P) + N + p : (row * rc.P + p) * (N + 1) + N] =
+          mod_i128(V, bt->rc.q[p]);
   } else {
     ((uint32_t*)a.out)[row * (N + 1) + N] = switch_exact(V, rc);
   }

@@ -154,6 +154,12 @@ struct Mat {
 
 }  // namespace
 
+struct rlwe_ksk {
+  rlwe_ctx* ctx = nullptr;
+  uint64_t* khat = nullptr;  // [N][ell][P][2][N][2], NTT domain, bit-reversed, with companions
+  KsConst kc{};
+};
+
 struct rlwe_weights {
   rlwe_ctx* ctx = nullptr;
   Mat fwd, tr;
@@ -660,11 +666,13 @@ static size_t batch_ws(const rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n)
   return total;
 }
 
-// Enqueue a validated batch using workspace `ws` (at least batch_ws bytes).
+// Enqueue a validated batch using workspace `ws` (at least batch_ws bytes). With a
+// key `gk` (NTT method only), masks are rounded to 2^K for its gadget decomposition
+// and the outputs are [T][M][N+P] (a~, then the body residues).
 static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_t flags,
-                     hipStream_t s, unsigned char* ws) {
+                     hipStream_t s, unsigned char* ws, const rlwe_ksk* gk = nullptr) {
   const RingConst& rc = ctx->rc;
-  const bool raw = flags & RLWE_OUT_RAW_Q;
+  const bool raw = (flags & RLWE_OUT_RAW_Q) || gk;
   // longest contraction first: its tiles are the most expensive (tail balance)
   uint32_t order[kMaxBatch];
   uint32_t cnt = 0;
@@ -685,6 +693,11 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
   all.raw = raw;
   all.force_exact = (flags & RLWE_OUT_FORCE_EXACT) ? 1 : 0;
   all.seeded = (flags & RLWE_IN_SEEDED) ? 1 : 0;
+  if (gk) {
+    all.gadget = 1;
+    all.kmask = gk->kc.kmask;
+    all.kr = gk->kc.rd;
+  }
   size_t off = 0;
   for (uint32_t x = 0; x < cnt; ++x) {
     const ct_matmul_desc& dd = d[order[x]];
@@ -731,6 +744,9 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
     mb.ntt = all.ntt;
     mb.raw = all.raw;
     mb.force_exact = all.force_exact;
+    mb.gadget = all.gadget;
+    mb.kmask = all.kmask;
+    mb.kr = all.kr;
     for (uint32_t y = x; y < cnt; ++y) {
       if (done[y] || (all.it[y].method == 1) != ntt || (!ntt && all.it[y].sc.dk != dk) ||
           (ntt && lclass(all.it[y]) != lc))
@@ -925,12 +941,6 @@ int ct_pack_bits(rlwe_ctx* ctx, const uint32_t* in, size_t count, uint32_t len, 
 
 // ------------------------------------------------------------------ KeySwitch packing
 
-struct rlwe_ksk {
-  rlwe_ctx* ctx = nullptr;
-  uint64_t* khat = nullptr;  // [N][ell][P][2][N][2], NTT domain, bit-reversed, with companions
-  KsConst kc{};
-};
-
 namespace {
 KsArgs ks_args_base(const rlwe_ctx* ctx) {
   KsArgs a{};
@@ -939,6 +949,30 @@ KsArgs ks_args_base(const rlwe_ctx* ctx) {
   return a;
 }
 // Output groups per pass and the workspace of one pass.
+// Constants of the gadget rounding to 2^K (K <= 64) for the primes of rc.
+void make_ks_round(const RingConst& rc, uint32_t K, KsRound* kr) {
+  *kr = KsRound{};
+  for (uint32_t r = 0; r < rc.P; ++r) {
+    // inv_p 2^K = f q_p + g (inv_p < 2^54, so the product fits in 118 bits)
+    const u128 x = (u128)(rc.P == 1 ? 1 : rc.crt_inv[r]) << K, q = rc.q[r];
+    kr->q[r] = rc.q[r];
+    kr->f[r] = (uint64_t)(x / q);  // mod 2^64
+    kr->g[r] = (uint64_t)(x % q);
+    kr->g_shoup[r] = (uint64_t)(((u128)kr->g[r] << 64) / q);
+    u128 rem = kr->g[r];  // G = floor(g 2^96 / q_p), one 32-bit word at a time
+    uint32_t Gw[3];
+    for (int w = 2; w >= 0; --w) {
+      const u128 n = rem << 32;
+      Gw[w] = (uint32_t)(n / q);
+      rem = n % q;
+    }
+    kr->G_lo[r] = ((uint64_t)Gw[1] << 32) | Gw[0];
+    kr->G_hi[r] = Gw[2];
+  }
+  kr->Q_hi = rc.Q_hi;
+  kr->Q_lo = rc.Q_lo;
+}
+
 uint32_t ks_pass_groups(size_t M, uint32_t n_pack) {
   const size_t G = (M + n_pack - 1) / n_pack;
   return (uint32_t)std::min<size_t>(G, kKsGroups);
@@ -949,6 +983,38 @@ size_t ks_ws_bytes(const rlwe_ctx* ctx, const rlwe_ksk* k, size_t M, uint32_t n_
   const size_t part = GB * (N / 64) * ctx->rc.P * 2 * N * 8;
   return align_up(dig, 256) + part;
 }
+// The KeySwitch passes over `count` LWE ciphertexts (raw, or with masks already
+// rounded when `pre`), workspace `ws` of ks_ws_bytes.
+int ks_run(rlwe_ctx* ctx, const rlwe_ksk* k, const uint64_t* lwe_in, size_t count,
+           uint32_t n_pack, void* out, bool raw_out, bool pre, unsigned char* ws, hipStream_t s) {
+  const size_t G = (count + n_pack - 1) / n_pack;
+  hipError_t e;
+  const uint32_t GBmax = ks_pass_groups(count, n_pack);
+  KsArgs a = ks_args_base(ctx);
+  a.kc = k->kc;
+  a.lwe = lwe_in;
+  a.M = count;
+  a.n_pack = n_pack;
+  a.raw = raw_out ? 1 : 0;
+  a.pre = pre ? 1 : 0;
+  a.khat = k->khat;
+  a.dig = (int64_t*)ws;
+  a.part = (uint64_t*)(ws +
+                       align_up((size_t)GBmax * ctx->rc.N * k->kc.ell * ctx->rc.N * 8, 256));
+  a.out = out;
+  for (size_t g0 = 0; g0 < G; g0 += GBmax) {
+    a.g0 = (uint32_t)g0;
+    a.GB = (uint32_t)std::min<size_t>(GBmax, G - g0);
+    e = timed(ctx, K_KSDIG, s, [&] { return launch_ks_digits(a, s); });
+    if (e != hipSuccess) return hip_fail(e, "KeySwitch digits kernel");
+    e = timed(ctx, K_KSACC, s, [&] { return launch_ks_accum(a, s); });
+    if (e != hipSuccess) return hip_fail(e, "KeySwitch accumulate kernel");
+    e = timed(ctx, K_KSFIN, s, [&] { return launch_ks_finish(a, s); });
+    if (e != hipSuccess) return hip_fail(e, "KeySwitch finish kernel");
+  }
+  return RLWE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -979,14 +1045,7 @@ int rlwe_ksk_load(rlwe_ctx* ctx, const uint64_t* ksk_dev, uint32_t log2_base, ui
   kc.kmask = kc.K == 64 ? ~0ull : (1ull << kc.K) - 1;
   kc.H = 0;
   for (uint32_t m = 0; m < levels; ++m) kc.H += (1ull << (log2_base - 1)) << (log2_base * m);
-  for (uint32_t r = 0; r < rc.P; ++r) {
-    // inv_p 2^K = f q_p + g (inv_p < 2^54, so the product fits in 118 bits)
-    const u128 x = (u128)(rc.P == 1 ? 1 : rc.crt_inv[r]) << kc.K, q = rc.q[r];
-    kc.f[r] = (uint64_t)(x / q);  // mod 2^64
-    kc.g[r] = (uint64_t)(x % q);
-    kc.g_shoup[r] = (uint64_t)(((u128)kc.g[r] << 64) / q);
-    kc.rq[r] = 1.0 / (double)q;
-  }
+  make_ks_round(rc, kc.K, &kc.rd);
   const size_t N = rc.N;
   const size_t bytes = N * levels * rc.P * 2 * N * 16;
   e = hipMalloc(&k->khat, bytes);
@@ -1050,28 +1109,81 @@ int ct_keyswitch_pack(rlwe_ctx* ctx, const rlwe_ksk* k, const uint64_t* lwe_in, 
     const int r = ensure_ws(ctx, need, s);
     if (r != RLWE_OK) return r;
   }
-  const uint32_t GBmax = ks_pass_groups(count, n_pack);
-  KsArgs a = ks_args_base(ctx);
-  a.kc = k->kc;
-  a.lwe = lwe_in;
-  a.M = count;
-  a.n_pack = n_pack;
-  a.raw = (flags & RLWE_OUT_RAW_Q) ? 1 : 0;
-  a.khat = k->khat;
-  a.dig = (int64_t*)ctx->ws;
-  a.part = (uint64_t*)((unsigned char*)ctx->ws +
-                       align_up((size_t)GBmax * ctx->rc.N * k->kc.ell * ctx->rc.N * 8, 256));
-  a.out = out;
-  for (size_t g0 = 0; g0 < G; g0 += GBmax) {
-    a.g0 = (uint32_t)g0;
-    a.GB = (uint32_t)std::min<size_t>(GBmax, G - g0);
-    e = timed(ctx, K_KSDIG, s, [&] { return launch_ks_digits(a, s); });
-    if (e != hipSuccess) return hip_fail(e, "KeySwitch digits kernel");
-    e = timed(ctx, K_KSACC, s, [&] { return launch_ks_accum(a, s); });
-    if (e != hipSuccess) return hip_fail(e, "KeySwitch accumulate kernel");
-    e = timed(ctx, K_KSFIN, s, [&] { return launch_ks_finish(a, s); });
-    if (e != hipSuccess) return hip_fail(e, "KeySwitch finish kernel");
+  const int r = ks_run(ctx, k, lwe_in, count, n_pack, out, flags & RLWE_OUT_RAW_Q, false,
+                       (unsigned char*)ctx->ws, s);
+  if (r != RLWE_OK) return r;
+  return ok();
+}
+
+// Workspace of ct_matmul_pack: the product's, the LWE outputs between the two steps
+// (rounded masks and bodies [M][N+P] with the NTT method, raw [M][P][N+1] otherwise),
+// and the KeySwitch passes'.
+static size_t matmul_pack_ws(const rlwe_ctx* ctx, const Mat& m, uint32_t tokens,
+                             const rlwe_ksk* k, uint32_t n_pack, size_t* off_inter,
+                             size_t* off_ks) {
+  const RingConst& rc = ctx->rc;
+  const size_t M = (size_t)tokens * m.args.rows;
+  const size_t inter = M * (m.ntt ? rc.N + rc.P : (size_t)rc.P * (rc.N + 1)) * 8;
+  *off_inter = align_up(ws_item(rc, m.args, tokens, m.ntt), 256);
+  *off_ks = *off_inter + align_up(inter, 256);
+  return *off_ks + ks_ws_bytes(ctx, k, M, n_pack);
+}
+
+size_t rlwe_matmul_pack_workspace_bytes(const rlwe_ctx* ctx, const rlwe_weights* w,
+                                        uint32_t transpose, uint32_t tokens, const rlwe_ksk* k,
+                                        uint32_t n_pack) {
+  if (!ctx || !w || !k || transpose > 1 || tokens == 0 || n_pack < 1 || n_pack > ctx->rc.N)
+    return 0;
+  const Mat& m = transpose ? w->tr : w->fwd;
+  if (!m.present) return 0;
+  size_t a, b;
+  return matmul_pack_ws(ctx, m, tokens, k, n_pack, &a, &b);
+}
+
+int ct_matmul_pack(rlwe_ctx* ctx, const rlwe_weights* w, uint32_t transpose, const uint64_t* ct_in,
+                   uint32_t tokens, const rlwe_ksk* k, uint32_t n_pack, void* out, uint32_t flags,
+                   rlwe_stream_t stream) {
+  if (!ctx || !w || !k) return fail(RLWE_EINVAL, "ct_matmul_pack: null context, weights or key");
+  if (k->ctx != ctx) return fail(RLWE_EINVAL, "ct_matmul_pack: key of another context");
+  if (flags & ~(RLWE_OUT_RAW_Q | RLWE_OUT_FORCE_EXACT | RLWE_IN_SEEDED))
+    return fail(RLWE_EINVAL, "ct_matmul_pack: unknown flags 0x%x", flags);
+  if (n_pack < 1 || n_pack > ctx->rc.N)
+    return fail(RLWE_ESHAPE, "n_pack = %u outside [1, N]", n_pack);
+  ct_matmul_desc d{};
+  d.w = w;
+  d.transpose = transpose;
+  d.ct_in = ct_in;
+  d.tokens = tokens;
+  d.out = out;
+  const Mat* m;
+  int r = validate_desc(ctx, d, &m);
+  if (r != RLWE_OK) return r;
+  if (tokens == 0) return ok();
+  const size_t M = (size_t)tokens * m->args.rows;
+  if ((M + n_pack - 1) / n_pack >= (1ull << 31))
+    return fail(RLWE_ESHAPE, "ct_matmul_pack: %zu ciphertexts too many", M);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  size_t off_inter, off_ks;
+  const size_t need = matmul_pack_ws(ctx, *m, tokens, k, n_pack, &off_inter, &off_ks);
+  if (need > ctx->ws_bytes) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+      return fail(RLWE_EINVAL, "workspace must be reserved (rlwe_workspace_reserve) before capture");
+    r = ensure_ws(ctx, need, s);
+    if (r != RLWE_OK) return r;
   }
+  unsigned char* ws = (unsigned char*)ctx->ws;
+  d.out = ws + off_inter;
+  // NTT method: the product rounds the masks for the key's decomposition; otherwise
+  // it writes raw residues and the digit kernel rounds them
+  const uint32_t pflags = (flags & (RLWE_OUT_FORCE_EXACT | RLWE_IN_SEEDED)) | (m->ntt ? 0 : RLWE_OUT_RAW_Q);
+  r = run_batch(ctx, &d, 1, pflags, s, ws, m->ntt ? k : nullptr);
+  if (r != RLWE_OK) return r;
+  r = ks_run(ctx, k, (const uint64_t*)(ws + off_inter), M, n_pack, out, flags & RLWE_OUT_RAW_Q,
+             m->ntt, ws + off_ks, s);
+  if (r != RLWE_OK) return r;
   return ok();
 }
 

@@ -177,6 +177,18 @@ __host__ __device__ inline uint32_t body_blocks_per_token(const MatArgs& m) {
   return m.n_o > 1 ? (m.n_o * body_group_pad(m) + 255) / 256 : (m.rows + 255) / 256;
 }
 
+// Constants of the gadget rounding a~ = round(c 2^K / q) mod 2^K of a coefficient
+// given by its residues (Decomp's first step). With inv_p = (q/q_p)^-1 mod q_p (1 for
+// one prime): inv_p 2^K = f_p q_p + g_p.
+struct KsRound {
+  uint64_t q[kMaxPrimes];
+  uint64_t Q_hi, Q_lo;               // q = prod q_p (two primes)
+  uint64_t f[kMaxPrimes];            // floor(inv_p 2^K / q_p) mod 2^64
+  uint64_t g[kMaxPrimes];            // inv_p 2^K mod q_p
+  uint64_t g_shoup[kMaxPrimes];      // floor(g 2^64 / q_p)
+  uint64_t G_lo[kMaxPrimes];         // G = floor(g 2^96 / q_p) < 2^96: bits 0..63
+  uint32_t G_hi[kMaxPrimes];         //   and bits 64..95
+};
 // One product of a batch: weights, input ciphertexts, workspace planes, output.
 struct Item {
   MatArgs m;
@@ -187,7 +199,7 @@ struct Item {
   const uint64_t* ct;  // [T][L][2][P][N]
   int8_t* emask;       // [T][D][L][2N]: per digit plane, index m <-> Toeplitz offset m - N
   int8_t* ebody;       // [T][D][L][N]
-  void* out;           // switched u32 [T][M][N+1] or raw u64 [T][M][P][N+1]
+  void* out;           // switched u32 [T][M][N+1], raw u64 [T][M][P][N+1], or rounded u64 [T][M][N+P]
   uint32_t T;
 };
 
@@ -201,6 +213,9 @@ struct Batch {
   uint32_t raw;
   uint32_t force_exact;
   uint32_t seeded;  // inputs in the seeded layout: per block [seed, 0, B residues]
+  uint32_t gadget;  // (with raw) masks rounded to 2^K: outputs [T][M][N+P], a~ then bodies
+  uint64_t kmask;   // 2^K - 1
+  KsRound kr;
   NttConst ntt;
   uint32_t prep_start[kMaxBatch + 1];  // blocks of 256 threads over T*L*N coefficients
   uint32_t fwd_start[kMaxBatch + 1];   // NTT method: one transform per (token, block, prime)
@@ -216,11 +231,7 @@ struct KsConst {
   uint32_t beta, ell, K;             // digit bits, levels, K = beta ell rounding bits (<= 64)
   uint64_t kmask;                    // 2^K - 1
   uint64_t H;                        // sum_m 2^(beta-1) 2^(beta m) mod 2^64
-  // with inv_p = (q / q_p)^-1 mod q_p (1 for one prime):
-  uint64_t f[kMaxPrimes];            // floor(inv_p 2^K / q_p) mod 2^64
-  uint64_t g[kMaxPrimes];            // inv_p 2^K mod q_p
-  uint64_t g_shoup[kMaxPrimes];      // floor(g 2^64 / q_p)
-  double rq[kMaxPrimes];             // 1 / q_p (estimate only; near ties are redone exactly)
+  KsRound rd;
 };
 // Arguments of the KeySwitch kernels (read in place through the kernarg segment).
 struct KsArgs {
@@ -232,6 +243,8 @@ struct KsArgs {
   uint32_t n_pack;       // slots filled per packed output
   uint32_t g0, GB;       // first output group of this pass, groups in the pass
   uint32_t raw;          // outputs modulo q per prime (else switched to 2^qbits)
+  uint32_t pre;          // lwe holds rounded masks: [M][N+P] (a~ mod 2^K, then the P body
+                         // residues), else raw LWE ciphertexts [M][P][N+1]
   int64_t* dig;          // workspace: digits [GB][N][ell][N]
   const uint64_t* khat;  // key in the NTT domain [N][ell][P][2][N][2] (value, Shoup companion), lane-major
   uint64_t* part;        // workspace: partial sums [GB][N / 64][P][2][N]

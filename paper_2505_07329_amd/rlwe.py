@@ -41,7 +41,7 @@ EXPORTS = ("rlwe_params_init", "rlwe_params_destroy", "rlwe_weights_load", "rlwe
            "rlwe_graph_destroy", "rlwe_weights_method", "ct_pack_bits", "rlwe_packed_words",
            "rlwe_weights_rows_per_product", "rlwe_ksk_load", "rlwe_ksk_free",
            "rlwe_packed_count", "rlwe_keyswitch_workspace_bytes", "ct_keyswitch_pack",
-           "rlwe_last_error")
+           "rlwe_matmul_pack_workspace_bytes", "ct_matmul_pack", "rlwe_last_error")
 
 
 class RlweError(RuntimeError):
@@ -125,12 +125,17 @@ def lib() -> ctypes.CDLL:
     L.rlwe_keyswitch_workspace_bytes.restype = ctypes.c_size_t
     L.ct_keyswitch_pack.argtypes = [vp, vp, vp, ctypes.c_size_t, ctypes.c_uint32, vp,
                                     ctypes.c_uint32, vp]
+    L.rlwe_matmul_pack_workspace_bytes.argtypes = [vp, vp, ctypes.c_uint32, ctypes.c_uint32, vp,
+                                                   ctypes.c_uint32]
+    L.rlwe_matmul_pack_workspace_bytes.restype = ctypes.c_size_t
+    L.ct_matmul_pack.argtypes = [vp, vp, ctypes.c_uint32, vp, ctypes.c_uint32, vp,
+                                 ctypes.c_uint32, vp, ctypes.c_uint32, vp]
     L.rlwe_last_error.argtypes = []
     L.rlwe_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name not in ("rlwe_last_error", "rlwe_workspace_bytes", "rlwe_batch_workspace_bytes",
                         "rlwe_packed_words", "rlwe_packed_count",
-                        "rlwe_keyswitch_workspace_bytes"):
+                        "rlwe_keyswitch_workspace_bytes", "rlwe_matmul_pack_workspace_bytes"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -293,6 +298,19 @@ def ct_keyswitch_pack(ctx: int, k: int, lwe, count: int, n_pack: int, out,
                                    _stream(stream)))
 
 
+def rlwe_matmul_pack_workspace_bytes(ctx: int, w: int, transpose: bool, tokens: int, k: int,
+                                     n_pack: int) -> int:
+    return int(lib().rlwe_matmul_pack_workspace_bytes(ctx, w, int(bool(transpose)), tokens, k,
+                                                      n_pack))
+
+
+def ct_matmul_pack(ctx: int, w: int, ct, tokens: int, k: int, n_pack: int, out,
+                   transpose: bool = False, flags: int = RLWE_OUT_SWITCHED, stream=None) -> None:
+    """ct as for ct_matmul_clear; out as for ct_keyswitch_pack with count = tokens * rows."""
+    _check(lib().ct_matmul_pack(ctx, w, int(bool(transpose)), _ptr(ct), tokens, k, n_pack,
+                                _ptr(out), flags, _stream(stream)))
+
+
 def rlwe_profile_begin(ctx: int) -> None:
     _check(lib().rlwe_profile_begin(ctx))
 
@@ -411,4 +429,22 @@ def keyswitch_pack(ctx: Context, k: KeySwitchKey, lwe, n_pack: int | None = None
         out = torch.empty(shape, dtype=torch.int64 if raw else torch.int32, device=lwe.device)
     ct_keyswitch_pack(ctx.handle, k.handle, lwe, count, n_pack, out,
                       RLWE_OUT_RAW_Q if raw else RLWE_OUT_SWITCHED, stream)
+    return out
+
+
+def matmul_pack(ctx: Context, w: Weights, ct, k: KeySwitchKey, n_pack: int | None = None,
+                transpose: bool = False, raw: bool = False, force_exact: bool = False,
+                seeded: bool = False, out=None, stream=None):
+    """ct_matmul_pack (torch): the product's LWE outputs, in (token, row) order, packed into
+    RLWE ciphertexts (G, 2, N) int32 switched, or (G, 2, P, N) int64 with raw=True."""
+    import torch
+    n_pack = ctx.N if n_pack is None else int(n_pack)
+    T = ct.shape[0]
+    G = rlwe_packed_count(T * w.out_rows(transpose), n_pack)
+    if out is None:
+        shape = (G, 2, ctx.P, ctx.N) if raw else (G, 2, ctx.N)
+        out = torch.empty(shape, dtype=torch.int64 if raw else torch.int32, device=ct.device)
+    flags = (RLWE_OUT_RAW_Q if raw else 0) | (RLWE_OUT_FORCE_EXACT if force_exact else 0)
+    flags |= RLWE_IN_SEEDED if seeded else 0
+    ct_matmul_pack(ctx.handle, w.handle, ct, T, k.handle, n_pack, out, transpose, flags, stream)
     return out

@@ -82,6 +82,8 @@ def test_keyswitch_entry_points_reject_null_arguments():
     assert L.ct_keyswitch_pack(None, None, None, 0, 1, None, 0, None) == -1
     assert L.rlwe_ksk_free(None) == 0
     assert L.rlwe_keyswitch_workspace_bytes(None, None, 1, 1) == 0
+    assert L.ct_matmul_pack(None, None, 0, None, 0, None, 1, None, 0, None) == -1
+    assert L.rlwe_matmul_pack_workspace_bytes(None, None, 0, 1, None, 1) == 0
     assert L.rlwe_packed_count(10, 4) == 3
     assert L.rlwe_packed_count(8192, 4096) == 2
     assert L.rlwe_packed_count(10, 0) == 0

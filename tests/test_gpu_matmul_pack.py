@@ -1,0 +1,166 @@
+"""The product and KeySwitch packing in one call (ct_matmul_pack, Eq. (LWEdot) then
+Eq. (pack_rotate)) against the two calls it replaces and against the oracle, bit for
+bit, through the C ABI.
+
+With the NTT method the product kernel rounds every mask coefficient for the key's
+gadget decomposition itself; with the matrix-core method raw residues pass between the
+two steps. Covered: two primes with one and two gadget levels, one prime with three,
+one and two input blocks, packed rows, the matrix-core method, ragged last groups and
+n_pack below N, raw and switched outputs, every rounding through the exact route,
+seeded inputs, two calls in a row with different shapes, errors, and end-to-end
+decryption of a packed product under the packing key.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2505_07329_amd import synth
+from tests.cases import make_case
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N = 4096
+P2 = synth.PRIMES_4096
+P1 = synth.PRIMES_4096[:1]
+
+
+def rl():
+    from paper_2505_07329_amd import rlwe
+    return rlwe
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a.view(np.int64) if a.dtype == np.uint64 else a)).cuda()
+
+
+def host_u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def uniform(primes, lead, n, salt):
+    return synth.uniform_mod_primes(synth.rng(0, synth.P_MISC, 500 + salt), primes, lead, n)
+
+
+FLAGS = {"ntt": "RLWE_W_NTT", "toeplitz": "RLWE_W_TOEPLITZ", "rowpack": None}
+
+
+def method_flag(r, method):
+    if method == "rowpack":
+        return r.RLWE_W_NTT | r.RLWE_W_ROWPACK
+    return getattr(r, FLAGS[method])
+
+
+@pytest.mark.parametrize("method,primes,beta,ell,d_out,d_in,T,n_pack", [
+    ("ntt", P2, 54, 1, 1500, 2048, 3, N),    # 4500 LWE ciphertexts: a ragged second group
+    ("ntt", P2, 27, 2, 700, 5000, 2, 500),   # two input blocks, n_pack below N
+    ("ntt", P1, 12, 3, 300, 4096, 2, 700),   # one prime, three levels
+    ("rowpack", P2, 54, 1, 1000, 2048, 2, N),  # two rows per weight polynomial
+    ("toeplitz", P2, 54, 1, 200, 512, 2, N),   # matrix cores: raw residues between the steps
+])
+def test_fused_equals_two_calls_and_oracle(method, primes, beta, ell, d_out, d_in, T, n_pack):
+    print(f"case: matmul_pack {method} P={len(primes)} beta={beta} ell={ell} "
+          f"{d_out}x{d_in} T={T} n_pack={n_pack}", flush=True)
+    r = rl()
+    L = (d_in + N - 1) // N
+    ct = uniform(primes, (T, L, 2), N, d_in + d_out)
+    W = synth.int8_uniform(np.random.default_rng(d_out + 7), (d_out, d_in))
+    ksk = uniform(primes, (N, ell, 2), N, beta)
+    with r.Context(N, primes, 30) as ctx:
+        w = r.Weights(ctx, dev(W), r.RLWE_W_FWD | method_flag(r, method))
+        k = r.KeySwitchKey(ctx, dev(ksk), beta, ell)
+        x = dev(ct)
+        lwe = r.matmul(ctx, w, x, raw=True)
+        ref = r.keyswitch_pack(ctx, k, lwe, n_pack, raw=True)
+        ref_sw = r.keyswitch_pack(ctx, k, lwe, n_pack)
+        got = r.matmul_pack(ctx, w, x, k, n_pack, raw=True)
+        got_sw = r.matmul_pack(ctx, w, x, k, n_pack)
+        got_ex = r.matmul_pack(ctx, w, x, k, n_pack, raw=True, force_exact=True)
+        torch.cuda.synchronize()
+        lw = host_u64(lwe)
+        g = host_u64(got)
+        assert np.array_equal(g, host_u64(ref)), f"{int((g != host_u64(ref)).sum())} residues differ"
+        assert np.array_equal(host_u64(got_ex), g)
+        assert np.array_equal(got_sw.cpu().numpy(), ref_sw.cpu().numpy())
+        w.close()
+        k.close()
+    want = orc.keyswitch_pack(N, primes, beta, ell, lw.reshape(-1, len(primes), N + 1), ksk, n_pack)
+    assert np.array_equal(g, want)
+    assert np.array_equal(got_sw.cpu().numpy().view(np.uint32), orc.rlwe_modswitch_bits(primes, want, 32))
+
+
+def test_seeded_inputs_calls_in_a_row_and_errors():
+    """Seeded inputs (masks expanded on the GPU); a larger call, then a smaller one with
+    another n_pack on the same context; tokens = 0 is a no-op; invalid n_pack, a key of
+    another context and weights loaded without the orientation are refused."""
+    print("case: matmul_pack seeded, calls in a row, errors", flush=True)
+    r = rl()
+    d_out, d_in, T = 600, 3000, 3
+    g = np.random.default_rng(77)
+    seeds = g.integers(0, 2**63, size=(T, 1), dtype=np.uint64)
+    A = orc.expand_masks(seeds, N, P2)
+    B = synth.uniform_mod_primes(g, P2, (T, 1), N)
+    ct = np.stack([A, B], axis=2)
+    sl = orc.seeded_layout(ct, seeds)
+    W = synth.int8_uniform(g, (d_out, d_in))
+    ksk = uniform(P2, (N, 1, 2), N, 3)
+    with r.Context(N, P2, 30) as ctx:
+        w = r.Weights(ctx, dev(W), r.RLWE_W_FWD | r.RLWE_W_NTT)
+        k = r.KeySwitchKey(ctx, dev(ksk), 54, 1)
+        big = r.matmul_pack(ctx, w, dev(sl), k, N, raw=True, seeded=True)
+        small = r.matmul_pack(ctx, w, dev(ct[:1]), k, 250, raw=True)
+        torch.cuda.synchronize()
+        lw = orc.matmul_clear(N, P2, W, ct).reshape(-1, 2, N + 1)
+        assert np.array_equal(host_u64(big), orc.keyswitch_pack(N, P2, 54, 1, lw, ksk, N))
+        assert np.array_equal(host_u64(small), orc.keyswitch_pack(N, P2, 54, 1, lw[:d_out], ksk, 250))
+        dummy = torch.zeros(1, dtype=torch.int64, device="cuda")
+        r.ct_matmul_pack(ctx.handle, w.handle, dummy, 0, k.handle, N, dummy)  # no-op
+        for n_pack in (0, N + 1):
+            with pytest.raises(r.RlweError) as ei:
+                r.ct_matmul_pack(ctx.handle, w.handle, dummy, 1, k.handle, n_pack, dummy)
+            assert ei.value.code == r.RLWE_ESHAPE
+        with pytest.raises(r.RlweError) as ei:  # loaded without RLWE_W_TRANSPOSE
+            r.ct_matmul_pack(ctx.handle, w.handle, dummy, 1, k.handle, N, dummy, transpose=True)
+        assert ei.value.code == r.RLWE_EINVAL
+        with r.Context(N, P2, 30) as other:
+            k2 = r.KeySwitchKey(other, dev(ksk), 54, 1)
+            with pytest.raises(r.RlweError) as ei:
+                r.ct_matmul_pack(ctx.handle, w.handle, dummy, 1, k2.handle, N, dummy)
+            assert ei.value.code == r.RLWE_EINVAL
+            k2.close()
+        w.close()
+        k.close()
+
+
+def test_packed_product_decrypts():
+    """A real encryption and a real key: every slot of the packed product decrypts under
+    the packing key to W x (one token per ciphertext), the empty slots to 0, switched
+    to 2^32 as well as modulo q."""
+    print("case: matmul_pack end to end", flush=True)
+    r = rl()
+    d_in, d_out, T, log2_t = 2048, 1200, 2, 26
+    case = make_case(N, P2, log2_t, d_out, d_in, T, config=2, salt=57)
+    A = synth.uniform_mod_primes(synth.rng(2, synth.P_MASK, 58), P2, (N, 1), N)
+    E = synth.rounded_gaussian(synth.rng(2, synth.P_ERROR, 58), (N, 1, N))
+    S_dst = synth.ternary(synth.rng(2, synth.P_SECRET, 58), N)
+    ksk = orc.ksk_gen(N, P2, 54, 1, case.S, S_dst, A, E)
+    with r.Context(N, P2, log2_t) as ctx:
+        w = r.Weights(ctx, dev(case.W), r.RLWE_W_FWD | r.RLWE_W_NTT)
+        k = r.KeySwitchKey(ctx, dev(ksk), 54, 1)
+        packed = r.matmul_pack(ctx, w, dev(case.ct), k, d_out, raw=True)
+        sw = r.matmul_pack(ctx, w, dev(case.ct), k, d_out)
+        torch.cuda.synchronize()
+        pk = host_u64(packed)
+        s32 = sw.cpu().numpy().view(np.uint32)
+        w.close()
+        k.close()
+    lw = orc.matmul_clear(N, P2, case.W, case.ct).reshape(-1, 2, N + 1)
+    assert np.array_equal(pk, orc.keyswitch_pack(N, P2, 54, 1, lw, ksk, d_out))
+    assert np.array_equal(s32, orc.rlwe_modswitch_bits(P2, pk, 32))
+    y = case.x.astype(np.int64) @ case.W.astype(np.int64).T
+    ph = orc.rlwe_decrypt_slots(N, P2, S_dst, pk)
+    for t in range(T):
+        dec = [orc.decode(v, case.delta) for v in ph[t]]
+        assert dec[:d_out] == [int(v) for v in y[t]]
+        assert all(v == 0 for v in dec[d_out:])
