@@ -94,12 +94,16 @@ def roofline(products, kt, N, P, traffic=None):
 KERNEL_TRAFFIC = {
     "mask": {"sources": ["k_mask.hip"], "fetch_bytes": 4382392135, "write_bytes": 4766662645,
              "sha256": "b71d09264e517098c1179f16657d1e4fa62f1eaae851294a6d0fdb5115986154"},
-    "ntt": {"sources": ["k_ntt.hip", "ntt_device.hpp"], "fetch_bytes": 5229068197,
-            "write_bytes": 4353263073,
-            "sha256": "5940a3bc95d060bc17cb8c97bb71eac99c2dc47ccb3a55101a7b0f99ea1a3184"},
-    "ksacc": {"sources": ["k_keyswitch.hip", "ntt_device.hpp"], "fetch_bytes": 13024574302,
-              "write_bytes": 536870912,
-              "sha256": "a3b7e0769e8f43109b006a44a3a6a099f51728e1743497e52c6a70a19a93380e"},
+    "ntt": {"sources": ["k_ntt.hip", "ntt_device.hpp", "ks_round.hpp"], "fetch_bytes": 5235399093,
+            "write_bytes": 4353409833,
+            "sha256": "54bbd23bc851573e643c2b930121939d417596e893ad87097cd9f620a7f47c1c"},
+    # the product with masks rounded for KeySwitch packing (ct_matmul_pack, --keyswitch)
+    "ntt_ks": {"sources": ["k_ntt.hip", "ntt_device.hpp", "ks_round.hpp"],
+               "fetch_bytes": 6243685734, "write_bytes": 8676000492,
+               "sha256": "54bbd23bc851573e643c2b930121939d417596e893ad87097cd9f620a7f47c1c"},
+    "ksacc": {"sources": ["k_keyswitch.hip", "ntt_device.hpp", "ks_round.hpp"],
+              "fetch_bytes": 13018531221, "write_bytes": 536870912,
+              "sha256": "5b9871e8647d89080280f9a7251d9bb93aa902e4164191062aea659d500d3815"},
 }
 
 
@@ -194,6 +198,7 @@ def source_sha256(kind):
 
 
 KERNEL_SOURCES = {"mask": ["k_mask.hip"], "ntt": ["k_ntt.hip", "ntt_device.hpp", "ks_round.hpp"],
+                  "ntt_ks": ["k_ntt.hip", "ntt_device.hpp", "ks_round.hpp"],
                   "ksacc": ["k_keyswitch.hip", "ntt_device.hpp", "ks_round.hpp"]}
 
 
@@ -790,7 +795,8 @@ def main():
     roof, _ = roofline([dict(T=T, M=d_out, K=d_in, kept=kept, ntt=is_ntt, n_o=n_o)], one, N,
                        len(primes),
                        traffic={"mfma": None if ks else kernel_traffic("mask"),
-                                "alu": kernel_traffic("ntt") if n_o == 1 and not ks else None})
+                                "alu": None if n_o != 1 else
+                                kernel_traffic("ntt_ks" if ks else "ntt")})
     ks_roof = None
     if ks and kt["ksacc_n"]:
         ks_ms = {k: kt[f"ks{k}_ms"] / max(1, kt[f"ks{k}_n"]) * kt[f"ks{k}_n"] / args.steps
