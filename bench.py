@@ -92,8 +92,8 @@ def roofline(products, kt, N, P, traffic=None):
 # (--copy-calibration). Valid for the kernel source it was taken on (sha256); for any
 # other source the roofline reports traffic as null.
 KERNEL_TRAFFIC = {
-    "mask": {"sources": ["k_mask.hip"], "fetch_bytes": 4382392135, "write_bytes": 4766662645,
-             "sha256": "b71d09264e517098c1179f16657d1e4fa62f1eaae851294a6d0fdb5115986154"},
+    "mask": {"sources": ["k_mask.hip"], "fetch_bytes": 4382214101, "write_bytes": 4766672373,
+             "sha256": "37b3392ace8226fcd057a2f461259544933971d70c4ba84b554979c7875ac123"},
     "ntt": {"sources": ["k_ntt.hip", "ntt_device.hpp", "ks_round.hpp"], "fetch_bytes": 5235399093,
             "write_bytes": 4353409833,
             "sha256": "54bbd23bc851573e643c2b930121939d417596e893ad87097cd9f620a7f47c1c"},
