@@ -7,8 +7,9 @@ gadget decomposition itself; with the matrix-core method raw residues pass betwe
 two steps. Covered: two primes with one and two gadget levels, one prime with three,
 one and two input blocks, packed rows, the matrix-core method, ragged last groups and
 n_pack below N, raw and switched outputs, every rounding through the exact route,
-seeded inputs, two calls in a row with different shapes, errors, and end-to-end
-decryption of a packed product under the packing key.
+seeded inputs, two calls in a row with different shapes, the transposed orientation with
+two passes of the KeySwitch kernels, errors, and end-to-end decryption of a packed
+product under the packing key.
 """
 
 import numpy as np
@@ -164,3 +165,35 @@ def test_packed_product_decrypts():
         dec = [orc.decode(v, case.delta) for v in ph[t]]
         assert dec[:d_out] == [int(v) for v in y[t]]
         assert all(v == 0 for v in dec[d_out:])
+
+
+def test_transposed_weights_and_several_passes():
+    """The backward orientation (W^T.[g], weights loaded with RLWE_W_TRANSPOSE) with 4096
+    outputs per token packed 60 per ciphertext: 69 packed ciphertexts, two passes of the
+    KeySwitch kernels; equal to the two calls, switched and raw."""
+    print("case: matmul_pack transposed, two passes", flush=True)
+    r = rl()
+    d_out, d_in, T, n_pack = 130, 4096, 1, 60
+    W = synth.int8_uniform(np.random.default_rng(11), (d_out, d_in))
+    ct = uniform(P2, (T, 1, 2), N, 99)  # one input block of d_out = 130 coefficients
+    ksk = uniform(P2, (N, 1, 2), N, 5)
+    with r.Context(N, P2, 30) as ctx:
+        w = r.Weights(ctx, dev(W), r.RLWE_W_FWD | r.RLWE_W_TRANSPOSE | r.RLWE_W_NTT)
+        k = r.KeySwitchKey(ctx, dev(ksk), 54, 1)
+        x = dev(ct)
+        lwe = r.matmul(ctx, w, x, transpose=True, raw=True)
+        assert lwe.shape == (T, d_in, 2, N + 1)
+        ref = r.keyswitch_pack(ctx, k, lwe, n_pack, raw=True)
+        ref_sw = r.keyswitch_pack(ctx, k, lwe, n_pack)
+        got = r.matmul_pack(ctx, w, x, k, n_pack, transpose=True, raw=True)
+        got_sw = r.matmul_pack(ctx, w, x, k, n_pack, transpose=True)
+        torch.cuda.synchronize()
+        assert got.shape[0] == 69
+        assert np.array_equal(host_u64(got), host_u64(ref))
+        assert np.array_equal(got_sw.cpu().numpy(), ref_sw.cpu().numpy())
+        lw = host_u64(lwe).reshape(-1, 2, N + 1)
+        w.close()
+        k.close()
+    # the first packed ciphertext against the oracle
+    want = orc.keyswitch_pack(N, P2, 54, 1, lw[:n_pack], ksk, n_pack)
+    assert np.array_equal(host_u64(got)[:1], want)
