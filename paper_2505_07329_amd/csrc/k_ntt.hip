@@ -221,7 +221,8 @@ __global__ void __launch_bounds__(kInvThreads, LC == 2 ? 4 : 1) ntt_mask_kernel(
       }
     } else {
       uint32_t res[8];
-      uint32_t tie = 0;  // coefficients within 8 units below a rounding tie
+      // coefficients within 8 units below a rounding tie (all of them when forced)
+      uint32_t tie = bt->force_exact ? 0xffu : 0u;
       const uint32_t qbits = bt->rc.qbits;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {

@@ -1,0 +1,136 @@
+"""CPU model of the switched epilogue of the NTT product kernel (ModulusSwitch, Sec. 3.2):
+round(c 2^k / q) mod 2^k from unreduced residues c_p of a coefficient c.
+
+The kernel forms X = sum_p c_p H_p mod 2^32 in 32.32 fixed point, H_p = ((q/q_p)^-1 mod
+q_p) 2^32 / q_p held as h_p = floor(crt_p 2^128 / q_p) mod 2^128, taking only the
+partial products of c_p h_p at and above bit 64 (the 64-bit word `fixed_part`). The
+model repeats those integer steps (32-bit halves, 64-bit wrapping sums) and checks,
+against exact big-integer arithmetic, the facts the kernel relies on:
+  * the estimate is never above floor(c 2^64 / q) mod 2^64 and at most 7 units of
+    2^-32 below it, for any 64-bit lift of the residues (the inverse transform hands
+    over values below 64 q_p, not reduced);
+  * its rounding to 2^k (k = 1..32) is the exact rounding unless the fraction lies
+    within 8 units below one half (then the kernel recomputes exactly);
+  * values next to rounding ties reach that window.
+Inputs: uniform c, random lifts of its residues, c next to ties of every k tested,
+c at the window's edge; one prime (N = 2048 parameters) and two (N = 4096).
+"""
+
+import random
+
+import pytest
+
+M32, M64 = (1 << 32) - 1, (1 << 64) - 1
+P2 = (18014398509309953, 18014398509293569)
+P1 = (18014398509404161,)
+
+
+def modulus(primes):
+    q = 1
+    for p in primes:
+        q *= p
+    return q
+
+
+def epilogue_constants(primes):
+    """h_p = floor(crt_p 2^128 / q_p) mod 2^128 as four 32-bit words (little-endian)."""
+    q = modulus(primes)
+    hs = []
+    for p in primes:
+        crt = pow(q // p, -1, p) if len(primes) > 1 else 1
+        h = ((crt << 128) // p) & ((1 << 128) - 1)
+        hs.append([(h >> (32 * w)) & M32 for w in range(4)])
+    return hs
+
+
+def fixed_part(c, h):
+    """The kernel's word: bits 64..127 of c h mod 2^128 without the partial products
+    that end below bit 64 (c0 h0 and the low halves of c0 h1, c1 h0)."""
+    c0, c1 = c & M32, c >> 32
+    a = ((c0 * h[1]) >> 32) + ((c1 * h[0]) >> 32)
+    a = (a + c0 * h[2] + c1 * h[1]) & M64
+    a = (a + ((((c0 * h[3]) + (c1 * h[2])) & M32) << 32)) & M64
+    return a
+
+
+def estimate(cs, hs):
+    a = 0
+    for c, h in zip(cs, hs):
+        a = (a + fixed_part(c, h)) & M64
+    return a
+
+
+def round_qout(W, k):
+    """The kernel's rounding of 32.32 fixed point W to 2^k: value, and the fraction
+    minus one half in units of W."""
+    sh = 64 - k
+    frac = W & ((1 << sh) - 1)
+    half = 1 << (sh - 1)
+    val = ((W >> sh) + (1 if frac >= half else 0)) & ((1 << k) - 1)
+    return val, frac - half
+
+
+def exact_units(c, q):
+    return ((c << 64) // q) & M64
+
+
+def exact_round(c, q, k):
+    return ((2 * (c << k) + q) // (2 * q)) % (1 << k)
+
+
+def lift(c, p, rng, bound):
+    """A residue of c mod p lifted by a random multiple of p, below `bound`."""
+    r = c % p
+    return r + p * rng.randrange((bound - r) // p)
+
+
+def near_tie_values(q, k, rng, n, span_units=8):
+    """c whose exact c 2^k / q lies within span_units units of 2^-32 (of c 2^32 / q) of
+    a rounding tie m + 1/2, on either side."""
+    out = []
+    step = max(1, q >> 64)  # one unit of 2^-32 of c 2^32 / q in steps of c (two primes)
+    for _ in range(n):
+        m = rng.randrange(1 << k)
+        tie = ((2 * m + 1) * q) >> (k + 1)
+        d = rng.randrange(-span_units * step, span_units * step + 1)
+        out.append(min(q - 1, max(0, tie + d)))
+    return out
+
+
+@pytest.mark.parametrize("primes", [P2, P1])
+@pytest.mark.parametrize("k", [32, 26, 20, 1])
+def test_epilogue_estimate_and_rounding(primes, k):
+    q = modulus(primes)
+    hs = epilogue_constants(primes)
+    rng = random.Random(20250507 + 17 * k + len(primes))
+    values = [rng.randrange(q) for _ in range(2000)] + near_tie_values(q, k, rng, 2000)
+    values += [0, 1, q - 1, (q - 1) // 2, (q + 1) // 2]
+    window_hits = 0
+    for c in values:
+        for bound in (64 * max(primes), 1 << 64):  # the transform's bound, any 64-bit lift
+            cs = [lift(c, p, rng, bound) for p in primes]
+            A = estimate(cs, hs)
+            deficit = (exact_units(c, q) - A) & M64
+            assert 0 <= deficit <= 7, (c, cs, deficit)
+            val, dist = round_qout(A, k)
+            if -8 <= dist < 0:
+                window_hits += 1
+            else:
+                assert val == exact_round(c, q, k), (c, k)
+    if len(primes) == 2:  # the window spans values of c: the near-tie draws reach it
+        assert window_hits > 0
+
+
+def test_window_needs_the_exact_route():
+    """Some coefficients just above a tie are estimated below it (inside the window): a
+    kernel that skipped the exact route there would round them down, one unit wrong."""
+    q = modulus(P2)
+    hs = epilogue_constants(P2)
+    rng = random.Random(5)
+    wrong_if_skipped = 0
+    for c in near_tie_values(q, 32, rng, 4000, span_units=4):
+        A = estimate([c % p for p in P2], hs)
+        val, dist = round_qout(A, 32)
+        if -8 <= dist < 0 and val != exact_round(c, q, 32):
+            wrong_if_skipped += 1
+    assert wrong_if_skipped > 0
