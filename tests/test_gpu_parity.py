@@ -142,12 +142,17 @@ def test_attention_shape_all_paths_agree():
 
 def test_config2_full_size_sampled():
     """The benchmark workload: 2048x2048, 128 tokens, N = 4096, t = 2^26, in the
-    launch configuration the benchmark times. Sampled rows against the oracle;
-    a larger sample satisfies the deterministic switched-noise bound."""
+    launch configuration the benchmark times. Every output of one full tile of 8
+    tokens (tokens 8..15, all 2048 rows) and sampled outputs elsewhere against the
+    oracle; a larger sample satisfies the deterministic switched-noise bound."""
     print("case: config2 2048x2048 T128 N4096", flush=True)
     case = make_case(4096, P4096, 26, 2048, 2048, 128, config=2)
     s = Setup(case)
     out = s.run()  # (128, 2048, 4097) int32 on the GPU
+    tile = host_u32(out[8:16])
+    want = orc.modswitch(case.primes, orc.matmul_clear(case.N, case.primes, case.W, case.ct[8:16]))
+    assert np.array_equal(tile, want), f"{int((tile != want).sum())} coefficients of the tile differ"
+    del tile, want
     g = np.random.default_rng(2)
     pairs = np.stack([g.integers(0, 128, 12), g.integers(0, 2048, 12)], 1).astype(np.uint32)
     pairs = np.concatenate([pairs, np.array([[0, 0], [127, 2047]], dtype=np.uint32)])
@@ -224,38 +229,44 @@ def _switched_bound_holds(case, W, out, g, n=512):
     return bool(np.all(np.abs(ph - dprime * v) <= bound))
 
 
-def test_config3_mlp_chunk_launch_config():
-    """Down projection of the MLP workload (W 2048 x 8192, t = 2^28) in the launch
-    configuration the benchmark times: 256-token chunks, forward (L = 2, 2048 outputs)
-    and transposed (L = 1, 8192 outputs). Sampled outputs against the oracle, and the
-    switched-noise bound on random outputs."""
-    print("case: mlp down 2048x8192 fwd+transposed, chunk 256", flush=True)
+def _sampled_against_oracle(case, W, out, g, n=32):
+    """n random outputs and the two corners of `out` (T, M, N+1) against the oracle."""
+    T, M = out.shape[0], out.shape[1]
+    pairs = np.stack([g.integers(0, T, n), g.integers(0, M, n)], 1).astype(np.uint32)
+    pairs = np.concatenate([pairs, np.array([[0, 0], [T - 1, M - 1]], dtype=np.uint32)])
+    ref = orc.modswitch(case.primes, orc.matmul_clear(case.N, case.primes, W, case.ct, pairs=pairs))
+    got = host_u32(out[torch.from_numpy(pairs[:, 0].astype(np.int64)).cuda(),
+                       torch.from_numpy(pairs[:, 1].astype(np.int64)).cuda()])
+    return np.array_equal(got, ref)
+
+
+MLP = [("gate", 2048, 8192), ("up", 2048, 8192), ("down", 8192, 2048)]
+
+
+@pytest.mark.parametrize("name,d_in,d_out", MLP)
+def test_config3_mlp_products_launch_config(name, d_in, d_out):
+    """The MLP workload (t = 2^28) in the launch configuration the benchmark times:
+    256-token calls of one projection forward (W x) and transposed (W^T g) with the
+    default method. 34 sampled outputs of each product against the oracle, and the
+    switched-noise bound on 512 random outputs."""
+    print(f"case: mlp {name} {d_in}->{d_out} fwd+transposed, chunk 256", flush=True)
     N, primes, log2_t, C = 4096, P4096, 28, 256
-    fwd = make_case(N, primes, log2_t, 2048, 8192, C, config=3, salt=11)
+    salt = {"gate": 21, "up": 23, "down": 11}[name]
+    fwd = make_case(N, primes, log2_t, d_out, d_in, C, config=3, salt=salt)
     r = rl()
     ctx = r.Context(N, primes, log2_t)
     w = r.Weights(ctx, dev(fwd.W), r.RLWE_W_FWD | r.RLWE_W_TRANSPOSE)
-    g = np.random.default_rng(3)
+    g = np.random.default_rng(3 + salt)
     out = r.matmul(ctx, w, dev(fwd.ct))
     torch.cuda.synchronize()
-    pf = np.stack([g.integers(0, C, 8), g.integers(0, 2048, 8)], 1).astype(np.uint32)
-    pf = np.concatenate([pf, np.array([[0, 0], [C - 1, 2047]], dtype=np.uint32)])
-    ref = orc.modswitch(primes, orc.matmul_clear(N, primes, fwd.W, fwd.ct, pairs=pf))
-    got = host_u32(out[torch.from_numpy(pf[:, 0].astype(np.int64)).cuda(),
-                       torch.from_numpy(pf[:, 1].astype(np.int64)).cuda()])
-    assert np.array_equal(got, ref)
+    assert _sampled_against_oracle(fwd, fwd.W, out, g)
     assert _switched_bound_holds(fwd, fwd.W, out, g)
     del out
     WT = np.ascontiguousarray(fwd.W.T)
-    bwd = make_case(N, primes, log2_t, 8192, 2048, C, config=3, salt=12, W=WT)
+    bwd = make_case(N, primes, log2_t, d_in, d_out, C, config=3, salt=salt + 1, W=WT)
     out = r.matmul(ctx, w, dev(bwd.ct), transpose=True)
     torch.cuda.synchronize()
-    pb = np.stack([g.integers(0, C, 8), g.integers(0, 8192, 8)], 1).astype(np.uint32)
-    pb = np.concatenate([pb, np.array([[0, 0], [C - 1, 8191]], dtype=np.uint32)])
-    ref = orc.modswitch(primes, orc.matmul_clear(N, primes, WT, bwd.ct, pairs=pb))
-    got = host_u32(out[torch.from_numpy(pb[:, 0].astype(np.int64)).cuda(),
-                       torch.from_numpy(pb[:, 1].astype(np.int64)).cuda()])
-    assert np.array_equal(got, ref)
+    assert _sampled_against_oracle(bwd, WT, out, g)
     assert _switched_bound_holds(bwd, WT, out, g)
     del out
     w.close()
