@@ -165,6 +165,22 @@ int ct_matmul_clear(rlwe_ctx* ctx, const rlwe_weights* w, uint32_t transpose,
                     const uint64_t* ct_in, uint32_t tokens, void* out, uint32_t flags,
                     rlwe_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): ct_matmul_clear with the
+ * same arguments, flags and results, bit for bit, whose workspace is a fixed device
+ * array of RLWE_NOALLOC_SCRATCH_BYTES in the library instead of the context
+ * workspace. The array exists once per GPU, is held until the process ends and keeps
+ * the last call's contents; calls never allocate or free memory and record no
+ * profiling events. Calls that overlap on one GPU (any context, any stream) race on
+ * the array: order them on one stream. RLWE_ESHAPE if the call needs more workspace
+ * than the array holds (rlwe_workspace_bytes: e.g. at most 356 tokens of a 2048-input
+ * product at N = 4096 with two primes on the NTT method); other errors as for
+ * ct_matmul_clear. */
+#define RLWE_NOALLOC_SCRATCH_BYTES (64u << 20)
+int ct_matmul_clear_noalloc(rlwe_ctx* ctx, const rlwe_weights* w, uint32_t transpose,
+                            const uint64_t* ct_in, uint32_t tokens, void* out, uint32_t flags,
+                            rlwe_stream_t stream);
+
 /* One product of a batch: W.[x] (transpose = 0) or W^T.[g] (transpose = 1) for
  * `tokens` inputs; ct_in and out are device buffers laid out as for
  * ct_matmul_clear. */

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -77,6 +78,34 @@ bool is_prime_h(uint64_t n) {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Workspace of ct_matmul_clear_noalloc: a fixed device array, one copy per GPU the
+// library runs on, held until the process ends. In host code `scratch` names a
+// host-side stand-in; its device address on each GPU comes from hipGetSymbolAddress
+// (taken once per device by rlwe_params_init, with that device current).
+constexpr size_t kScratchBytes = RLWE_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `dev` (looked up once).
+int scratch_lookup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return RLWE_OK;  // such devices get no scratch
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return RLWE_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+             hipGetErrorString(e));
+    g_err = buf;
+    return RLWE_EHIP;
+  }
+  g_scratch_ptr[dev] = ptr;
+  return RLWE_OK;
+}
+
 }  // namespace
 
 namespace {
@@ -112,7 +141,7 @@ namespace {
 // Runs `launch` on stream s; while profiling, brackets it with two events.
 template <class F>
 hipError_t timed(rlwe_ctx* ctx, int kind, hipStream_t s, F launch) {
-  Profiler* p = ctx->prof;
+  Profiler* p = ctx ? ctx->prof : nullptr;
   if (!p || !p->on) return launch();
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
@@ -389,6 +418,10 @@ int rlwe_params_init(const rlwe_params* p, int hip_device, rlwe_ctx** out) {
   ctx->device = hip_device;
   ctx->log2_t = p->log2_t;
   ctx->rc = rc;
+  if (scratch_lookup(hip_device) != RLWE_OK) {
+    delete ctx;
+    return RLWE_EHIP;
+  }
   if (N <= kNttN) {
     const int r = build_ntt(ctx);
     if (r != RLWE_OK) {
@@ -670,8 +703,10 @@ static size_t batch_ws(const rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n)
 // key `gk` (NTT method only), masks are rounded to 2^K for its gadget decomposition
 // and the outputs are [T][M][N+P] (a~, then the body residues).
 static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_t flags,
-                     hipStream_t s, unsigned char* ws, const rlwe_ksk* gk = nullptr) {
+                     hipStream_t s, unsigned char* ws, const rlwe_ksk* gk = nullptr,
+                     bool profile = true) {
   const RingConst& rc = ctx->rc;
+  rlwe_ctx* pc = profile ? ctx : nullptr;  // kernel timing events, unless switched off
   const bool raw = (flags & RLWE_OUT_RAW_Q) || gk;
   // longest contraction first: its tiles are the most expensive (tail balance)
   uint32_t order[kMaxBatch];
@@ -725,10 +760,10 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
     all.body_start[x + 1] = all.body_start[x] + dd.tokens * body_blocks_per_token(m.args);
   }
   all.n = cnt;
-  hipError_t e = timed(ctx, K_PREP, s, [&] { return launch_prep(all, s); });
+  hipError_t e = timed(pc, K_PREP, s, [&] { return launch_prep(all, s); });
   if (e != hipSuccess) return hip_fail(e, "prep kernel");
   if (all.fwd_start[cnt]) {
-    e = timed(ctx, K_PREP, s, [&] { return launch_ntt_mask_fwd(all, s); });
+    e = timed(pc, K_PREP, s, [&] { return launch_ntt_mask_fwd(all, s); });
     if (e != hipSuccess) return hip_fail(e, "mask NTT kernel");
   }
   // matrix-core method: one mask launch per distinct number of kept digits;
@@ -760,11 +795,11 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
       mb.mask_start[mb.n + 1] = mb.mask_start[mb.n] + blocks;
       ++mb.n;
     }
-    e = timed(ctx, ntt ? K_NTT : K_MASK, s,
+    e = timed(pc, ntt ? K_NTT : K_MASK, s,
               [&] { return ntt ? launch_ntt_mask(mb, lc, s) : launch_mask(mb, dk, s); });
     if (e != hipSuccess) return hip_fail(e, "mask kernel");
   }
-  e = timed(ctx, K_BODY, s, [&] { return launch_body(all, s); });
+  e = timed(pc, K_BODY, s, [&] { return launch_body(all, s); });
   if (e != hipSuccess) return hip_fail(e, "body kernel");
   return RLWE_OK;
 }
@@ -814,6 +849,39 @@ int ct_matmul_clear(rlwe_ctx* ctx, const rlwe_weights* w, uint32_t transpose,
   d.tokens = tokens;
   d.out = out;
   return ct_matmul_batch(ctx, &d, 1, flags, stream);
+}
+
+int ct_matmul_clear_noalloc(rlwe_ctx* ctx, const rlwe_weights* w, uint32_t transpose,
+                            const uint64_t* ct_in, uint32_t tokens, void* out, uint32_t flags,
+                            rlwe_stream_t stream) {
+  if (!ctx || !w) return fail(RLWE_EINVAL, "ct_matmul_clear_noalloc: null context or weights");
+  if (flags & ~(RLWE_OUT_RAW_Q | RLWE_OUT_FORCE_EXACT | RLWE_IN_SEEDED))
+    return fail(RLWE_EINVAL, "ct_matmul_clear_noalloc: unknown flags 0x%x", flags);
+  ct_matmul_desc d{};
+  d.w = w;
+  d.transpose = transpose;
+  d.ct_in = ct_in;
+  d.tokens = tokens;
+  d.out = out;
+  const Mat* m;
+  const int r = validate_desc(ctx, d, &m);
+  if (r != RLWE_OK) return r;
+  if (tokens == 0) return ok();
+  const size_t need = ws_item(ctx->rc, m->args, tokens, m->ntt);
+  if (need > kScratchBytes)
+    return fail(RLWE_ESHAPE,
+                "ct_matmul_clear_noalloc: %u tokens need %zu bytes of workspace, above the "
+                "fixed %zu; split the tokens or use ct_matmul_clear",
+                tokens, need, kScratchBytes);
+  void* ws = ctx->device >= 0 && ctx->device < kMaxDevices ? g_scratch_ptr[ctx->device] : nullptr;
+  if (!ws) return fail(RLWE_EINVAL, "ct_matmul_clear_noalloc: no scratch on device %d", ctx->device);
+  const hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  // the kernels write every workspace word they read (digit planes, transformed
+  // masks) before reading it: nothing in the array has to start at zero
+  const int r2 = run_batch(ctx, &d, 1, flags, (hipStream_t)stream, (unsigned char*)ws, nullptr,
+                           /*profile=*/false);
+  return r2 == RLWE_OK ? ok() : r2;
 }
 
 size_t rlwe_batch_workspace_bytes(const rlwe_ctx* ctx, const ct_matmul_desc* descs, uint32_t n) {

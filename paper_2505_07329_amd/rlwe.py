@@ -41,7 +41,9 @@ EXPORTS = ("rlwe_params_init", "rlwe_params_destroy", "rlwe_weights_load", "rlwe
            "rlwe_graph_destroy", "rlwe_weights_method", "ct_pack_bits", "rlwe_packed_words",
            "rlwe_weights_rows_per_product", "rlwe_ksk_load", "rlwe_ksk_free",
            "rlwe_packed_count", "rlwe_keyswitch_workspace_bytes", "ct_keyswitch_pack",
-           "rlwe_matmul_pack_workspace_bytes", "ct_matmul_pack", "rlwe_last_error")
+           "rlwe_matmul_pack_workspace_bytes", "ct_matmul_pack", "ct_matmul_clear_noalloc",
+           "rlwe_last_error")
+RLWE_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class RlweError(RuntimeError):
@@ -96,6 +98,8 @@ def lib() -> ctypes.CDLL:
     L.rlwe_weights_free.argtypes = [vp]
     L.ct_matmul_clear.argtypes = [vp, vp, ctypes.c_uint32, vp, ctypes.c_uint32, vp,
                                   ctypes.c_uint32, vp]
+    L.ct_matmul_clear_noalloc.argtypes = [vp, vp, ctypes.c_uint32, vp, ctypes.c_uint32, vp,
+                                          ctypes.c_uint32, vp]
     L.ct_modswitch.argtypes = [vp, vp, ctypes.c_size_t, vp, vp]
     L.ct_pack_bits.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_uint32, vp, vp]
     L.rlwe_packed_words.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
@@ -196,6 +200,14 @@ def ct_matmul_clear(ctx: int, w: int, ct, tokens: int, out, transpose: bool = Fa
     int64 [tokens][M][P][N+1] (RLWE_OUT_RAW_Q)."""
     _check(lib().ct_matmul_clear(ctx, w, int(bool(transpose)), _ptr(ct), tokens, _ptr(out), flags,
                                  _stream(stream)))
+
+
+def ct_matmul_clear_noalloc(ctx: int, w: int, ct, tokens: int, out, transpose: bool = False,
+                            flags: int = RLWE_OUT_SWITCHED, stream=None) -> None:
+    """ct_matmul_clear with its workspace in the library's fixed device array (no
+    allocation); same buffers and flags."""
+    _check(lib().ct_matmul_clear_noalloc(ctx, w, int(bool(transpose)), _ptr(ct), tokens,
+                                         _ptr(out), flags, _stream(stream)))
 
 
 def ct_modswitch(ctx: int, raw, count: int, out, stream=None) -> None:
