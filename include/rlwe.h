@@ -127,6 +127,15 @@ int rlwe_weights_free(rlwe_weights* w);
 #define RLWE_OUT_FORCE_EXACT 2u /* switched outputs through the slow exact path
                                    for every coefficient (same bits; test hook) */
 #define RLWE_IN_SEEDED 4u       /* inputs in the seeded layout (masks expanded on the GPU) */
+/* Launch shape (same bits either way). By default a call or batch whose products all
+ * use the NTT method runs as one persistent launch: a grid of at most two workgroups
+ * per compute unit takes the steps of every product (mask transforms and body digit
+ * planes per token and block, product tiles, bodies) from one work queue, each
+ * product's tiles waiting on its own transforms; otherwise grouped launches (one per
+ * step and kernel class) run. */
+#define RLWE_LAUNCH_PERSISTENT 8u /* require the persistent launch (RLWE_EINVAL if a
+                                     product uses the matrix cores) */
+#define RLWE_LAUNCH_GROUPED 16u   /* grouped launches even where all products use NTT */
 
 /* The encrypted clear-weight product of Eq. (LWEdot) for `tokens` inputs.
  * With transpose = 0 it computes W.[x] (d_in -> d_out); with transpose = 1,
@@ -268,6 +277,8 @@ typedef struct rlwe_kernel_times {
   uint32_t dropped;
   double ksdig_ms, ksacc_ms, ksfin_ms;
   uint32_t ksdig_n, ksacc_n, ksfin_n;
+  double persist_ms; /* persistent batch launches (all steps of their products) */
+  uint32_t persist_n;
 } rlwe_kernel_times;
 
 int rlwe_profile_begin(rlwe_ctx* ctx);

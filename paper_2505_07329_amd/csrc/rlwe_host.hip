@@ -111,7 +111,7 @@ int scratch_lookup(int dev) {
 namespace {
 enum KernelKind {
   K_PREP = 0, K_MASK = 1, K_BODY = 2, K_MODSWITCH = 3, K_NTT = 4, K_PACK = 5,
-  K_KSDIG = 6, K_KSACC = 7, K_KSFIN = 8, K_KINDS = 9
+  K_KSDIG = 6, K_KSACC = 7, K_KSFIN = 8, K_PERSIST = 9, K_KINDS = 10
 };
 constexpr int kMaxProfiled = 4096;
 struct Profiler {
@@ -135,6 +135,8 @@ struct rlwe_ctx {
   bool tw_ok = false;       // twiddle tables built (N <= kNttN): KeySwitch packing available
   NttConst ntt{};
   uint64_t* ntt_tables = nullptr;
+  uint32_t cus = 0;         // compute units of the device
+  uint32_t* sync = nullptr; // counters of the persistent launch (zero between launches)
 };
 
 namespace {
@@ -422,10 +424,21 @@ int rlwe_params_init(const rlwe_params* p, int hip_device, rlwe_ctx** out) {
     delete ctx;
     return RLWE_EHIP;
   }
+  int cus = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device);
+  if (e == hipSuccess) e = hipMalloc(&ctx->sync, kSyncWords * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemset(ctx->sync, 0, kSyncWords * sizeof(uint32_t));
+  if (e != hipSuccess) {
+    if (ctx->sync) (void)hipFree(ctx->sync);
+    delete ctx;
+    return hip_fail(e, "device attributes / persistent-launch counters");
+  }
+  ctx->cus = (uint32_t)cus;
   if (N <= kNttN) {
     const int r = build_ntt(ctx);
     if (r != RLWE_OK) {
       if (ctx->ntt_tables) (void)hipFree(ctx->ntt_tables);
+      (void)hipFree(ctx->sync);
       delete ctx;
       return r;
     }
@@ -456,10 +469,10 @@ int rlwe_profile_end(rlwe_ctx* ctx, rlwe_kernel_times* out) {
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   double* ms[K_KINDS] = {&out->prep_ms,  &out->mask_ms,  &out->body_ms,
                          &out->modswitch_ms, &out->ntt_ms, &out->pack_ms,
-                         &out->ksdig_ms, &out->ksacc_ms, &out->ksfin_ms};
+                         &out->ksdig_ms, &out->ksacc_ms, &out->ksfin_ms, &out->persist_ms};
   uint32_t* n[K_KINDS] = {&out->prep_n,  &out->mask_n,  &out->body_n,
                           &out->modswitch_n, &out->ntt_n, &out->pack_n,
-                          &out->ksdig_n, &out->ksacc_n, &out->ksfin_n};
+                          &out->ksdig_n, &out->ksacc_n, &out->ksfin_n, &out->persist_n};
   for (int i = 0; i < p->used; ++i) {
     e = hipEventSynchronize(p->ev[i][1]);
     if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
@@ -487,6 +500,10 @@ int rlwe_params_destroy(rlwe_ctx* ctx) {
   if (ctx->ntt_tables) {
     (void)hipSetDevice(ctx->device);
     (void)hipFree(ctx->ntt_tables);
+  }
+  if (ctx->sync) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipFree(ctx->sync);
   }
   if (ctx->ws) {
     (void)hipSetDevice(ctx->device);
@@ -703,8 +720,8 @@ static size_t batch_ws(const rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n)
 // key `gk` (NTT method only), masks are rounded to 2^K for its gadget decomposition
 // and the outputs are [T][M][N+P] (a~, then the body residues).
 static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_t flags,
-                     hipStream_t s, unsigned char* ws, const rlwe_ksk* gk = nullptr,
-                     bool profile = true) {
+                     hipStream_t s, unsigned char* ws, uint32_t* sync,
+                     const rlwe_ksk* gk = nullptr, bool profile = true) {
   const RingConst& rc = ctx->rc;
   rlwe_ctx* pc = profile ? ctx : nullptr;  // kernel timing events, unless switched off
   const bool raw = (flags & RLWE_OUT_RAW_Q) || gk;
@@ -754,12 +771,37 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
     off += ws_item(rc, m.args, dd.tokens, m.ntt);
     it.out = dd.out;
     it.T = dd.tokens;
+    it.tt_log2 = kTokTileLog2;
+    it.order = 0;
+    it.groups = (m.args.rows + m.args.n_o - 1) / m.args.n_o;
     const uint32_t prep_per = rc.N >= 256 ? rc.N / 256 : 1;
     all.prep_start[x + 1] = all.prep_start[x] + dd.tokens * m.args.L * prep_per;
     all.fwd_start[x + 1] = all.fwd_start[x] + (m.ntt ? dd.tokens * m.args.L * rc.P : 0);
     all.body_start[x + 1] = all.body_start[x] + dd.tokens * body_blocks_per_token(m.args);
   }
   all.n = cnt;
+  // One persistent launch for a batch whose products all use the NTT method (not for
+  // the rounded-mask output of ct_matmul_pack), unless grouped launches are asked for.
+  bool all_ntt = true;
+  for (uint32_t x = 0; x < cnt; ++x) all_ntt = all_ntt && all.it[x].method == 1;
+  const bool persist = sync && all_ntt && !gk && !(flags & RLWE_LAUNCH_GROUPED);
+  if (persist) {
+    all.sync = sync;
+    for (uint32_t x = 0; x < cnt; ++x) {
+      const Item& it = all.it[x];
+      all.unit_start[x + 1] = all.unit_start[x] + it.T * it.m.L;
+      const uint32_t tiles = (it.T + (1u << it.tt_log2) - 1) >> it.tt_log2;
+      all.mask_start[x + 1] = all.mask_start[x] + it.groups * tiles;
+    }
+    const uint64_t total = (uint64_t)all.unit_start[cnt] + all.mask_start[cnt] +
+                           (all.body_start[cnt] + 1) / 2;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(total, (uint64_t)ctx->cus * 2);
+    hipError_t e = timed(pc, K_PERSIST, s, [&] { return launch_persist(all, grid, s); });
+    if (e != hipSuccess) return hip_fail(e, "persistent batch kernel");
+    return RLWE_OK;
+  }
+  if (flags & RLWE_LAUNCH_PERSISTENT)
+    return fail(RLWE_EINVAL, "RLWE_LAUNCH_PERSISTENT needs every product on the NTT method");
   hipError_t e = timed(pc, K_PREP, s, [&] { return launch_prep(all, s); });
   if (e != hipSuccess) return hip_fail(e, "prep kernel");
   if (all.fwd_start[cnt]) {
@@ -790,7 +832,7 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
       const Item& it = all.it[y];
       mb.it[mb.n] = it;
       const uint32_t groups = (it.m.rows + it.m.n_o - 1) / it.m.n_o;
-      const uint32_t blocks = ntt ? groups * ((it.T + kTokTile - 1) / kTokTile)
+      const uint32_t blocks = ntt ? groups * ((it.T + (1u << it.tt_log2) - 1) >> it.tt_log2)
                                   : it.T * (it.m.rows_pad / 32) * (rc.N / 64);
       mb.mask_start[mb.n + 1] = mb.mask_start[mb.n] + blocks;
       ++mb.n;
@@ -809,7 +851,9 @@ int ct_matmul_batch(rlwe_ctx* ctx, const ct_matmul_desc* descs, uint32_t n, uint
   if (!ctx) return fail(RLWE_EINVAL, "ct_matmul_batch: null context");
   if (n == 0) return ok();
   if (!descs) return fail(RLWE_EINVAL, "ct_matmul_batch: null descriptors");
-  if (flags & ~(RLWE_OUT_RAW_Q | RLWE_OUT_FORCE_EXACT | RLWE_IN_SEEDED))
+  if (flags & ~(RLWE_OUT_RAW_Q | RLWE_OUT_FORCE_EXACT | RLWE_IN_SEEDED | RLWE_LAUNCH_PERSISTENT |
+                RLWE_LAUNCH_GROUPED) ||
+      (flags & RLWE_LAUNCH_PERSISTENT && flags & RLWE_LAUNCH_GROUPED))
     return fail(RLWE_EINVAL, "ct_matmul_batch: unknown flags 0x%x", flags);
   for (uint32_t i = 0; i < n; ++i) {
     const Mat* m;
@@ -832,7 +876,7 @@ int ct_matmul_batch(rlwe_ctx* ctx, const ct_matmul_desc* descs, uint32_t n, uint
   }
   for (uint32_t i = 0; i < n; i += kMaxBatch) {
     const int r = run_batch(ctx, descs + i, std::min<uint32_t>(kMaxBatch, n - i), flags, s,
-                            (unsigned char*)ctx->ws);
+                            (unsigned char*)ctx->ws, ctx->sync);
     if (r != RLWE_OK) return r;
   }
   return ok();
@@ -855,7 +899,7 @@ int ct_matmul_clear_noalloc(rlwe_ctx* ctx, const rlwe_weights* w, uint32_t trans
                             const uint64_t* ct_in, uint32_t tokens, void* out, uint32_t flags,
                             rlwe_stream_t stream) {
   if (!ctx || !w) return fail(RLWE_EINVAL, "ct_matmul_clear_noalloc: null context or weights");
-  if (flags & ~(RLWE_OUT_RAW_Q | RLWE_OUT_FORCE_EXACT | RLWE_IN_SEEDED))
+  if (flags & ~(RLWE_OUT_RAW_Q | RLWE_OUT_FORCE_EXACT | RLWE_IN_SEEDED | RLWE_LAUNCH_GROUPED))
     return fail(RLWE_EINVAL, "ct_matmul_clear_noalloc: unknown flags 0x%x", flags);
   ct_matmul_desc d{};
   d.w = w;
@@ -879,8 +923,8 @@ int ct_matmul_clear_noalloc(rlwe_ctx* ctx, const rlwe_weights* w, uint32_t trans
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   // the kernels write every workspace word they read (digit planes, transformed
   // masks) before reading it: nothing in the array has to start at zero
-  const int r2 = run_batch(ctx, &d, 1, flags, (hipStream_t)stream, (unsigned char*)ws, nullptr,
-                           /*profile=*/false);
+  const int r2 = run_batch(ctx, &d, 1, flags | RLWE_LAUNCH_GROUPED, (hipStream_t)stream,
+                           (unsigned char*)ws, nullptr, nullptr, /*profile=*/false);
   return r2 == RLWE_OK ? ok() : r2;
 }
 
@@ -898,6 +942,7 @@ size_t rlwe_batch_workspace_bytes(const rlwe_ctx* ctx, const ct_matmul_desc* des
 struct rlwe_graph {
   rlwe_ctx* ctx = nullptr;
   void* ws = nullptr;
+  uint32_t* sync = nullptr;  // counters of a captured persistent launch (zeroed here)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -906,7 +951,9 @@ int rlwe_graph_capture_batch(rlwe_ctx* ctx, const ct_matmul_desc* descs, uint32_
                              uint32_t flags, rlwe_graph** out) {
   if (!ctx || !descs || !out || n == 0) return fail(RLWE_EINVAL, "rlwe_graph_capture_batch: bad argument");
   *out = nullptr;
-  if (flags & ~(RLWE_OUT_RAW_Q | RLWE_OUT_FORCE_EXACT | RLWE_IN_SEEDED))
+  if (flags & ~(RLWE_OUT_RAW_Q | RLWE_OUT_FORCE_EXACT | RLWE_IN_SEEDED | RLWE_LAUNCH_PERSISTENT |
+                RLWE_LAUNCH_GROUPED) ||
+      (flags & RLWE_LAUNCH_PERSISTENT && flags & RLWE_LAUNCH_GROUPED))
     return fail(RLWE_EINVAL, "rlwe_graph_capture_batch: unknown flags 0x%x", flags);
   for (uint32_t i = 0; i < n; ++i) {
     const Mat* m;
@@ -925,6 +972,13 @@ int rlwe_graph_capture_batch(rlwe_ctx* ctx, const ct_matmul_desc* descs, uint32_
     delete g;
     return fail(RLWE_ENOMEM, "hipMalloc(graph workspace, %zu bytes)", need);
   }
+  if (hipMalloc(&g->sync, kSyncWords * sizeof(uint32_t)) != hipSuccess ||
+      hipMemset(g->sync, 0, kSyncWords * sizeof(uint32_t)) != hipSuccess) {
+    if (g->sync) (void)hipFree(g->sync);
+    if (g->ws) (void)hipFree(g->ws);
+    delete g;
+    return fail(RLWE_ENOMEM, "graph counters");
+  }
   hipStream_t cs = nullptr;
   e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   int r = RLWE_OK;
@@ -935,7 +989,7 @@ int rlwe_graph_capture_batch(rlwe_ctx* ctx, const ct_matmul_desc* descs, uint32_
   if (e == hipSuccess) {
     for (uint32_t i = 0; i < n && r == RLWE_OK; i += kMaxBatch)
       r = run_batch(ctx, descs + i, std::min<uint32_t>(kMaxBatch, n - i), flags, cs,
-                    (unsigned char*)g->ws);
+                    (unsigned char*)g->ws, g->sync);
     const hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
     if (r == RLWE_OK && e2 != hipSuccess) e = e2;
   }
@@ -947,6 +1001,7 @@ int rlwe_graph_capture_batch(rlwe_ctx* ctx, const ct_matmul_desc* descs, uint32_
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     if (g->ws) (void)hipFree(g->ws);
+    if (g->sync) (void)hipFree(g->sync);
     delete g;
     g_err = msg;
     return r != RLWE_OK ? r : RLWE_EHIP;
@@ -969,6 +1024,7 @@ int rlwe_graph_destroy(rlwe_graph* g) {
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
   if (g->ws) (void)hipFree(g->ws);
+  if (g->sync) (void)hipFree(g->sync);
   delete g;
   return ok();
 }
@@ -1247,7 +1303,7 @@ int ct_matmul_pack(rlwe_ctx* ctx, const rlwe_weights* w, uint32_t transpose, con
   // NTT method: the product rounds the masks for the key's decomposition; otherwise
   // it writes raw residues and the digit kernel rounds them
   const uint32_t pflags = (flags & (RLWE_OUT_FORCE_EXACT | RLWE_IN_SEEDED)) | (m->ntt ? 0 : RLWE_OUT_RAW_Q);
-  r = run_batch(ctx, &d, 1, pflags, s, ws, m->ntt ? k : nullptr);
+  r = run_batch(ctx, &d, 1, pflags | RLWE_LAUNCH_GROUPED, s, ws, nullptr, m->ntt ? k : nullptr);
   if (r != RLWE_OK) return r;
   r = ks_run(ctx, k, (const uint64_t*)(ws + off_inter), M, n_pack, out, flags & RLWE_OUT_RAW_Q,
              m->ntt, ws + off_ks, s);

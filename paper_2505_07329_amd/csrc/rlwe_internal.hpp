@@ -40,7 +40,7 @@ struct RingConst {
 
 // Constants of the number-theoretic-transform method (N = kNttN only).
 constexpr uint32_t kNttN = 4096;
-constexpr uint32_t kTokTile = 8;  // tokens per workgroup of the NTT product kernel
+constexpr uint32_t kTokTileLog2 = 3;  // default: 8 tokens per workgroup of the NTT product kernel
 struct NttConst {
   const uint64_t* fwd[kMaxPrimes];  // [N] (psi^bitrev(k), Shoup companion), device
   const uint64_t* inv[kMaxPrimes];  // [N] (psi^-bitrev(k), Shoup companion), device
@@ -201,6 +201,10 @@ struct Item {
   int8_t* ebody;       // [T][D][L][N]
   void* out;           // switched u32 [T][M][N+1], raw u64 [T][M][P][N+1], or rounded u64 [T][M][N+P]
   uint32_t T;
+  uint32_t tt_log2;    // NTT method: log2 of the tokens per workgroup (token tile)
+  uint32_t order;      // NTT method: 0 token tiles vary fastest in the block order, 1 weight
+                       // polynomials do
+  uint32_t groups;     // weight polynomials: ceil(rows / n_o)
 };
 
 constexpr int kMaxBatch = 16;
@@ -221,8 +225,16 @@ struct Batch {
   uint32_t fwd_start[kMaxBatch + 1];   // NTT method: one transform per (token, block, prime)
   uint32_t mask_start[kMaxBatch + 1];  // workgroups over T * rows_pad/32 * N/64 tiles (NTT: rows * token tiles)
   uint32_t body_start[kMaxBatch + 1];  // blocks of 256 threads over T * rows
+  uint32_t unit_start[kMaxBatch + 1];  // persistent launch: units (token, input block) per item
+  uint32_t* sync;                      // persistent launch: queue counters (kSync* words)
   Item it[kMaxBatch];
 };
+// Words of the persistent launch's counter block (zero between launches).
+constexpr uint32_t kSyncHead = 0;   // next work item
+constexpr uint32_t kSyncExit = 1;   // workgroups finished
+constexpr uint32_t kSyncErr = 2;    // set if a bounded wait gave up
+constexpr uint32_t kSyncDone = 4;   // + item: units of the item done
+constexpr uint32_t kSyncWords = kSyncDone + kMaxBatch;
 
 // KeySwitch packing (Sec. 3.2 KeySwitching, Eq. (pack_rotate)); N = kNttN only.
 constexpr uint32_t kMaxLevels = 4;   // gadget levels ell
@@ -293,6 +305,8 @@ hipError_t launch_body(const Batch& b, hipStream_t s);
 hipError_t launch_ntt_mask_fwd(const Batch& b, hipStream_t s);
 // lclass: every item of b has L = 2 (2), or any L (0)
 hipError_t launch_ntt_mask(const Batch& b, uint32_t lclass, hipStream_t s);
+// every item of b on the NTT method, sync set; grid workgroups of kInvThreads threads
+hipError_t launch_persist(const Batch& b, uint32_t grid, hipStream_t s);
 hipError_t launch_ntt_weights(const MatArgs& m, const NttConst& ntt, const RingConst& rc,
                               uint64_t* what, hipStream_t s);
 hipError_t launch_pack_bits(const uint32_t* in, size_t count, uint32_t len, uint32_t k,

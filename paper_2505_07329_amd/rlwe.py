@@ -33,6 +33,8 @@ RLWE_OUT_SWITCHED = 0
 RLWE_OUT_RAW_Q = 1
 RLWE_OUT_FORCE_EXACT = 2
 RLWE_IN_SEEDED = 4
+RLWE_LAUNCH_PERSISTENT = 8
+RLWE_LAUNCH_GROUPED = 16
 
 EXPORTS = ("rlwe_params_init", "rlwe_params_destroy", "rlwe_weights_load", "rlwe_weights_free",
            "ct_matmul_clear", "ct_modswitch", "rlwe_workspace_bytes", "rlwe_workspace_reserve",
@@ -62,7 +64,8 @@ class KernelTimes(ctypes.Structure):
                 ("dropped", ctypes.c_uint32),
                 ("ksdig_ms", ctypes.c_double), ("ksacc_ms", ctypes.c_double),
                 ("ksfin_ms", ctypes.c_double), ("ksdig_n", ctypes.c_uint32),
-                ("ksacc_n", ctypes.c_uint32), ("ksfin_n", ctypes.c_uint32)]
+                ("ksacc_n", ctypes.c_uint32), ("ksfin_n", ctypes.c_uint32),
+                ("persist_ms", ctypes.c_double), ("persist_n", ctypes.c_uint32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
