@@ -225,7 +225,7 @@ struct Batch {
   uint32_t fwd_start[kMaxBatch + 1];   // NTT method: one transform per (token, block, prime)
   uint32_t mask_start[kMaxBatch + 1];  // workgroups over T * rows_pad/32 * N/64 tiles (NTT: rows * token tiles)
   uint32_t body_start[kMaxBatch + 1];  // blocks of 256 threads over T * rows
-  uint32_t unit_start[kMaxBatch + 1];  // persistent launch: units (token, input block) per item
+  uint32_t unit_start[kMaxBatch + 1];  // persistent launch: transform units (token, input block)
   uint32_t* sync;                      // persistent launch: queue counters (kSync* words)
   Item it[kMaxBatch];
 };
@@ -233,8 +233,9 @@ struct Batch {
 constexpr uint32_t kSyncHead = 0;   // next work item
 constexpr uint32_t kSyncExit = 1;   // workgroups finished
 constexpr uint32_t kSyncErr = 2;    // set if a bounded wait gave up
-constexpr uint32_t kSyncDone = 4;   // + item: units of the item done
-constexpr uint32_t kSyncWords = kSyncDone + kMaxBatch;
+constexpr uint32_t kSyncDone = 4;   // + item: transform units of the item done
+constexpr uint32_t kSyncPrep = kSyncDone + kMaxBatch;  // + item: digit blocks of the item done
+constexpr uint32_t kSyncWords = kSyncPrep + kMaxBatch;
 
 // KeySwitch packing (Sec. 3.2 KeySwitching, Eq. (pack_rotate)); N = kNttN only.
 constexpr uint32_t kMaxLevels = 4;   // gadget levels ell
