@@ -97,11 +97,12 @@ int rlwe_params_destroy(rlwe_ctx* ctx);
  *           RLWE_W_NTT keeps the reversed blocks in the NTT domain per prime
  *           (rows * L * P * N * 8 bytes; RLWE_EPARAM unless N = 4096),
  *           RLWE_W_TOEPLITZ keeps int8 only; without one, each orientation
- *           (N = 4096) takes the method with the smaller estimated time per
- *           output: matrix cores 8 + 0.0033 K dk ns (K the contraction length,
- *           dk the digit planes kept, rlwe_weights_digits), transforms
- *           (12.75 + 11.25 L) P ns (L = ceil(K / N) blocks, P primes), fitted to
- *           MI355X timings; at other N the matrix-core method.
+ *           (N = 4096) takes the method a tuner attached to the context measured
+ *           fastest for its shape (rlwe_ctx_set_tuner), else the one with the
+ *           smaller estimated time per output: matrix cores 8 + 0.0033 K dk ns (K
+ *           the contraction length, dk the digit planes kept, rlwe_weights_digits),
+ *           transforms (5 + 12.35 L) P ns (L = ceil(K / N) blocks, P primes),
+ *           fitted to MI355X timings; at other N the matrix-core method.
  *           RLWE_W_ROWPACK (N = 4096, not with RLWE_W_TOEPLITZ): an orientation
  *           whose contraction length K is at most N/2 packs n_o = floor(N / K)
  *           rows into each weight polynomial, row g n_o + rho reversed in
@@ -384,6 +385,76 @@ size_t rlwe_matmul_pack_workspace_bytes(const rlwe_ctx* ctx, const rlwe_weights*
 int ct_matmul_pack(rlwe_ctx* ctx, const rlwe_weights* w, uint32_t transpose, const uint64_t* ct_in,
                    uint32_t tokens, const rlwe_ksk* k, uint32_t n_pack, void* out, uint32_t flags,
                    rlwe_stream_t stream);
+
+/* ------------------------------------------------------------------ autotuning
+ * The paper times its products per shape (Sec. 6.3, Table 4) and gives no tuning. These
+ * calls choose, by timing on the device, among launch shapes of the same arithmetic;
+ * no choice changes a result bit:
+ *   method   RLWE_METHOD_NTT or RLWE_METHOD_TOEPLITZ, for an orientation loaded without
+ *            a method flag (rlwe_weights_load);
+ *   tt_log2  NTT method: 1 << tt_log2 tokens per workgroup (0..5);
+ *   order    NTT method: 0 token tiles vary fastest in the block order, 1 rows do;
+ *   launch   0 grouped launches, 1 one persistent launch (RLWE_LAUNCH_*).
+ * A tuner holds measured choices keyed by N, P, the product's shape (K inputs, M outputs,
+ * n_o rows per weight polynomial), raw or switched output and the token count rounded
+ * up to a power of two, for one device. Attached to a context it is consulted by
+ * rlwe_weights_load and by every product call and batch of the context: the entry of
+ * the shape at the nearest token bucket; for a batch of several products, the batch
+ * entry of that many products at the nearest bucket of their largest token count.
+ * Without an entry: the cost model of rlwe_weights_load, 8 tokens per workgroup,
+ * order 0, grouped launches. RLWE_LAUNCH_* flags of a call override the launch. */
+typedef struct rlwe_schedule {
+  uint32_t method, tt_log2, order, launch;
+  float ms; /* measured time of the tuned call with this choice, milliseconds */
+} rlwe_schedule;
+typedef struct rlwe_tuner rlwe_tuner;
+
+/* A tuner for the device named by device_key (host string, e.g. rlwe_device_key);
+ * host memory only, no device needed. */
+int rlwe_tuner_create(const char* device_key, rlwe_tuner** out);
+int rlwe_tuner_destroy(rlwe_tuner* t);
+size_t rlwe_tuner_size(const rlwe_tuner* t); /* number of entries */
+/* Key of a product choice (rlwe_tuner_put/get) written to buf (host, len bytes). */
+int rlwe_tune_key(uint32_t N, uint32_t P, uint32_t K, uint32_t M, uint32_t n_o, uint32_t raw,
+                  uint32_t tokens, char* buf, size_t len);
+/* Record / read the entry of a key; get returns RLWE_EINVAL if the key has none. */
+int rlwe_tuner_put(rlwe_tuner* t, const char* key, const rlwe_schedule* s);
+int rlwe_tuner_get(const rlwe_tuner* t, const char* key, rlwe_schedule* s);
+/* The entry a product call uses (nearest token bucket of its shape): 1 and *s if there
+ * is one, 0 if not, RLWE_EINVAL for null arguments. */
+int rlwe_tuner_lookup(const rlwe_tuner* t, uint32_t N, uint32_t P, uint32_t K, uint32_t M,
+                      uint32_t n_o, uint32_t raw, uint32_t tokens, rlwe_schedule* s);
+/* JSON file at a host path. Load adds the entries recorded for this tuner's device
+ * (*loaded = their number; NULL ok) and skips the entries of a file written for another
+ * device; RLWE_EINVAL for an unreadable or malformed file (the tuner is then unchanged). */
+int rlwe_tuner_save(const rlwe_tuner* t, const char* path);
+int rlwe_tuner_load(rlwe_tuner* t, const char* path, size_t* loaded);
+/* "<gcnArchName>|<name>|<compute units>" of HIP device hip_device into buf. */
+int rlwe_device_key(int hip_device, char* buf, size_t len);
+/* Attach a tuner to a context (NULL detaches); it must outlive the attachment and must
+ * not change while calls of the context are being issued. */
+int rlwe_ctx_set_tuner(rlwe_ctx* ctx, rlwe_tuner* t);
+
+/* Times the candidates for one product shape on the context's device and records the
+ * fastest in t (and *best, NULL ok):
+ *   K, M     inputs and outputs of the product (one orientation, K -> M)
+ *   wflags   0, or RLWE_W_ROWPACK (packed rows where K <= N/2; NTT method)
+ *   tokens   token count of the calls tuned for, 1..65535
+ *   oflags   RLWE_OUT_SWITCHED or RLWE_OUT_RAW_Q
+ * Candidates: the matrix-core method (not with packed rows), and on the NTT method
+ * (N = 4096) every tt_log2 with 1 << tt_log2 <= 16 and below 2 tokens, both orders, both
+ * launches. Uses random weights and inputs in its own device memory (allocated and
+ * freed here) and the context workspace; synchronises `stream`. */
+int rlwe_autotune_product(rlwe_ctx* ctx, rlwe_tuner* t, uint32_t K, uint32_t M, uint32_t wflags,
+                          uint32_t tokens, uint32_t oflags, rlwe_stream_t stream,
+                          rlwe_schedule* best);
+/* Times a batch (as for ct_matmul_batch, with flags RLWE_OUT_* / RLWE_IN_SEEDED; the
+ * tuner's per-product choices apply) with grouped launches and, where every product uses
+ * the NTT method, with the persistent launch, and records the faster launch for batches
+ * of n products at the bucket of their largest token count. Runs the batch (its outputs
+ * are written) a few times; synchronises `stream`. */
+int rlwe_autotune_batch(rlwe_ctx* ctx, rlwe_tuner* t, const ct_matmul_desc* descs, uint32_t n,
+                        uint32_t flags, rlwe_stream_t stream, rlwe_schedule* best);
 
 /* Description of the last error on this thread ("" if none). */
 const char* rlwe_last_error(void);

@@ -200,4 +200,41 @@ hipError_t launch_row_l1(const int8_t* w, uint32_t rows, uint32_t kw, uint32_t* 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- tuning inputs
+
+// Random inputs for timing (the kernels are data-oblivious): uint64 words of the
+// ciphertext layout [..][P][N], word w a residue mod q[(w / N) % P]; int8 values in
+// [-s, s]. Counter-based (SplitMix64 finalizer of seed + w), reproducible.
+__global__ void fill_residues_kernel(uint64_t* dst, size_t count, uint32_t N, uint32_t P,
+                                     uint64_t q0, uint64_t q1, uint64_t seed) {
+  const size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= count) return;
+  const uint64_t q = ((w / N) % P) == 0 ? q0 : q1;
+  dst[w] = splitmix64_at(seed, w) % q;
+}
+__global__ void fill_int8_kernel(int8_t* dst, size_t count, uint32_t s, uint64_t seed) {
+  const size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= count) return;
+  dst[w] = (int8_t)((int)(splitmix64_at(seed, w) % (2 * s + 1)) - (int)s);
+}
+
+hipError_t launch_fill_residues(uint64_t* dst, size_t count, const RingConst& rc, uint64_t seed,
+                                hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  const size_t blocks = (count + 255) / 256;
+  if (blocks >= (1ull << 31)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fill_residues_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, dst, count,
+                     rc.N, rc.P, rc.q[0], rc.P > 1 ? rc.q[1] : rc.q[0], seed);
+  return hipGetLastError();
+}
+hipError_t launch_fill_int8(int8_t* dst, size_t count, uint32_t mag, uint64_t seed,
+                            hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  const size_t blocks = (count + 255) / 256;
+  if (blocks >= (1ull << 31) || mag > 127) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fill_int8_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, dst, count, mag,
+                     seed);
+  return hipGetLastError();
+}
+
 }  // namespace rlwe

@@ -13,6 +13,7 @@
 
 #include "rlwe.h"
 #include "rlwe_internal.hpp"
+#include "tune_cache.hpp"
 
 using namespace rlwe;
 
@@ -137,6 +138,8 @@ struct rlwe_ctx {
   uint64_t* ntt_tables = nullptr;
   uint32_t cus = 0;         // compute units of the device
   uint32_t* sync = nullptr; // counters of the persistent launch (zero between launches)
+  rlwe_tuner* tuner = nullptr;            // measured launch choices (rlwe_ctx_set_tuner)
+  const rlwe_schedule* forced = nullptr;  // while tuning: the candidate being timed
 };
 
 namespace {
@@ -574,16 +577,22 @@ static int load_mat(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32_t
                 transpose ? " (transposed)" : "");
   const int rc2 = make_switch_const(rc, mx, &m.sc);
   if (rc2 != RLWE_OK) return rc2;
-  // method: as asked for, else the one with the smaller estimated time per output
-  // (token x output row). The matrix-core cost grows with K times the digit planes
-  // kept, the transform cost with the blocks L only; the constants are fitted to
-  // MI355X timings of both kernels at N = 4096 with two primes (K = 512 .. 8192),
-  // the transform cost taken per prime.
+  // method: as asked for, else the tuner's measured choice for this shape, else the one
+  // with the smaller estimated time per output (token x output row). The matrix-core
+  // cost grows with K times the digit planes kept, the transform cost with the blocks L
+  // only; the constants are fitted to MI355X timings of both kernels at N = 4096 with
+  // two primes (matrix cores, K = 512 .. 8192; transforms 34.7 ns per output at K =
+  // 2048, 128 tokens), the transform cost taken per prime.
   m.ntt = method == 1 || a.n_o > 1;
   if (method == 0 && a.n_o == 1 && ctx->ntt_ok) {
-    const double mfma_ns = 8.0 + 0.0033 * (double)a.k * m.sc.dk;
-    const double ntt_ns = (12.75 + 11.25 * a.L) * rc.P;
-    m.ntt = ntt_ns < mfma_ns;
+    uint32_t tuned;
+    if (ctx->tuner && tune::find_method(ctx->tuner->cache, rc.N, rc.P, a.k, a.rows, &tuned)) {
+      m.ntt = tuned == RLWE_METHOD_NTT;
+    } else {
+      const double mfma_ns = 8.0 + 0.0033 * (double)a.k * m.sc.dk;
+      const double ntt_ns = (5.0 + 12.35 * a.L) * rc.P;
+      m.ntt = ntt_ns < mfma_ns;
+    }
   }
   if (m.ntt) {
     if (!ctx->ntt_ok) return fail(RLWE_EPARAM, "the NTT method needs N = %u", kNttN);
@@ -780,11 +789,39 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
     all.body_start[x + 1] = all.body_start[x] + dd.tokens * body_blocks_per_token(m.args);
   }
   all.n = cnt;
+  // Launch choices: the candidate being timed while tuning, else the tuner's entries
+  // (token tile and order per NTT product; for the launch, the product's entry alone,
+  // or the entry of batches of this many products), else the defaults. RLWE_LAUNCH_*
+  // flags decide the launch.
+  bool want_persist = false;
+  {
+    const tune::Cache* tc = ctx->tuner ? &ctx->tuner->cache : nullptr;
+    uint32_t maxT = 0;
+    for (uint32_t x = 0; x < cnt; ++x) {
+      Item& it = all.it[x];
+      maxT = std::max(maxT, it.T);
+      rlwe_schedule sc{};
+      const bool have = ctx->forced ? (sc = *ctx->forced, true)
+                        : tc ? tune::find_product(*tc, rc.N, rc.P, it.m.k, it.m.rows, it.m.n_o,
+                                                  raw, it.T, &sc)
+                             : false;
+      if (have && it.method == 1) {
+        it.tt_log2 = std::min<uint32_t>(sc.tt_log2, 5);
+        it.order = sc.order ? 1 : 0;
+      }
+      if (have && cnt == 1) want_persist = sc.launch == 1;
+    }
+    rlwe_schedule sb{};
+    if (!ctx->forced && tc && cnt > 1 && tune::find_batch(*tc, rc.N, rc.P, cnt, raw, maxT, &sb))
+      want_persist = sb.launch == 1;
+    if (flags & RLWE_LAUNCH_PERSISTENT) want_persist = true;
+    if (flags & RLWE_LAUNCH_GROUPED) want_persist = false;
+  }
   // One persistent launch for a batch whose products all use the NTT method (not for
-  // the rounded-mask output of ct_matmul_pack), unless grouped launches are asked for.
+  // the rounded-mask output of ct_matmul_pack).
   bool all_ntt = true;
   for (uint32_t x = 0; x < cnt; ++x) all_ntt = all_ntt && all.it[x].method == 1;
-  const bool persist = sync && all_ntt && !gk && !(flags & RLWE_LAUNCH_GROUPED);
+  const bool persist = sync && all_ntt && !gk && want_persist;
   if (persist) {
     all.sync = sync;
     for (uint32_t x = 0; x < cnt; ++x) {
@@ -1308,6 +1345,273 @@ int ct_matmul_pack(rlwe_ctx* ctx, const rlwe_weights* w, uint32_t transpose, con
   r = ks_run(ctx, k, (const uint64_t*)(ws + off_inter), M, n_pack, out, flags & RLWE_OUT_RAW_Q,
              m->ntt, ws + off_ks, s);
   if (r != RLWE_OK) return r;
+  return ok();
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ autotuning
+
+extern "C" {
+
+int rlwe_tuner_create(const char* device_key, rlwe_tuner** out) {
+  if (!device_key || !out) return fail(RLWE_EINVAL, "rlwe_tuner_create: null argument");
+  *out = new (std::nothrow) rlwe_tuner;
+  if (!*out) return fail(RLWE_ENOMEM, "out of host memory");
+  (*out)->cache.device = device_key;
+  return ok();
+}
+
+int rlwe_tuner_destroy(rlwe_tuner* t) {
+  delete t;
+  return ok();
+}
+
+size_t rlwe_tuner_size(const rlwe_tuner* t) { return t ? t->cache.entries.size() : 0; }
+
+int rlwe_tune_key(uint32_t N, uint32_t P, uint32_t K, uint32_t M, uint32_t n_o, uint32_t raw,
+                  uint32_t tokens, char* buf, size_t len) {
+  if (!buf || len == 0) return fail(RLWE_EINVAL, "rlwe_tune_key: null buffer");
+  const std::string k = tune::product_key(N, P, K, M, n_o, raw, tokens);
+  if (k.size() + 1 > len) return fail(RLWE_EINVAL, "rlwe_tune_key: buffer of %zu bytes too small", len);
+  memcpy(buf, k.c_str(), k.size() + 1);
+  return ok();
+}
+
+static bool schedule_valid(const rlwe_schedule& s) {
+  return s.method <= 1 && s.tt_log2 <= 5 && s.order <= 1 && s.launch <= 1;
+}
+
+int rlwe_tuner_put(rlwe_tuner* t, const char* key, const rlwe_schedule* s) {
+  if (!t || !key || !s) return fail(RLWE_EINVAL, "rlwe_tuner_put: null argument");
+  if (tune::parse_key(key).kind < 0) return fail(RLWE_EINVAL, "rlwe_tuner_put: malformed key '%s'", key);
+  if (!schedule_valid(*s)) return fail(RLWE_EINVAL, "rlwe_tuner_put: schedule out of range");
+  t->cache.entries[key] = *s;
+  return ok();
+}
+
+int rlwe_tuner_get(const rlwe_tuner* t, const char* key, rlwe_schedule* s) {
+  if (!t || !key || !s) return fail(RLWE_EINVAL, "rlwe_tuner_get: null argument");
+  const auto it = t->cache.entries.find(key);
+  if (it == t->cache.entries.end()) return fail(RLWE_EINVAL, "rlwe_tuner_get: no entry '%s'", key);
+  *s = it->second;
+  return ok();
+}
+
+int rlwe_tuner_lookup(const rlwe_tuner* t, uint32_t N, uint32_t P, uint32_t K, uint32_t M,
+                      uint32_t n_o, uint32_t raw, uint32_t tokens, rlwe_schedule* s) {
+  if (!t || !s) return fail(RLWE_EINVAL, "rlwe_tuner_lookup: null argument");
+  g_err.clear();
+  return tune::find_product(t->cache, N, P, K, M, n_o, raw, tokens, s) ? 1 : 0;
+}
+
+int rlwe_tuner_save(const rlwe_tuner* t, const char* path) {
+  if (!t || !path) return fail(RLWE_EINVAL, "rlwe_tuner_save: null argument");
+  const std::string text = tune::to_json(t->cache);
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "wb");
+  if (!f) return fail(RLWE_EINVAL, "rlwe_tuner_save: cannot open %s", tmp.c_str());
+  const bool wrote = fwrite(text.data(), 1, text.size(), f) == text.size();
+  if (fclose(f) != 0 || !wrote || rename(tmp.c_str(), path) != 0) {
+    (void)remove(tmp.c_str());
+    return fail(RLWE_EINVAL, "rlwe_tuner_save: cannot write %s", path);
+  }
+  return ok();
+}
+
+int rlwe_tuner_load(rlwe_tuner* t, const char* path, size_t* loaded) {
+  if (!t || !path) return fail(RLWE_EINVAL, "rlwe_tuner_load: null argument");
+  if (loaded) *loaded = 0;
+  FILE* f = fopen(path, "rb");
+  if (!f) return fail(RLWE_EINVAL, "rlwe_tuner_load: cannot open %s", path);
+  std::string text;
+  char buf[65536];
+  size_t got;
+  while ((got = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+  fclose(f);
+  size_t n = 0;
+  std::string err;
+  if (!tune::from_json(text, &t->cache, &n, &err))
+    return fail(RLWE_EINVAL, "rlwe_tuner_load: %s: %s", path, err.c_str());
+  if (loaded) *loaded = n;
+  return ok();
+}
+
+int rlwe_device_key(int hip_device, char* buf, size_t len) {
+  if (!buf || len == 0) return fail(RLWE_EINVAL, "rlwe_device_key: null buffer");
+  hipDeviceProp_t prop;
+  const hipError_t e = hipGetDeviceProperties(&prop, hip_device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  const int n = snprintf(buf, len, "%s|%s|%d", prop.gcnArchName, prop.name, prop.multiProcessorCount);
+  if (n < 0 || (size_t)n >= len) return fail(RLWE_EINVAL, "rlwe_device_key: buffer too small");
+  return ok();
+}
+
+int rlwe_ctx_set_tuner(rlwe_ctx* ctx, rlwe_tuner* t) {
+  if (!ctx) return fail(RLWE_EINVAL, "rlwe_ctx_set_tuner: null context");
+  ctx->tuner = t;
+  return ok();
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device memory freed on scope exit.
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+// Mean time of `reps` calls of fn on stream s after one untimed call (ms); <0 on error.
+template <class F>
+float time_calls(hipStream_t s, F fn, int reps) {
+  hipEvent_t a = nullptr, b = nullptr;
+  float ms = -1.f;
+  if (fn() != RLWE_OK) return -1.f;
+  if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess &&
+      hipEventRecord(a, s) == hipSuccess) {
+    bool good = true;
+    for (int r = 0; r < reps && good; ++r) good = fn() == RLWE_OK;
+    if (good && hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess &&
+        hipEventElapsedTime(&ms, a, b) == hipSuccess)
+      ms /= (float)reps;
+    else
+      ms = -1.f;
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  return ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rlwe_autotune_product(rlwe_ctx* ctx, rlwe_tuner* t, uint32_t K, uint32_t M, uint32_t wflags,
+                          uint32_t tokens, uint32_t oflags, rlwe_stream_t stream,
+                          rlwe_schedule* best) {
+  if (!ctx || !t) return fail(RLWE_EINVAL, "rlwe_autotune_product: null context or tuner");
+  if (K < 1 || M < 1 || K > 65536 || M > 65536 || tokens < 1 || tokens > 65535)
+    return fail(RLWE_ESHAPE, "rlwe_autotune_product: K = %u, M = %u, tokens = %u out of range", K,
+                M, tokens);
+  if ((wflags & ~RLWE_W_ROWPACK) || (oflags & ~RLWE_OUT_RAW_Q))
+    return fail(RLWE_EINVAL, "rlwe_autotune_product: flags 0x%x / 0x%x invalid", wflags, oflags);
+  const bool rowpack = wflags & RLWE_W_ROWPACK;
+  if (rowpack && !ctx->ntt_ok) return fail(RLWE_EPARAM, "RLWE_W_ROWPACK needs N = %u", kNttN);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const RingConst& rc = ctx->rc;
+  const bool raw = oflags & RLWE_OUT_RAW_Q;
+  // weights of the largest magnitude that loads at this t (127 s K < t / 2): the
+  // kernels' time does not depend on the values, only the matrix cores' kept digits
+  // on the row norms
+  const uint64_t t_half = 1ull << (ctx->log2_t - 1);
+  const uint64_t mag = std::min<uint64_t>(127, (t_half - 1) / (127ull * K));
+  if (mag == 0) return fail(RLWE_EOVERFLOW, "rlwe_autotune_product: K = %u cannot load at t = 2^%u", K, ctx->log2_t);
+  DevBuf W, ct, out;
+  const uint32_t L = (K + rc.N - 1) / rc.N;
+  const size_t ct_words = (size_t)tokens * L * 2 * rc.P * rc.N;
+  const size_t out_bytes = (size_t)tokens * M * (raw ? (size_t)rc.P * (rc.N + 1) * 8 : (size_t)(rc.N + 1) * 4);
+  if ((e = hipMalloc(&W.p, (size_t)M * K)) != hipSuccess ||
+      (e = hipMalloc(&ct.p, ct_words * 8)) != hipSuccess ||
+      (e = hipMalloc(&out.p, out_bytes)) != hipSuccess)
+    return fail(RLWE_ENOMEM, "rlwe_autotune_product: hipMalloc: %s", hipGetErrorString(e));
+  e = launch_fill_int8((int8_t*)W.p, (size_t)M * K, (uint32_t)mag, 0x5eed0001ull, s);
+  if (e == hipSuccess) e = launch_fill_residues((uint64_t*)ct.p, ct_words, rc, 0x5eed0002ull, s);
+  if (e != hipSuccess) return hip_fail(e, "tuning inputs");
+  // weights on each method to try (explicit method flags: the tuner is not consulted)
+  rlwe_weights* wn = nullptr;
+  rlwe_weights* wt = nullptr;
+  int r = RLWE_OK;
+  if (ctx->ntt_ok)
+    r = rlwe_weights_load(ctx, (const int8_t*)W.p, M, K,
+                          RLWE_W_FWD | RLWE_W_NTT | (rowpack ? RLWE_W_ROWPACK : 0), stream, &wn);
+  if (r == RLWE_OK && !rowpack)
+    r = rlwe_weights_load(ctx, (const int8_t*)W.p, M, K, RLWE_W_FWD | RLWE_W_TOEPLITZ, stream, &wt);
+  size_t need = 0;
+  if (wn) need = std::max(need, rlwe_workspace_bytes(ctx, wn, 0, tokens));
+  if (wt) need = std::max(need, rlwe_workspace_bytes(ctx, wt, 0, tokens));
+  if (r == RLWE_OK) r = ensure_ws(ctx, need, s);
+  const uint32_t n_o = wn ? wn->fwd.args.n_o : 1;
+  std::vector<rlwe_schedule> cands;
+  if (wt) cands.push_back(rlwe_schedule{RLWE_METHOD_TOEPLITZ, kTokTileLog2, 0, 0, 0.f});
+  if (wn)
+    for (uint32_t tl = 0; tl <= 4; ++tl) {
+      if (tl > 0 && (1u << tl) >= 2 * tokens) break;
+      for (uint32_t order = 0; order < 2; ++order)
+        for (uint32_t launch = 0; launch < 2; ++launch)
+          cands.push_back(rlwe_schedule{RLWE_METHOD_NTT, tl, order, launch, 0.f});
+    }
+  rlwe_schedule pick{};
+  float pick_ms = -1.f;
+  for (size_t c = 0; c < cands.size() && r == RLWE_OK; ++c) {
+    rlwe_weights* w = cands[c].method == RLWE_METHOD_NTT ? wn : wt;
+    ctx->forced = &cands[c];
+    auto call = [&] { return ct_matmul_clear(ctx, w, 0, (const uint64_t*)ct.p, tokens, out.p, oflags, stream); };
+    float ms = time_calls(s, call, 1);  // a first estimate decides the repetitions
+    if (ms >= 0.f && ms < 100.f) ms = time_calls(s, call, ms < 5.f ? 5 : 2);
+    ctx->forced = nullptr;
+    if (ms < 0.f) {
+      if (g_err.empty()) r = fail(RLWE_EHIP, "rlwe_autotune_product: timing failed");
+      else r = RLWE_EHIP;
+      break;
+    }
+    cands[c].ms = ms;
+    if (pick_ms < 0.f || ms < pick_ms) {
+      pick = cands[c];
+      pick_ms = ms;
+    }
+  }
+  ctx->forced = nullptr;
+  const std::string msg = g_err;
+  (void)hipStreamSynchronize(s);
+  rlwe_weights_free(wn);
+  rlwe_weights_free(wt);
+  if (r != RLWE_OK) {
+    g_err = msg;
+    return r;
+  }
+  t->cache.entries[tune::product_key(rc.N, rc.P, K, M, n_o, raw, tokens)] = pick;
+  if (best) *best = pick;
+  return ok();
+}
+
+int rlwe_autotune_batch(rlwe_ctx* ctx, rlwe_tuner* t, const ct_matmul_desc* descs, uint32_t n,
+                        uint32_t flags, rlwe_stream_t stream, rlwe_schedule* best) {
+  if (!ctx || !t || !descs) return fail(RLWE_EINVAL, "rlwe_autotune_batch: null argument");
+  if (n < 1 || n > kMaxBatch) return fail(RLWE_EINVAL, "rlwe_autotune_batch: 1 <= n <= %d", kMaxBatch);
+  if (flags & ~(RLWE_OUT_RAW_Q | RLWE_IN_SEEDED))
+    return fail(RLWE_EINVAL, "rlwe_autotune_batch: flags 0x%x invalid", flags);
+  uint32_t cnt = 0, maxT = 0;
+  bool all_ntt = true;
+  for (uint32_t i = 0; i < n; ++i) {
+    const Mat* m;
+    const int r = validate_desc(ctx, descs[i], &m);
+    if (r != RLWE_OK) return r;
+    if (descs[i].tokens) {
+      ++cnt;
+      maxT = std::max(maxT, descs[i].tokens);
+      all_ntt = all_ntt && m->ntt;
+    }
+  }
+  if (cnt == 0) return fail(RLWE_EINVAL, "rlwe_autotune_batch: no tokens");
+  hipStream_t s = (hipStream_t)stream;
+  auto run = [&](uint32_t launch) { return ct_matmul_batch(ctx, descs, n, flags | launch, stream); };
+  const float g = time_calls(s, [&] { return run(RLWE_LAUNCH_GROUPED); }, 3);
+  const float p = all_ntt ? time_calls(s, [&] { return run(RLWE_LAUNCH_PERSISTENT); }, 3) : -1.f;
+  if (g < 0.f || (all_ntt && p < 0.f))
+    return g_err.empty() ? fail(RLWE_EHIP, "rlwe_autotune_batch: timing failed") : RLWE_EHIP;
+  rlwe_schedule pick{all_ntt ? RLWE_METHOD_NTT : RLWE_METHOD_TOEPLITZ, kTokTileLog2, 0, 0, g};
+  if (all_ntt && p < g) {
+    pick.launch = 1;
+    pick.ms = p;
+  }
+  t->cache.entries[tune::batch_key(ctx->rc.N, ctx->rc.P, cnt, flags & RLWE_OUT_RAW_Q, maxT)] = pick;
+  if (best) *best = pick;
   return ok();
 }
 

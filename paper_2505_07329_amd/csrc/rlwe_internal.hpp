@@ -323,5 +323,9 @@ hipError_t launch_ks_accum(const KsArgs& a, hipStream_t s);
 hipError_t launch_ks_finish(const KsArgs& a, hipStream_t s);
 hipError_t launch_row_l1(const int8_t* w, uint32_t rows, uint32_t kw, uint32_t* out,
                          hipStream_t s);
+hipError_t launch_fill_residues(uint64_t* dst, size_t count, const RingConst& rc, uint64_t seed,
+                                hipStream_t s);
+hipError_t launch_fill_int8(int8_t* dst, size_t count, uint32_t mag, uint64_t seed,
+                            hipStream_t s);
 
 }  // namespace rlwe

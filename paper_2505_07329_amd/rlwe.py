@@ -44,7 +44,10 @@ EXPORTS = ("rlwe_params_init", "rlwe_params_destroy", "rlwe_weights_load", "rlwe
            "rlwe_weights_rows_per_product", "rlwe_ksk_load", "rlwe_ksk_free",
            "rlwe_packed_count", "rlwe_keyswitch_workspace_bytes", "ct_keyswitch_pack",
            "rlwe_matmul_pack_workspace_bytes", "ct_matmul_pack", "ct_matmul_clear_noalloc",
-           "rlwe_last_error")
+           "rlwe_tuner_create", "rlwe_tuner_destroy", "rlwe_tuner_size", "rlwe_tune_key",
+           "rlwe_tuner_put", "rlwe_tuner_get", "rlwe_tuner_lookup", "rlwe_tuner_save",
+           "rlwe_tuner_load", "rlwe_device_key", "rlwe_ctx_set_tuner", "rlwe_autotune_product",
+           "rlwe_autotune_batch", "rlwe_last_error")
 RLWE_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
@@ -74,6 +77,14 @@ class KernelTimes(ctypes.Structure):
 class CtMatmulDesc(ctypes.Structure):
     _fields_ = [("w", ctypes.c_void_p), ("transpose", ctypes.c_uint32),
                 ("ct_in", ctypes.c_void_p), ("tokens", ctypes.c_uint32), ("out", ctypes.c_void_p)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_uint32), ("tt_log2", ctypes.c_uint32),
+                ("order", ctypes.c_uint32), ("launch", ctypes.c_uint32), ("ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class _Params(ctypes.Structure):
@@ -137,11 +148,27 @@ def lib() -> ctypes.CDLL:
     L.rlwe_matmul_pack_workspace_bytes.restype = ctypes.c_size_t
     L.ct_matmul_pack.argtypes = [vp, vp, ctypes.c_uint32, vp, ctypes.c_uint32, vp,
                                  ctypes.c_uint32, vp, ctypes.c_uint32, vp]
+    u32, sz = ctypes.c_uint32, ctypes.c_size_t
+    L.rlwe_tuner_create.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
+    L.rlwe_tuner_destroy.argtypes = [vp]
+    L.rlwe_tuner_size.argtypes = [vp]
+    L.rlwe_tuner_size.restype = sz
+    L.rlwe_tune_key.argtypes = [u32, u32, u32, u32, u32, u32, u32, ctypes.c_char_p, sz]
+    L.rlwe_tuner_put.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(Schedule)]
+    L.rlwe_tuner_get.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(Schedule)]
+    L.rlwe_tuner_lookup.argtypes = [vp, u32, u32, u32, u32, u32, u32, u32, ctypes.POINTER(Schedule)]
+    L.rlwe_tuner_save.argtypes = [vp, ctypes.c_char_p]
+    L.rlwe_tuner_load.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(sz)]
+    L.rlwe_device_key.argtypes = [ctypes.c_int, ctypes.c_char_p, sz]
+    L.rlwe_ctx_set_tuner.argtypes = [vp, vp]
+    L.rlwe_autotune_product.argtypes = [vp, vp, u32, u32, u32, u32, u32, vp, ctypes.POINTER(Schedule)]
+    L.rlwe_autotune_batch.argtypes = [vp, vp, ctypes.POINTER(CtMatmulDesc), u32, u32, vp,
+                                      ctypes.POINTER(Schedule)]
     L.rlwe_last_error.argtypes = []
     L.rlwe_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name not in ("rlwe_last_error", "rlwe_workspace_bytes", "rlwe_batch_workspace_bytes",
-                        "rlwe_packed_words", "rlwe_packed_count",
+                        "rlwe_packed_words", "rlwe_packed_count", "rlwe_tuner_size",
                         "rlwe_keyswitch_workspace_bytes", "rlwe_matmul_pack_workspace_bytes"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -326,6 +353,83 @@ def ct_matmul_pack(ctx: int, w: int, ct, tokens: int, k: int, n_pack: int, out,
                                 _ptr(out), flags, _stream(stream)))
 
 
+def rlwe_tuner_create(device_key: str) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().rlwe_tuner_create(device_key.encode(), ctypes.byref(h)))
+    return h.value
+
+
+def rlwe_tuner_destroy(t: int) -> None:
+    _check(lib().rlwe_tuner_destroy(t))
+
+
+def rlwe_tuner_size(t: int) -> int:
+    return int(lib().rlwe_tuner_size(t))
+
+
+def rlwe_tune_key(N: int, P: int, K: int, M: int, n_o: int = 1, raw: bool = False,
+                  tokens: int = 1) -> str:
+    buf = ctypes.create_string_buffer(160)
+    _check(lib().rlwe_tune_key(N, P, K, M, n_o, int(bool(raw)), tokens, buf, len(buf)))
+    return buf.value.decode()
+
+
+def rlwe_tuner_put(t: int, key: str, sched: dict) -> None:
+    s = Schedule(**{k: sched[k] for k in ("method", "tt_log2", "order", "launch", "ms")})
+    _check(lib().rlwe_tuner_put(t, key.encode(), ctypes.byref(s)))
+
+
+def rlwe_tuner_get(t: int, key: str) -> dict:
+    s = Schedule()
+    _check(lib().rlwe_tuner_get(t, key.encode(), ctypes.byref(s)))
+    return s.as_dict()
+
+
+def rlwe_tuner_lookup(t: int, N: int, P: int, K: int, M: int, n_o: int = 1, raw: bool = False,
+                      tokens: int = 1):
+    """The entry a product call uses (nearest token bucket of its shape), or None."""
+    s = Schedule()
+    rc = lib().rlwe_tuner_lookup(t, N, P, K, M, n_o, int(bool(raw)), tokens, ctypes.byref(s))
+    if rc < 0:
+        _check(rc)
+    return s.as_dict() if rc == 1 else None
+
+
+def rlwe_tuner_save(t: int, path: str) -> None:
+    _check(lib().rlwe_tuner_save(t, os.fsencode(path)))
+
+
+def rlwe_tuner_load(t: int, path: str) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().rlwe_tuner_load(t, os.fsencode(path), ctypes.byref(n)))
+    return n.value
+
+
+def rlwe_device_key(device: int = 0) -> str:
+    buf = ctypes.create_string_buffer(512)
+    _check(lib().rlwe_device_key(device, buf, len(buf)))
+    return buf.value.decode()
+
+
+def rlwe_ctx_set_tuner(ctx: int, t) -> None:
+    _check(lib().rlwe_ctx_set_tuner(ctx, t or None))
+
+
+def rlwe_autotune_product(ctx: int, t: int, K: int, M: int, tokens: int, wflags: int = 0,
+                          oflags: int = RLWE_OUT_SWITCHED, stream=None) -> dict:
+    s = Schedule()
+    _check(lib().rlwe_autotune_product(ctx, t, K, M, wflags, tokens, oflags, _stream(stream),
+                                       ctypes.byref(s)))
+    return s.as_dict()
+
+
+def rlwe_autotune_batch(ctx: int, t: int, items, flags: int = RLWE_OUT_SWITCHED, stream=None) -> dict:
+    arr = _descs(items)
+    s = Schedule()
+    _check(lib().rlwe_autotune_batch(ctx, t, arr, len(items), flags, _stream(stream), ctypes.byref(s)))
+    return s.as_dict()
+
+
 def rlwe_profile_begin(ctx: int) -> None:
     _check(lib().rlwe_profile_begin(ctx))
 
@@ -358,6 +462,27 @@ class Context:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Tuner:
+    """Owns an rlwe_tuner handle (measured launch choices for one device)."""
+
+    def __init__(self, device_key: str):
+        self.handle = rlwe_tuner_create(device_key)
+
+    def close(self) -> None:
+        if self.handle:
+            rlwe_tuner_destroy(self.handle)
+            self.handle = 0
+
+    def __len__(self) -> int:
+        return rlwe_tuner_size(self.handle)
+
+    def load(self, path: str) -> int:
+        return rlwe_tuner_load(self.handle, path)
+
+    def save(self, path: str) -> None:
+        rlwe_tuner_save(self.handle, path)
 
 
 class Weights:
