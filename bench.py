@@ -1,22 +1,29 @@
 #!/usr/bin/env python3
-"""Throughput of the encrypted clear-weight product W.[x]_HE on one MI355X.
+"""Throughput and latency of the encrypted clear-weight product W.[x]_HE on one MI355X.
 
-Workload (default): a Llama-3.2-1B attention projection, W 2048 x 2048 int8,
-128 encrypted int8 tokens, RLWE N = 4096, q = two 54-bit primes, t = 2^26, every
-output LWE switched to 2^32 (Sec. 4.3, Eq. (LWEdot) + ModulusSwitch). One step
-is one ct_matmul_clear call: digit preparation of the ciphertexts, the mask
-product on the int8 matrix cores, the body product, the fused modulus switch
-and the write of 128 x 2048 LWE ciphertexts of 4097 coefficients.
+Workloads (--workload):
+  serve (default)  requests from 16 clients (Poisson arrivals) over a resident 16-layer
+                   Llama-3.2-1B-shaped model, each one projection forward or backward with
+                   1..512 encrypted tokens, N = 4096, two 54-bit primes; HBM-budget
+                   admission. Reports the sustained encrypted MACs/s of the request loop,
+                   the same requests as plain per-call products, and p50/p99 latency at
+                   fractions of the saturated rate.
+  attn             one 2048 x 2048 projection, 128 tokens, t = 2^26 (a single
+                   ct_matmul_clear per step; options for seeded input, bit-packing, packed
+                   rows, KeySwitch packing).
+  layer            the 14 products of one layer (7 projections forward and transposed),
+                   uneven token counts, one captured graph per step, against plain calls.
+  mlp              gate/up/down forward and transposed over 2048 tokens in chunks.
 
-Inputs are synthetic and seeded: int8 weights uniform in [-127, 127] and
-ciphertext residues uniform in [0, q_p) (the distribution of RLWE ciphertexts
-under a uniform mask), resident in HBM before the timed region. The kernels are
-data-oblivious apart from a rare exact-rounding fallback.
+Every step computes Eq. (LWEdot) and the ModulusSwitch of Sec. 3.2 on synthetic, seeded
+inputs resident in HBM before the timed region: int8 weights uniform in [-127, 127] and
+ciphertext residues uniform in [0, q_p) (the distribution of RLWE ciphertexts under a
+uniform mask). The kernels are data-oblivious apart from a rare exact-rounding route.
 
-Prints one JSON line: value = encrypted MACs/s (d_in * d_out * tokens / s),
-with the roofline of the dominant kernel (measured with HIP events on its
-launch stream over the timed region) and the CPU oracle timed on a bounded
-sample of the same workload.
+Prints one JSON line: value = encrypted MACs/s (d_in * d_out * tokens / s), the roofline
+of the dominant kernel (its time from HIP events on its launch stream over the timed
+region, its peak measured on the device by the library's microbenchmarks) and the CPU
+oracle timed on a bounded sample of the same workload.
 """
 
 from __future__ import annotations
@@ -31,15 +38,41 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix peak, 5.0 POP/s
-# NTT method: VALU-bound. A wave64 VALU instruction occupies a 16-lane SIMD for four
-# clocks (measured on MI355X for the 32-bit multiplies, 64-bit mads and adds, carry
-# chains and selects the transforms use; only plain 32-bit add/sub/move issue faster), so
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 lane operations/s, the rate behind the
-# 78.6 TFLOP/s fp64 and unpacked fp32 vector peaks. One lazy Gentleman-Sande butterfly
-# on 54-bit residues is 17 of them: 4 for the sum and the biased difference, 13 for the
-# Shoup product with a truncated quotient. A pointwise product counts as one butterfly.
-NTT_PEAK_GBFLY = 256 * 4 * 16 * 2.4e9 / 17 / 1e9
+INT8_PEAK_TOPS = 5000.0  # MI355X published dense int8 matrix peak, 5.0 POP/s
+# The NTT method is bound by VALU issue. Its algorithmic work is counted in 54-bit modular
+# products: one per butterfly of the inverse transforms and one per pointwise product. The
+# peak is the device's measured rate of that product (rlwe_measure_peaks: the kernel's
+# truncated-quotient Shoup product in register-only chains). A lazy Gentleman-Sande
+# butterfly is that product plus a sum and a biased difference, 17 VALU instructions
+# against the product's 13; the butterfly rate at the measured issue rate is reported as
+# a kernel-model ceiling beside it.
+BFLY_MODEL_INSTR = 17
+
+
+def measured_peaks():
+    from paper_2505_07329_amd import rlwe
+    pk = rlwe.rlwe_measure_peaks(0)
+    return {"mul32_lane_ops_T": pk["mul32_lane_ops"] / 1e12, "modmul_G": pk["modmul"] / 1e9,
+            "butterfly_G": pk["butterfly"] / 1e9, "mfma_int8_TOPS": pk["mfma_int8_ops"] / 1e12,
+            "clock_mhz": pk["clock_mhz"], "compute_units": pk["compute_units"],
+            "source": "rlwe_measure_peaks (register-only microbenchmarks on this GPU)"}
+
+
+def tuner_path():
+    """The autotuner's cache for this device, next to the package."""
+    from paper_2505_07329_amd import tune
+    return tune.cache_path(0)
+
+
+def attach_tuner(rlwe, ctx):
+    """Attach the committed autotuner cache of this device, if there is one."""
+    path = tuner_path()
+    t = rlwe.Tuner(rlwe.rlwe_device_key(0))
+    n = t.load(path) if os.path.exists(path) else 0
+    if n:
+        rlwe.rlwe_ctx_set_tuner(ctx.handle, t.handle)
+    info = {"file": os.path.relpath(path, ROOT), "entries": n}
+    return t, info
 
 
 def method_flag(args):
@@ -55,30 +88,45 @@ def product_info(rlwe, w, tr, T, M, K):
     return dict(T=T, M=M, K=K, kept=kept, ntt=ntt, n_o=n_o)
 
 
-def roofline(products, kt, N, P, traffic=None):
+def roofline(products, kt, N, P, peaks, traffic=None):
     """Roofline of the dominant mask kernel of a set of products, each a dict with
     T, M (outputs per token), K, kept (digits on the matrix cores), ntt (method), n_o
     (outputs per weight polynomial, 1 unless rows are packed). Matrix cores: 2 T M N K
-    kept int8 ops; NTT: per weight polynomial, token and prime one inverse transform
-    ((N/2) log2 N butterflies) and L N pointwise products. traffic: measured
-    HBM bytes per launch by kernel kind ("mfma", "alu"), where known."""
+    kept int8 ops against the published int8 peak; NTT: per weight polynomial, token and
+    prime (N/2) log2 N butterflies and L N pointwise products, one 54-bit modular product
+    each, against the measured modular-product rate (the persistent launch's time counts
+    as the NTT product's: its transforms and bodies are a few per cent of it). traffic:
+    measured HBM bytes per launch by kernel kind ("mfma", "alu"), where known."""
     traffic = traffic or {}
     import math
     mf_ops = sum(2.0 * p["T"] * p["M"] * N * p["K"] * p["kept"] for p in products if not p["ntt"])
     nt_ops = sum(p["T"] * -(-p["M"] // p.get("n_o", 1)) * P
                  * ((N // 2) * math.log2(N) + ((p["K"] + N - 1) // N) * N)
                  for p in products if p["ntt"])
+    bfly = sum(p["T"] * -(-p["M"] // p.get("n_o", 1)) * P * (N // 2) * math.log2(N)
+               for p in products if p["ntt"])
     parts = {}
     if mf_ops and kt["mask_ms"] > 0:
         a = mf_ops / (kt["mask_ms"] * 1e-3) / 1e12
         parts["mfma"] = {"bound": "mfma", "achieved": a, "peak": INT8_PEAK_TOPS,
                          "unit": "TOP/s (int8)", "frac": a / INT8_PEAK_TOPS,
-                         "traffic": traffic.get("mfma"), "ms": kt["mask_ms"]}
-    if nt_ops and kt.get("ntt_ms", 0) > 0:
-        a = nt_ops / (kt["ntt_ms"] * 1e-3) / 1e9
-        parts["alu"] = {"bound": "alu", "achieved": a, "peak": NTT_PEAK_GBFLY,
-                        "unit": "G butterfly/s (54-bit lazy Shoup, NTT method)",
-                        "frac": a / NTT_PEAK_GBFLY, "traffic": traffic.get("alu"), "ms": kt["ntt_ms"]}
+                         "traffic": traffic.get("mfma"), "ms": kt["mask_ms"],
+                         "measured_peak": peaks["mfma_int8_TOPS"],
+                         "frac_of_measured": a / peaks["mfma_int8_TOPS"]}
+    ntt_ms = kt.get("ntt_ms", 0) + kt.get("persist_ms", 0)
+    if nt_ops and ntt_ms > 0:
+        a = nt_ops / (ntt_ms * 1e-3) / 1e9
+        model = peaks["mul32_lane_ops_T"] * 1e3 / BFLY_MODEL_INSTR
+        parts["alu"] = {"bound": "alu", "achieved": a, "peak": peaks["modmul_G"],
+                        "unit": "G modmul/s (54-bit modular products: one per butterfly and "
+                                "per pointwise product, NTT method)",
+                        "frac": a / peaks["modmul_G"], "traffic": traffic.get("alu"), "ms": ntt_ms,
+                        "peak_source": "measured: rlwe_measure_peaks modmul",
+                        "kernel_model": {"butterflies_G_per_s": bfly / (ntt_ms * 1e-3) / 1e9,
+                                         "instr_per_butterfly": BFLY_MODEL_INSTR,
+                                         "ceiling_G_per_s": model,
+                                         "measured_butterfly_G_per_s": peaks["butterfly_G"],
+                                         "frac_of_ceiling": a / model}}
     if not parts:
         return None, None
     dom = max(parts.values(), key=lambda x: x["ms"])
@@ -94,11 +142,12 @@ def roofline(products, kt, N, P, traffic=None):
 KERNEL_TRAFFIC = {
     "mask": {"sources": ["k_mask.hip"], "fetch_bytes": 4382214101, "write_bytes": 4766672373,
              "sha256": "37b3392ace8226fcd057a2f461259544933971d70c4ba84b554979c7875ac123"},
-    "ntt": {"sources": ["k_ntt.hip", "ntt_device.hpp", "ks_round.hpp"], "fetch_bytes": 5235399093,
+    "ntt": {"sources": ["k_ntt.hip", "ntt_product.hpp", "ntt_device.hpp", "ks_round.hpp"],
+            "fetch_bytes": 5235399093,
             "write_bytes": 4353409833,
             "sha256": "54bbd23bc851573e643c2b930121939d417596e893ad87097cd9f620a7f47c1c"},
     # the product with masks rounded for KeySwitch packing (ct_matmul_pack, --keyswitch)
-    "ntt_ks": {"sources": ["k_ntt.hip", "ntt_device.hpp", "ks_round.hpp"],
+    "ntt_ks": {"sources": ["k_ntt.hip", "ntt_product.hpp", "ntt_device.hpp", "ks_round.hpp"],
                "fetch_bytes": 6243685734, "write_bytes": 8676000492,
                "sha256": "54bbd23bc851573e643c2b930121939d417596e893ad87097cd9f620a7f47c1c"},
     "ksacc": {"sources": ["k_keyswitch.hip", "ntt_device.hpp", "ks_round.hpp"],
@@ -107,18 +156,19 @@ KERNEL_TRAFFIC = {
 }
 
 
-def keyswitch_roofline(M, N, P, ell, acc_s):
+def keyswitch_roofline(M, N, P, ell, acc_s, peaks):
     """Roofline of the KeySwitch accumulate kernel for M LWE ciphertexts packed N per RLWE
     ciphertext: per packed ciphertext, key coefficient, level and prime one forward
     transform ((N/2) log2 N butterflies) and 2 N pointwise products (mask and body of the
-    key), each counted as one butterfly."""
+    key), one 54-bit modular product each, against the measured modular-product rate."""
     import math
     G = -(-M // N)
     work = G * N * ell * P * ((N // 2) * math.log2(N) + 2 * N)
     a = work / acc_s / 1e9
-    return {"bound": "alu", "achieved": a, "peak": NTT_PEAK_GBFLY,
-            "unit": "G butterfly/s (54-bit lazy Shoup, KeySwitch transforms)",
-            "frac": a / NTT_PEAK_GBFLY, "traffic": None}
+    return {"bound": "alu", "achieved": a, "peak": peaks["modmul_G"],
+            "unit": "G modmul/s (54-bit modular products, KeySwitch transforms)",
+            "frac": a / peaks["modmul_G"], "traffic": None,
+            "peak_source": "measured: rlwe_measure_peaks modmul"}
 
 
 def keyswitch_cpu_baseline(prod, N, primes, d_in, beta, ell):
@@ -197,8 +247,9 @@ def source_sha256(kind):
     return h.hexdigest()
 
 
-KERNEL_SOURCES = {"mask": ["k_mask.hip"], "ntt": ["k_ntt.hip", "ntt_device.hpp", "ks_round.hpp"],
-                  "ntt_ks": ["k_ntt.hip", "ntt_device.hpp", "ks_round.hpp"],
+KERNEL_SOURCES = {"mask": ["k_mask.hip"],
+                  "ntt": ["k_ntt.hip", "ntt_product.hpp", "ntt_device.hpp", "ks_round.hpp"],
+                  "ntt_ks": ["k_ntt.hip", "ntt_product.hpp", "ntt_device.hpp", "ks_round.hpp"],
                   "ksacc": ["k_keyswitch.hip", "ntt_device.hpp", "ks_round.hpp"]}
 
 
@@ -208,7 +259,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default 20; mlp: 1 pass over all 2048 tokens of 6 products)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 3; mlp: 1)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target CPU time of the oracle baseline sample (0 disables it)")
     ap.add_argument("--chunk", type=int, default=256, help="mlp: tokens per call")
     ap.add_argument("--method", choices=["auto", "ntt", "toeplitz"], default="auto",
@@ -236,14 +287,17 @@ def parse():
                     help="attn: before the timed region, run one plain elementwise copy kernel "
                          "(int32 bitwise not) reading and writing GIB GiB each, as the known-size "
                          "reference for the FETCH_SIZE / WRITE_SIZE counters")
-    ap.add_argument("--workload", choices=["attn", "layer", "mlp", "serve"], default="attn",
-                    help="attn: one 2048x2048 projection, 128 tokens (default); layer: the 14 "
+    ap.add_argument("--workload", choices=["attn", "layer", "mlp", "serve"], default="serve",
+                    help="serve (default): Poisson requests from 16 clients over a resident "
+                         "16-layer model, vs plain per-call kernels, p50/p99; "
+                         "attn: one 2048x2048 projection, 128 tokens; layer: the 14 "
                          "products of a Llama-3.2-1B layer, forward and transposed, with uneven "
                          "token counts, captured once as a graph and replayed; mlp: gate/up/down "
-                         "forward and transposed over 2048 tokens in chunks; serve: Poisson "
-                         "requests from 16 clients over a resident 16-layer model")
-    ap.add_argument("--requests", type=int, default=96,
-                    help="serve: requests per run (saturated run and each load point)")
+                         "forward and transposed over 2048 tokens in chunks")
+    ap.add_argument("--requests", type=int, default=500,
+                    help="serve: requests per load point of the latency sweep")
+    ap.add_argument("--max-tokens", type=int, default=16,
+                    help="layer: token counts drawn uniformly in 1..max-tokens")
     ap.add_argument("--budget-gib", type=float, default=128.0,
                     help="serve: HBM budget of the output arena")
     ap.add_argument("--round-macs", type=float, default=1e9,
@@ -258,43 +312,98 @@ def parse():
     return args
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def oracle_rates(sample, target_s, label):
+    """The oracle's rate in its two modes (NTT: a psi-twisted transform per output and
+    prime; schoolbook: the closed form of Eq. (LWEdot), d_in (N + 1) products per output
+    and prime), each on all host threads and on one thread, plus the exact switch.
+    sample(mode) runs one chunk of the workload's sampled outputs and returns the MACs
+    it credits; each of the four runs takes about target_s / 4 seconds. value = NTT mode
+    on all threads (the fastest plain-CPU form)."""
+    from oracle import oracle as orc
+    orc.lib()
+    all_threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or (os.cpu_count() or 1)
+    rates, notes = {}, []
+    for mode, mname in ((1, "ntt"), (0, "schoolbook")):
+        for threads, tname in ((all_threads, "all_cores"), (1, "one_core")):
+            orc.set_threads(threads)
+            macs, el = 0, 0.0
+            while el < target_s / 4:
+                t0 = time.perf_counter()
+                macs += sample(mode)
+                el += time.perf_counter() - t0
+            rates[f"{mname}_{tname}"] = macs / el
+            notes.append(f"{mname} on {threads} thread(s) {el:.1f} s")
+    orc.set_threads(all_threads)
+    return {"value": rates["ntt_all_cores"], "unit": "encrypted MAC/s", "cores": all_threads,
+            "kind": "oracle", "cpu_model": cpu_model(), "modes": rates,
+            "sample": f"{label}; oracle plus exact switch to 2^32, " + ", ".join(notes)
+                      + "; scaled per MAC (the cost is linear in tokens and outputs)"}
+
+
 def cpu_baseline(W, ct_np, N, primes, T, d_out, d_in, target_s, n_o=1):
-    """The oracle (NTT mode + exact modulus switch) on sampled (token, row) outputs; with
-    packed rows (n_o > 1), on sampled (token, group of n_o rows) products."""
+    """The oracle on sampled (token, row) outputs of the same workload (same weights and
+    ciphertexts); with packed rows (n_o > 1), on sampled (token, group of n_o rows)
+    products by the oracle's packed-row product (one form: both mode entries are it)."""
     import numpy as np
 
     from oracle import oracle as orc
-    orc.lib()
     g = np.random.default_rng(7)
-    done = 0
-    t0 = time.perf_counter()
-    batch = 64
     groups = -(-d_out // n_o)
-    while True:
+
+    def sample(mode):
         if n_o > 1:
             t, gr = int(g.integers(0, T)), int(g.integers(0, groups))
             rows = W[gr * n_o:(gr + 1) * n_o]
-            raw = orc.matmul_rowpacked(N, primes, rows, ct_np[t:t + 1])
-            orc.modswitch(primes, raw)
-            done += rows.shape[0]
-            el = time.perf_counter() - t0
-            if el >= target_s:
-                break
-            continue
-        pairs = np.stack([g.integers(0, T, batch), g.integers(0, d_out, batch)], 1).astype(np.uint32)
-        raw = orc.matmul_clear(N, primes, W, ct_np, pairs=pairs, mode=1)
-        orc.modswitch(primes, raw)
-        done += batch
-        el = time.perf_counter() - t0
-        if el >= target_s:
-            break
-        batch = min(4096, batch * 2)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": done * d_in / el, "unit": "encrypted MAC/s", "cores": cores, "kind": "oracle",
-            "sample": f"{done} (token, row) outputs of the same workload"
-                      + (f" in groups of {n_o} packed rows" if n_o > 1 else "")
-                      + f", NTT-mode oracle plus exact switch, {el:.1f} s on {cores} threads, "
-                        f"scaled per MAC"}
+            orc.modswitch(primes, orc.matmul_rowpacked(N, primes, rows, ct_np[t:t + 1]))
+            return rows.shape[0] * d_in
+        pairs = np.stack([g.integers(0, T, 16), g.integers(0, d_out, 16)], 1).astype(np.uint32)
+        orc.modswitch(primes, orc.matmul_clear(N, primes, W, ct_np, pairs=pairs, mode=mode))
+        return len(pairs) * d_in
+
+    label = ("sampled (token, row) outputs of the same workload, 16 per chunk" if n_o == 1 else
+             f"sampled (token, group of {n_o} packed rows) products of the same workload")
+    return oracle_rates(sample, target_s, label)
+
+
+def mix_cpu_baseline(shapes, N, primes, target_s, label, seed):
+    """The oracle on sampled output LWEs of a mix of products (K inputs, M outputs each),
+    8 outputs of each product in turn, on seeded random weights and ciphertexts of those
+    shapes (the oracle's cost does not depend on the values), credited K MACs per output."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    g = np.random.default_rng(seed)
+    data = {}
+    for K, M in shapes:
+        if (K, M) not in data:
+            W = g.integers(-127, 128, size=(M, K), dtype=np.int64).astype(np.int8)
+            L = (K + N - 1) // N
+            ct = np.stack([g.integers(0, q, size=(8, L, 2, N), dtype=np.uint64) for q in primes], -2)
+            data[(K, M)] = (W, ct)
+    order = list(shapes)
+    state = {"i": 0}
+
+    def sample(mode):
+        K, M = order[state["i"] % len(order)]
+        state["i"] += 1
+        W, ct = data[(K, M)]
+        pairs = np.stack([g.integers(0, 8, 8), g.integers(0, M, 8)], 1).astype(np.uint32)
+        orc.modswitch(primes, orc.matmul_clear(N, primes, W, ct, pairs=pairs, mode=mode))
+        return len(pairs) * K
+
+    return oracle_rates(sample, target_s, label)
 
 
 LAYER_BUDGET = 250e9  # output bytes per captured graph
@@ -302,8 +411,10 @@ LAYER_BUDGET = 250e9  # output bytes per captured graph
 
 def layer_workload(args):
     """All 7 projections of one Llama-3.2-1B layer, forward and transposed (14 products),
-    token counts drawn uniformly in 1..512, one captured graph replayed per step, against
-    the same 14 products issued as plain ct_matmul_clear calls."""
+    token counts drawn uniformly in 1..max_tokens (16 by default: the paper's training step
+    runs one sequence of 16 tokens per call, Sec. 6.3), one captured graph replayed per
+    step (launch shape from the autotuner's cache when it has the batch, else grouped),
+    against the same 14 products issued as plain ct_matmul_clear calls."""
     import numpy as np
     import torch
 
@@ -313,7 +424,9 @@ def layer_workload(args):
     N, primes, log2_t = cfg["N"], cfg["primes"], cfg["log2_t"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    peaks = measured_peaks()
     ctx = rlwe.Context(N, primes, log2_t, device=0)
+    tuner, tuner_info = attach_tuner(rlwe, ctx)
     g = synth.rng(4, synth.P_MISC)
     products, weights = [], []
     for pi, (name, (d_in, d_out)) in enumerate(synth.LLAMA_1B_PROJ.items()):
@@ -323,7 +436,7 @@ def layer_workload(args):
         weights.append(w)
         for tr in (False, True):
             K, M = (d_out, d_in) if tr else (d_in, d_out)
-            T = int(g.integers(1, 513))
+            T = int(g.integers(1, args.max_tokens + 1))
             products.append(dict(name=name + ("^T" if tr else ""), w=w, tr=tr, K=K, M=M, T=T))
     macs = sum(p["T"] * p["K"] * p["M"] for p in products)
     groups, cur, cur_bytes = [], [], 0
@@ -346,9 +459,13 @@ def layer_workload(args):
             items.append((p["w"].handle, p["tr"], p["ct"], p["T"], p["out"]))
         items_per_group.append(items)
     stream = torch.cuda.current_stream()
-    graphs = [rlwe.rlwe_graph_capture_batch(ctx.handle, items) for items in items_per_group]
+    all_ntt = all(rlwe.rlwe_weights_method(p["w"].handle, p["tr"]) == rlwe.RLWE_METHOD_NTT
+                  for p in products)
 
-    def step_graph():
+    def capture(flags):
+        return [rlwe.rlwe_graph_capture_batch(ctx.handle, items, flags) for items in items_per_group]
+
+    def step_graph(graphs):
         for gr in graphs:
             rlwe.rlwe_graph_launch(gr, stream)
 
@@ -367,40 +484,57 @@ def layer_workload(args):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
-    plain_steps = max(1, args.steps // 4)
     rlwe.rlwe_workspace_reserve(ctx.handle, max(
         rlwe.rlwe_workspace_bytes(ctx.handle, p["w"].handle, p["tr"], p["T"]) for p in products))
-    t_plain = timed(step_plain, plain_steps, 1)
-    t_graph = timed(step_graph, args.steps, args.warmup)
+    t_plain = timed(step_plain, max(1, args.steps // 2), 1)
+    shapes = {}
+    for name, flags in (("grouped", rlwe.RLWE_LAUNCH_GROUPED),
+                        ("persistent", rlwe.RLWE_LAUNCH_PERSISTENT if all_ntt else None)):
+        if flags is None:
+            continue
+        gr = capture(flags)
+        shapes[name] = timed(lambda: step_graph(gr), max(1, args.steps // 2), 1) * 1e3
+        for x in gr:
+            rlwe.rlwe_graph_destroy(x)
+    graphs = capture(rlwe.RLWE_OUT_SWITCHED)  # the launch the tuner chose
+    t_graph = timed(lambda: step_graph(graphs), args.steps, args.warmup)
     rlwe.rlwe_profile_begin(ctx.handle)
     step_plain()
     torch.cuda.synchronize()
     kt = rlwe.rlwe_profile_end(ctx.handle)
     roof, roof_other = roofline([product_info(rlwe, p["w"], p["tr"], p["T"], p["M"], p["K"])
-                                 for p in products], kt, N, len(primes))
+                                 for p in products], kt, N, len(primes), peaks)
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = mix_cpu_baseline([(p["K"], p["M"]) for p in products], N, primes, args.cpu_seconds,
+                               "sampled output LWEs, 8 from each of the 14 products in turn", 4)
     value = macs / t_graph
     result = {
         "metric": "encrypted MACs/s (sum d_in*d_out*tokens / s), one Llama-3.2-1B layer, 7 projections "
-                  "forward and transposed in one captured graph",
+                  "forward and transposed in one captured graph, vs plain per-call kernels",
         "value": value, "unit": "MAC/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": t_graph * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "int8",
+        "vs_baseline": None, "dtype": "u64 (54-bit RNS residues)",
         "data": "synthetic (seeded uniform int8 weights, uniform ciphertext residues)",
         "config": {"workload": cfg["name"], "N": N, "primes": len(primes), "log2_t": log2_t,
+                   "tokens": f"U{{1..{args.max_tokens}}}",
                    "products": [f'{p["name"]}:{p["K"]}->{p["M"]}x{p["T"]}' for p in products],
                    "graphs": len(graphs),
                    "output_GB": sum(p["T"] * p["M"] * (N + 1) * 4 for p in products) / 1e9},
         "plain_per_call": {"value": macs / t_plain, "ms_per_step": t_plain * 1e3,
                            "speedup_graph": t_plain / t_graph},
+        "launch_shapes_ms": shapes, "tuner": tuner_info,
         "methods": {p["name"]: ("ntt" if rlwe.rlwe_weights_method(p["w"].handle, p["tr"]) else "toeplitz")
                     for p in products},
-        "roofline": roof, "roofline_other_method": roof_other,
-        "cpu_baseline": None,
+        "roofline": roof, "roofline_other_method": roof_other, "peaks": peaks,
+        "cpu_baseline": cpu,
     }
     for gr in graphs:
         rlwe.rlwe_graph_destroy(gr)
     for w in weights:
         w.close()
+    rlwe.rlwe_ctx_set_tuner(ctx.handle, None)
+    tuner.close()
     ctx.close()
     print(json.dumps(result), flush=True)
 
@@ -426,7 +560,9 @@ def mlp_workload(args):
         raise SystemExit("--chunk must divide 2048")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    peaks = measured_peaks()
     ctx = rlwe.Context(N, primes, log2_t, device=0)
+    tuner, tuner_info = attach_tuner(rlwe, ctx)
     mats = {}
     for pi, name in enumerate(("gate", "up", "down")):
         d_in, d_out = synth.LLAMA_1B_PROJ[name]
@@ -473,16 +609,17 @@ def mlp_workload(args):
     kt = rlwe.rlwe_profile_end(ctx.handle)
     macs = args.steps * T * sum(p["K"] * p["M"] for p in products)
     roof, roof_other = roofline([product_info(rlwe, p["w"], p["tr"], args.steps * T, p["M"], p["K"])
-                                 for p in products], kt, N, len(primes))
+                                 for p in products], kt, N, len(primes), peaks)
     cpu = None
     if args.cpu_seconds > 0:
-        cpu = mlp_cpu_baseline(products, N, primes, args.cpu_seconds)
+        cpu = mix_cpu_baseline([(p["K"], p["M"]) for p in products], N, primes, args.cpu_seconds,
+                               "sampled output LWEs, 8 from each of the six products in turn", 9)
     result = {
         "metric": "encrypted MACs/s (sum d_in*d_out*tokens / s), Llama-3.2-1B MLP forward and backward "
                   "through the frozen weights, outputs switched to 2^32",
         "value": macs / wall, "unit": "MAC/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "int8",
+        "vs_baseline": None, "dtype": "u64 (54-bit RNS residues)",
         "data": "synthetic (seeded uniform int8 weights, uniform ciphertext residues)",
         "config": {"workload": cfg["name"], "N": N, "primes": len(primes), "log2_t": log2_t,
                    "tokens": T, "chunk": C,
@@ -490,47 +627,18 @@ def mlp_workload(args):
                    "digits_on_matrix_cores": {p["name"]: rlwe.rlwe_weights_digits(p["w"].handle, p["tr"])[0]
                                               for p in products}},
         "kernels_ms": {"prep": kt["prep_ms"], "mask": kt["mask_ms"], "ntt": kt["ntt_ms"],
-                       "body": kt["body_ms"]},
+                       "persistent": kt["persist_ms"], "body": kt["body_ms"]},
         "methods": {p["name"]: ("ntt" if rlwe.rlwe_weights_method(p["w"].handle, p["tr"]) else "toeplitz")
                     for p in products},
-        "roofline": roof, "roofline_other_method": roof_other,
-        "cpu_baseline": cpu,
+        "roofline": roof, "roofline_other_method": roof_other, "peaks": peaks,
+        "tuner": tuner_info, "cpu_baseline": cpu,
     }
     for w in mats.values():
         w.close()
+    rlwe.rlwe_ctx_set_tuner(ctx.handle, None)
+    tuner.close()
     ctx.close()
     print(json.dumps(result), flush=True)
-
-
-def mlp_cpu_baseline(products, N, primes, target_s):
-    """The oracle on 32 sampled output LWEs of each of the six products in turn, credited
-    d_in MACs per output LWE (its cost is linear in the token count)."""
-    import numpy as np
-
-    from oracle import oracle as orc
-    orc.lib()
-    g = np.random.default_rng(9)
-    data = []
-    for p in products:
-        W = g.integers(-127, 128, size=(p["M"], p["K"]), dtype=np.int64).astype(np.int8)
-        ct = np.stack([g.integers(0, q, size=(8, p["L"], 2, N), dtype=np.uint64) for q in primes], -2)
-        data.append((p, W, ct))
-    done = macs = 0
-    el = 0.0
-    i = 0
-    while el < target_s:
-        p, W, ct = data[i % len(data)]
-        i += 1
-        pairs = np.stack([g.integers(0, 8, 32), g.integers(0, p["M"], 32)], 1).astype(np.uint32)
-        t0 = time.perf_counter()
-        orc.modswitch(primes, orc.matmul_clear(N, primes, W, ct, pairs=pairs, mode=1))
-        el += time.perf_counter() - t0
-        done += len(pairs)
-        macs += len(pairs) * p["K"]
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": macs / el, "unit": "encrypted MAC/s", "cores": cores, "kind": "oracle",
-            "sample": f"{done} output LWEs, 32 from each of the six products in turn, NTT-mode oracle "
-                      f"plus exact switch, {el:.1f} s on {cores} threads, scaled per MAC"}
 
 
 SERVE_LAYERS = 16
@@ -538,12 +646,17 @@ SERVE_CLIENTS = 16
 SERVE_MAX_TOKENS = 512
 
 
+SERVE_STEP_REQUESTS = 25  # requests per step of the saturated run
+
+
 def serve_workload(args):
-    """Requests from 16 clients (Poisson arrivals) over a resident 16-layer Llama-3.2-1B-shaped
-    model, each one projection forward or backward with 1..512 tokens. Runs: all requests
-    queued at once (saturated; grouped launches of up to 16 requests, then one call per
-    request as the plain comparator), then Poisson arrivals at fractions of the saturated
-    request rate, each reporting p50/p99 latency and sustained MACs/s."""
+    """Requests from 16 clients over a resident 16-layer Llama-3.2-1B-shaped model, each one
+    projection forward or backward with 1..512 tokens. One step is SERVE_STEP_REQUESTS
+    requests; the timed region serves `steps` steps of requests queued at once (saturated:
+    grouped launches of up to 16 requests per scheduling round), after `warmup` steps
+    served untimed. The same requests as one plain call each are the comparator. Then
+    Poisson arrivals at fractions of the saturated request rate, `requests` per load
+    point, report p50/p99 latency and sustained MACs/s."""
     import math
 
     import numpy as np
@@ -555,7 +668,9 @@ def serve_workload(args):
     N, primes, log2_t = cfg["N"], cfg["primes"], cfg["log2_t"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    peaks = measured_peaks()
     ctx = rlwe.Context(N, primes, log2_t, device=0)
+    tuner, tuner_info = attach_tuner(rlwe, ctx)
     t_setup = time.perf_counter()
     weights = {}
     for layer in range(SERVE_LAYERS):
@@ -580,9 +695,9 @@ def serve_workload(args):
     backend = serve.GpuBackend(ctx, weights, pools, arena, stream)
     out_bytes = serve.switched_out_bytes(N)
 
-    def requests(rate, salt):
+    def requests(n, rate, salt):
         g = synth.rng(5, synth.P_MISC, salt)
-        return serve.make_requests(synth.LLAMA_1B_PROJ, SERVE_LAYERS, SERVE_CLIENTS, args.requests,
+        return serve.make_requests(synth.LLAMA_1B_PROJ, SERVE_LAYERS, SERVE_CLIENTS, n,
                                    rate, g, out_bytes, SERVE_MAX_TOKENS)
 
     def run(reqs, max_batch):
@@ -591,90 +706,78 @@ def serve_workload(args):
         return serve.run_loop(reqs, sched, backend, time.perf_counter,
                               lambda dt: time.sleep(min(dt, 0.05)))
 
-    # warm-up: a few requests through both paths
-    run(requests(math.inf, 99)[:4], 16)
-    run(requests(math.inf, 99)[:2], 1)
-    torch.cuda.synchronize()
-
-    sat_reqs = requests(math.inf, 0)
+    n_sat = args.steps * SERVE_STEP_REQUESTS
+    if args.warmup:
+        run(requests(args.warmup * SERVE_STEP_REQUESTS, math.inf, 99), 16)
+        run(requests(2, math.inf, 98), 1)
+    sat_reqs = requests(n_sat, math.inf, 0)
     rlwe.rlwe_profile_begin(ctx.handle)
+    torch.cuda.synchronize()  # one GPU: the barrier is this synchronisation
+    t0 = time.perf_counter()
     sat = run(sat_reqs, 16)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
     kt = rlwe.rlwe_profile_end(ctx.handle)
+    print(json.dumps({"progress": "saturated", "requests": sat["requests"], "wall_s": wall}),
+          file=sys.stderr, flush=True)
     roof, roof_other = roofline([product_info(rlwe, weights[(r.layer, r.proj)], r.transpose, r.tokens,
-                                              r.d_out, r.d_in) for r in sat_reqs], kt, N, len(primes))
-    plain = run(requests(math.inf, 0), 1)
-    sat_rate = sat["requests"] / sat["span_s"]
+                                              r.d_out, r.d_in) for r in sat_reqs], kt, N, len(primes),
+                                peaks)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plain = run(requests(n_sat, math.inf, 0), 1)
+    torch.cuda.synchronize()
+    plain_wall = time.perf_counter() - t1
+    print(json.dumps({"progress": "plain per call", "wall_s": plain_wall}), file=sys.stderr, flush=True)
+    macs = sat["macs"]
+    sat_rate = sat["requests"] / wall
     sweep = []
     for i, f in enumerate(float(x) for x in args.loads.split(",") if x):
-        res = run(requests(f * sat_rate, 1 + i), 16)
+        res = run(requests(args.requests, f * sat_rate, 1 + i), 16)
         sweep.append({"load": f, "rate_req_s": f * sat_rate, "p50_ms": res["p50_s"] * 1e3,
                       "p99_ms": res["p99_s"] * 1e3, "mean_ms": res["mean_s"] * 1e3,
-                      "macs_per_s": res["macs_per_s"], "requests": res["requests"]})
+                      "macs_per_s": res["macs_per_s"], "requests": res["requests"],
+                      "rejected": res["rejected"], "expired": res["expired"]})
         print(json.dumps({"progress": "load point", **sweep[-1]}), file=sys.stderr, flush=True)
     head = min(sweep, key=lambda x: abs(x["load"] - 0.8)) if sweep else None
     cpu = None
     if args.cpu_seconds > 0:
-        cpu = serve_cpu_baseline(sat_reqs, N, primes, args.cpu_seconds)
+        cpu = mix_cpu_baseline([(r.d_in, r.d_out) for r in sat_reqs], N, primes, args.cpu_seconds,
+                               "sampled output LWEs, 8 from each request of the served mix in "
+                               "turn", 8)
     result = {
-        "metric": "encrypted MACs/s (sum d_in*d_out*tokens / s) sustained by the request loop; "
-                  "p50/p99 request latency",
-        "value": sat["macs_per_s"], "unit": "MAC/s", "n_gpus": 1, "steps": sat["requests"],
-        "warmup": 6, "ms_per_step": sat["span_s"] * 1e3 / max(sat["requests"], 1),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int8",
+        "metric": "encrypted MACs/s (sum d_in*d_out*tokens / s) vs plain kernel; p50/p99 request "
+                  "latency",
+        "value": macs / wall, "unit": "MAC/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64 (54-bit RNS residues)",
         "data": "synthetic (seeded uniform int8 weights of 16 layers, uniform ciphertext residues, "
                 "Poisson arrivals)",
         "config": {"workload": cfg["name"], "N": N, "primes": len(primes), "log2_t": log2_t,
                    "layers": SERVE_LAYERS, "clients": SERVE_CLIENTS, "tokens": "U{1..512}",
-                   "requests": args.requests, "budget_GiB": args.budget_gib, "max_batch": 16,
-                   "round_macs": args.round_macs,
+                   "requests_per_step": SERVE_STEP_REQUESTS, "requests_per_load_point": args.requests,
+                   "budget_GiB": args.budget_gib, "max_batch": 16, "round_macs": args.round_macs,
                    "setup_s": t_setup},
-        "latency_ms": {"load": head["load"], "p50": head["p50_ms"], "p99": head["p99_ms"]} if head else None,
-        "saturated": {"p50_ms": sat["p50_s"] * 1e3, "p99_ms": sat["p99_s"] * 1e3,
-                      "rate_req_s": sat_rate, "span_s": sat["span_s"]},
-        "plain_per_call": {"value": plain["macs_per_s"], "speedup_grouped": sat["macs_per_s"] / plain["macs_per_s"]},
-        "sweep": sweep,
-        "roofline": roof, "roofline_other_method": roof_other,
+        "latency_ms": ({"load": head["load"], "p50": head["p50_ms"], "p99": head["p99_ms"],
+                        "requests": head["requests"]} if head else None),
+        "saturated": {"requests": sat["requests"], "p50_ms": sat["p50_s"] * 1e3,
+                      "p99_ms": sat["p99_s"] * 1e3, "rate_req_s": sat_rate, "wall_s": wall},
+        "plain_per_call": {"value": macs / plain_wall, "ms_per_step": plain_wall * 1e3 / args.steps,
+                           "speedup_served": plain_wall / wall,
+                           "what": "the same requests, one ct_matmul_clear each, in arrival order"},
+        "sweep": sweep, "tuner": tuner_info,
+        "kernels_ms": {"ntt": kt["ntt_ms"], "persistent": kt["persist_ms"], "mask": kt["mask_ms"],
+                       "prep": kt["prep_ms"], "body": kt["body_ms"]},
+        "roofline": roof, "roofline_other_method": roof_other, "peaks": peaks,
         "cpu_baseline": cpu,
     }
     for w in weights.values():
         w.close()
+    rlwe.rlwe_ctx_set_tuner(ctx.handle, None)
+    tuner.close()
     ctx.close()
     print(json.dumps(result), flush=True)
-
-
-def serve_cpu_baseline(reqs, N, primes, target_s):
-    """The oracle on 32 sampled output LWEs of each request in turn (the request mix of the
-    workload), credited d_in MACs per output LWE."""
-    import numpy as np
-
-    from oracle import oracle as orc
-    orc.lib()
-    g = np.random.default_rng(8)
-    Ws, cts = {}, {}
-    for r in reqs:  # one weight matrix and ciphertext set per shape (values do not change cost)
-        key = (r.d_in, r.d_out)
-        if key not in Ws:
-            Ws[key] = g.integers(-127, 128, size=(r.d_out, r.d_in), dtype=np.int64).astype(np.int8)
-            L = (r.d_in + N - 1) // N
-            cts[key] = np.stack([g.integers(0, q, size=(8, L, 2, N), dtype=np.uint64) for q in primes], -2)
-    done = macs = 0
-    el = 0.0
-    i = 0
-    while el < target_s:
-        r = reqs[i % len(reqs)]
-        i += 1
-        key = (r.d_in, r.d_out)
-        pairs = np.stack([g.integers(0, 8, 32), g.integers(0, r.d_out, 32)], 1).astype(np.uint32)
-        t0 = time.perf_counter()
-        raw = orc.matmul_clear(N, primes, Ws[key], cts[key], pairs=pairs, mode=1)
-        orc.modswitch(primes, raw)
-        el += time.perf_counter() - t0
-        done += len(pairs)
-        macs += len(pairs) * r.d_in
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": macs / el, "unit": "encrypted MAC/s", "cores": cores, "kind": "oracle",
-            "sample": f"{done} output LWEs, 32 from each request of the served mix in turn, NTT-mode "
-                      f"oracle plus exact switch, {el:.1f} s on {cores} threads, scaled per MAC"}
 
 
 def main():
@@ -717,8 +820,10 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    peaks = measured_peaks()
     qbits = args.q_out_bits
     ctx = rlwe.Context(N, primes, log2_t, device=0, log2_q_out=qbits)
+    tuner, tuner_info = attach_tuner(rlwe, ctx)
     w = rlwe.Weights(ctx, torch.from_numpy(W).to(dev), rlwe.RLWE_W_FWD | method_flag(args))
     ct = torch.from_numpy(in_np.view(np.int64)).to(dev)
     in_flags = rlwe.RLWE_IN_SEEDED if args.seeded else 0
@@ -788,12 +893,14 @@ def main():
     macs = d_in * d_out * T
     value = macs * args.steps / wall
     lat = np.array([marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps)])
-    per_launch = {k: kt[k] / max(1, kt[k.replace("_ms", "_n")]) for k in ("prep_ms", "mask_ms", "ntt_ms", "body_ms")}
-    one = dict(kt, mask_ms=per_launch["mask_ms"], ntt_ms=per_launch["ntt_ms"])
+    per_launch = {k: kt[k] / max(1, kt[k.replace("_ms", "_n")])
+                  for k in ("prep_ms", "mask_ms", "ntt_ms", "body_ms", "persist_ms")}
+    one = dict(kt, mask_ms=per_launch["mask_ms"], ntt_ms=per_launch["ntt_ms"],
+               persist_ms=per_launch["persist_ms"])
     is_ntt = rlwe.rlwe_weights_method(w.handle) == rlwe.RLWE_METHOD_NTT
     n_o = rlwe.rlwe_weights_rows_per_product(w.handle)
     roof, _ = roofline([dict(T=T, M=d_out, K=d_in, kept=kept, ntt=is_ntt, n_o=n_o)], one, N,
-                       len(primes),
+                       len(primes), peaks,
                        traffic={"mfma": None if ks else kernel_traffic("mask"),
                                 "alu": None if n_o != 1 else
                                 kernel_traffic("ntt_ks" if ks else "ntt")})
@@ -801,7 +908,7 @@ def main():
     if ks and kt["ksacc_n"]:
         ks_ms = {k: kt[f"ks{k}_ms"] / max(1, kt[f"ks{k}_n"]) * kt[f"ks{k}_n"] / args.steps
                  for k in ("dig", "acc", "fin")}  # per step (a step may hold several passes)
-        ks_roof = keyswitch_roofline(T * d_out, N, P, args.ks_levels, ks_ms["acc"] * 1e-3)
+        ks_roof = keyswitch_roofline(T * d_out, N, P, args.ks_levels, ks_ms["acc"] * 1e-3, peaks)
         ks_roof["traffic"] = kernel_traffic("ksacc")
         # the digit kernel reads the rounded masks (NTT method) or the raw residues
         read = 8 * N if is_ntt else P * 8 * (N + 1)
@@ -832,7 +939,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8",
+        "dtype": "u64 (54-bit RNS residues)",
         "data": "synthetic (seeded uniform int8 weights, uniform ciphertext residues)",
         "config": {"workload": cfg["name"], "d_in": d_in, "d_out": d_out, "tokens": T, "N": N,
                    "primes": len(primes), "log2_t": log2_t, "q_out": f"2^{qbits}",
@@ -845,8 +952,9 @@ def main():
                                  if ks else None)},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "kernels_ms": {"prep": per_launch["prep_ms"], "mask": per_launch["mask_ms"],
-                       "ntt": per_launch["ntt_ms"], "body": per_launch["body_ms"]},
-        "roofline": roof,
+                       "ntt": per_launch["ntt_ms"], "persistent": per_launch["persist_ms"],
+                       "body": per_launch["body_ms"]},
+        "roofline": roof, "peaks": peaks, "tuner": tuner_info,
         "cpu_baseline": None,
     }
     if pack_roof:
@@ -857,12 +965,15 @@ def main():
         result["kernels_ms"].update({"ks_digits": ks_ms["dig"], "ks_accum": ks_ms["acc"],
                                      "ks_finish": ks_ms["fin"]})
         # the dominant kernel of the step carries the headline roofline
-        if roof is None or ks_ms["acc"] > max(per_launch["ntt_ms"], per_launch["mask_ms"]):
+        if roof is None or ks_ms["acc"] > max(per_launch["ntt_ms"], per_launch["mask_ms"],
+                                              per_launch["persist_ms"]):
             result["roofline"], result["roofline_product"] = ks_roof, roof
         else:
             result["roofline_keyswitch"] = ks_roof
         key.close()
     w.close()
+    rlwe.rlwe_ctx_set_tuner(ctx.handle, None)
+    tuner.close()
     ctx.close()
     if args.cpu_seconds > 0:
         result["cpu_baseline"] = cpu_baseline(W, ct_np, N, primes, T, d_out, d_in,

@@ -456,6 +456,24 @@ int rlwe_autotune_product(rlwe_ctx* ctx, rlwe_tuner* t, uint32_t K, uint32_t M, 
 int rlwe_autotune_batch(rlwe_ctx* ctx, rlwe_tuner* t, const ct_matmul_desc* descs, uint32_t n,
                         uint32_t flags, rlwe_stream_t stream, rlwe_schedule* best);
 
+/* Peak rates measured on a device by register-only microbenchmarks (independent
+ * dependency chains, four waves per SIMD), the denominators of the roofline fractions:
+ *   mul32_lane_ops  32-bit multiplies (v_mul_lo_u32) per second, per lane
+ *   modmul          54-bit modular products per second (the product kernel's
+ *                   truncated-quotient Shoup product, below 4p for any 64-bit input)
+ *   butterfly       lazy Gentleman-Sande butterflies per second (the product kernel's
+ *                   inverse-transform butterfly: one Shoup product, a sum, a biased
+ *                   difference)
+ *   mfma_int8_ops   int8 matrix-core operations per second (v_mfma_i32_32x32x32_i8,
+ *                   two per multiply-add)
+ *   clock_mhz, compute_units  as the device reports them (maximum clock)
+ * Takes some milliseconds; allocates a scratch buffer; synchronises the device. */
+typedef struct rlwe_peaks {
+  double mul32_lane_ops, modmul, butterfly, mfma_int8_ops, clock_mhz;
+  uint32_t compute_units;
+} rlwe_peaks;
+int rlwe_measure_peaks(int hip_device, rlwe_peaks* out);
+
 /* Description of the last error on this thread ("" if none). */
 const char* rlwe_last_error(void);
 

@@ -84,10 +84,21 @@ def lib() -> ctypes.CDLL:
         L.orc_gadget.argtypes = [ctypes.c_uint32, _u64p, ctypes.c_uint32, ctypes.c_uint32, _u64p]
         L.orc_ksk_gen.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u64p, ctypes.c_uint32,
                                   ctypes.c_uint32, _i8p, _i8p, _u64p, _i64p, _u64p]
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_max_threads.restype = ctypes.c_int
         L.orc_keyswitch_pack.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _u64p, ctypes.c_uint32,
                                          ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _u64p,
                                          _u64p, ctypes.c_int, _u64p]
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (timing only)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def _p(a: np.ndarray, t):

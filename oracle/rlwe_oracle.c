@@ -11,6 +11,8 @@
  */
 #include "rlwe_oracle.h"
 
+#include <omp.h>
+
 #include <stdlib.h>
 #include <string.h>
 
@@ -636,3 +638,7 @@ void orc_keyswitch_pack(uint32_t N, uint32_t P, const uint64_t* primes, uint32_t
   }
   free(dg);
 }
+
+/* Threads the oracle's parallel loops use (timing on a chosen number of cores). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }

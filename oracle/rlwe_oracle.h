@@ -140,4 +140,8 @@ void orc_ksk_gen(uint32_t N, uint32_t P, const uint64_t* primes, uint32_t beta, 
 void orc_keyswitch_pack(uint32_t N, uint32_t P, const uint64_t* primes, uint32_t beta,
                         uint32_t ell, uint32_t M, uint32_t n_pack, const uint64_t* lwe,
                         const uint64_t* ksk, int mode, uint64_t* out);
+/* Threads of the parallel loops (timing only; results do not depend on it). */
+void orc_set_threads(int n);
+int orc_max_threads(void);
+
 #endif

@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librlwe.so")
 
 SOURCES = ["rlwe_host.hip", "k_prep.hip", "k_mask.hip", "k_ntt.hip", "k_keyswitch.hip",
-           "k_persist.hip"]
+           "k_persist.hip", "k_peaks.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1352,7 +1352,18 @@ int ct_matmul_pack(rlwe_ctx* ctx, const rlwe_weights* w, uint32_t transpose, con
 
 // ------------------------------------------------------------------ autotuning
 
+namespace rlwe {
+int measure_peaks(int hip_device, rlwe_peaks* out, const char** why);
+}
+
 extern "C" {
+
+int rlwe_measure_peaks(int hip_device, rlwe_peaks* out) {
+  if (!out) return fail(RLWE_EINVAL, "rlwe_measure_peaks: null argument");
+  const char* why = "";
+  const int r = measure_peaks(hip_device, out, &why);
+  return r == RLWE_OK ? ok() : fail(r, "rlwe_measure_peaks: %s", why);
+}
 
 int rlwe_tuner_create(const char* device_key, rlwe_tuner** out) {
   if (!device_key || !out) return fail(RLWE_EINVAL, "rlwe_tuner_create: null argument");

@@ -47,7 +47,7 @@ EXPORTS = ("rlwe_params_init", "rlwe_params_destroy", "rlwe_weights_load", "rlwe
            "rlwe_tuner_create", "rlwe_tuner_destroy", "rlwe_tuner_size", "rlwe_tune_key",
            "rlwe_tuner_put", "rlwe_tuner_get", "rlwe_tuner_lookup", "rlwe_tuner_save",
            "rlwe_tuner_load", "rlwe_device_key", "rlwe_ctx_set_tuner", "rlwe_autotune_product",
-           "rlwe_autotune_batch", "rlwe_last_error")
+           "rlwe_autotune_batch", "rlwe_measure_peaks", "rlwe_last_error")
 RLWE_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
@@ -82,6 +82,15 @@ class CtMatmulDesc(ctypes.Structure):
 class Schedule(ctypes.Structure):
     _fields_ = [("method", ctypes.c_uint32), ("tt_log2", ctypes.c_uint32),
                 ("order", ctypes.c_uint32), ("launch", ctypes.c_uint32), ("ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Peaks(ctypes.Structure):
+    _fields_ = [("mul32_lane_ops", ctypes.c_double), ("modmul", ctypes.c_double),
+                ("butterfly", ctypes.c_double), ("mfma_int8_ops", ctypes.c_double),
+                ("clock_mhz", ctypes.c_double), ("compute_units", ctypes.c_uint32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -164,6 +173,7 @@ def lib() -> ctypes.CDLL:
     L.rlwe_autotune_product.argtypes = [vp, vp, u32, u32, u32, u32, u32, vp, ctypes.POINTER(Schedule)]
     L.rlwe_autotune_batch.argtypes = [vp, vp, ctypes.POINTER(CtMatmulDesc), u32, u32, vp,
                                       ctypes.POINTER(Schedule)]
+    L.rlwe_measure_peaks.argtypes = [ctypes.c_int, ctypes.POINTER(Peaks)]
     L.rlwe_last_error.argtypes = []
     L.rlwe_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -428,6 +438,13 @@ def rlwe_autotune_batch(ctx: int, t: int, items, flags: int = RLWE_OUT_SWITCHED,
     s = Schedule()
     _check(lib().rlwe_autotune_batch(ctx, t, arr, len(items), flags, _stream(stream), ctypes.byref(s)))
     return s.as_dict()
+
+
+def rlwe_measure_peaks(device: int = 0) -> dict:
+    """Measured peak rates of the device (microbenchmarks in the library)."""
+    pk = Peaks()
+    _check(lib().rlwe_measure_peaks(device, ctypes.byref(pk)))
+    return pk.as_dict()
 
 
 def rlwe_profile_begin(ctx: int) -> None:
