@@ -81,7 +81,7 @@ int rlwe_params_destroy(rlwe_ctx* ctx);
 /* Flags of rlwe_weights_load */
 #define RLWE_W_FWD 1u       /* keep W for products W.[x] */
 #define RLWE_W_TRANSPOSE 2u /* keep W^T for products W^T.[g] (backward pass) */
-#define RLWE_W_NTT 4u       /* mask product by number-theoretic transforms (N = 4096 only) */
+#define RLWE_W_NTT 4u       /* mask product by number-theoretic transforms (N = 2048, 4096) */
 #define RLWE_W_TOEPLITZ 8u  /* mask product on the int8 matrix cores (digit planes) */
 #define RLWE_W_ROWPACK 16u  /* several rows per weight polynomial where K <= N/2 (NTT) */
 
@@ -95,15 +95,16 @@ int rlwe_params_destroy(rlwe_ctx* ctx);
  *           (symmetric quantization, Sec. 4.2); read during the call only
  *   flags   RLWE_W_FWD and/or RLWE_W_TRANSPOSE, plus at most one method flag:
  *           RLWE_W_NTT keeps the reversed blocks in the NTT domain per prime
- *           (rows * L * P * N * 8 bytes; RLWE_EPARAM unless N = 4096),
+ *           (rows * L * P * N * 8 bytes; RLWE_EPARAM unless N = 2048 or 4096),
  *           RLWE_W_TOEPLITZ keeps int8 only; without one, each orientation
- *           (N = 4096) takes the method a tuner attached to the context measured
+ *           (N = 2048, 4096) takes the method a tuner attached to the context measured
  *           fastest for its shape (rlwe_ctx_set_tuner), else the one with the
  *           smaller estimated time per output: matrix cores 8 + 0.0033 K dk ns (K
  *           the contraction length, dk the digit planes kept, rlwe_weights_digits),
  *           transforms (5 + 12.35 L) P ns (L = ceil(K / N) blocks, P primes),
- *           fitted to MI355X timings; at other N the matrix-core method.
- *           RLWE_W_ROWPACK (N = 4096, not with RLWE_W_TOEPLITZ): an orientation
+ *           both scaled by N / 4096, fitted to MI355X timings; at other N the
+ *           matrix-core method.
+ *           RLWE_W_ROWPACK (N = 2048, 4096; not with RLWE_W_TOEPLITZ): an orientation
  *           whose contraction length K is at most N/2 packs n_o = floor(N / K)
  *           rows into each weight polynomial, row g n_o + rho reversed in
  *           coefficients [rho K, rho K + K) (the coefficient packing of Sec.
@@ -135,7 +136,7 @@ int rlwe_weights_free(rlwe_weights* w);
  * product's tiles waiting on its own transforms; otherwise grouped launches (one per
  * step and kernel class) run. */
 #define RLWE_LAUNCH_PERSISTENT 8u /* require the persistent launch (RLWE_EINVAL if a
-                                     product uses the matrix cores) */
+                                     product uses the matrix cores, or N != 4096) */
 #define RLWE_LAUNCH_GROUPED 16u   /* grouped launches even where all products use NTT */
 
 /* The encrypted clear-weight product of Eq. (LWEdot) for `tokens` inputs.
@@ -442,9 +443,10 @@ int rlwe_ctx_set_tuner(rlwe_ctx* ctx, rlwe_tuner* t);
  *   tokens   token count of the calls tuned for, 1..65535
  *   oflags   RLWE_OUT_SWITCHED or RLWE_OUT_RAW_Q
  * Candidates: the matrix-core method (not with packed rows), and on the NTT method
- * (N = 4096) every tt_log2 with 1 << tt_log2 <= 16 and below 2 tokens, both orders, both
- * launches. Uses random weights and inputs in its own device memory (allocated and
- * freed here) and the context workspace; synchronises `stream`. */
+ * (N = 2048, 4096) every tt_log2 with 1 << tt_log2 <= 16 and below 2 tokens, both
+ * orders, and both launches at N = 4096. Uses random weights and inputs in its own
+ * device memory (allocated and freed here) and the context workspace; synchronises
+ * `stream`. */
 int rlwe_autotune_product(rlwe_ctx* ctx, rlwe_tuner* t, uint32_t K, uint32_t M, uint32_t wflags,
                           uint32_t tokens, uint32_t oflags, rlwe_stream_t stream,
                           rlwe_schedule* best);

@@ -398,22 +398,6 @@ __global__ void __launch_bounds__(kThreads) ksk_fwd_kernel(KsArgs) {
 namespace {
 constexpr int kGenThreads = 256;
 
-// Cooley-Tukey, natural -> bit-reversed order, in place in LDS; inputs and outputs
-// below 4p. Ends with a barrier.
-__device__ void gen_forward(uint64_t* x, uint32_t N, const uint64_t* tw, uint64_t p) {
-  for (uint32_t t = N / 2; t >= 1; t >>= 1) {
-    __syncthreads();
-    for (uint32_t j = threadIdx.x; j < N / 2; j += kGenThreads) {
-      const uint32_t pos = (j / t) * 2 * t + (j % t);
-      uint64_t X = x[pos], Y = x[pos + t];
-      ct_bfly(X, Y, ld_tw(tw, N / (2 * t) + pos / (2 * t)), p);
-      x[pos] = X;
-      x[pos + t] = Y;
-    }
-  }
-  __syncthreads();
-}
-
 // Gentleman-Sande, bit-reversed -> natural order, without the factor 1/N, in place
 // in LDS; inputs and outputs below 2p. Ends with a barrier.
 __device__ void gen_inverse(uint64_t* x, uint32_t N, const uint64_t* tw, uint64_t p) {
@@ -445,7 +429,7 @@ __global__ void __launch_bounds__(kGenThreads) ksk_fwd_generic(KsArgs) {
   const uint64_t p = a->rc.q[r];
   const uint64_t* src = a->ksk_in + (size_t)loc * N;
   for (uint32_t n = threadIdx.x; n < N; n += kGenThreads) x[n] = src[n];
-  gen_forward(x, N, a->ntt.fwd[r], p);
+  gen_forward(x, N, a->ntt.fwd[r], p, kGenThreads);
   uint64_t* dst = a->khat_out + (((size_t)im * P + r) * 2 + c) * N * 2;
   const uint64_t r1 = a->ntt.rq[r][0], r0 = a->ntt.rq[r][1];
   for (uint32_t n = threadIdx.x; n < N; n += kGenThreads) {
@@ -485,7 +469,7 @@ __global__ void __launch_bounds__(kGenThreads) ks_accum_generic(KsArgs) {
         const int64_t v = dsrc[n];
         x[n] = v < 0 ? (uint64_t)(v + (int64_t)p) : (uint64_t)v;
       }
-      gen_forward(x, N, tw, p);
+      gen_forward(x, N, tw, p, kGenThreads);
       const uint64_t* kh = a->khat + (((size_t)i * ell + m) * P + r) * 4 * N;
 #pragma unroll
       for (int e = 0; e < 16; ++e) {

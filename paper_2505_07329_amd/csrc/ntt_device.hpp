@@ -1,6 +1,7 @@
-// Device helpers of the number-theoretic transforms (N = 4096): modular products,
-// butterflies, register layouts and LDS exchanges of the forward and inverse
-// transforms. Shared by the product kernels and the KeySwitch packing kernels.
+// Device helpers of the number-theoretic transforms (N = 4096, and N = 2048 for the
+// inverse of the product): modular products, butterflies, register layouts and LDS
+// exchanges of the forward and inverse transforms. Shared by the product kernels and
+// the KeySwitch packing kernels.
 //
 // Transforms used by the mask part of Eq. (LWEdot), for N = 4096.
 //
@@ -127,11 +128,12 @@ __device__ __forceinline__ void gs_bfly(uint64_t& X, uint64_t& Y, const Tw& t, u
 }
 
 // Storage index of bit-reversed position pos in the lane-major layout of operands
-// read by the 512-thread kernels, whose thread t holds positions 8 t .. 8 t + 7
-// (layout Q1): position 8 t + k is stored at k 512 + t, so each of a wave's loads
-// of one k covers consecutive words.
+// read by the NN / 8-thread kernels (512 threads at N = 4096), whose thread t holds
+// positions 8 t .. 8 t + 7 (layout Q1): position 8 t + k is stored at k NN / 8 + t,
+// so each of a wave's loads of one k covers consecutive words.
+template <int NN = kNttN>
 __host__ __device__ __forceinline__ uint32_t lane_major(uint32_t pos) {
-  return (pos % 8) * 512 + pos / 8;
+  return (pos % 8) * (NN / 8) + pos / 8;
 }
 __device__ __forceinline__ uint32_t pad(uint32_t pos) { return pos + pos / 16; }
 
@@ -201,15 +203,22 @@ __device__ __forceinline__ void ntt_forward(uint64_t* x, uint64_t* lds, const ui
 // one in which it took a product (k's highest set bit), so at the end elements
 // 0, 1 are below 64p, 16p and the rest below 8p. END brings elements 0, 1 below
 // 3p, so the next pass again starts below 8p.
-template <int PASS>
+template <int PASS, int NN = kNttN>
 struct InvLayout {
-  static constexpr int S = PASS == 0 ? 1 : PASS == 1 ? 8 : PASS == 2 ? 64 : 512;  // stride in k
+  static constexpr int S = PASS == 0 ? 1 : PASS == 1 ? 8 : PASS == 2 ? 64 : NN / 8;  // stride in k
   __device__ static uint32_t base(int tid) {
     return PASS == 0   ? 8 * tid
            : PASS == 1 ? 64 * (tid >> 3) + (tid & 7)
            : PASS == 2 ? 512 * (tid >> 6) + (tid & 63)
                        : tid;
   }
+};
+// Sizes of the inverse transforms of ring degree NN: NN / 8 threads, and the words of
+// one prime's exchange buffer (blocks of 576 words per 512 positions).
+template <int NN>
+struct InvSize {
+  static constexpr int kThreads = NN / 8;
+  static constexpr int kLds = NN + NN / 8;
 };
 // Exchange buffer addresses (8-byte words) of position pos in exchange EX (1:
 // Q1 -> Q2, 2: Q2 -> Q3, 3: Q3 -> Q4). 64-bit LDS accesses are served 32 lanes at
@@ -235,31 +244,37 @@ __device__ __forceinline__ uint32_t xaddr(uint32_t pos) {
 // give (512 w + 64 k) / (2t) for t >= 64, since l never carries; those are read with
 // scalar loads, the others per lane.
 typedef const __attribute__((address_space(4))) uint64_t* TwScalarPtr;
-template <int PASS>
+template <int PASS, int NN = kNttN>
 __device__ __forceinline__ Tw tw512(const uint64_t* tw, uint32_t t, int k, int tid) {
   if (PASS >= 2) {
+    // positions tid + (NN / 8) k in Q4 with t >= NN / 8 (tid < NN / 8 never carries)
     const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane(tid) >> 6;
-    const uint32_t upos = PASS == 3 ? 512u * k : 512u * wave + 64u * k;
-    const uint32_t idx = kN / (2 * t) + upos / (2 * t);
+    const uint32_t upos = PASS == 3 ? (uint32_t)(NN / 8) * k : 512u * wave + 64u * k;
+    const uint32_t idx = NN / (2 * t) + upos / (2 * t);
     return Tw{((TwScalarPtr)tw)[2 * idx], ((TwScalarPtr)tw)[2 * idx + 1]};
   }
-  return ld_tw(tw, kN / (2 * t) + (InvLayout<PASS>::base(tid) + InvLayout<PASS>::S * k) / (2 * t));
+  return ld_tw(tw, NN / (2 * t) +
+                       (InvLayout<PASS, NN>::base(tid) + InvLayout<PASS, NN>::S * k) / (2 * t));
 }
 
-template <int NP, int PASS, bool END>
+// At N = 2048 (S = 256 in Q4) the last pass has only the spans 512 and 1024: its
+// stage of span 256 was Q3's last, and is skipped (the bound of a skipped stage's
+// successor is then larger than needed, which only widens the biased differences).
+template <int NP, int PASS, bool END, int NN = kNttN>
 __device__ __forceinline__ void inv_pass(uint64_t (&x)[NP][8], int tid,
                                          const uint64_t* const (&tw)[NP], const InvMod (&md)[NP]) {
-  constexpr int S = InvLayout<PASS>::S;
+  constexpr int S = InvLayout<PASS, NN>::S;
 #pragma unroll
   for (int st = 0; st < 3; ++st) {
     const int sp = 1 << st;
     const uint32_t t = S * sp;
+    if (PASS == 3 && t <= 256) continue;  // done in Q3 (N = 2048)
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       if (k & sp) continue;
 #pragma unroll
       for (int r = 0; r < NP; ++r)
-        gs_bfly(x[r][k], x[r][k + sp], tw512<PASS>(tw[r], t, k, tid), md[r].p8 << st, md[r].pn);
+        gs_bfly(x[r][k], x[r][k + sp], tw512<PASS, NN>(tw[r], t, k, tid), md[r].p8 << st, md[r].pn);
     }
   }
   if (END) {
@@ -269,21 +284,23 @@ __device__ __forceinline__ void inv_pass(uint64_t (&x)[NP][8], int tid,
       for (int k = 0; k < 2; ++k) x[r][k] = reduce_barrett(x[r][k], md[r]);
   }
 }
-template <int NP, int PASS, int EX>
+template <int NP, int PASS, int EX, int NN = kNttN>
 __device__ __forceinline__ void inv_store(uint64_t* lds, const uint64_t (&x)[NP][8], int tid) {
-  const uint32_t base = InvLayout<PASS>::base(tid);
+  const uint32_t base = InvLayout<PASS, NN>::base(tid);
 #pragma unroll
   for (int r = 0; r < NP; ++r)
 #pragma unroll
-    for (int k = 0; k < 8; ++k) lds[r * kInvLdsWords + xaddr<EX>(base + InvLayout<PASS>::S * k)] = x[r][k];
+    for (int k = 0; k < 8; ++k)
+      lds[r * InvSize<NN>::kLds + xaddr<EX>(base + InvLayout<PASS, NN>::S * k)] = x[r][k];
 }
-template <int NP, int PASS, int EX>
+template <int NP, int PASS, int EX, int NN = kNttN>
 __device__ __forceinline__ void inv_load(const uint64_t* lds, uint64_t (&x)[NP][8], int tid) {
-  const uint32_t base = InvLayout<PASS>::base(tid);
+  const uint32_t base = InvLayout<PASS, NN>::base(tid);
 #pragma unroll
   for (int r = 0; r < NP; ++r)
 #pragma unroll
-    for (int k = 0; k < 8; ++k) x[r][k] = lds[r * kInvLdsWords + xaddr<EX>(base + InvLayout<PASS>::S * k)];
+    for (int k = 0; k < 8; ++k)
+      x[r][k] = lds[r * InvSize<NN>::kLds + xaddr<EX>(base + InvLayout<PASS, NN>::S * k)];
 }
 // Orders a wave's LDS stores before its following loads (the exchange partners
 // are lanes of the same wave; the LDS serves one wave's operations in order).
@@ -296,26 +313,47 @@ __device__ __forceinline__ void wave_exchange_fence() {
 // Inverse transforms of NP primes without the 1/N factor: x[r] in layout Q1,
 // bit-reversed order, below 8p_r -> layout Q4, natural order, congruent to the
 // result mod p_r (below 64p_r, not reduced). lds holds NP exchange buffers.
-template <int NP>
+template <int NP, int NN = kNttN>
 __device__ __forceinline__ void ntt_inverse(uint64_t (&x)[NP][8], uint64_t* lds,
                                             const uint64_t* const (&tw)[NP],
                                             const InvMod (&md)[NP], int tid) {
-  inv_pass<NP, 0, true>(x, tid, tw, md);
+  inv_pass<NP, 0, true, NN>(x, tid, tw, md);
   __syncthreads();  // no wave still reads the previous transform's Q4 positions
-  inv_store<NP, 0, 1>(lds, x, tid);
+  inv_store<NP, 0, 1, NN>(lds, x, tid);
   wave_exchange_fence();
-  inv_load<NP, 1, 1>(lds, x, tid);
-  inv_pass<NP, 1, true>(x, tid, tw, md);
+  inv_load<NP, 1, 1, NN>(lds, x, tid);
+  inv_pass<NP, 1, true, NN>(x, tid, tw, md);
   wave_exchange_fence();  // every lane of the wave has read its Q2 positions
-  inv_store<NP, 1, 2>(lds, x, tid);
+  inv_store<NP, 1, 2, NN>(lds, x, tid);
   wave_exchange_fence();
-  inv_load<NP, 2, 2>(lds, x, tid);
-  inv_pass<NP, 2, true>(x, tid, tw, md);
+  inv_load<NP, 2, 2, NN>(lds, x, tid);
+  inv_pass<NP, 2, true, NN>(x, tid, tw, md);
   __syncthreads();  // every wave is done with its own block
-  inv_store<NP, 2, 3>(lds, x, tid);
+  inv_store<NP, 2, 3, NN>(lds, x, tid);
   __syncthreads();
-  inv_load<NP, 3, 3>(lds, x, tid);
-  inv_pass<NP, 3, false>(x, tid, tw, md);
+  inv_load<NP, 3, 3, NN>(lds, x, tid);
+  inv_pass<NP, 3, false, NN>(x, tid, tw, md);
+}
+
+// Plain radix-2 transforms in LDS for any ring degree N <= kNttN (one stage per
+// barrier, exact Shoup products): the forward transforms of small rings. nthreads
+// threads (threadIdx.x < nthreads) take part; all threads of the block meet the
+// barriers.
+// Cooley-Tukey, natural -> bit-reversed order, in place in LDS; inputs and outputs
+// below 4p. Ends with a barrier.
+__device__ inline void gen_forward(uint64_t* x, uint32_t N, const uint64_t* tw, uint64_t p,
+                                   uint32_t nthreads) {
+  for (uint32_t t = N / 2; t >= 1; t >>= 1) {
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < N / 2; j += nthreads) {
+      const uint32_t pos = (j / t) * 2 * t + (j % t);
+      uint64_t X = x[pos], Y = x[pos + t];
+      ct_bfly(X, Y, ld_tw(tw, N / (2 * t) + pos / (2 * t)), p);
+      x[pos] = X;
+      x[pos + t] = Y;
+    }
+  }
+  __syncthreads();
 }
 
 }  // namespace

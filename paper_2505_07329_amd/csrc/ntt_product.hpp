@@ -75,13 +75,41 @@ __device__ __forceinline__ void mask_forward(BatchPtr bt, uint32_t ii, uint32_t 
   }
 }
 
+// NTT of one mask at a ring degree NN below kNttN: the plain radix-2 transform on
+// nthreads threads (all threads of the block meet its barriers), lds of NN words;
+// loc = (t L + i) P + p as above, stored lane-major for the NN / 8-thread product.
+template <int NN>
+__device__ __forceinline__ void mask_forward_small(BatchPtr bt, uint32_t ii, uint32_t loc,
+                                                   uint64_t* lds, uint32_t nthreads) {
+  const uint32_t P = bt->rc.P;
+  const uint32_t p_idx = loc % P, ti = loc / P;
+  const uint64_t p = bt->rc.q[p_idx];
+  const bool seeded = bt->seeded != 0;
+  const uint64_t* blk_in = bt->it[ii].ct + ti * ct_block_words(P, NN, seeded);
+  const uint64_t seed = seeded ? blk_in[0] : 0;
+  for (uint32_t n = threadIdx.x; n < (uint32_t)NN; n += nthreads)
+    lds[n] = seeded ? seeded_mask(seed, NN, p_idx, n, p) : blk_in[(size_t)p_idx * NN + n];
+  gen_forward(lds, NN, bt->ntt.fwd[p_idx], p, nthreads);
+  uint64_t* dst = bt->it[ii].ahat + 2 * (size_t)loc * NN;
+  const uint64_t r1 = bt->ntt.rq[p_idx][0], r0 = bt->ntt.rq[p_idx][1];
+  for (uint32_t n = threadIdx.x; n < (uint32_t)NN; n += nthreads) {  // n: bit-reversed position
+    const uint64_t v = reduce4(lds[n], p);
+    uint64_t c = v * r1 + __umul64hi(v, r0);
+    c += (0 - c * p) >= p ? 1 : 0;
+    const uint32_t at = 2 * lane_major<NN>(n);
+    dst[at] = v;
+    dst[at + 1] = c;
+  }
+}
+
 // One tile of the product: weight polynomial j (a row, or a group of n_o packed rows)
 // of item ii and the tokens of one token tile, on kInvThreads threads; the NP = P
 // primes of a token are transformed together. LC = 2: the item has exactly two input
 // blocks; LC = 0: any number. OUT: 0 switched to 2^qbits (u32), 1 raw residues (u64
 // per prime), 2 masks rounded to 2^K for the gadget decomposition (u64, bodies written
-// by the body kernel). loc is the tile's index within the item (product_tile).
-template <int OUT, int NP, int LC>
+// by the body kernel). loc is the tile's index within the item (product_tile). NN: the
+// ring degree (4096, or 2048 on 256 threads); lds holds NP * InvSize<NN>::kLds words.
+template <int OUT, int NP, int LC, int NN = kNttN>
 __device__ __forceinline__ void ntt_product(BatchPtr bt, uint32_t ii, uint32_t loc, uint64_t* lds) {
   static_assert(LC == 0 || LC == 2, "block classes: exactly two, or any");
   const uint32_t L = bt->it[ii].m.L, rows = bt->it[ii].m.rows;
@@ -121,15 +149,15 @@ __device__ __forceinline__ void ntt_product(BatchPtr bt, uint32_t ii, uint32_t l
         uint64_t wv[NP][8], av[NP][16];
 #pragma unroll
         for (int r = 0; r < NP; ++r) {
-          // lane-major operands: position 8 tid + k at k 512 + tid
-          const uint64_t* a = ahat + 2 * ((((size_t)t * NB + i) * NP + r) * kN + tid);
-          const uint64_t* w = what + (((size_t)j * NB + i) * NP + r) * kN + tid;
+          // lane-major operands: position 8 tid + k at k NN / 8 + tid
+          const uint64_t* a = ahat + 2 * ((((size_t)t * NB + i) * NP + r) * NN + tid);
+          const uint64_t* w = what + (((size_t)j * NB + i) * NP + r) * NN + tid;
 #pragma unroll
-          for (int k = 0; k < 8; ++k) wv[r][k] = w[512 * k];
+          for (int k = 0; k < 8; ++k) wv[r][k] = w[(NN / 8) * k];
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
-            av[r][2 * k] = a[1024 * k];
-            av[r][2 * k + 1] = a[1024 * k + 1];
+            av[r][2 * k] = a[(NN / 4) * k];
+            av[r][2 * k + 1] = a[(NN / 4) * k + 1];
           }
         }
 #pragma unroll
@@ -146,23 +174,23 @@ __device__ __forceinline__ void ntt_product(BatchPtr bt, uint32_t ii, uint32_t l
 #pragma unroll
         for (int k = 0; k < 8; ++k) x[r][k] = 0;
         for (uint32_t i = 0; i < L; ++i) {  // positions 8 tid + k (layout Q1)
-          const uint64_t* a = ahat + 2 * ((((size_t)t * L + i) * NP + r) * kN + tid);
-          const uint64_t* w = what + (((size_t)j * L + i) * NP + r) * kN + tid;
+          const uint64_t* a = ahat + 2 * ((((size_t)t * L + i) * NP + r) * NN + tid);
+          const uint64_t* w = what + (((size_t)j * L + i) * NP + r) * NN + tid;
           if (L <= 2) {
 #pragma unroll
             for (int k = 0; k < 8; ++k)
-              x[r][k] += mul_shoup4(w[512 * k], a[1024 * k], a[1024 * k + 1], md[r].pn);
+              x[r][k] += mul_shoup4(w[(NN / 8) * k], a[(NN / 4) * k], a[(NN / 4) * k + 1], md[r].pn);
           } else {
 #pragma unroll
             for (int k = 0; k < 8; ++k)
               x[r][k] = reduce_barrett(
-                  x[r][k] + mul_shoup4(w[512 * k], a[1024 * k], a[1024 * k + 1], md[r].pn), md[r]);
+                  x[r][k] + mul_shoup4(w[(NN / 8) * k], a[(NN / 4) * k], a[(NN / 4) * k + 1], md[r].pn), md[r]);
           }
         }
       }
     }
-    ntt_inverse<NP>(x, lds, tw, md, tid);
-    // Coefficient m = tid + 512 k of C (layout Q4). Row rho of the group (row
+    ntt_inverse<NP, NN>(x, lds, tw, md, tid);
+    // Coefficient m = tid + (NN / 8) k of C (layout Q4). Row rho of the group (row
     // j n_o + rho) is SampleExtract at h = (rho + 1) slot - 1 (Sec. 3.2): a'[n] =
     // C[h - n] for n <= h, -C[N + h - n] otherwise, so C[m] lands at n = h - m, or
     // negated at n = h - m + N. Unpacked rows: n_o = 1, slot = N, h = N - 1.
@@ -198,14 +226,14 @@ __device__ __forceinline__ void ntt_product(BatchPtr bt, uint32_t ii, uint32_t l
       const uint64_t km = bt->kmask;
       for (uint32_t rho = 0; rho < n_o && j * n_o + rho < rows; ++rho) {
         const uint32_t h = (rho + 1) * slot - 1;
-        uint64_t* o = (uint64_t*)out + ((size_t)t * rows + j * n_o + rho) * (kN + NP);
+        uint64_t* o = (uint64_t*)out + ((size_t)t * rows + j * n_o + rho) * (NN + NP);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-          const uint32_t m = tid + 512 * k;
+          const uint32_t m = tid + (NN / 8) * k;
           if (m <= h)
             o[h - m] = av[k] & km;
           else
-            o[h + kN - m] = (0 - av[k]) & km;
+            o[h + NN - m] = (0 - av[k]) & km;
         }
       }
     } else if (OUT == 1) {
@@ -220,15 +248,15 @@ __device__ __forceinline__ void ntt_product(BatchPtr bt, uint32_t ii, uint32_t l
         const uint32_t h = (rho + 1) * slot - 1;
 #pragma unroll
         for (int r = 0; r < NP; ++r) {
-          uint64_t* o = (uint64_t*)out + ((size_t)t * rows + j * n_o + rho) * NP * (kN + 1) +
-                        r * (kN + 1);
+          uint64_t* o = (uint64_t*)out + ((size_t)t * rows + j * n_o + rho) * NP * (NN + 1) +
+                        r * (NN + 1);
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
-            const uint32_t m = tid + 512 * k;
+            const uint32_t m = tid + (NN / 8) * k;
             if (m <= h)
               o[h - m] = c[r][k];
             else
-              o[h + kN - m] = c[r][k] ? p[r] - c[r][k] : 0;
+              o[h + NN - m] = c[r][k] ? p[r] - c[r][k] : 0;
           }
         }
       }
@@ -278,14 +306,14 @@ __device__ __forceinline__ void ntt_product(BatchPtr bt, uint32_t ii, uint32_t l
       const uint32_t qmask = qout_mask(qbits);
       for (uint32_t rho = 0; rho < n_o && j * n_o + rho < rows; ++rho) {
         const uint32_t h = (rho + 1) * slot - 1;
-        uint32_t* o = (uint32_t*)out + ((size_t)t * rows + j * n_o + rho) * (kN + 1);
+        uint32_t* o = (uint32_t*)out + ((size_t)t * rows + j * n_o + rho) * (NN + 1);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-          const uint32_t m = tid + 512 * k;
+          const uint32_t m = tid + (NN / 8) * k;
           if (m <= h)
             o[h - m] = res[k];
           else
-            o[h + kN - m] = (0u - res[k]) & qmask;
+            o[h + NN - m] = (0u - res[k]) & qmask;
         }
       }
     }

@@ -337,7 +337,8 @@ int build_ntt(rlwe_ctx* ctx) {
     ctx->ntt.fwd[pi] = ctx->ntt_tables + (2 * pi) * per;
     ctx->ntt.inv[pi] = ctx->ntt_tables + (2 * pi + 1) * per;
   }
-  ctx->ntt_ok = N == kNttN;  // the tuned transforms of the product are written for N = 4096
+  // the product's inverse transforms are written for N = 4096 and N = 2048
+  ctx->ntt_ok = N == kNttN || N == kNttN / 2;
   ctx->tw_ok = true;
   return RLWE_OK;
 }
@@ -588,14 +589,15 @@ static int load_mat(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32_t
     uint32_t tuned;
     if (ctx->tuner && tune::find_method(ctx->tuner->cache, rc.N, rc.P, a.k, a.rows, &tuned)) {
       m.ntt = tuned == RLWE_METHOD_NTT;
-    } else {
-      const double mfma_ns = 8.0 + 0.0033 * (double)a.k * m.sc.dk;
-      const double ntt_ns = (5.0 + 12.35 * a.L) * rc.P;
+    } else {  // both costs scale about linearly with N
+      const double scale = (double)rc.N / kNttN;
+      const double mfma_ns = (8.0 + 0.0033 * (double)a.k * m.sc.dk) * scale;
+      const double ntt_ns = (5.0 + 12.35 * a.L) * rc.P * scale;
       m.ntt = ntt_ns < mfma_ns;
     }
   }
   if (m.ntt) {
-    if (!ctx->ntt_ok) return fail(RLWE_EPARAM, "the NTT method needs N = %u", kNttN);
+    if (!ctx->ntt_ok) return fail(RLWE_EPARAM, "the NTT method needs N = %u or %u", kNttN / 2, kNttN);
     const size_t groups = (a.rows + a.n_o - 1) / a.n_o;
     const size_t bytes = groups * a.L * rc.P * rc.N * 8;
     e = hipMalloc(&m.what, bytes);
@@ -618,8 +620,8 @@ int rlwe_weights_load(rlwe_ctx* ctx, const int8_t* W_dev, uint32_t d_out, uint32
       ((flags & RLWE_W_ROWPACK) && (flags & RLWE_W_TOEPLITZ)))
     return fail(RLWE_EINVAL, "rlwe_weights_load: flags 0x%x invalid", flags);
   if ((flags & (RLWE_W_NTT | RLWE_W_ROWPACK)) && !ctx->ntt_ok)
-    return fail(RLWE_EPARAM, "RLWE_W_NTT and RLWE_W_ROWPACK need N = %u (N = %u)", kNttN,
-                ctx->rc.N);
+    return fail(RLWE_EPARAM, "RLWE_W_NTT and RLWE_W_ROWPACK need N = %u or %u (N = %u)",
+                kNttN / 2, kNttN, ctx->rc.N);
   const int method = (flags & RLWE_W_NTT) ? 1 : (flags & RLWE_W_TOEPLITZ) ? 2 : 0;
   if (d_out < 1 || d_in < 1 || d_out > 65536 || d_in > 65536)
     return fail(RLWE_ESHAPE, "d_out = %u, d_in = %u must lie in [1, 65536]", d_out, d_in);
@@ -821,7 +823,7 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
   // the rounded-mask output of ct_matmul_pack).
   bool all_ntt = true;
   for (uint32_t x = 0; x < cnt; ++x) all_ntt = all_ntt && all.it[x].method == 1;
-  const bool persist = sync && all_ntt && !gk && want_persist;
+  const bool persist = sync && all_ntt && !gk && want_persist && rc.N == kNttN;
   if (persist) {
     all.sync = sync;
     for (uint32_t x = 0; x < cnt; ++x) {
@@ -838,7 +840,8 @@ static int run_batch(rlwe_ctx* ctx, const ct_matmul_desc* d, uint32_t n, uint32_
     return RLWE_OK;
   }
   if (flags & RLWE_LAUNCH_PERSISTENT)
-    return fail(RLWE_EINVAL, "RLWE_LAUNCH_PERSISTENT needs every product on the NTT method");
+    return fail(RLWE_EINVAL,
+                "RLWE_LAUNCH_PERSISTENT needs every product on the NTT method and N = %u", kNttN);
   hipError_t e = timed(pc, K_PREP, s, [&] { return launch_prep(all, s); });
   if (e != hipSuccess) return hip_fail(e, "prep kernel");
   if (all.fwd_start[cnt]) {
@@ -1284,7 +1287,8 @@ static size_t matmul_pack_ws(const rlwe_ctx* ctx, const Mat& m, uint32_t tokens,
                              size_t* off_ks) {
   const RingConst& rc = ctx->rc;
   const size_t M = (size_t)tokens * m.args.rows;
-  const size_t inter = M * (m.ntt ? rc.N + rc.P : (size_t)rc.P * (rc.N + 1)) * 8;
+  const bool gadget = m.ntt && rc.N == kNttN;  // the product rounds the masks itself
+  const size_t inter = M * (gadget ? rc.N + rc.P : (size_t)rc.P * (rc.N + 1)) * 8;
   *off_inter = align_up(ws_item(rc, m.args, tokens, m.ntt), 256);
   *off_ks = *off_inter + align_up(inter, 256);
   return *off_ks + ks_ws_bytes(ctx, k, M, n_pack);
@@ -1337,13 +1341,14 @@ int ct_matmul_pack(rlwe_ctx* ctx, const rlwe_weights* w, uint32_t transpose, con
   }
   unsigned char* ws = (unsigned char*)ctx->ws;
   d.out = ws + off_inter;
-  // NTT method: the product rounds the masks for the key's decomposition; otherwise
-  // it writes raw residues and the digit kernel rounds them
-  const uint32_t pflags = (flags & (RLWE_OUT_FORCE_EXACT | RLWE_IN_SEEDED)) | (m->ntt ? 0 : RLWE_OUT_RAW_Q);
-  r = run_batch(ctx, &d, 1, pflags | RLWE_LAUNCH_GROUPED, s, ws, nullptr, m->ntt ? k : nullptr);
+  // NTT method at N = 4096: the product rounds the masks for the key's decomposition;
+  // otherwise it writes raw residues and the digit kernel rounds them
+  const bool gadget = m->ntt && ctx->rc.N == kNttN;
+  const uint32_t pflags = (flags & (RLWE_OUT_FORCE_EXACT | RLWE_IN_SEEDED)) | (gadget ? 0 : RLWE_OUT_RAW_Q);
+  r = run_batch(ctx, &d, 1, pflags | RLWE_LAUNCH_GROUPED, s, ws, nullptr, gadget ? k : nullptr);
   if (r != RLWE_OK) return r;
   r = ks_run(ctx, k, (const uint64_t*)(ws + off_inter), M, n_pack, out, flags & RLWE_OUT_RAW_Q,
-             m->ntt, ws + off_ks, s);
+             gadget, ws + off_ks, s);
   if (r != RLWE_OK) return r;
   return ok();
 }
@@ -1554,7 +1559,7 @@ int rlwe_autotune_product(rlwe_ctx* ctx, rlwe_tuner* t, uint32_t K, uint32_t M, 
     for (uint32_t tl = 0; tl <= 4; ++tl) {
       if (tl > 0 && (1u << tl) >= 2 * tokens) break;
       for (uint32_t order = 0; order < 2; ++order)
-        for (uint32_t launch = 0; launch < 2; ++launch)
+        for (uint32_t launch = 0; launch < (rc.N == kNttN ? 2u : 1u); ++launch)
           cands.push_back(rlwe_schedule{RLWE_METHOD_NTT, tl, order, launch, 0.f});
     }
   rlwe_schedule pick{};
@@ -1613,6 +1618,7 @@ int rlwe_autotune_batch(rlwe_ctx* ctx, rlwe_tuner* t, const ct_matmul_desc* desc
   hipStream_t s = (hipStream_t)stream;
   auto run = [&](uint32_t launch) { return ct_matmul_batch(ctx, descs, n, flags | launch, stream); };
   const float g = time_calls(s, [&] { return run(RLWE_LAUNCH_GROUPED); }, 3);
+  all_ntt = all_ntt && ctx->rc.N == kNttN;  // the persistent launch is written for N = 4096
   const float p = all_ntt ? time_calls(s, [&] { return run(RLWE_LAUNCH_PERSISTENT); }, 3) : -1.f;
   if (g < 0.f || (all_ntt && p < 0.f))
     return g_err.empty() ? fail(RLWE_EHIP, "rlwe_autotune_batch: timing failed") : RLWE_EHIP;

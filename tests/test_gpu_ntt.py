@@ -121,12 +121,12 @@ def test_default_method_and_errors():
     with pytest.raises(r.RlweError):
         r.Weights(ctx, dev(W2), r.RLWE_W_FWD | r.RLWE_W_NTT | r.RLWE_W_TOEPLITZ)
     ctx.close()
-    ctx2 = r.Context(2048, synth.PRIMES_2048, 28)
+    ctx2 = r.Context(1024, synth.PRIMES_2048, 28)
     with pytest.raises(r.RlweError) as ei:
         r.Weights(ctx2, dev(W2[:, :512]), r.RLWE_W_FWD | r.RLWE_W_NTT)
     assert ei.value.code == r.RLWE_EPARAM
     w3 = r.Weights(ctx2, dev(synth.int8_uniform(g, (8, 5000))))
-    assert r.rlwe_weights_method(w3.handle) == r.RLWE_METHOD_TOEPLITZ  # NTT needs N = 4096
+    assert r.rlwe_weights_method(w3.handle) == r.RLWE_METHOD_TOEPLITZ  # NTT needs N = 2048, 4096
     w3.close()
     ctx2.close()
 

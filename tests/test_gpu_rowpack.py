@@ -123,7 +123,7 @@ def test_rowpack_flag_validation():
         r.Weights(ctx, W, r.RLWE_W_FWD | r.RLWE_W_ROWPACK | r.RLWE_W_TOEPLITZ)
     assert e.value.code == r.RLWE_EINVAL
     ctx.close()
-    ctx2 = r.Context(2048, synth.PRIMES_2048, 24)
+    ctx2 = r.Context(1024, synth.PRIMES_2048, 24)  # packed rows need the NTT method: N = 2048, 4096
     with pytest.raises(r.RlweError) as e:
         r.Weights(ctx2, W, r.RLWE_W_FWD | r.RLWE_W_ROWPACK)
     assert e.value.code == r.RLWE_EPARAM
