@@ -143,9 +143,9 @@ KERNEL_TRAFFIC = {
     "mask": {"sources": ["k_mask.hip"], "fetch_bytes": 4382214101, "write_bytes": 4766672373,
              "sha256": "37b3392ace8226fcd057a2f461259544933971d70c4ba84b554979c7875ac123"},
     "ntt": {"sources": ["k_ntt.hip", "ntt_product.hpp", "ntt_device.hpp", "ks_round.hpp"],
-            "fetch_bytes": 5235399093,
-            "write_bytes": 4353409833,
-            "sha256": "54bbd23bc851573e643c2b930121939d417596e893ad87097cd9f620a7f47c1c"},
+            "fetch_bytes": 5271064556,
+            "write_bytes": 4354464267,
+            "sha256": "bc9a037db00f4e0025010260585fe77adb165f398aac7906030046d2690056e3"},
     # the product with masks rounded for KeySwitch packing (ct_matmul_pack, --keyswitch)
     "ntt_ks": {"sources": ["k_ntt.hip", "ntt_product.hpp", "ntt_device.hpp", "ks_round.hpp"],
                "fetch_bytes": 6243685734, "write_bytes": 8676000492,
@@ -287,13 +287,14 @@ def parse():
                     help="attn: before the timed region, run one plain elementwise copy kernel "
                          "(int32 bitwise not) reading and writing GIB GiB each, as the known-size "
                          "reference for the FETCH_SIZE / WRITE_SIZE counters")
-    ap.add_argument("--workload", choices=["attn", "layer", "mlp", "serve"], default="serve",
+    ap.add_argument("--workload", choices=["attn", "layer", "mlp", "serve", "table4"], default="serve",
                     help="serve (default): Poisson requests from 16 clients over a resident "
                          "16-layer model, vs plain per-call kernels, p50/p99; "
                          "attn: one 2048x2048 projection, 128 tokens; layer: the 14 "
                          "products of a Llama-3.2-1B layer, forward and transposed, with uneven "
                          "token counts, captured once as a graph and replayed; mlp: gate/up/down "
-                         "forward and transposed over 2048 tokens in chunks")
+                         "forward and transposed over 2048 tokens in chunks; table4: the paper's "
+                         "Table 4 shapes at N = 2048, one and 16 tokens per call")
     ap.add_argument("--requests", type=int, default=500,
                     help="serve: requests per load point of the latency sweep")
     ap.add_argument("--max-tokens", type=int, default=16,
@@ -646,6 +647,113 @@ SERVE_CLIENTS = 16
 SERVE_MAX_TOKENS = 512
 
 
+# Sec. 6.3, Table 4: latency of one encrypted product W.[x] per shape (d_in -> d_out) on one
+# NVIDIA RTX 4060 Laptop GPU at the Table 1 parameters (N = 2048, 39-bit input and
+# 26-bit output moduli), seconds. Context only: other hardware, other moduli.
+TABLE4_PAPER_S = {(768, 768): 0.0809, (3072, 768): 0.1528, (2048, 2048): 0.2402,
+                  (768, 3072): 0.3389, (8192, 2048): 0.6368, (2048, 8192): 1.0539}
+
+
+def table4_workload(args):
+    """The six product shapes of the paper's Table 4 at N = 2048 with one 54-bit prime,
+    outputs switched to 2^26 (Table 1's output modulus), t = 2^28 (room for 8192-input
+    rows). One step is one call of each shape with one token; the same with 16 tokens
+    (the paper's training step runs 16 tokens per call) is timed after it. Each shape's
+    launch is tuned on the spot (rlwe_autotune_product)."""
+    import numpy as np
+    import torch
+
+    from paper_2505_07329_amd import rlwe, synth
+
+    N, primes, log2_t, qbits = 2048, synth.PRIMES_2048, 28, 26
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    peaks = measured_peaks()
+    ctx = rlwe.Context(N, primes, log2_t, device=0, log2_q_out=qbits)
+    tuner = rlwe.Tuner(rlwe.rlwe_device_key(0))
+    for (d_in, d_out) in TABLE4_PAPER_S:
+        for T in (1, 16):
+            rlwe.rlwe_autotune_product(ctx.handle, tuner.handle, d_in, d_out, T)
+    rlwe.rlwe_ctx_set_tuner(ctx.handle, tuner.handle)
+    stream = torch.cuda.current_stream()
+    shapes = []
+    for si, (d_in, d_out) in enumerate(TABLE4_PAPER_S):
+        W = synth.int8_uniform(synth.rng(1, synth.P_WEIGHTS, 10 + si), (d_out, d_in))
+        w = rlwe.Weights(ctx, torch.from_numpy(W).to(dev), rlwe.RLWE_W_FWD)
+        L = (d_in + N - 1) // N
+        per_T = {}
+        for T in (1, 16):
+            ct = synth.uniform_mod_primes(synth.rng(1, synth.P_MASK, 10 + si), primes, (T, L, 2), N)
+            per_T[T] = (torch.from_numpy(ct.view(np.int64)).to(dev),
+                        torch.empty((T, d_out, N + 1), dtype=torch.int32, device=dev))
+        shapes.append(dict(d_in=d_in, d_out=d_out, w=w, per_T=per_T,
+                           method="ntt" if rlwe.rlwe_weights_method(w.handle) else "toeplitz"))
+    rlwe.rlwe_workspace_reserve(ctx.handle, max(
+        rlwe.rlwe_workspace_bytes(ctx.handle, sh["w"].handle, False, 16) for sh in shapes))
+
+    def call(sh, T):
+        ct, out = sh["per_T"][T]
+        rlwe.ct_matmul_clear(ctx.handle, sh["w"].handle, ct, T, out, False, rlwe.RLWE_OUT_SWITCHED,
+                             stream)
+
+    def step(T):
+        for sh in shapes:
+            call(sh, T)
+
+    for _ in range(args.warmup):
+        step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    macs1 = sum(sh["d_in"] * sh["d_out"] for sh in shapes)
+    rows = []
+    for sh in shapes:
+        lat = {}
+        for T in (1, 16):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            call(sh, T)
+            e0.record(stream)
+            for _ in range(args.steps):
+                call(sh, T)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            lat[T] = e0.elapsed_time(e1) / args.steps
+        paper = TABLE4_PAPER_S[(sh["d_in"], sh["d_out"])]
+        rows.append({"d_in": sh["d_in"], "d_out": sh["d_out"], "method": sh["method"],
+                     "ms_1_token": lat[1], "ms_16_tokens": lat[16],
+                     "macs_per_s_1_token": sh["d_in"] * sh["d_out"] / (lat[1] * 1e-3),
+                     "macs_per_s_16_tokens": 16 * sh["d_in"] * sh["d_out"] / (lat[16] * 1e-3),
+                     "paper_s": paper, "paper_over_ours_1_token": paper / (lat[1] * 1e-3)})
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = mix_cpu_baseline([(sh["d_in"], sh["d_out"]) for sh in shapes], N, primes,
+                               args.cpu_seconds, "sampled output LWEs, 8 from each of the six shapes "
+                               "in turn", 1)
+    result = {
+        "metric": "encrypted MACs/s (d_in*d_out*tokens/s), one token per call, over the six product "
+                  "shapes of the paper's Table 4",
+        "value": args.steps * macs1 / wall, "unit": "MAC/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64 (54-bit residues)",
+        "data": "synthetic (seeded uniform int8 weights, uniform ciphertext residues)",
+        "config": {"workload": "table4-shapes-N2048-P1", "N": N, "primes": 1, "log2_t": log2_t,
+                   "q_out": f"2^{qbits}", "tokens": 1},
+        "shapes": rows,
+        "context": "paper: one RTX 4060 Laptop GPU, N = 2048, 39-bit input modulus (Sec. 6.3, "
+                   "Table 4); here: one MI355X, one 54-bit prime",
+        "peaks": peaks, "cpu_baseline": cpu,
+    }
+    for sh in shapes:
+        sh["w"].close()
+    rlwe.rlwe_ctx_set_tuner(ctx.handle, None)
+    tuner.close()
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
 SERVE_STEP_REQUESTS = 25  # requests per step of the saturated run
 
 
@@ -798,6 +906,9 @@ def main():
         return
     if args.workload == "mlp":
         mlp_workload(args)
+        return
+    if args.workload == "table4":
+        table4_workload(args)
         return
     import numpy as np
     import torch
