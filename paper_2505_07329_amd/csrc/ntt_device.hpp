@@ -82,7 +82,10 @@ __device__ __forceinline__ uint64_t fixed_part(uint64_t c, HP h) {
 
 // a * w mod p in [0, 4p) for any a < 2^64, pn = 2^64 - p: Shoup's quotient
 // floor(a wp / 2^64) less the partial products below bit 64 (at most 2 low), and
-// the remainder a w + q pn taken mod 2^64.
+// the remainder a w + q pn taken mod 2^64. Two shorter forms measured slower in the
+// product kernel: the four cross products chained through 64-bit v_mad_u64_u32
+// (two instructions fewer, longer dependency chains), and the high word added in
+// place by inline asm (one fewer, but opaque to the scheduler's latency model).
 __device__ __forceinline__ uint64_t mul_shoup4(uint64_t a, uint64_t w, uint64_t wp, uint64_t pn) {
   const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
   const uint32_t wp0 = (uint32_t)wp, wp1 = (uint32_t)(wp >> 32);
@@ -260,10 +263,14 @@ __device__ __forceinline__ Tw tw512(const uint64_t* tw, uint32_t t, int k, int t
 // At N = 2048 (S = 256 in Q4) the last pass has only the spans 512 and 1024: its
 // stage of span 256 was Q3's last, and is skipped (the bound of a skipped stage's
 // successor is then larger than needed, which only widens the biased differences).
-template <int NP, int PASS, bool END, int NN = kNttN>
+// LASTMUL = false (last pass only): the last stage (span N/2, one twiddle) leaves its
+// differences X + B - Y unmultiplied, for an epilogue that folds the twiddle into its
+// own constants.
+template <int NP, int PASS, bool END, int NN = kNttN, bool LASTMUL = true>
 __device__ __forceinline__ void inv_pass(uint64_t (&x)[NP][8], int tid,
                                          const uint64_t* const (&tw)[NP], const InvMod (&md)[NP]) {
   constexpr int S = InvLayout<PASS, NN>::S;
+  static_assert(LASTMUL || PASS == 3, "only the last pass can leave its last stage open");
 #pragma unroll
   for (int st = 0; st < 3; ++st) {
     const int sp = 1 << st;
@@ -273,8 +280,15 @@ __device__ __forceinline__ void inv_pass(uint64_t (&x)[NP][8], int tid,
     for (int k = 0; k < 8; ++k) {
       if (k & sp) continue;
 #pragma unroll
-      for (int r = 0; r < NP; ++r)
-        gs_bfly(x[r][k], x[r][k + sp], tw512<PASS, NN>(tw[r], t, k, tid), md[r].p8 << st, md[r].pn);
+      for (int r = 0; r < NP; ++r) {
+        if (!LASTMUL && st == 2) {
+          const uint64_t d = x[r][k] + (md[r].p8 << st) - x[r][k + sp];
+          x[r][k] += x[r][k + sp];
+          x[r][k + sp] = d;
+        } else {
+          gs_bfly(x[r][k], x[r][k + sp], tw512<PASS, NN>(tw[r], t, k, tid), md[r].p8 << st, md[r].pn);
+        }
+      }
     }
   }
   if (END) {
@@ -312,8 +326,10 @@ __device__ __forceinline__ void wave_exchange_fence() {
 
 // Inverse transforms of NP primes without the 1/N factor: x[r] in layout Q1,
 // bit-reversed order, below 8p_r -> layout Q4, natural order, congruent to the
-// result mod p_r (below 64p_r, not reduced). lds holds NP exchange buffers.
-template <int NP, int NN = kNttN>
+// result mod p_r (below 64p_r, not reduced). lds holds NP exchange buffers. With
+// LASTMUL = false, x[r][4..7] are congruent to the result divided by the last
+// stage's twiddle (psi^-bitrev(1)).
+template <int NP, int NN = kNttN, bool LASTMUL = true>
 __device__ __forceinline__ void ntt_inverse(uint64_t (&x)[NP][8], uint64_t* lds,
                                             const uint64_t* const (&tw)[NP],
                                             const InvMod (&md)[NP], int tid) {
@@ -332,7 +348,7 @@ __device__ __forceinline__ void ntt_inverse(uint64_t (&x)[NP][8], uint64_t* lds,
   inv_store<NP, 2, 3, NN>(lds, x, tid);
   __syncthreads();
   inv_load<NP, 3, 3, NN>(lds, x, tid);
-  inv_pass<NP, 3, false, NN>(x, tid, tw, md);
+  inv_pass<NP, 3, false, NN, LASTMUL>(x, tid, tw, md);
 }
 
 // Plain radix-2 transforms in LDS for any ring degree N <= kNttN (one stage per

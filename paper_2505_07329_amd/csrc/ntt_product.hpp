@@ -189,7 +189,8 @@ __device__ __forceinline__ void ntt_product(BatchPtr bt, uint32_t ii, uint32_t l
         }
       }
     }
-    ntt_inverse<NP, NN>(x, lds, tw, md, tid);
+    // the switched epilogue takes the last stage's differences unmultiplied
+    ntt_inverse<NP, NN, OUT != 0>(x, lds, tw, md, tid);
     // Coefficient m = tid + (NN / 8) k of C (layout Q4). Row rho of the group (row
     // j n_o + rho) is SampleExtract at h = (rho + 1) slot - 1 (Sec. 3.2): a'[n] =
     // C[h - n] for n <= h, -C[N + h - n] otherwise, so C[m] lands at n = h - m, or
@@ -267,13 +268,14 @@ __device__ __forceinline__ void ntt_product(BatchPtr bt, uint32_t ii, uint32_t l
       const uint32_t qbits = bt->rc.qbits;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        uint64_t A = fixed_part(x[0][k], bt->ntt.h[0]);
-        if (NP == 2) A += fixed_part(x[NP - 1][k], bt->ntt.h[NP - 1]);
+        // k >= 4: x holds C[m] / w (w the last stage's twiddle), and hl carries w
+        uint64_t A = fixed_part(x[0][k], k < 4 ? bt->ntt.h[0] : bt->ntt.hl[0]);
+        if (NP == 2) A += fixed_part(x[NP - 1][k], k < 4 ? bt->ntt.h[NP - 1] : bt->ntt.hl[NP - 1]);
         // A = bits 64..127 of sum_p c_p H_p 2^96 (mod 2^128), at most 7 units low:
         // c 2^32 / q mod 2^32 in 32.32 fixed point, rounded to q_out = 2^qbits
-        int64_t dist;
-        res[k] = round_qout(A, qbits, dist);
-        if (dist < 0 && dist >= -8) tie |= 1u << k;
+        bool near;
+        res[k] = round_qout_low8(A, qbits, near);
+        tie |= (near ? 1u : 0u) << k;
       }
       while (tie) {  // rare: exact CRT and switch of the coefficient
         const int k = __builtin_ctz(tie);
@@ -289,7 +291,8 @@ __device__ __forceinline__ void ntt_product(BatchPtr bt, uint32_t ii, uint32_t l
         uint64_t y[NP];
 #pragma unroll
         for (int r = 0; r < NP; ++r) {
-          y[r] = mul_shoup(c[r], bt->ntt.crt[r], bt->ntt.crt_shoup[r], p[r]);
+          y[r] = k < 4 ? mul_shoup(c[r], bt->ntt.crt[r], bt->ntt.crt_shoup[r], p[r])
+                       : mul_shoup(c[r], bt->ntt.crtl[r], bt->ntt.crtl_shoup[r], p[r]);
           y[r] = y[r] >= p[r] ? y[r] - p[r] : y[r];
         }
         u128 v = y[0];

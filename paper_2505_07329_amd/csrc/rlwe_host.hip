@@ -328,6 +328,12 @@ int build_ntt(rlwe_ctx* ctx) {
     }
     const u128 h = (u128)c * qd + ((u128)c * rm) / q;  // first product wraps mod 2^128
     for (int w = 0; w < 4; ++w) ctx->ntt.h[pi][w] = (uint32_t)(h >> (32 * w));
+    // the inverse transform's last stage multiplies by psi^-bitrev(1) (entry 1)
+    const uint64_t cl = (uint64_t)((u128)c * v[2] % q);
+    ctx->ntt.crtl[pi] = cl;
+    ctx->ntt.crtl_shoup[pi] = (uint64_t)(((u128)cl << 64) / q);
+    const u128 hl = (u128)cl * qd + ((u128)cl * rm) / q;
+    for (int w = 0; w < 4; ++w) ctx->ntt.hl[pi][w] = (uint32_t)(hl >> (32 * w));
   }
   hipError_t e = hipMalloc(&ctx->ntt_tables, host.size() * 8);
   if (e != hipSuccess) return fail(RLWE_ENOMEM, "hipMalloc(NTT tables): %s", hipGetErrorString(e));

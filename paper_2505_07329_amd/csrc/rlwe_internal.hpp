@@ -55,6 +55,13 @@ struct NttConst {
   // the switched coefficient is round(sum_p c_p H_p) mod 2^32 for any integers
   // c_p = C mod q_p (multiples of q_p change the sum by multiples of 2^32)
   uint32_t h[kMaxPrimes][4];
+  // The same for the outputs of the inverse transform's last stage that its twiddle w
+  // (one value for the whole stage) would multiply: the product kernel's switched
+  // epilogue takes those differences unmultiplied, with w folded into the constants:
+  // crtl = crt w mod q_p (and its Shoup companion), hl = H_p for crtl.
+  uint64_t crtl[kMaxPrimes];
+  uint64_t crtl_shoup[kMaxPrimes];
+  uint32_t hl[kMaxPrimes][4];
 };
 
 // Per weight-matrix constants of the switched epilogue.
@@ -142,6 +149,19 @@ __device__ inline uint32_t round_qout(uint64_t W, uint32_t k, int64_t& dist) {
   const uint64_t half = 1ull << (sh - 1);
   dist = (int64_t)(frac - half);
   return (uint32_t)((W >> sh) + (frac >= half ? 1 : 0)) & qout_mask(k);
+}
+
+// The same rounding for a W known to be at most 7 units low: floor((W + 2^(sh-1)) /
+// 2^sh) mod 2^k (adding one half carries into the integer part exactly when the
+// fraction reaches it, and a wrap past 2^64 is a multiple of 2^sh 2^k), and in near
+// whether the fraction lies within 8 units below one half, where the exact value may
+// round the other way: then the fraction of V = W + half is at least 2^sh - 8, i.e.
+// the low sh bits of V + 8 are below 8, i.e. (V + 8) 2^k mod 2^64 < 8 2^k.
+__device__ __forceinline__ uint32_t round_qout_low8(uint64_t W, uint32_t k, bool& near) {
+  const uint32_t sh = 64 - k;  // fraction bits, 32..63
+  const uint64_t V = W + (1ull << (sh - 1));
+  near = ((V + 8) << k) < (8ull << k);
+  return (uint32_t)(V >> sh);
 }
 
 // Shoup multiplication a * w mod q, wp = floor(w 2^64 / q), a < 2^64, q < 2^63.

@@ -70,6 +70,15 @@ def round_qout(W, k):
     return val, frac - half
 
 
+def round_qout_low8(W, k):
+    """The NTT kernel's form of the same rounding: V = W + one half (mod 2^64), value
+    V >> (64 - k), and the window flag from the low bits of V + 8 shifted up by k."""
+    sh = 64 - k
+    V = (W + (1 << (sh - 1))) & M64
+    near = (((V + 8) << k) & M64) < (8 << k)
+    return V >> sh, near
+
+
 def exact_units(c, q):
     return ((c << 64) // q) & M64
 
@@ -112,8 +121,8 @@ def test_epilogue_estimate_and_rounding(primes, k):
             A = estimate(cs, hs)
             deficit = (exact_units(c, q) - A) & M64
             assert 0 <= deficit <= 7, (c, cs, deficit)
-            val, dist = round_qout(A, k)
-            if -8 <= dist < 0:
+            val, near = round_qout_low8(A, k)
+            if near:
                 window_hits += 1
             else:
                 assert val == exact_round(c, q, k), (c, k)
@@ -134,3 +143,66 @@ def test_window_needs_the_exact_route():
         if -8 <= dist < 0 and val != exact_round(c, q, 32):
             wrong_if_skipped += 1
     assert wrong_if_skipped > 0
+
+
+@pytest.mark.parametrize("k", list(range(1, 33)))
+def test_rounding_forms_agree(k):
+    """round_qout_low8 (the NTT epilogue) gives round_qout's value and flags exactly the
+    fractions 1..8 units below one half, for W next to every kind of boundary: the
+    half, the integer steps, the window's edges, and the wrap past 2^64."""
+    sh = 64 - k
+    half = 1 << (sh - 1)
+    rng = random.Random(1000 + k)
+    Ws = [0, 1, M64, M64 - 7, M64 - 8, half, half - 1]
+    for _ in range(300):
+        m = rng.randrange(1 << k)
+        base = m << sh
+        for d in range(-12, 12):
+            Ws.append((base + half + d) & M64)  # around the tie
+            Ws.append((base + d) & M64)         # around the integer step
+        Ws.append(rng.randrange(1 << 64))
+    for W in Ws:
+        v_ref, dist = round_qout(W, k)
+        v, near = round_qout_low8(W, k)
+        assert v == v_ref, (W, k)
+        assert near == (-8 <= dist < 0), (W, k, dist)
+
+
+def last_stage_twiddle(p, N):
+    """psi^-bitrev(1) mod p for the psi-twisted inverse transform of degree N: the one
+    twiddle of its last stage (span N/2). bitrev(1) over log2 N bits is N/2, so this is
+    psi^(-N/2), a primitive fourth root of unity."""
+    for g in range(2, 100000):
+        psi = pow(g, (p - 1) // (2 * N), p)
+        if pow(psi, N, p) == p - 1:
+            return pow(pow(psi, p - 2, p), N // 2, p)
+    raise AssertionError("no 2N-th root")
+
+
+@pytest.mark.parametrize("primes,N", [(P2, 4096), (P1, 2048)])
+@pytest.mark.parametrize("k", [32, 26, 1])
+def test_last_stage_twiddle_folded_into_constants(primes, N, k):
+    """The switched epilogue of the NTT product takes the last inverse stage's
+    differences d (coefficient = d w mod p, w that stage's twiddle) with constants
+    built from crt w mod p: the estimate keeps the 0..7-unit deficit against the exact
+    value of the coefficient, and rounds exactly outside the window."""
+    q = modulus(primes)
+    ws = [last_stage_twiddle(p, N) for p in primes]
+    for p, w in zip(primes, ws):
+        assert pow(w, 4, p) == 1 and pow(w, 2, p) == p - 1
+    hl = []
+    for p, w in zip(primes, ws):
+        crt = pow(q // p, -1, p) if len(primes) > 1 else 1
+        h = (((crt * w % p) << 128) // p) & ((1 << 128) - 1)
+        hl.append([(h >> (32 * i)) & M32 for i in range(4)])
+    rng = random.Random(77 + k + len(primes))
+    values = [rng.randrange(q) for _ in range(1500)] + near_tie_values(q, k, rng, 1500)
+    for c in values:
+        # residues of c divided by w, lifted as the transform hands them over
+        ds = [lift(c * pow(w, p - 2, p) % p, p, rng, 64 * p) for p, w in zip(primes, ws)]
+        A = estimate(ds, hl)
+        deficit = (exact_units(c, q) - A) & M64
+        assert 0 <= deficit <= 7, (c, deficit)
+        val, near = round_qout_low8(A, k)
+        if not near:
+            assert val == exact_round(c, q, k)
