@@ -42,27 +42,6 @@ __host__ __device__ constexpr int copy_base(int s) { return s == 0 ? 0 : s == 1 
 constexpr int kDigitWords = 248 + kCopyWords;  // 328
 constexpr int kWRowWords = kKC / 4 + 4;    // LDS row pitch of the weight tile (dwords)
 
-// round(U * G * 2^(k - 32)) mod 2^k where U is a signed 128-bit integer (u0..u3),
-// G = g / 2^128 (g < 2^128) and U G = c 2^32 / q mod 2^32. Partial products of U*g
-// below bit 96 are dropped (error < 6 * 2^-32 in U G, always downwards), which
-// the caller's uncertainty band absorbs. Sets amb when the fraction at the
-// rounding position is within eps units of 2^-32 of one half.
-__device__ inline uint32_t fixed_round(uint32_t u0, uint32_t u1, uint32_t u2, uint32_t u3,
-                                       const uint32_t* g, uint32_t eps, uint32_t k, bool& amb) {
-  auto lo = [](uint32_t a, uint32_t b) -> uint64_t { return (uint32_t)(a * b); };
-  auto hi = [](uint32_t a, uint32_t b) -> uint64_t { return __umulhi(a, b); };
-  const uint64_t acc3 = hi(u0, g[2]) + hi(u1, g[1]) + hi(u2, g[0]) + lo(u0, g[3]) +
-                        lo(u1, g[2]) + lo(u2, g[1]) + lo(u3, g[0]);
-  const uint64_t acc4 = (acc3 >> 32) + hi(u0, g[3]) + hi(u1, g[2]) + hi(u2, g[1]) +
-                        hi(u3, g[0]) + lo(u1, g[3]) + lo(u2, g[2]) + lo(u3, g[1]);
-  uint64_t w34 = (acc4 << 32) | (uint32_t)acc3;
-  if ((int32_t)u3 < 0) w34 -= (uint64_t)g[0] << 32;  // U = U_unsigned - 2^128
-  int64_t dist;  // fraction - 1/2 in units of 2^-32 of U G
-  const uint32_t res = round_qout(w34, k, dist);
-  amb = (uint64_t)(dist + (int64_t)eps) <= 2ull * eps;
-  return res;
-}
-
 // Exact switched value of element (t, jj, nn), computed by the whole wave: every
 // lane accumulates a strided share of the contraction for all D digits, the
 // shares are summed across the wave, and the exact rounding is taken from the
@@ -355,50 +334,104 @@ mask_kernel(Batch) {
   }
 
   // accumulator element e of this lane: row jb + 8(e/4) + 4g + e%4, column n0 + 32b + c.
-  // Each wave folds its digits into int64 partials; the partials of the two column
-  // blocks meet in LDS in two rounds, and every wave finishes a share of the elements.
-  int64_t P0[16], P1[16];
+  // The partials of the waves meet in LDS in two rounds (one per column block), and
+  // every wave finishes a share of the elements.
+  if constexpr (RAW) {
+    // each wave folds its digits into int64 partials, V = sum_l 255^l S_l is then
+    // rebuilt exactly (128-bit) and reduced mod every prime
+    int64_t P0[16], P1[16];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    P0[e] = 0;
-    P1[e] = 0;
+    for (int e = 0; e < 16; ++e) {
+      P0[e] = 0;
+      P1[e] = 0;
 #pragma unroll
-    for (int d = DPW - 1; d >= 0; --d) {
-      if (d < cnt) {
-        P0[e] = P0[e] * 255 + acc0[d][e];
-        P1[e] = P1[e] * 255 + acc1[d][e];
+      for (int d = DPW - 1; d >= 0; --d) {
+        if (d < cnt) {
+          P0[e] = P0[e] * 255 + acc0[d][e];
+          P1[e] = P1[e] * 255 + acc1[d][e];
+        }
       }
     }
-  }
 #pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    __syncthreads();  // LDS windows (or the previous round's partials) are no longer read
+    for (int b = 0; b < 2; ++b) {
+      __syncthreads();  // LDS windows (or the previous round's partials) are no longer read
 #pragma unroll
-    for (int e = 0; e < 16; ++e) part[(role * 16 + e) * 64 + lane] = b == 0 ? P0[e] : P1[e];
-    __syncthreads();
-    const uint32_t n = n0 + 32 * b + c;
-    for (int e = wave; e < 16; e += NW) {
-      const uint32_t j = jb + 8 * (e >> 2) + 4 * g + (e & 3);
-      // U = sum over roles of 255^dlo_r P_r, Horner from the highest role
-      i128 U = 0;
+      for (int e = 0; e < 16; ++e) part[(role * 16 + e) * 64 + lane] = b == 0 ? P0[e] : P1[e];
+      __syncthreads();
+      const uint32_t n = n0 + 32 * b + c;
+      for (int e = wave; e < 16; e += NW) {
+        const uint32_t j = jb + 8 * (e >> 2) + 4 * g + (e & 3);
+        // U = sum over roles of 255^dlo_r P_r, Horner from the highest role
+        i128 U = 0;
 #pragma unroll
-      for (int r = NW - 1; r >= 0; --r) {
-        const int cr = DK / NW + (r < DK % NW ? 1 : 0);
-        i128 scale = 1;
-        for (int x = 0; x < cr; ++x) scale *= 255;
-        U = U * scale + part[(r * 16 + e) * 64 + lane];
-      }
-      const bool live = j < m.rows;
-      const size_t row = (size_t)t * m.rows + j;
-      if (RAW) {
-        if (live) {
+        for (int r = NW - 1; r >= 0; --r) {
+          const int cr = DK / NW + (r < DK % NW ? 1 : 0);
+          i128 scale = 1;
+          for (int x = 0; x < cr; ++x) scale *= 255;
+          U = U * scale + part[(r * 16 + e) * 64 + lane];
+        }
+        if (j < m.rows) {
+          const size_t row = (size_t)t * m.rows + j;
           uint64_t* o = (uint64_t*)out;
           for (uint32_t p = 0; p < rc.P; ++p) o[(row * rc.P + p) * (N + 1) + n] = mod_i128(U, rc.q[p]);
         }
-      } else {
-        bool amb;
-        uint32_t res = fixed_round((uint32_t)U, (uint32_t)(U >> 32), (uint32_t)(U >> 64),
-                                   (uint32_t)(U >> 96), sc.g, sc.eps, rc.qbits, amb);
+      }
+    }
+  } else {
+    // Switched output: c 2^32 / q mod 2^32 = sum_l S_l 255^l 2^32 / q mod 2^32. Each
+    // wave adds, for its digits l = l0 + dlo + d, S_l G_l (G_l = round(255^l 2^96 / q)
+    // in the balanced words a, b, c of RingConst::dg) in 32.32 fixed point mod 2^64:
+    // floor(S a / 2^32) + S b + (S c mod 2^32) 2^32, exact but for the floor (at most one
+    // unit low per digit) and the rounding of G_l; the waves' words then simply add.
+    // The digits below l0 are left out; sc.epsw bounds all of it.
+    int32_t ga[DPW], gb[DPW];
+    uint32_t gc[DPW];
+#pragma unroll
+    for (int d = 0; d < DPW; ++d) {
+      const int l = (int)l0 + dlo + (d < cnt ? d : 0);
+      ga[d] = bt->rc.dg[l][0];
+      gb[d] = bt->rc.dg[l][1];
+      gc[d] = (uint32_t)bt->rc.dg[l][2];
+    }
+    uint64_t W0[16], W1[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      uint32_t H0 = 0, H1 = 0;
+      int64_t w0 = 0, w1 = 0;  // sums mod 2^64 (each term below 2^62 in magnitude)
+#pragma unroll
+      for (int d = 0; d < DPW; ++d) {
+        if (d < cnt) {
+          const int32_t s0 = acc0[d][e], s1 = acc1[d][e];
+          w0 += (int64_t)s0 * gb[d] + __mulhi(s0, ga[d]);
+          w1 += (int64_t)s1 * gb[d] + __mulhi(s1, ga[d]);
+          H0 += (uint32_t)s0 * gc[d];
+          H1 += (uint32_t)s1 * gc[d];
+        }
+      }
+      W0[e] = (uint64_t)w0 + ((uint64_t)H0 << 32);
+      W1[e] = (uint64_t)w1 + ((uint64_t)H1 << 32);
+    }
+    uint64_t* partw = reinterpret_cast<uint64_t*>(smem);
+    const uint32_t k = rc.qbits, sh = 64 - k;
+    const uint64_t half = 1ull << (sh - 1), E = sc.epsw;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      __syncthreads();  // LDS windows (or the previous round's partials) are no longer read
+#pragma unroll
+      for (int e = 0; e < 16; ++e) partw[(role * 16 + e) * 64 + lane] = b == 0 ? W0[e] : W1[e];
+      __syncthreads();
+      const uint32_t n = n0 + 32 * b + c;
+      for (int e = wave; e < 16; e += NW) {
+        const uint32_t j = jb + 8 * (e >> 2) + 4 * g + (e & 3);
+        uint64_t Wt = 0;
+#pragma unroll
+        for (int r = 0; r < NW; ++r) Wt += partw[(r * 16 + e) * 64 + lane];
+        // round(Wt / 2^sh) mod 2^k, ties up; uncertain when the fraction lies within E
+        // units of one half: then V = Wt + half is within E of a multiple of 2^sh
+        const uint64_t V = Wt + half;
+        uint32_t res = (uint32_t)(V >> sh);
+        const bool amb = ((V + E) << k) < ((2 * E) << k);
+        const bool live = j < m.rows;
         uint64_t pending = __ballot(live && (amb || force_exact));
         while (pending) {
           const int src = __ffsll((unsigned long long)pending) - 1;
@@ -407,7 +440,7 @@ mask_kernel(Batch) {
           const uint32_t r = exact_element_wave<D>(bt, ii, t, jj, nn, lane);
           if (lane == src) res = r;
         }
-        if (live) ((uint32_t*)out)[row * (N + 1) + n] = res;
+        if (live) ((uint32_t*)out)[((size_t)t * m.rows + j) * (N + 1) + n] = res;
       }
     }
   }

@@ -210,10 +210,10 @@ u128 pow255(uint32_t e) {
 
 double u128_to_double(u128 v) { return (double)(uint64_t)(v >> 64) * 18446744073709551616.0 + (double)(uint64_t)v; }
 
-// floor(num * 2^128 / den) rounded to nearest, for num < den < 2^126.
-u128 frac_128(u128 num, u128 den) {
+// num * 2^bits / den rounded to nearest, for num < den < 2^126 and bits <= 128.
+u128 frac_bits(u128 num, u128 den, int bits) {
   u128 r = num, quo = 0;
-  for (int b = 0; b < 128; ++b) {
+  for (int b = 0; b < bits; ++b) {
     r <<= 1;
     quo <<= 1;
     if (r >= den) {
@@ -245,22 +245,16 @@ int make_switch_const(const RingConst& rc, uint32_t max_l1, SwitchConst* sc) {
     if (dk == 13) dk = 14;
   }
   l0 = rc.D - dk;
-  // G = 255^l0 2^32 / q must be < 1 so that g = round(G 2^128) fits 128 bits.
-  const u128 num = pow255(l0) << 32;
-  if (num >= q) return fail(RLWE_ESHAPE, "internal: switching scale out of range (l0=%u)", l0);
-  const u128 g = frac_128(num, q);
-  for (int i = 0; i < 4; ++i) sc->g[i] = (uint32_t)(g >> (32 * i));
   sc->l0 = l0;
   sc->dk = dk;
-  // Uncertainty: skipped digits + representation error of g times |U| + dropped
-  // partial products (< 5 * 2^-32), with a factor 2 margin.
+  // Uncertainty of the per-digit fixed-point sum (RingConst::dg), in units of 2^-32 of
+  // V 2^32 / q: the skipped digits (factor 2 margin), one unit of floor per kept digit,
+  // the rounding of each G_l (|S| 2^-33 units, below one unit for |S| < 2^32), and a
+  // margin.
   const double skipped = maxS * ((pow(255.0, (double)l0) - 1.0) / 254.0) * 4294967296.0 / qd;
-  const double umax = (maxS / 127.0) * (qd / (2.0 * pow(255.0, (double)l0)) + 1.0);
-  const double gerr = umax * ldexp(1.0, -129);
-  const double eps = 2.0 * (skipped + gerr) + ldexp(6.0, -32);
-  const double eps32 = ceil(eps * 4294967296.0);
-  if (eps32 > 1073741824.0) return fail(RLWE_ESHAPE, "internal: rounding band too wide");
-  sc->eps = (uint32_t)eps32 + 1;
+  const double band = ceil(2.0 * skipped * 4294967296.0) + 2.0 * dk + 4.0;
+  if (band > 1073741824.0) return fail(RLWE_ESHAPE, "internal: rounding band too wide");
+  sc->epsw = (uint32_t)band;
   return RLWE_OK;
 }
 
@@ -417,6 +411,16 @@ int rlwe_params_init(const rlwe_params* p, int hip_device, rlwe_ctx** out) {
   rc.half_hi = (uint64_t)(half >> 64);
   rc.qbits = p->log2_q_out;
   rc.inv_qout = ldexp(1.0, (int)rc.qbits) / u128_to_double(Q);
+  for (uint32_t l = 0; l < rc.D; ++l) {
+    // G_l mod 2^96 (the integer part of 255^l / q only adds multiples of 2^96)
+    const i128 G = (i128)frac_bits(pow255(l) % Q, Q, 96);
+    const int32_t a = (int32_t)(uint32_t)(uint64_t)G;
+    const i128 g1 = (G - a) >> 32;
+    const int32_t b = (int32_t)(uint32_t)(uint64_t)g1;
+    rc.dg[l][0] = a;
+    rc.dg[l][1] = b;
+    rc.dg[l][2] = (int32_t)(uint32_t)(uint64_t)((g1 - b) >> 32);
+  }
 
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);

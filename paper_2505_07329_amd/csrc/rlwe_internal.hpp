@@ -36,6 +36,11 @@ struct RingConst {
   uint64_t half_lo, half_hi;       // (q - 1) / 2
   uint32_t qbits;                  // switched outputs are modulo q_out = 2^qbits (1..32)
   double inv_qout;                 // 2^qbits / q (estimate only; results are corrected exactly)
+  // Digit l of the balanced base-255 expansion carries G_l = round(255^l 2^96 / q) mod 2^96
+  // (255^l 2^32 / q mod 2^32 in 32.64 fixed point), as words G_l = a + b 2^32 + c 2^64 with
+  // a, b in [-2^31, 2^31): the matrix-core epilogue adds floor(S a / 2^32) + S b +
+  // (S c mod 2^32) 2^32 for a digit sum S.
+  int32_t dg[kMaxDigits][3];
 };
 
 // Constants of the number-theoretic-transform method (N = kNttN only).
@@ -64,12 +69,12 @@ struct NttConst {
   uint32_t hl[kMaxPrimes][4];
 };
 
-// Per weight-matrix constants of the switched epilogue.
+// Per weight-matrix constants of the switched epilogue (matrix-core method).
 struct SwitchConst {
   uint32_t l0;        // digits below l0 are left out of the matrix-core sums
   uint32_t dk;        // digits kept: D - l0
-  uint32_t g[4];      // round(255^l0 * 2^160 / q) as 4 little-endian words (< 2^128)
-  uint32_t eps;       // half-width of the uncertain band around a rounding tie, in 2^-32 units
+  uint32_t epsw;      // half-width of the uncertain band around a rounding tie of the
+                      // per-digit fixed-point sum (RingConst::dg), in 2^-32 units
 };
 
 // ---------------------------------------------------------------- integer helpers

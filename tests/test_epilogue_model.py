@@ -206,3 +206,103 @@ def test_last_stage_twiddle_folded_into_constants(primes, N, k):
         val, near = round_qout_low8(A, k)
         if not near:
             assert val == exact_round(c, q, k)
+
+
+# ---------------------------------------------------------------------------------
+# Switched epilogue of the matrix-core product: V = sum_l 255^l S_l (S_l the int32 digit
+# sums of the balanced base-255 expansion), c 2^32 / q mod 2^32 formed per digit in 32.32
+# fixed point from G_l = round(255^l 2^96 / q) mod 2^96 in balanced 32-bit words.
+
+def digit_constants(q, D):
+    """The (a, b, c) words of every digit: G_l = a + b 2^32 + c 2^64, a and b in
+    [-2^31, 2^31) (the host's table)."""
+    out = []
+    for l in range(D):
+        num = pow(255, l) % q
+        G = ((num << 96) + q // 2) // q  # round to nearest (q odd)
+        a = G & M32
+        a = a - (1 << 32) if a >= 1 << 31 else a
+        g1 = (G - a) >> 32
+        b = g1 & M32
+        b = b - (1 << 32) if b >= 1 << 31 else b
+        c = ((g1 - b) >> 32) & M32
+        assert G == a + (b << 32) + (c << 64)
+        out.append((a, b, c))
+    return out
+
+
+def switch_plan(q, D, maxS):
+    """The host's choice of kept digits and uncertainty band (units of 2^-32)."""
+    l0 = 0
+    for c in range(1, D):
+        if maxS * ((255.0 ** c - 1) / 254.0) * 2.0 ** 32 / q <= 2.0 ** -16:
+            l0 = c
+    dk = D - l0
+    if D == 7:
+        dk = 7
+    else:
+        dk = max(dk, 8)
+        if dk == 13:
+            dk = 14
+    l0 = D - dk
+    skipped = maxS * ((255.0 ** l0 - 1) / 254.0) * 2.0 ** 32 / q
+    import math
+    band = math.ceil(2.0 * skipped * 2.0 ** 32) + 2 * dk + 4
+    return l0, dk, band
+
+
+def digit_word(S, abc):
+    """The kernel's word of one digit: floor(S a / 2^32) + S b + (S c mod 2^32) 2^32."""
+    a, b, c = abc
+    return ((S * a) >> 32) + S * b + (((S * c) & M32) << 32)
+
+
+@pytest.mark.parametrize("primes", [P2, P1])
+@pytest.mark.parametrize("k", [32, 26, 1])
+@pytest.mark.parametrize("K", [512, 2048, 8192])
+def test_matrix_core_digit_epilogue(primes, k, K):
+    """The per-digit fixed-point sum stays within the host's band of the exact value, and
+    rounds exactly outside it, for digit sums up to the bound of K int8 products; digit
+    sums are drawn at random, at the bound, and next to rounding ties of V."""
+    q = modulus(primes)
+    D = 14 if len(primes) == 2 else 7
+    maxS = 127 * 127 * K
+    l0, dk, band = switch_plan(q, D, maxS)
+    G = digit_constants(q, D)
+    rng = random.Random(K + 3 * k + len(primes))
+    sh = 64 - k
+    checked = window = 0
+    for trial in range(1500):
+        S = [rng.randrange(-maxS, maxS + 1) for _ in range(D)]
+        if trial % 7 == 0:
+            S = [maxS if rng.random() < 0.5 else -maxS for _ in range(D)]
+        if trial % 3 == 1:
+            # move V next to a rounding tie of c 2^k / q: add the balanced base-255 digits
+            # of the difference (at most 127 each) to digit sums drawn below maxS - 127
+            S = [rng.randrange(-maxS + 127, maxS - 126) for _ in range(D)]
+            V = sum(pow(255, l) * s for l, s in enumerate(S))
+            m = rng.randrange(1 << k)
+            tie = ((2 * m + 1) * q) >> (k + 1)
+            delta = (tie - V % q + rng.randrange(-2, 3) * pow(255, l0)) % q
+            delta = delta - q if delta > q // 2 else delta
+            for l in range(D):
+                dl = ((delta + 127) % 255) - 127
+                S[l] += dl
+                delta = (delta - dl) // 255
+            assert delta == 0
+        V = sum(pow(255, l) * s for l, s in enumerate(S))
+        c = V % q
+        W = sum(digit_word(S[l], G[l]) for l in range(l0, D)) & M64
+        exact = exact_units(c, q)  # floor(c 2^64 / q) mod 2^64
+        err = ((W - exact + (1 << 63)) & M64) - (1 << 63)
+        assert abs(err) <= band, (err, band)
+        V_ = (W + (1 << (sh - 1))) & M64
+        amb = (((V_ + band) << k) & M64) < ((2 * band) << k)
+        if not amb:
+            assert V_ >> sh == exact_round(c, q, k), (k, c)
+            checked += 1
+        else:
+            window += 1
+    assert checked >= 1000
+    if len(primes) == 2:  # the near-tie draws reach the exact route (one prime: a window of
+        assert window > 0  # 2 dk + 4 units, narrower than one step of c)
