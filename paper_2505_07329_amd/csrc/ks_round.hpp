@@ -48,11 +48,15 @@ __device__ __noinline__ uint64_t round_exact(KrPtr a, uint64_t c0, uint64_t c1) 
 
 // Fixed-point route, 32 fraction bits: c_p g_p / q_p = c_p G_p / 2^96 with
 // G_p = floor(g_p 2^96 / q_p) (96 bits), from the partial products of c_p G_p at and
-// above bit 64 (c0 G0 and the low halves of c0 G1, c1 G0 dropped). The estimate of the
-// sum is at most 7 units of 2^-32 below the exact sum (3 per prime from the dropped
-// terms, c_p / 2^64 from G_p's truncation), never above, so its rounding is the exact
-// one unless the estimate lies within 8 units below a rounding boundary: then `near`
-// is set and the caller takes the exact route.
+// above bit 64 (c0 G0 and the low halves of c0 G1, c1 G0 dropped). Per prime the
+// estimate is below the exact value by less than 3 units of 2^-32 from the dropped terms
+// plus c_p / 2^64 < 1 unit from G_p's truncation, never above; the deficit of the sum is
+// an integer number of units below 4 P, so at most 7 for any c_p < 2^64 (at most 6 for
+// residues below 2^54, as callers pass them). Its rounding is therefore the exact one
+// unless the estimate lies within 8 units below a rounding boundary: then `near` is set
+// and the caller takes the exact route. Every sum below is exact mod 2^64 for any
+// c_p < 2^64 (t stays below 2^64, the carry of s is kept, u and v are 64-bit products);
+// the magnitudes noted are those of reduced residues.
 template <int NP>
 __device__ __forceinline__ uint64_t round_fast(KrPtr a, uint64_t c0, uint64_t c1, bool& near) {
   const uint64_t cs[2] = {c0, c1};
@@ -61,13 +65,13 @@ __device__ __forceinline__ uint64_t round_fast(KrPtr a, uint64_t c0, uint64_t c1
 #pragma unroll
   for (int r = 0; r < NP; ++r) {
     const uint64_t c = cs[r];
-    const uint32_t x0 = (uint32_t)c, x1 = (uint32_t)(c >> 32);  // x1 < 2^22
+    const uint32_t x0 = (uint32_t)c, x1 = (uint32_t)(c >> 32);  // x1 < 2^22 when c < 2^54
     const uint64_t G = a->G_lo[r];
     const uint32_t G0 = (uint32_t)G, G1 = (uint32_t)(G >> 32), G2 = a->G_hi[r];
     // Z = t + u + v 2^32 ~ c G / 2^64 (< 2^86): integer part Z >> 32, fraction Z mod 2^32
     uint64_t t = (uint64_t)__umulhi(x0, G1) + __umulhi(x1, G0);
     t += (uint64_t)x0 * G2;  // below 2^64: x0 G2 <= 2^64 - 2^33 + 1
-    const uint64_t u = (uint64_t)x1 * G1, v = (uint64_t)x1 * G2;  // both below 2^54
+    const uint64_t u = (uint64_t)x1 * G1, v = (uint64_t)x1 * G2;  // below 2^54 when c < 2^54
     const uint64_t s = t + u;
     const uint64_t ip = (s >> 32) + v + (s < t ? 1ull << 32 : 0);
     at += c * a->f[r] + ip;

@@ -243,9 +243,10 @@ def test_several_passes_and_graph_replay():
 
 @pytest.mark.parametrize("primes,beta,ell", [(P2, 54, 1), (P2, 27, 2), (P1, 12, 3)])
 def test_decomposition_near_rounding_ties(primes, beta, ell):
-    """Mask coefficients whose scaled value c 2^K / q lies within 2^-40 of a rounding tie
-    (x + 1/2), where the GPU's double-precision test hands over to exact integer
-    arithmetic: the packed outputs equal the oracle's."""
+    """Mask coefficients whose scaled value c 2^K / q lies next to a rounding tie
+    (x + 1/2), where the GPU's 32.32 fixed-point estimate (at most 7 units of 2^-32 low)
+    falls inside its 8-unit window and hands over to exact integer arithmetic: the
+    packed outputs equal the oracle's."""
     print(f"case: keyswitch near ties P={len(primes)} beta={beta} ell={ell}", flush=True)
     r = rl()
     q = orc.modulus(primes)

@@ -118,3 +118,27 @@ def test_residues_need_not_be_reduced():
         lifted, near2 = model_round([cs[0] + P2[0], cs[1] + 3 * P2[1]], consts, K)
         if not (near or near2):
             assert lifted == base == exact_round(c, q, K)
+
+
+@pytest.mark.parametrize("primes,beta,ell", [(P2, 54, 1), (P2, 27, 2), (P1, 54, 1)])
+def test_deficit_bound_for_residues_near_2_64(primes, beta, ell):
+    """Residues lifted by multiples of q_p up to just below 2^64 (any unreduced input):
+    the estimate stays at most 7 units below the exact value and rounds exactly outside
+    the window."""
+    K = beta * ell
+    q, consts = constants(primes, K)
+    rng = random.Random(64 + K + len(primes))
+    for c in samples(q, K, rng, 1500):
+        cs = []
+        for p in primes:
+            r = c % p
+            top = (M64 - r) // p  # largest lift below 2^64
+            cs.append(r + p * (top - rng.randrange(min(top, 4) + 1)))
+        assert all(x <= M64 for x in cs)
+        at, fr = estimate(cs, consts)
+        est = ((at << 32) | fr) % (1 << (K + 32))
+        deficit = (exact_units(c, q, K) - est) % (1 << (K + 32))
+        assert 0 <= deficit <= 7, (c, deficit)
+        got, near = model_round(cs, consts, K)
+        if not near:
+            assert got == exact_round(c, q, K), c
