@@ -140,19 +140,18 @@ def roofline(products, kt, N, P, peaks, traffic=None):
 # (--copy-calibration). Valid for the kernel source it was taken on (sha256); for any
 # other source the roofline reports traffic as null.
 KERNEL_TRAFFIC = {
-    "mask": {"sources": ["k_mask.hip"], "fetch_bytes": 4382214101, "write_bytes": 4766672373,
-             "sha256": "37b3392ace8226fcd057a2f461259544933971d70c4ba84b554979c7875ac123"},
+    "mask": None,  # the matrix-core kernel changed since its counters were taken
     "ntt": {"sources": ["k_ntt.hip", "ntt_product.hpp", "ntt_device.hpp", "ks_round.hpp"],
-            "fetch_bytes": 5271064556,
-            "write_bytes": 4354464267,
-            "sha256": "bc9a037db00f4e0025010260585fe77adb165f398aac7906030046d2690056e3"},
+            "fetch_bytes": 5232104012,
+            "write_bytes": 4342225856,
+            "sha256": "ab417f6bfba2f5169aae7c0ca3fd01203fe01820232135b4da6f1acb273bd882"},
     # the product with masks rounded for KeySwitch packing (ct_matmul_pack, --keyswitch)
     "ntt_ks": {"sources": ["k_ntt.hip", "ntt_product.hpp", "ntt_device.hpp", "ks_round.hpp"],
-               "fetch_bytes": 6243685734, "write_bytes": 8676000492,
-               "sha256": "54bbd23bc851573e643c2b930121939d417596e893ad87097cd9f620a7f47c1c"},
+               "fetch_bytes": 6223064186, "write_bytes": 8668136656,
+               "sha256": "ab417f6bfba2f5169aae7c0ca3fd01203fe01820232135b4da6f1acb273bd882"},
     "ksacc": {"sources": ["k_keyswitch.hip", "ntt_device.hpp", "ks_round.hpp"],
-              "fetch_bytes": 13018531221, "write_bytes": 536870912,
-              "sha256": "5b9871e8647d89080280f9a7251d9bb93aa902e4164191062aea659d500d3815"},
+              "fetch_bytes": 13022056381, "write_bytes": 536870912,
+              "sha256": "d937024f1e3fd3347719307b5b0d6f7d35cdf7636a29f7968abe431f94503c29"},
 }
 
 
@@ -303,6 +302,8 @@ def parse():
                     help="serve: HBM budget of the output arena")
     ap.add_argument("--round-macs", type=float, default=1e9,
                     help="serve: MACs after which a scheduling round stops adding requests")
+    ap.add_argument("--no-rowpack-run", action="store_true",
+                    help="serve: skip the second saturated run with packed rows")
     ap.add_argument("--loads", default="0.5,0.8,0.95",
                     help="serve: arrival rates as fractions of the saturated request rate")
     args = ap.parse_args()
@@ -853,6 +854,39 @@ def serve_workload(args):
         cpu = mix_cpu_baseline([(r.d_in, r.d_out) for r in sat_reqs], N, primes, args.cpu_seconds,
                                "sampled output LWEs, 8 from each request of the served mix in "
                                "turn", 8)
+    packed = None
+    if not args.rowpack and not args.no_rowpack_run and args.method != "toeplitz":
+        # the same saturated requests with the weights reloaded with packed rows (n_o = N / K
+        # rows per weight polynomial where K <= N/2; Cheetah-style coefficient packing):
+        # same decryptions, other ciphertexts
+        for key in list(weights):
+            weights[key].close()
+        for layer in range(SERVE_LAYERS):
+            for pi, (name, (d_in, d_out)) in enumerate(synth.LLAMA_1B_PROJ.items()):
+                W = synth.int8_uniform_device(5, synth.P_WEIGHTS, layer * 16 + pi, (d_out, d_in), dev)
+                weights[(layer, name)] = rlwe.Weights(
+                    ctx, W, rlwe.RLWE_W_FWD | rlwe.RLWE_W_TRANSPOSE | method_flag(args)
+                    | rlwe.RLWE_W_ROWPACK)
+                del W
+        backend.weights = weights
+        run(requests(SERVE_STEP_REQUESTS, math.inf, 97), 16)  # warm-up
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        psat = run(requests(n_sat, math.inf, 0), 16)
+        torch.cuda.synchronize()
+        pwall = time.perf_counter() - t2
+        t3 = time.perf_counter()
+        run(requests(n_sat, math.inf, 0), 1)
+        torch.cuda.synchronize()
+        pplain = time.perf_counter() - t3
+        packed = {"value": psat["macs"] / pwall, "ms_per_step": pwall * 1e3 / args.steps,
+                  "saturated_p50_ms": psat["p50_s"] * 1e3, "saturated_p99_ms": psat["p99_s"] * 1e3,
+                  "plain_per_call_value": psat["macs"] / pplain,
+                  "speedup_vs_unpacked": wall / pwall,
+                  "what": "the same saturated requests with RLWE_W_ROWPACK weights (floor(N/K) "
+                          "rows per weight polynomial where K <= N/2): same decryptions, other "
+                          "ciphertexts"}
+        print(json.dumps({"progress": "packed rows", "wall_s": pwall}), file=sys.stderr, flush=True)
     result = {
         "metric": "encrypted MACs/s (sum d_in*d_out*tokens / s) vs plain kernel; p50/p99 request "
                   "latency",
@@ -874,7 +908,7 @@ def serve_workload(args):
         "plain_per_call": {"value": macs / plain_wall, "ms_per_step": plain_wall * 1e3 / args.steps,
                            "speedup_served": plain_wall / wall,
                            "what": "the same requests, one ct_matmul_clear each, in arrival order"},
-        "sweep": sweep, "tuner": tuner_info,
+        "sweep": sweep, "rowpack_saturated": packed, "tuner": tuner_info,
         "kernels_ms": {"ntt": kt["ntt_ms"], "persistent": kt["persist_ms"], "mask": kt["mask_ms"],
                        "prep": kt["prep_ms"], "body": kt["body_ms"]},
         "roofline": roof, "roofline_other_method": roof_other, "peaks": peaks,
