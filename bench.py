@@ -140,7 +140,8 @@ def roofline(products, kt, N, P, peaks, traffic=None):
 # (--copy-calibration). Valid for the kernel source it was taken on (sha256); for any
 # other source the roofline reports traffic as null.
 KERNEL_TRAFFIC = {
-    "mask": None,  # the matrix-core kernel changed since its counters were taken
+    "mask": {"sources": ["k_mask.hip"], "fetch_bytes": 4382826959, "write_bytes": 4766587301,
+             "sha256": "8ab8cb6fb513b23f1ce566dc604e2116b7a46302abe49a7d36941d71ad8942ee"},
     "ntt": {"sources": ["k_ntt.hip", "ntt_product.hpp", "ntt_device.hpp", "ks_round.hpp"],
             "fetch_bytes": 5232104012,
             "write_bytes": 4342225856,
@@ -277,6 +278,10 @@ def parse():
                          "Eq. (pack_rotate)), N per ciphertext, switched to 2^q-out-bits")
     ap.add_argument("--ks-base-bits", type=int, default=54, help="KeySwitch: digit bits")
     ap.add_argument("--ks-levels", type=int, default=1, help="KeySwitch: gadget levels")
+    ap.add_argument("--d-in", type=int, default=None,
+                    help="attn: contraction length K instead of 2048 (shape studies; the bench "
+                         "line is then not the attention workload's)")
+    ap.add_argument("--d-out", type=int, default=None, help="attn: output rows M instead of 2048")
     ap.add_argument("--rowpack", action="store_true",
                     help="load every weight matrix with RLWE_W_ROWPACK (floor(N / K) rows per "
                          "weight polynomial where the contraction length K <= N/2; NTT method)")
@@ -949,9 +954,12 @@ def main():
 
     from paper_2505_07329_amd import rlwe, synth
 
-    cfg = synth.WORKLOADS[2]
+    cfg = dict(synth.WORKLOADS[2])
     N, primes, log2_t = cfg["N"], cfg["primes"], cfg["log2_t"]
-    d_in, d_out, T = cfg["d_in"], cfg["d_out"], cfg["tokens"]
+    d_in, d_out, T = args.d_in or cfg["d_in"], args.d_out or cfg["d_out"], cfg["tokens"]
+    shape_default = (d_in, d_out) == (cfg["d_in"], cfg["d_out"])
+    if not shape_default:  # a shape study: named by its shape, no traffic record applies
+        cfg["name"] = f"shape-{d_out}x{d_in}-T{T}-N{N}-P{len(primes)}"
     L = (d_in + N - 1) // N
     W = synth.int8_uniform(synth.rng(2, synth.P_WEIGHTS), (d_out, d_in))
     ct_np = synth.uniform_mod_primes(synth.rng(2, synth.P_MASK), primes, (T, L, 2), N)
@@ -1046,15 +1054,15 @@ def main():
     n_o = rlwe.rlwe_weights_rows_per_product(w.handle)
     roof, _ = roofline([dict(T=T, M=d_out, K=d_in, kept=kept, ntt=is_ntt, n_o=n_o)], one, N,
                        len(primes), peaks,
-                       traffic={"mfma": None if ks else kernel_traffic("mask"),
-                                "alu": None if n_o != 1 else
+                       traffic={"mfma": None if ks or not shape_default else kernel_traffic("mask"),
+                                "alu": None if n_o != 1 or not shape_default else
                                 kernel_traffic("ntt_ks" if ks else "ntt")})
     ks_roof = None
     if ks and kt["ksacc_n"]:
         ks_ms = {k: kt[f"ks{k}_ms"] / max(1, kt[f"ks{k}_n"]) * kt[f"ks{k}_n"] / args.steps
                  for k in ("dig", "acc", "fin")}  # per step (a step may hold several passes)
         ks_roof = keyswitch_roofline(T * d_out, N, P, args.ks_levels, ks_ms["acc"] * 1e-3, peaks)
-        ks_roof["traffic"] = kernel_traffic("ksacc")
+        ks_roof["traffic"] = kernel_traffic("ksacc") if shape_default else None
         # the digit kernel reads the rounded masks (NTT method) or the raw residues
         read = 8 * N if is_ntt else P * 8 * (N + 1)
         ks_roof["digits_hbm_gbs"] = (T * d_out * (read + args.ks_levels * 8 * N)
