@@ -64,6 +64,26 @@ __device__ __forceinline__ Tw ld_tw(const uint64_t* t, uint32_t k) {
 __device__ __forceinline__ uint64_t mul_shoup(uint64_t a, uint64_t w, uint64_t wp, uint64_t p) {
   return a * w - __umul64hi(a, wp) * p;
 }
+// Buffer access (MUBUF): a resource of `bytes` bytes from a wave-uniform base, a per-lane
+// byte offset in a VGPR and a uniform byte offset in an SGPR, so a thread's loads of one
+// operand share one offset register and need no 64-bit address arithmetic. Accesses
+// past `bytes` read zeros and write nothing.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+__device__ __forceinline__ Rsrc buf_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                           0x00020000 /* 32-bit data format (gfx9) */);
+}
+__device__ __forceinline__ uint64_t buf_ld64(Rsrc r, uint32_t voff, uint32_t soff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+  return ((uint64_t)v[1] << 32) | v[0];
+}
+__device__ __forceinline__ void buf_ld128(Rsrc r, uint32_t voff, uint32_t soff, uint64_t& x,
+                                          uint64_t& y) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+  x = ((uint64_t)v[1] << 32) | v[0];
+  y = ((uint64_t)v[3] << 32) | v[2];
+}
+
 __device__ __forceinline__ uint64_t reduce4(uint64_t x, uint64_t p) {  // [0, 4p) -> [0, p)
   x = x >= 2 * p ? x - 2 * p : x;
   return x >= p ? x - p : x;
@@ -256,8 +276,12 @@ __device__ __forceinline__ Tw tw512(const uint64_t* tw, uint32_t t, int k, int t
     const uint32_t idx = NN / (2 * t) + upos / (2 * t);
     return Tw{((TwScalarPtr)tw)[2 * idx], ((TwScalarPtr)tw)[2 * idx + 1]};
   }
-  return ld_tw(tw, NN / (2 * t) +
-                       (InvLayout<PASS, NN>::base(tid) + InvLayout<PASS, NN>::S * k) / (2 * t));
+  // per lane: one 16-byte buffer load at byte 16 idx of the table (N entries)
+  const uint32_t idx =
+      NN / (2 * t) + (InvLayout<PASS, NN>::base(tid) + InvLayout<PASS, NN>::S * k) / (2 * t);
+  uint64_t w, wp;
+  buf_ld128(buf_rsrc(tw, NN * 16), 16 * idx, 0, w, wp);
+  return Tw{w, wp};
 }
 
 // At N = 2048 (S = 256 in Q4) the last pass has only the spans 512 and 1024: its

@@ -144,21 +144,22 @@ __device__ __forceinline__ void ntt_product(BatchPtr bt, uint32_t ii, uint32_t l
     // are issued together, before any use.
     if (LC == 2 || L == 1) {
       constexpr int NB = LC == 2 ? 2 : 1;
+      // the token's transformed masks and the polynomial's transformed weights as buffers:
+      // position 8 tid + k of (block i, prime r) at element k NN / 8 + tid (lane-major), the
+      // mask elements as (residue, companion) pairs
+      const Rsrc ra = buf_rsrc(ahat + (size_t)t * NB * NP * NN * 2, NB * NP * NN * 16);
+      const Rsrc rw = buf_rsrc(what + (size_t)j * NB * NP * NN, NB * NP * NN * 8);
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
         uint64_t wv[NP][8], av[NP][16];
 #pragma unroll
         for (int r = 0; r < NP; ++r) {
-          // lane-major operands: position 8 tid + k at k NN / 8 + tid
-          const uint64_t* a = ahat + 2 * ((((size_t)t * NB + i) * NP + r) * NN + tid);
-          const uint64_t* w = what + (((size_t)j * NB + i) * NP + r) * NN + tid;
+          const uint32_t e0 = (i * NP + r) * NN;  // element offset of (block, prime)
 #pragma unroll
-          for (int k = 0; k < 8; ++k) wv[r][k] = w[(NN / 8) * k];
+          for (int k = 0; k < 8; ++k) wv[r][k] = buf_ld64(rw, 8 * tid, 8 * (e0 + (NN / 8) * k));
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            av[r][2 * k] = a[(NN / 4) * k];
-            av[r][2 * k + 1] = a[(NN / 4) * k + 1];
-          }
+          for (int k = 0; k < 8; ++k)
+            buf_ld128(ra, 16 * tid, 16 * (e0 + (NN / 8) * k), av[r][2 * k], av[r][2 * k + 1]);
         }
 #pragma unroll
         for (int r = 0; r < NP; ++r)
@@ -307,6 +308,16 @@ __device__ __forceinline__ void ntt_product(BatchPtr bt, uint32_t ii, uint32_t l
       }
       // the switch of -c is -(switch of c) mod 2^qbits (q is odd: no ties)
       const uint32_t qmask = qout_mask(qbits);
+      if (n_o == 1) {
+        // one row per polynomial: h = NN - 1 >= m, coefficient m at word NN - 1 - m of the
+        // row, i.e. at byte 4 (NN - 1 - tid - (NN/8) 7) + 4 (NN/8)(7 - k) >= 0
+        const Rsrc ro = buf_rsrc((uint32_t*)out + ((size_t)t * rows + j) * (NN + 1), (NN + 1) * 4);
+        const uint32_t vo = 4 * (NN - 1 - tid - (NN / 8) * 7);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          __builtin_amdgcn_raw_buffer_store_b32(res[k], ro, (int)vo, (int)(4 * (NN / 8) * (7 - k)), 0);
+        continue;
+      }
       for (uint32_t rho = 0; rho < n_o && j * n_o + rho < rows; ++rho) {
         const uint32_t h = (rho + 1) * slot - 1;
         uint32_t* o = (uint32_t*)out + ((size_t)t * rows + j * n_o + rho) * (NN + 1);
