@@ -960,6 +960,9 @@ def main():
     shape_default = (d_in, d_out) == (cfg["d_in"], cfg["d_out"])
     if not shape_default:  # a shape study: named by its shape, no traffic record applies
         cfg["name"] = f"shape-{d_out}x{d_in}-T{T}-N{N}-P{len(primes)}"
+        # t large enough that no row can overflow (127 * row 1-norm < t / 2)
+        while (1 << (log2_t - 1)) <= 127 * 127 * d_in:
+            log2_t += 1
     L = (d_in + N - 1) // N
     W = synth.int8_uniform(synth.rng(2, synth.P_WEIGHTS), (d_out, d_in))
     ct_np = synth.uniform_mod_primes(synth.rng(2, synth.P_MASK), primes, (T, L, 2), N)

@@ -140,8 +140,7 @@ __device__ __forceinline__ void ntt_product(BatchPtr bt, uint32_t ii, uint32_t l
     asm volatile("" : "+v"(tid));
     uint64_t x[NP][8];
     // pointwise products below 4p each: two blocks stay below 8p, more are reduced.
-    // One block (LC = 0, L = 1) or two (LC = 2): the loads of every prime of a block
-    // are issued together, before any use.
+    // One block (LC = 0, L = 1) or two (LC = 2).
     if (LC == 2 || L == 1) {
       constexpr int NB = LC == 2 ? 2 : 1;
       // the token's transformed masks and the polynomial's transformed weights as buffers:
@@ -149,25 +148,34 @@ __device__ __forceinline__ void ntt_product(BatchPtr bt, uint32_t ii, uint32_t l
       // mask elements as (residue, companion) pairs
       const Rsrc ra = buf_rsrc(ahat + (size_t)t * NB * NP * NN * 2, NB * NP * NN * 16);
       const Rsrc rw = buf_rsrc(what + (size_t)j * NB * NP * NN, NB * NP * NN * 8);
+      // The first block's operands of every prime are loaded together (48 words per
+      // thread); a second block's prime by prime, while the first block's sums are live.
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
-        uint64_t wv[NP][8], av[NP][16];
 #pragma unroll
-        for (int r = 0; r < NP; ++r) {
-          const uint32_t e0 = (i * NP + r) * NN;  // element offset of (block, prime)
+        for (int rg = 0; rg < (i == 0 ? 1 : NP); ++rg) {
+          const int r0 = i == 0 ? 0 : rg, r1 = i == 0 ? NP : rg + 1;  // primes of this group
+          uint64_t wv[NP][8], av[NP][16];
 #pragma unroll
-          for (int k = 0; k < 8; ++k) wv[r][k] = buf_ld64(rw, 8 * tid, 8 * (e0 + (NN / 8) * k));
+          for (int r = 0; r < NP; ++r) {
+            if (r < r0 || r >= r1) continue;
+            const uint32_t e0 = (i * NP + r) * NN;  // element offset of (block, prime)
 #pragma unroll
-          for (int k = 0; k < 8; ++k)
-            buf_ld128(ra, 16 * tid, 16 * (e0 + (NN / 8) * k), av[r][2 * k], av[r][2 * k + 1]);
-        }
+            for (int k = 0; k < 8; ++k) wv[r][k] = buf_ld64(rw, 8 * tid, 8 * (e0 + (NN / 8) * k));
 #pragma unroll
-        for (int r = 0; r < NP; ++r)
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            const uint64_t v = mul_shoup4(wv[r][k], av[r][2 * k], av[r][2 * k + 1], md[r].pn);
-            x[r][k] = i == 0 ? v : x[r][k] + v;
+            for (int k = 0; k < 8; ++k)
+              buf_ld128(ra, 16 * tid, 16 * (e0 + (NN / 8) * k), av[r][2 * k], av[r][2 * k + 1]);
           }
+#pragma unroll
+          for (int r = 0; r < NP; ++r) {
+            if (r < r0 || r >= r1) continue;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const uint64_t v = mul_shoup4(wv[r][k], av[r][2 * k], av[r][2 * k + 1], md[r].pn);
+              x[r][k] = i == 0 ? v : x[r][k] + v;
+            }
+          }
+        }
       }
     } else {
 #pragma unroll
@@ -190,6 +198,10 @@ __device__ __forceinline__ void ntt_product(BatchPtr bt, uint32_t ii, uint32_t l
         }
       }
     }
+    // The inverse transform's loads stay below the pointwise stage: hoisted into it, they
+    // pushed the two-block products past 128 VGPRs into spills (152 bytes per thread, the
+    // kernel 27 % slower at K = 8192 than with this barrier and 20 bytes).
+    __builtin_amdgcn_sched_barrier(0);
     // the switched epilogue takes the last stage's differences unmultiplied
     ntt_inverse<NP, NN, OUT != 0>(x, lds, tw, md, tid);
     // Coefficient m = tid + (NN / 8) k of C (layout Q4). Row rho of the group (row
