@@ -462,10 +462,11 @@ int rlwe_autotune_batch(rlwe_ctx* ctx, rlwe_tuner* t, const ct_matmul_desc* desc
  * dependency chains, four waves per SIMD), the denominators of the roofline fractions:
  *   mul32_lane_ops  32-bit multiplies (v_mul_lo_u32) per second, per lane
  *   modmul          54-bit modular products per second (the product kernel's
- *                   truncated-quotient Shoup product, below 4p for any 64-bit input)
+ *                   truncated-quotient Shoup product, below 4p for any 64-bit input;
+ *                   the faster of its two instruction forms)
  *   butterfly       lazy Gentleman-Sande butterflies per second (the product kernel's
  *                   inverse-transform butterfly: one Shoup product, a sum, a biased
- *                   difference)
+ *                   difference; the faster of the product's two forms)
  *   mfma_int8_ops   int8 matrix-core operations per second (v_mfma_i32_32x32x32_i8,
  *                   two per multiply-add)
  *   clock_mhz, compute_units  as the device reports them (maximum clock)

@@ -3,6 +3,8 @@
 // Gentleman-Sande butterfly of the NTT product kernel, and int8 matrix-core products.
 // Every kernel keeps its operands in registers (independent dependency chains, enough
 // waves per SIMD to hide latency) and writes one word per thread so nothing is removed.
+#include <algorithm>
+
 #include "ntt_device.hpp"
 #include "rlwe.h"
 
@@ -30,7 +32,9 @@ __global__ void __launch_bounds__(kPeakThreads) peak_mul32_kernel(uint32_t* out,
   out[blockIdx.x * kPeakThreads + threadIdx.x] = r;
 }
 
-// 8 chains of the truncated-quotient Shoup product (mul_shoup4, the product kernel's).
+// 8 chains of the truncated-quotient Shoup product (mul_shoup4, the product kernel's),
+// in either instruction form (SPLIT); the faster one is reported.
+template <bool SPLIT>
 __global__ void __launch_bounds__(kPeakThreads) peak_modmul_kernel(uint64_t* out, uint32_t iters,
                                                                    uint64_t p, uint64_t w,
                                                                    uint64_t wp) {
@@ -41,7 +45,7 @@ __global__ void __launch_bounds__(kPeakThreads) peak_modmul_kernel(uint64_t* out
   for (uint32_t i = 0; i < iters; ++i) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      a[k] = mul_shoup4(a[k], w, wp, pn);
+      a[k] = mul_shoup4<SPLIT>(a[k], w, wp, pn);
       asm volatile("" : "+v"(a[k]));  // opaque: no cross-iteration value analysis
     }
   }
@@ -54,7 +58,8 @@ __global__ void __launch_bounds__(kPeakThreads) peak_modmul_kernel(uint64_t* out
 // 8 independent lazy Gentleman-Sande butterflies per iteration (gs_bfly, the inverse
 // transform's: a biased difference, a sum and a truncated-quotient Shoup product).
 // The sums wrap modulo 2^64 over many iterations; the instruction stream is the
-// kernel's.
+// kernel's, in either form of the product (the faster is reported).
+template <bool SPLIT>
 __global__ void __launch_bounds__(kPeakThreads) peak_bfly_kernel(uint64_t* out, uint32_t iters,
                                                                  uint64_t p, uint64_t w,
                                                                  uint64_t wp) {
@@ -66,7 +71,7 @@ __global__ void __launch_bounds__(kPeakThreads) peak_bfly_kernel(uint64_t* out, 
   for (uint32_t i = 0; i < iters; ++i) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      gs_bfly(x[k], x[k + 8], tw, B, pn);
+      gs_bfly<SPLIT>(x[k], x[k + 8], tw, B, pn);
       asm volatile("" : "+v"(x[k]), "+v"(x[k + 8]));  // opaque, as above
     }
   }
@@ -144,13 +149,18 @@ int measure_peaks(int hip_device, rlwe_peaks* out, const char** why) {
       hipLaunchKernelGGL(peak_mul32_kernel, dim3(blocks), dim3(kPeakThreads), 0, 0, (uint32_t*)buf, it);
     });
     out->mul32_lane_ops = threads * it * 64 / (ms * 1e-3);
-    const float ms2 = best_ms([&] {
-      hipLaunchKernelGGL(peak_modmul_kernel, dim3(blocks), dim3(kPeakThreads), 0, 0, (uint64_t*)buf, it, p, w, wp);
-    });
+    // both instruction forms of the modular product; the faster time of each kernel
+    const float ms2 = std::min(best_ms([&] {
+      hipLaunchKernelGGL(peak_modmul_kernel<true>, dim3(blocks), dim3(kPeakThreads), 0, 0, (uint64_t*)buf, it, p, w, wp);
+    }), best_ms([&] {
+      hipLaunchKernelGGL(peak_modmul_kernel<false>, dim3(blocks), dim3(kPeakThreads), 0, 0, (uint64_t*)buf, it, p, w, wp);
+    }));
     out->modmul = threads * it * 8 / (ms2 * 1e-3);
-    const float ms3 = best_ms([&] {
-      hipLaunchKernelGGL(peak_bfly_kernel, dim3(blocks), dim3(kPeakThreads), 0, 0, (uint64_t*)buf, it, p, w, wp);
-    });
+    const float ms3 = std::min(best_ms([&] {
+      hipLaunchKernelGGL(peak_bfly_kernel<true>, dim3(blocks), dim3(kPeakThreads), 0, 0, (uint64_t*)buf, it, p, w, wp);
+    }), best_ms([&] {
+      hipLaunchKernelGGL(peak_bfly_kernel<false>, dim3(blocks), dim3(kPeakThreads), 0, 0, (uint64_t*)buf, it, p, w, wp);
+    }));
     out->butterfly = threads * it * 8 / (ms3 * 1e-3);
     const uint32_t mit = 2 * it;
     const float ms4 = best_ms([&] {
