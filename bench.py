@@ -143,16 +143,16 @@ KERNEL_TRAFFIC = {
     "mask": {"sources": ["k_mask.hip"], "fetch_bytes": 4382826959, "write_bytes": 4766587301,
              "sha256": "8ab8cb6fb513b23f1ce566dc604e2116b7a46302abe49a7d36941d71ad8942ee"},
     "ntt": {"sources": ["k_ntt.hip", "ntt_product.hpp", "ntt_device.hpp", "ks_round.hpp"],
-            "fetch_bytes": 5232104012,
-            "write_bytes": 4342225856,
-            "sha256": "ab417f6bfba2f5169aae7c0ca3fd01203fe01820232135b4da6f1acb273bd882"},
+            "fetch_bytes": 5373620313,
+            "write_bytes": 4337019275,
+            "sha256": "31910bb99b9286a6f27116520a9aefba74e307878218bd8f2e0d4df78c5ddafd"},
     # the product with masks rounded for KeySwitch packing (ct_matmul_pack, --keyswitch)
     "ntt_ks": {"sources": ["k_ntt.hip", "ntt_product.hpp", "ntt_device.hpp", "ks_round.hpp"],
-               "fetch_bytes": 6223064186, "write_bytes": 8668136656,
-               "sha256": "ab417f6bfba2f5169aae7c0ca3fd01203fe01820232135b4da6f1acb273bd882"},
+               "fetch_bytes": 6254459648, "write_bytes": 8674174168,
+               "sha256": "31910bb99b9286a6f27116520a9aefba74e307878218bd8f2e0d4df78c5ddafd"},
     "ksacc": {"sources": ["k_keyswitch.hip", "ntt_device.hpp", "ks_round.hpp"],
-              "fetch_bytes": 13022056381, "write_bytes": 536870912,
-              "sha256": "d937024f1e3fd3347719307b5b0d6f7d35cdf7636a29f7968abe431f94503c29"},
+              "fetch_bytes": 12998295864, "write_bytes": 536870912,
+              "sha256": "e7adfe24524553db64447694479e95145df1ec7bb62cc55de4fc9d042be57c54"},
 }
 
 
