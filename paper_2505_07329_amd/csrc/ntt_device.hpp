@@ -38,8 +38,8 @@
 // its Shoup products take the quotient without the partial products that end
 // below bit 64 (results below 4p for any 64-bit input), its sums are left
 // unreduced inside a pass (each difference is biased by the stage's bound) and a
-// Barrett step at the end of a pass brings back the two elements that can exceed
-// 8p. With q_p < 2^54 every intermediate stays below 64 q_p < 2^60.
+// Barrett step at the end of every second pass brings back the two elements that can
+// exceed 8p. With q_p < 2^54 every intermediate stays below 512 q_p < 2^63.
 #pragma once
 
 #include "rlwe_internal.hpp"
@@ -88,16 +88,33 @@ __device__ __forceinline__ uint64_t reduce4(uint64_t x, uint64_t p) {  // [0, 4p
   x = x >= 2 * p ? x - 2 * p : x;
   return x >= p ? x - p : x;
 }
-// Bits 64..127 of c * h (mod 2^128) for any 64-bit c and 128-bit h, dropping the
-// partial products that end below bit 64 (the result is at most 3 units low);
-// carries past bit 127 fall off, as the sum is wanted mod 2^128.
-template <class HP>  // h: a pointer to the four words, in any address space
-__device__ __forceinline__ uint64_t fixed_part(uint64_t c, HP h) {
-  const uint32_t c0 = (uint32_t)c, c1 = (uint32_t)(c >> 32);
-  uint64_t a = (uint64_t)__umulhi(c0, h[1]) + __umulhi(c1, h[0]);
-  a += (uint64_t)c0 * h[2] + (uint64_t)c1 * h[1];
-  a += (uint64_t)(c0 * h[3] + c1 * h[2]) << 32;
-  return a;
+// bias + bits 64..127 of sum_r c_r h_r (mod 2^64) for any 64-bit c_r and 128-bit h_r
+// (four words each, h_r a pointer in any address space), as its low and high words,
+// dropping the partial products that end below bit 64 (the result is at most 3 NP
+// units low); carries past bit 127 fall off, as the sum is wanted mod 2^128.
+// one[r][i]: the value 1, in scalar registers the compiler cannot see through, so that
+// each 32-bit high product is added as (u64) x one + a, one v_mad_u64_u32 (a
+// zero-extending 64-bit add would need a register pair with a zero high word, a copy
+// per term; one shared value would let the compiler sum the high products first, with
+// the same copies). The high word is summed in 32-bit arithmetic behind an empty asm
+// (as in mul_shoup4).
+template <int NP, class HP>
+__device__ __forceinline__ void fixed_sum(const uint64_t (&c)[NP], const HP (&h)[NP], uint64_t bias,
+                                          const uint32_t (&one)[NP][2], uint32_t& lo, uint32_t& hi) {
+  uint64_t a = bias;
+  hi = 0;
+#pragma unroll
+  for (int r = 0; r < NP; ++r) {
+    const uint32_t c0 = (uint32_t)c[r], c1 = (uint32_t)(c[r] >> 32);
+    a = (uint64_t)c0 * h[r][2] + a;
+    a = (uint64_t)c1 * h[r][1] + a;
+    a = (uint64_t)__umulhi(c0, h[r][1]) * one[r][0] + a;
+    a = (uint64_t)__umulhi(c1, h[r][0]) * one[r][1] + a;
+    hi += c0 * h[r][3] + c1 * h[r][2];
+  }
+  hi += (uint32_t)(a >> 32);
+  __asm__("" : "+v"(hi));
+  lo = (uint32_t)a;
 }
 
 // a * w mod p in [0, 4p) for any a < 2^64, pn = 2^64 - p: Shoup's quotient
@@ -234,11 +251,15 @@ __device__ __forceinline__ void ntt_forward(uint64_t* x, uint64_t* lds, const ui
 }
 
 // Inverse pass PASS (layout Q1..Q4) on NP transforms at once: three
-// Gentleman-Sande stages, spans S, 2S, 4S, on inputs below 8p. Stage s sees
-// inputs below 8p 2^s; element k keeps its sum through the stages after the last
-// one in which it took a product (k's highest set bit), so at the end elements
-// 0, 1 are below 64p, 16p and the rest below 8p. END brings elements 0, 1 below
-// 3p, so the next pass again starts below 8p.
+// Gentleman-Sande stages, spans S, 2S, 4S, on inputs below B = 8p 2^EIN. Stage s
+// sees inputs below B 2^s; element k keeps its sum through the stages after the
+// last one in which it took a product (k's highest set bit), so at the end element
+// 0 is below 8B, element 1 below 16p and the rest below 8p. END brings elements 0, 1
+// below 3p. Passes alternate: one from below 8p (EIN = 0) leaves everything below
+// 64p, the next starts there (EIN = 3) and ends below 512p < 2^63 (p < 2^54), where
+// END reduces; half the passes need no reduction. Every difference of a pass is
+// biased by the bound of its last stage, 4B (one constant per pass and prime, where
+// one per stage ran out of scalar registers); the differences stay below 8B.
 template <int PASS, int NN = kNttN>
 struct InvLayout {
   static constexpr int S = PASS == 0 ? 1 : PASS == 1 ? 8 : PASS == 2 ? 64 : NN / 8;  // stride in k
@@ -303,7 +324,7 @@ __device__ __forceinline__ Tw tw512(const uint64_t* tw, uint32_t t, int k, int t
 // LASTMUL = false (last pass only): the last stage (span N/2, one twiddle) leaves its
 // differences X + B - Y unmultiplied, for an epilogue that folds the twiddle into its
 // own constants.
-template <int NP, int PASS, bool END, int NN = kNttN, bool LASTMUL = true>
+template <int NP, int PASS, bool END, int NN = kNttN, bool LASTMUL = true, int EIN = 0>
 __device__ __forceinline__ void inv_pass(uint64_t (&x)[NP][8], int tid,
                                          const uint64_t* const (&tw)[NP], const InvMod (&md)[NP]) {
   constexpr int S = InvLayout<PASS, NN>::S;
@@ -319,11 +340,12 @@ __device__ __forceinline__ void inv_pass(uint64_t (&x)[NP][8], int tid,
 #pragma unroll
       for (int r = 0; r < NP; ++r) {
         if (!LASTMUL && st == 2) {
-          const uint64_t d = x[r][k] + (md[r].p8 << st) - x[r][k + sp];
+          const uint64_t d = x[r][k] + (md[r].p8 << (2 + EIN)) - x[r][k + sp];
           x[r][k] += x[r][k + sp];
           x[r][k + sp] = d;
         } else {
-          gs_bfly(x[r][k], x[r][k + sp], tw512<PASS, NN>(tw[r], t, k, tid), md[r].p8 << st, md[r].pn);
+          gs_bfly(x[r][k], x[r][k + sp], tw512<PASS, NN>(tw[r], t, k, tid), md[r].p8 << (2 + EIN),
+                  md[r].pn);
         }
       }
     }
@@ -363,29 +385,29 @@ __device__ __forceinline__ void wave_exchange_fence() {
 
 // Inverse transforms of NP primes without the 1/N factor: x[r] in layout Q1,
 // bit-reversed order, below 8p_r -> layout Q4, natural order, congruent to the
-// result mod p_r (below 64p_r, not reduced). lds holds NP exchange buffers. With
+// result mod p_r (below 512p_r, not reduced). lds holds NP exchange buffers. With
 // LASTMUL = false, x[r][4..7] are congruent to the result divided by the last
 // stage's twiddle (psi^-bitrev(1)).
 template <int NP, int NN = kNttN, bool LASTMUL = true>
 __device__ __forceinline__ void ntt_inverse(uint64_t (&x)[NP][8], uint64_t* lds,
                                             const uint64_t* const (&tw)[NP],
                                             const InvMod (&md)[NP], int tid) {
-  inv_pass<NP, 0, true, NN>(x, tid, tw, md);
+  inv_pass<NP, 0, false, NN>(x, tid, tw, md);
   __syncthreads();  // no wave still reads the previous transform's Q4 positions
   inv_store<NP, 0, 1, NN>(lds, x, tid);
   wave_exchange_fence();
   inv_load<NP, 1, 1, NN>(lds, x, tid);
-  inv_pass<NP, 1, true, NN>(x, tid, tw, md);
+  inv_pass<NP, 1, true, NN, true, 3>(x, tid, tw, md);
   wave_exchange_fence();  // every lane of the wave has read its Q2 positions
   inv_store<NP, 1, 2, NN>(lds, x, tid);
   wave_exchange_fence();
   inv_load<NP, 2, 2, NN>(lds, x, tid);
-  inv_pass<NP, 2, true, NN>(x, tid, tw, md);
+  inv_pass<NP, 2, false, NN>(x, tid, tw, md);
   __syncthreads();  // every wave is done with its own block
   inv_store<NP, 2, 3, NN>(lds, x, tid);
   __syncthreads();
   inv_load<NP, 3, 3, NN>(lds, x, tid);
-  inv_pass<NP, 3, false, NN, LASTMUL>(x, tid, tw, md);
+  inv_pass<NP, 3, false, NN, LASTMUL, 3>(x, tid, tw, md);
 }
 
 // Plain radix-2 transforms in LDS for any ring degree N <= kNttN (one stage per

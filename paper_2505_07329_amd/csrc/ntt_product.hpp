@@ -279,15 +279,34 @@ __device__ __forceinline__ void ntt_product(BatchPtr bt, uint32_t ii, uint32_t l
       // coefficients within 8 units below a rounding tie (all of them when forced)
       uint32_t tie = bt->force_exact ? 0xffu : 0u;
       const uint32_t qbits = bt->rc.qbits;
+      const uint64_t half = 1ull << (63 - qbits);
+      uint32_t one[NP][2];
+#pragma unroll
+      for (int r = 0; r < NP; ++r)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          one[r][i] = 1;
+          __asm__ volatile("" : "+s"(one[r][i]));  // volatile: four distinct registers
+        }
+      typedef const __attribute__((address_space(4))) uint32_t* HPtr;
+      HPtr h0[NP], h1[NP];
+#pragma unroll
+      for (int r = 0; r < NP; ++r) {
+        h0[r] = (HPtr)bt->ntt.h[r];
+        h1[r] = (HPtr)bt->ntt.hl[r];
+      }
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        // k >= 4: x holds C[m] / w (w the last stage's twiddle), and hl carries w
-        uint64_t A = fixed_part(x[0][k], k < 4 ? bt->ntt.h[0] : bt->ntt.hl[0]);
-        if (NP == 2) A += fixed_part(x[NP - 1][k], k < 4 ? bt->ntt.h[NP - 1] : bt->ntt.hl[NP - 1]);
-        // A = bits 64..127 of sum_p c_p H_p 2^96 (mod 2^128), at most 7 units low:
-        // c 2^32 / q mod 2^32 in 32.32 fixed point, rounded to q_out = 2^qbits
+        // k >= 4: x holds C[m] / w (w the last stage's twiddle), and hl carries w.
+        // V = W + one half, W = bits 64..127 of sum_p c_p H_p 2^96 (mod 2^128), at most 7
+        // units low: c 2^32 / q mod 2^32 in 32.32 fixed point, rounded to q_out = 2^qbits
+        uint64_t c[NP];
+#pragma unroll
+        for (int r = 0; r < NP; ++r) c[r] = x[r][k];
+        uint32_t vlo, vhi;
+        fixed_sum<NP>(c, k < 4 ? h0 : h1, half, one, vlo, vhi);
         bool near;
-        res[k] = round_qout_low8(A, qbits, near);
+        res[k] = round_qout_near(vlo, vhi, qbits, near);
         tie |= (near ? 1u : 0u) << k;
       }
       while (tie) {  // rare: exact CRT and switch of the coefficient

@@ -156,17 +156,20 @@ __device__ inline uint32_t round_qout(uint64_t W, uint32_t k, int64_t& dist) {
   return (uint32_t)((W >> sh) + (frac >= half ? 1 : 0)) & qout_mask(k);
 }
 
-// The same rounding for a W known to be at most 7 units low: floor((W + 2^(sh-1)) /
-// 2^sh) mod 2^k (adding one half carries into the integer part exactly when the
-// fraction reaches it, and a wrap past 2^64 is a multiple of 2^sh 2^k), and in near
-// whether the fraction lies within 8 units below one half, where the exact value may
-// round the other way: then the fraction of V = W + half is at least 2^sh - 8, i.e.
-// the low sh bits of V + 8 are below 8, i.e. (V + 8) 2^k mod 2^64 < 8 2^k.
-__device__ __forceinline__ uint32_t round_qout_low8(uint64_t W, uint32_t k, bool& near) {
-  const uint32_t sh = 64 - k;  // fraction bits, 32..63
-  const uint64_t V = W + (1ull << (sh - 1));
-  near = ((V + 8) << k) < (8ull << k);
-  return (uint32_t)(V >> sh);
+// The same rounding for a W known to be at most 7 units low, from the words of
+// V = W + 2^(sh-1) (mod 2^64; the caller adds the half), k = 1..32, sh = 64 - k >= 32:
+// floor(V / 2^sh) mod 2^k = vhi >> (32 - k) (adding one half carries into the integer
+// part exactly when the fraction reaches it, and a wrap past 2^64 is a multiple of
+// 2^sh 2^k), and in near whether the fraction may lie within 8 units below one half,
+// where the exact value may round the other way. Then the fraction of V is at least
+// 2^sh - 8, so the low word of V is at least 2^32 - 8: that test flags every such W,
+// and when k < 32 also some others (with probability 2^-29), which only take the exact
+// route.
+__device__ __forceinline__ uint32_t round_qout_near(uint32_t vlo, uint32_t vhi, uint32_t k,
+                                                    bool& near) {
+  __asm__("" : "+v"(vlo));  // one 32-bit compare (else a masked 64-bit one)
+  near = vlo >= 0xFFFFFFF8u;
+  return vhi >> (32 - k);
 }
 
 // Shoup multiplication a * w mod q, wp = floor(w 2^64 / q), a < 2^64, q < 2^63.

@@ -3,14 +3,16 @@ round(c 2^k / q) mod 2^k from unreduced residues c_p of a coefficient c.
 
 The kernel forms X = sum_p c_p H_p mod 2^32 in 32.32 fixed point, H_p = ((q/q_p)^-1 mod
 q_p) 2^32 / q_p held as h_p = floor(crt_p 2^128 / q_p) mod 2^128, taking only the
-partial products of c_p h_p at and above bit 64 (the 64-bit word `fixed_part`). The
-model repeats those integer steps (32-bit halves, 64-bit wrapping sums) and checks,
-against exact big-integer arithmetic, the facts the kernel relies on:
+partial products of c_p h_p at and above bit 64 (a 64-bit word per prime; the kernel
+sums the words of all primes in one accumulation, `fixed_sum`). The model repeats those
+integer steps (32-bit halves, 64-bit wrapping sums) and checks, against exact
+big-integer arithmetic, the facts the kernel relies on:
   * the estimate is never above floor(c 2^64 / q) mod 2^64 and at most 7 units of
     2^-32 below it, for any 64-bit lift of the residues (the inverse transform hands
     over values below 64 q_p, not reduced);
   * its rounding to 2^k (k = 1..32) is the exact rounding unless the fraction lies
-    within 8 units below one half (then the kernel recomputes exactly);
+    within 8 units below one half (then the kernel recomputes exactly; its flag, the
+    low word of the estimate plus one half at least 2^32 - 8, covers that window);
   * values next to rounding ties reach that window.
 Inputs: uniform c, random lifts of its residues, c next to ties of every k tested,
 c at the window's edge; one prime (N = 2048 parameters) and two (N = 4096).
@@ -70,13 +72,30 @@ def round_qout(W, k):
     return val, frac - half
 
 
+def fixed_sum(cs, hs, bias):
+    """The kernel's accumulation of the same words for all primes at once: bias, then
+    per prime the two full products and the two high products into a 64-bit sum, and
+    the low halves of the top products into a separate 32-bit high word."""
+    a, hi = bias, 0
+    for c, h in zip(cs, hs):
+        c0, c1 = c & M32, c >> 32
+        a = (a + c0 * h[2] + c1 * h[1] + ((c0 * h[1]) >> 32) + ((c1 * h[0]) >> 32)) & M64
+        hi = (hi + c0 * h[3] + c1 * h[2]) & M32
+    hi = (hi + (a >> 32)) & M32
+    return a & M32, hi
+
+
+def round_qout_near(vlo, vhi, k):
+    """The NTT kernel's form of the same rounding from the words of V = W + one half
+    (mod 2^64): value vhi >> (32 - k) = V >> (64 - k), and the window flag: the low word
+    of V at least 2^32 - 8."""
+    return vhi >> (32 - k), vlo >= (1 << 32) - 8
+
+
 def round_qout_low8(W, k):
-    """The NTT kernel's form of the same rounding: V = W + one half (mod 2^64), value
-    V >> (64 - k), and the window flag from the low bits of V + 8 shifted up by k."""
-    sh = 64 - k
-    V = (W + (1 << (sh - 1))) & M64
-    near = (((V + 8) << k) & M64) < (8 << k)
-    return V >> sh, near
+    """round_qout_near of W + one half."""
+    V = (W + (1 << (63 - k))) & M64
+    return round_qout_near(V & M32, V >> 32, k)
 
 
 def exact_units(c, q):
@@ -147,9 +166,11 @@ def test_window_needs_the_exact_route():
 
 @pytest.mark.parametrize("k", list(range(1, 33)))
 def test_rounding_forms_agree(k):
-    """round_qout_low8 (the NTT epilogue) gives round_qout's value and flags exactly the
-    fractions 1..8 units below one half, for W next to every kind of boundary: the
-    half, the integer steps, the window's edges, and the wrap past 2^64."""
+    """round_qout_low8 (the NTT epilogue) gives round_qout's value and flags every
+    fraction 1..8 units below one half (exactly those at k = 32; at k < 32 also those
+    whose fraction is 1..8 units below any multiple of 2^32, which only take the exact
+    route), for W next to every kind of boundary: the half, the integer steps, the
+    window's edges, and the wrap past 2^64."""
     sh = 64 - k
     half = 1 << (sh - 1)
     rng = random.Random(1000 + k)
@@ -165,7 +186,25 @@ def test_rounding_forms_agree(k):
         v_ref, dist = round_qout(W, k)
         v, near = round_qout_low8(W, k)
         assert v == v_ref, (W, k)
-        assert near == (-8 <= dist < 0), (W, k, dist)
+        if -8 <= dist < 0:
+            assert near, (W, k, dist)
+        elif near:
+            assert k < 32 and (dist + 8) % (1 << 32) < 8, (W, k, dist)
+    # uniform fractions: the false alarms have probability 2^-29 each
+    assert not any(round_qout_low8(rng.randrange(1 << 64), k)[1] for _ in range(20000))
+
+
+def test_fixed_sum_equals_the_per_prime_words():
+    """The kernel's single accumulation (fixed_sum) equals the sum of the per-prime
+    words plus the bias, mod 2^64, for any 64-bit lifts."""
+    rng = random.Random(11)
+    for primes in (P2, P1):
+        hs = epilogue_constants(primes)
+        for _ in range(3000):
+            cs = [rng.randrange(1 << 64) for _ in primes]
+            bias = rng.randrange(1 << 64)
+            lo, hi = fixed_sum(cs, hs, bias)
+            assert (hi << 32 | lo) == (estimate(cs, hs) + bias) & M64
 
 
 def last_stage_twiddle(p, N):
