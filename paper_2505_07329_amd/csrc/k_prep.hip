@@ -42,9 +42,145 @@ __global__ void __launch_bounds__(256) body_kernel(Batch) {
   body_block<D, RAW>(bt, ii, blk - bt->body_start[ii], threadIdx.x);
 }
 
+// The body of unpacked rows on the int8 matrix cores: S_l[j][t] = sum_k w_j[k] d_l[t][k]
+// for every digit plane l of every token's body is an int8 matrix product (rows j against
+// columns (token, digit)), exact in int32 (|S_l| <= 127^2 K < 2^31 for K <= 2 N). A wave
+// owns 32 rows and NTW column tiles of 32 columns, each TPT tokens of SL digit slots (the
+// slots past D are zero), so it reads each weight fragment once for NTW products; the
+// four waves of a block take consecutive tokens of the same rows. The operands of four
+// k-steps are requested before their products (the loop is bound by load latency
+// otherwise). The digit sums of a (row, token) pair lie in one row of a tile; they meet
+// through LDS, and V = sum_l 255^l S_l is switched exactly, as in body_block.
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef int v16i_t __attribute__((ext_vector_type(16)));
+
+template <int D>
+struct BodyMma {
+  static constexpr int SL = D == 14 ? 16 : 8;  // digit slots per token
+  static constexpr int TPT = 32 / SL;          // tokens per column tile
+  static constexpr int NTW = 2;                // column tiles per wave
+  static constexpr int TPB = 4 * NTW * TPT;    // tokens per block
+};
+
+template <int D, bool RAW>
+__global__ void __launch_bounds__(256) body_mma_kernel(Batch) {
+  typedef BodyMma<D> G;
+  __shared__ int32_t tr[4][32][33];  // per wave: one column tile, rows x columns
+  const BatchPtr bt = kernarg_batch();
+  const uint32_t blk = linear_block();
+  const uint32_t nb = bt->n;
+  if (blk >= bt->body_start[nb]) return;
+  const uint32_t ii = find_item(bt->body_start, nb, blk);
+  const RingConst rc = kernarg_load(&bt->rc);
+  const Item a = kernarg_load(&bt->it[ii]);
+  const MatArgs& m = a.m;
+  const uint32_t N = rc.N;
+  const uint32_t loc = blk - bt->body_start[ii];
+  const uint32_t tgs = (a.T + G::TPB - 1) / G::TPB;  // token groups, fastest in the block order
+  const uint32_t j0 = (loc / tgs) * 32, tb = (loc % tgs) * G::TPB;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = lane & 31, g = lane >> 5;
+  // operands of this lane: row j0 + c of the weights; column c of each column tile,
+  // token tw + f TPT + c / SL, digit c % SL (zero past D or past the last token)
+  const uint32_t tw = tb + wave * G::NTW * G::TPT;
+  const int l = c % G::SL;
+  const int8_t* wrow = m.w + (size_t)(j0 + c) * m.kw + 16 * g;  // j0 + 32 <= rows_pad
+  const int8_t* eb[G::NTW];
+  bool live[G::NTW];
+#pragma unroll
+  for (int f = 0; f < G::NTW; ++f) {
+    const uint32_t t = tw + f * G::TPT + c / G::SL;
+    live[f] = l < D && t < a.T;
+    const uint32_t tc = min(t, a.T - 1), lc = min(l, D - 1);
+    eb[f] = a.ebody + (size_t)(tc * D + lc) * m.L * N + 16 * g;
+  }
+  v16i_t acc[G::NTW];
+#pragma unroll
+  for (int f = 0; f < G::NTW; ++f) acc[f] = v16i_t{0};
+  for (uint32_t i = 0; i < m.L; ++i) {
+    const uint32_t kb = min(N, m.k - i * N);
+    const uint32_t kp = (kb + 31u) & ~31u;  // the weight rows are zero from K on
+    for (uint32_t k = 0; k < kp; k += 128) {
+      const uint32_t steps = min(4u, (kp - k) >> 5);  // uniform
+      v4i_t wa[4], e[4][G::NTW];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        if ((uint32_t)s >= steps) break;
+        wa[s] = *(const v4i_t*)(wrow + (size_t)i * N + k + 32 * s);
+#pragma unroll
+        for (int f = 0; f < G::NTW; ++f) e[s][f] = *(const v4i_t*)(eb[f] + (size_t)i * N + k + 32 * s);
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        if ((uint32_t)s >= steps) break;
+#pragma unroll
+        for (int f = 0; f < G::NTW; ++f)
+          acc[f] = __builtin_amdgcn_mfma_i32_32x32x32_i8(wa[s], live[f] ? e[s][f] : v4i_t{0}, acc[f], 0,
+                                                         0, 0);
+      }
+    }
+  }
+  // accumulator element e of a lane: row 8 (e / 4) + 4 g + e % 4, column c
+#pragma unroll
+  for (int f = 0; f < G::NTW; ++f) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) tr[wave][8 * (e >> 2) + 4 * g + (e & 3)][c] = acc[f][e];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int q = lane; q < 32 * G::TPT; q += 64) {
+      const uint32_t r = q & 31, tt = q >> 5;
+      const uint32_t j = j0 + r, t = tw + f * G::TPT + tt;
+      i128 V = 0;
+#pragma unroll
+      for (int d = D - 1; d >= 0; --d) V = V * 255 + tr[wave][r][tt * G::SL + d];
+      if (j < m.rows && t < a.T) {
+        const size_t row = (size_t)t * m.rows + j;
+        if (RAW) {
+          uint64_t* o = (uint64_t*)a.out;
+          for (uint32_t p = 0; p < rc.P; ++p)
+            o[bt->gadget ? row * (N + rc.P) + N + p : (row * rc.P + p) * (N + 1) + N] =
+                mod_i128(V, bt->rc.q[p]);
+        } else {
+          ((uint32_t*)a.out)[row * (N + 1) + N] = switch_exact(V, rc);
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();  // every lane has read the tile before the next is written
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 hipError_t launch_body(const Batch& b, hipStream_t s) {
   const uint32_t blocks = b.body_start[b.n];
   if (blocks == 0) return hipSuccess;
+  // unpacked rows everywhere: the matrix-core body, blocks of 32 rows x TPB tokens
+  bool mma = true;
+  for (uint32_t x = 0; x < b.n; ++x)
+    mma = mma && b.it[x].m.n_o == 1 && b.it[x].m.k <= 2 * b.rc.N && b.it[x].m.rows_pad % 32 == 0 &&
+          (reinterpret_cast<uintptr_t>(b.it[x].ebody) & 15) == 0;
+  if (mma) {
+    Batch mb = b;
+    const uint32_t tpb = b.rc.D == 7 ? BodyMma<7>::TPB : BodyMma<14>::TPB;
+    for (uint32_t x = 0; x < b.n; ++x) {
+      const Item& it = b.it[x];
+      mb.body_start[x + 1] = mb.body_start[x] + (it.m.rows + 31) / 32 * ((it.T + tpb - 1) / tpb);
+    }
+    const dim3 grid = grid_for(mb.body_start[mb.n]);
+    if (b.rc.D == 7) {
+      if (b.raw)
+        hipLaunchKernelGGL((body_mma_kernel<7, true>), grid, dim3(256), 0, s, mb);
+      else
+        hipLaunchKernelGGL((body_mma_kernel<7, false>), grid, dim3(256), 0, s, mb);
+    } else {
+      if (b.raw)
+        hipLaunchKernelGGL((body_mma_kernel<14, true>), grid, dim3(256), 0, s, mb);
+      else
+        hipLaunchKernelGGL((body_mma_kernel<14, false>), grid, dim3(256), 0, s, mb);
+    }
+    return hipGetLastError();
+  }
   const dim3 grid = grid_for(blocks);
   if (b.rc.D == 7) {
     if (b.raw)
