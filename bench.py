@@ -143,16 +143,16 @@ KERNEL_TRAFFIC = {
     "mask": {"sources": ["k_mask.hip"], "fetch_bytes": 4382826959, "write_bytes": 4766587301,
              "sha256": "8ab8cb6fb513b23f1ce566dc604e2116b7a46302abe49a7d36941d71ad8942ee"},
     "ntt": {"sources": ["k_ntt.hip", "ntt_product.hpp", "ntt_device.hpp", "ks_round.hpp"],
-            "fetch_bytes": 5373620313,
-            "write_bytes": 4337019275,
-            "sha256": "31910bb99b9286a6f27116520a9aefba74e307878218bd8f2e0d4df78c5ddafd"},
+            "fetch_bytes": 5183104896,
+            "write_bytes": 4340102880,
+            "sha256": "7ee3cabe71b3653be70b16a8cce80823a6a055e28dafb73d71aedfa0edd5e3ae"},
     # the product with masks rounded for KeySwitch packing (ct_matmul_pack, --keyswitch)
     "ntt_ks": {"sources": ["k_ntt.hip", "ntt_product.hpp", "ntt_device.hpp", "ks_round.hpp"],
-               "fetch_bytes": 6254459648, "write_bytes": 8674174168,
-               "sha256": "31910bb99b9286a6f27116520a9aefba74e307878218bd8f2e0d4df78c5ddafd"},
+               "fetch_bytes": 6221142630, "write_bytes": 8675301344,
+               "sha256": "7ee3cabe71b3653be70b16a8cce80823a6a055e28dafb73d71aedfa0edd5e3ae"},
     "ksacc": {"sources": ["k_keyswitch.hip", "ntt_device.hpp", "ks_round.hpp"],
-              "fetch_bytes": 12998295864, "write_bytes": 536870912,
-              "sha256": "e7adfe24524553db64447694479e95145df1ec7bb62cc55de4fc9d042be57c54"},
+              "fetch_bytes": 12994951457, "write_bytes": 536870912,
+              "sha256": "83de4b46aa64c8d1505de406d17a52ae4d68c17ad971a6b9bc2f52fb6bb09092"},
 }
 
 
