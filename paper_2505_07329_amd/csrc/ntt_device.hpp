@@ -120,15 +120,18 @@ __device__ __forceinline__ void fixed_sum(const uint64_t (&c)[NP], const HP (&h)
 // a * w mod p in [0, 4p) for any a < 2^64, pn = 2^64 - p: Shoup's quotient
 // floor(a wp / 2^64) less the partial products below bit 64 (at most 2 low), and
 // the remainder a w + q pn taken mod 2^64.
-// SPLIT: the remainder's high word is summed in 32-bit arithmetic behind an empty asm.
-// Without it the combiner folds (h << 32) | lo(r) back into a 64-bit add of a
-// zero-extended word (a register copy and a 64-bit add where one 32-bit add does); the
-// split form is one instruction shorter in the transforms and measured 4.5 % faster on
-// the 2048 x 2048 projection, 9 % at K = 8192. An isolated chain of products runs
-// faster in the combined form, so the rate microbenchmarks time both. (Two other forms
-// measured slower: the cross products chained through 64-bit v_mad_u64_u32, and the
-// high-word add written as an instruction in inline asm, opaque to the scheduler's
-// latency model.)
+// SPLIT (the kernels' form): the remainder's high word r_hi + a0 w1 + a1 w0 + q0 n1 +
+// q1 n0 is formed from two 64-bit multiply-adds, a1 w0 + a0 w1 and q1 n0 + q0 n1 (kept
+// whole behind an empty asm, so each is one v_mad_u64_u32 on a 32-bit product), and one
+// three-way add, itself behind an empty asm: without them the compiler folds
+// (h << 32) | lo(r) back into a 64-bit add of a zero-extended word (a register copy and
+// a 64-bit add) and spends four multiplies and two three-way adds on the cross terms.
+// 11 instructions against 13; measured 4.5 % + 1.3 % faster on the 2048 x 2048
+// projection and 9 % at K = 8192. An isolated chain of products runs faster in the
+// combined form, so the rate microbenchmarks time both. (Two other forms measured
+// slower: the four cross products chained through 64-bit v_mad_u64_u32 with the high
+// word added by inline asm, and the high-word add written as an instruction in inline
+// asm, opaque to the scheduler's latency model.)
 template <bool SPLIT = true>
 __device__ __forceinline__ uint64_t mul_shoup4(uint64_t a, uint64_t w, uint64_t wp, uint64_t pn) {
   const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
@@ -140,8 +143,15 @@ __device__ __forceinline__ uint64_t mul_shoup4(uint64_t a, uint64_t w, uint64_t 
   const uint32_t n0 = (uint32_t)pn, n1 = (uint32_t)(pn >> 32);
   uint64_t r = (uint64_t)a0 * w0;
   r = (uint64_t)q0 * n0 + r;
-  uint32_t h = (uint32_t)(r >> 32) + a0 * w1 + a1 * w0 + q0 * n1 + q1 * n0;
-  if (SPLIT) __asm__("" : "+v"(h));
+  if (SPLIT) {
+    uint64_t t1 = (uint64_t)a1 * w0 + (uint32_t)(a0 * w1);
+    uint64_t t2 = (uint64_t)q1 * n0 + (uint32_t)(q0 * n1);
+    __asm__("" : "+v"(t1), "+v"(t2));
+    uint32_t h = (uint32_t)(r >> 32) + (uint32_t)t1 + (uint32_t)t2;
+    __asm__("" : "+v"(h));
+    return ((uint64_t)h << 32) | (uint32_t)r;
+  }
+  const uint32_t h = (uint32_t)(r >> 32) + a0 * w1 + a1 * w0 + q0 * n1 + q1 * n0;
   return ((uint64_t)h << 32) | (uint32_t)r;
 }
 
