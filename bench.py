@@ -43,10 +43,10 @@ INT8_PEAK_TOPS = 5000.0  # MI355X published dense int8 matrix peak, 5.0 POP/s
 # products: one per butterfly of the inverse transforms and one per pointwise product. The
 # peak is the device's measured rate of that product (rlwe_measure_peaks: the kernel's
 # truncated-quotient Shoup product in register-only chains). A lazy Gentleman-Sande
-# butterfly is that product plus a sum and a biased difference, 16 VALU instructions
-# against the product's 12 (the kernel's split form); the butterfly rate at the measured
-# issue rate is reported as a kernel-model ceiling beside it.
-BFLY_MODEL_INSTR = 16
+# butterfly is that product plus a sum and a biased difference, 15 VALU instructions
+# against the product's 11 (the kernels' form); the butterfly rate at the measured issue
+# rate is reported as a kernel-model ceiling beside it.
+BFLY_MODEL_INSTR = 15
 
 
 def measured_peaks():
