@@ -143,16 +143,16 @@ KERNEL_TRAFFIC = {
     "mask": {"sources": ["k_mask.hip"], "fetch_bytes": 4382826959, "write_bytes": 4766587301,
              "sha256": "8ab8cb6fb513b23f1ce566dc604e2116b7a46302abe49a7d36941d71ad8942ee"},
     "ntt": {"sources": ["k_ntt.hip", "ntt_product.hpp", "ntt_device.hpp", "ks_round.hpp"],
-            "fetch_bytes": 5183104896,
-            "write_bytes": 4340102880,
-            "sha256": "7ee3cabe71b3653be70b16a8cce80823a6a055e28dafb73d71aedfa0edd5e3ae"},
+            "fetch_bytes": 5427843915,
+            "write_bytes": 4331271291,
+            "sha256": "bcc9f3e766120b3e370f1708fee24df6bf2068c632dca36da064bcfe0e167f7b"},
     # the product with masks rounded for KeySwitch packing (ct_matmul_pack, --keyswitch)
     "ntt_ks": {"sources": ["k_ntt.hip", "ntt_product.hpp", "ntt_device.hpp", "ks_round.hpp"],
-               "fetch_bytes": 6221142630, "write_bytes": 8675301344,
-               "sha256": "7ee3cabe71b3653be70b16a8cce80823a6a055e28dafb73d71aedfa0edd5e3ae"},
+               "fetch_bytes": 6331299466, "write_bytes": 8669613432,
+               "sha256": "bcc9f3e766120b3e370f1708fee24df6bf2068c632dca36da064bcfe0e167f7b"},
     "ksacc": {"sources": ["k_keyswitch.hip", "ntt_device.hpp", "ks_round.hpp"],
-              "fetch_bytes": 12994951457, "write_bytes": 536870912,
-              "sha256": "83de4b46aa64c8d1505de406d17a52ae4d68c17ad971a6b9bc2f52fb6bb09092"},
+              "fetch_bytes": 13007274145, "write_bytes": 536870912,
+              "sha256": "282d0a1962e40c1e3caffecc5b42429e11efa078d072ba147b2bc9f0fa450cf4"},
 }
 
 
