@@ -14,8 +14,8 @@
 // Epilogue, switched output: the integer V = sum_l 255^l S_l satisfies
 // V = a'_j[n] (mod q), and round(V 2^32 / q) mod 2^32 is the switched
 // coefficient. Digits below l0 change V 2^32/q by less than the host-computed
-// bound eps; they are skipped, the rest is folded into a 128-bit integer U and
-// multiplied by G = 255^l0 2^32 / q in fixed point. Where the result lies
+// bound eps; they are skipped, and every kept digit adds S_l G_l in 32.32 fixed
+// point mod 2^64, G_l = round(255^l 2^96 / q) mod 2^96. Where the sum lies
 // within eps of a rounding tie, the element is recomputed exactly from all
 // digits (rare: probability about 2 eps). Raw output: all digits, V mod q_p.
 #include "rlwe_internal.hpp"
