@@ -141,7 +141,7 @@ def roofline(products, kt, N, P, peaks, traffic=None):
 # other source the roofline reports traffic as null.
 KERNEL_TRAFFIC = {
     "mask": {"sources": ["k_mask.hip"], "fetch_bytes": 4382826959, "write_bytes": 4766587301,
-             "sha256": "8ab8cb6fb513b23f1ce566dc604e2116b7a46302abe49a7d36941d71ad8942ee"},
+             "sha256": "d31818600eff6cf99abfb69ae5fdda8bf673103f1a029ac55bbd206c5b7eaf12"},
     "ntt": {"sources": ["k_ntt.hip", "ntt_product.hpp", "ntt_device.hpp", "ks_round.hpp"],
             "fetch_bytes": 5427843915,
             "write_bytes": 4331271291,
