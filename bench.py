@@ -145,11 +145,11 @@ KERNEL_TRAFFIC = {
     "ntt": {"sources": ["k_ntt.hip", "ntt_product.hpp", "ntt_device.hpp", "ks_round.hpp"],
             "fetch_bytes": 5427843915,
             "write_bytes": 4331271291,
-            "sha256": "bcc9f3e766120b3e370f1708fee24df6bf2068c632dca36da064bcfe0e167f7b"},
+            "sha256": "4b63e1dcc950517b63600462b23f1938014968164bad10c23eb08ca900a89691"},
     # the product with masks rounded for KeySwitch packing (ct_matmul_pack, --keyswitch)
     "ntt_ks": {"sources": ["k_ntt.hip", "ntt_product.hpp", "ntt_device.hpp", "ks_round.hpp"],
                "fetch_bytes": 6331299466, "write_bytes": 8669613432,
-               "sha256": "bcc9f3e766120b3e370f1708fee24df6bf2068c632dca36da064bcfe0e167f7b"},
+               "sha256": "4b63e1dcc950517b63600462b23f1938014968164bad10c23eb08ca900a89691"},
     "ksacc": {"sources": ["k_keyswitch.hip", "ntt_device.hpp", "ks_round.hpp"],
               "fetch_bytes": 13007274145, "write_bytes": 536870912,
               "sha256": "282d0a1962e40c1e3caffecc5b42429e11efa078d072ba147b2bc9f0fa450cf4"},

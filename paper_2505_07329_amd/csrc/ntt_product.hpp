@@ -148,32 +148,31 @@ __device__ __forceinline__ void ntt_product(BatchPtr bt, uint32_t ii, uint32_t l
       // mask elements as (residue, companion) pairs
       const Rsrc ra = buf_rsrc(ahat + (size_t)t * NB * NP * NN * 2, NB * NP * NN * 16);
       const Rsrc rw = buf_rsrc(what + (size_t)j * NB * NP * NN, NB * NP * NN * 8);
-      // The first block's operands of every prime are loaded together (48 words per
-      // thread); a second block's prime by prime, while the first block's sums are live.
+      // One block: the operands of every prime are loaded together (48 words per thread).
+      // Two blocks: prime by prime, both blocks' operands of the prime together (48 words),
+      // so that a token waits for two rounds of loads rather than three.
+      constexpr int NG = NB == 1 ? 1 : NP;  // load groups
 #pragma unroll
-      for (int i = 0; i < NB; ++i) {
+      for (int rg = 0; rg < NG; ++rg) {
+        constexpr int GB = NB == 1 ? NP : 2;  // (block, prime) pairs of a group
+        uint64_t wv[GB][8], av[GB][16];
 #pragma unroll
-        for (int rg = 0; rg < (i == 0 ? 1 : NP); ++rg) {
-          const int r0 = i == 0 ? 0 : rg, r1 = i == 0 ? NP : rg + 1;  // primes of this group
-          uint64_t wv[NP][8], av[NP][16];
+        for (int u = 0; u < GB; ++u) {
+          const int i = NB == 1 ? 0 : u, r = NB == 1 ? u : rg;
+          const uint32_t e0 = (i * NP + r) * NN;  // element offset of (block, prime)
 #pragma unroll
-          for (int r = 0; r < NP; ++r) {
-            if (r < r0 || r >= r1) continue;
-            const uint32_t e0 = (i * NP + r) * NN;  // element offset of (block, prime)
+          for (int k = 0; k < 8; ++k) wv[u][k] = buf_ld64(rw, 8 * tid, 8 * (e0 + (NN / 8) * k));
 #pragma unroll
-            for (int k = 0; k < 8; ++k) wv[r][k] = buf_ld64(rw, 8 * tid, 8 * (e0 + (NN / 8) * k));
+          for (int k = 0; k < 8; ++k)
+            buf_ld128(ra, 16 * tid, 16 * (e0 + (NN / 8) * k), av[u][2 * k], av[u][2 * k + 1]);
+        }
 #pragma unroll
-            for (int k = 0; k < 8; ++k)
-              buf_ld128(ra, 16 * tid, 16 * (e0 + (NN / 8) * k), av[r][2 * k], av[r][2 * k + 1]);
-          }
+        for (int u = 0; u < GB; ++u) {
+          const int i = NB == 1 ? 0 : u, r = NB == 1 ? u : rg;
 #pragma unroll
-          for (int r = 0; r < NP; ++r) {
-            if (r < r0 || r >= r1) continue;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-              const uint64_t v = mul_shoup4(wv[r][k], av[r][2 * k], av[r][2 * k + 1], md[r].pn);
-              x[r][k] = i == 0 ? v : x[r][k] + v;
-            }
+          for (int k = 0; k < 8; ++k) {
+            const uint64_t v = mul_shoup4(wv[u][k], av[u][2 * k], av[u][2 * k + 1], md[r].pn);
+            x[r][k] = i == 0 ? v : x[r][k] + v;
           }
         }
       }
