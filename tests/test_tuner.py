@@ -92,3 +92,46 @@ def test_malformed_files_are_refused(tmp_path, text):
     with pytest.raises(r.RlweError):
         r.rlwe_tuner_load(t, str(tmp_path / "missing.json"))
     r.rlwe_tuner_destroy(t)
+
+
+def test_mutated_files_load_whole_or_are_refused(tmp_path):
+    """Seeded byte mutations of a valid cache file (flipped and inserted bytes, cut
+    ranges, truncation): each load either succeeds or raises RLWE_EINVAL with the tuner
+    unchanged; none crashes the process."""
+    import random
+    t = r.rlwe_tuner_create("d")
+    for i, (K, M, T) in enumerate(((2048, 2048, 128), (512, 2048, 8), (8192, 2048, 256))):
+        r.rlwe_tuner_put(t, r.rlwe_tune_key(4096, 2, K, M, 1, False, T), sched(tt=i, ms=1.0 + i))
+    good = str(tmp_path / "good.json")
+    r.rlwe_tuner_save(t, good)
+    r.rlwe_tuner_destroy(t)
+    src = open(good, "rb").read()
+    rng = random.Random(7)
+    path = tmp_path / "m.json"
+    refused = 0
+    for _ in range(400):
+        b = bytearray(src)
+        for _ in range(rng.randint(1, 6)):
+            if not b:
+                break
+            pos, op = rng.randrange(len(b)), rng.random()
+            if op < 0.4:
+                b[pos] = rng.randrange(256)
+            elif op < 0.6:
+                del b[pos:pos + rng.randint(1, 30)]
+            elif op < 0.85:
+                b[pos:pos] = bytes(rng.choice(b'{}[]":,0123456789-eE.') for _ in range(rng.randint(1, 8)))
+            else:
+                del b[pos:]
+        path.write_bytes(bytes(b))
+        u = r.rlwe_tuner_create("d")
+        k = r.rlwe_tune_key(4096, 2, 1, 1, 1, False, 1)
+        r.rlwe_tuner_put(u, k, sched(tt=5))
+        try:
+            n = r.rlwe_tuner_load(u, str(path))
+            assert 0 <= n <= 3 and r.rlwe_tuner_size(u) == 1 + n
+        except r.RlweError as e:
+            refused += 1
+            assert e.code == r.RLWE_EINVAL and r.rlwe_tuner_size(u) == 1
+        r.rlwe_tuner_destroy(u)
+    assert refused > 300
