@@ -1,5 +1,6 @@
 """Host logic of bench.py (no GPU): the roofline accounting of both methods, the
-source-hash guard of the measured traffic records, and the one-GPU contract."""
+algorithmic bytes of the NTT products, the source-hash guard of the measured traffic
+records, and the one-GPU contract."""
 
 import math
 import os
@@ -44,6 +45,21 @@ def test_roofline_matrix_cores_and_the_dominant_kernel():
     assert other["achieved"] == pytest.approx(ops / 7e-3 / 1e12)
     assert other["peak"] == bench.INT8_PEAK_TOPS
     assert other["frac_of_measured"] == pytest.approx(other["achieved"] / PEAKS["mfma_int8_TOPS"])
+
+
+def test_algorithmic_bytes_of_the_ntt_products():
+    N, P = 4096, 2
+    prod = dict(T=128, M=2048, K=2048, kept=9, ntt=True, n_o=1)
+    out = 128 * 2048 * (N + 1) * 4         # switched outputs, u32
+    masks = 128 * 1 * P * N * 16           # transformed masks with Shoup companions
+    weights = 2048 * 1 * P * N * 8         # transformed weight polynomials
+    assert bench.ntt_algorithmic_bytes([prod], N, P) == out + masks + weights == 4447010816
+    two = dict(prod, K=8192)               # two input blocks: twice the masks and weights
+    assert bench.ntt_algorithmic_bytes([two], N, P) == out + 2 * masks + 2 * weights
+    packed = dict(prod, n_o=2)             # half the weight polynomials
+    assert bench.ntt_algorithmic_bytes([packed], N, P) == out + masks + weights // 2
+    mf = dict(prod, ntt=False)             # matrix-core products are not counted
+    assert bench.ntt_algorithmic_bytes([prod, mf], N, P) == out + masks + weights
 
 
 def test_traffic_records_follow_their_sources(monkeypatch):
